@@ -1,0 +1,228 @@
+"""Benchmark: binned CWB iterations per second at n = 1e6, p = 200 on one MI355X.
+
+One step = one full boosting iteration of the hot path (row pass, histogram
+pass over the uint16 bin-index matrix, per-learner FP64 solves and the
+selection) on the headline workload: plain CWB, L2 loss, n = 1,000,000 rows,
+p = 200 Uniform[0,1] features (20 informative), 1,000 bins, cubic P-splines
+with 24 bases, df = 5, nu = 0.1.  Inputs are synthetic (seed 2) and resident
+in HBM before timing starts.  Prints one JSON line.
+
+Extra legs (on by default, each a few seconds): the FP64 CPU oracle timed on
+the first iterations of the same input (cpu_baseline, and the selection
+parity of those iterations), batched fits (many heterogeneous fits per
+launch) against a plain loop of the same single fits, and the fit server
+under a Poisson request stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("CWB iters/sec at n=1e6,p=200 (HBM GB/s %peak); batched/served fits/s + p99")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hist_c2_traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2110_03513_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch: float):
+    """HBM bytes per hist launch from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def headline(args, torch, cwb, datagen):
+    n, p, nb = args.n, args.p, 1000
+    log(f"[bench] generating C2 input n={n} p={p}")
+    M = args.warmup + args.steps + args.profile_iters
+    prob = datagen.config2(n=n, p=p, M=M, n_bins=nb)
+    t0 = time.perf_counter()
+    fit = cwb.Fit(prob)
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] setup {setup_s:.2f}s; warmup {args.warmup} iterations")
+    fit.run(args.warmup)
+    fit.sync()
+    # timed region: exactly `steps` iterations, HIP events around every
+    # histogram-pass launch on the fit's stream
+    fit.set_timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit.run(args.steps)
+    fit.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hist_ms, hist_n = fit.kernel_time("hist")
+    # after the timed region: per-kernel durations of the other two kernels
+    st_us = sel_us = None
+    if args.profile_iters > 0:
+        fit.set_timing(6)
+        fit.run(args.profile_iters)
+        fit.sync()
+        ms, cnt = fit.kernel_time("state")
+        st_us = ms / max(cnt, 1) * 1e3
+        ms, cnt = fit.kernel_time("select")
+        sel_us = ms / max(cnt, 1) * 1e3
+    fit.set_timing(0)
+    tr = fit.trace()
+    fit.close()
+    per_iter = wall / args.steps
+    iters_s = 1.0 / per_iter
+    alg_iter_bytes = 2.0 * n * p + 14.0 * n
+    hist_bytes = 2.0 * n * p + 4.0 * n
+    hist_avg_s = hist_ms / 1e3 / max(hist_n, 1)
+    achieved = hist_bytes / hist_avg_s / 1e9
+    traffic = measured_traffic(hist_bytes)
+    return prob, tr, {
+        "iters_s": iters_s, "ms_per_step": per_iter * 1e3, "setup_s": setup_s,
+        "iter_gbs": alg_iter_bytes * iters_s / 1e9,
+        "hist_avg_us": hist_avg_s * 1e6, "state_avg_us": st_us, "select_avg_us": sel_us,
+        "hist_launches": hist_n,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "alg_iter_bytes": alg_iter_bytes, "hist_bytes_per_launch": hist_bytes,
+    }
+
+
+def cpu_baseline(args, prob, gpu_trace):
+    import oracle
+    iters = args.cpu_iters
+    cores = oracle.max_threads()
+    log(f"[bench] CPU oracle: {iters} iterations on {cores} threads")
+    t0 = time.perf_counter()
+    o1 = oracle.fit(dict(prob, M=1))
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o = oracle.fit(dict(prob, M=1 + iters))
+    t_all = time.perf_counter() - t0
+    per_iter = max((t_all - t_setup) / iters, 1e-9)
+    m = min(len(gpu_trace["k"]), 1 + iters)
+    match = int(np.sum(gpu_trace["k"][:m] == o["k"][:m]))
+    del o1
+    return {
+        "value": round(1.0 / per_iter, 4), "unit": "iters/s", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 C oracle, iterations 2..{1 + iters} of the same n={prob['x'].shape[0]} "
+                   f"p={prob['x'].shape[1]} input (setup excluded, {t_setup:.1f}s)"),
+    }, {"iterations_compared": m, "k_match": match}
+
+
+def batched(args, torch, cwb, datagen):
+    specs = datagen.config4_specs(count=args.batch_fits, M=args.batch_iters)
+    log(f"[bench] batched: {len(specs)} fits, M={args.batch_iters}")
+    probs = [datagen.config4_problem(s) for s in specs]
+    t0 = time.perf_counter()
+    fits = [cwb.Fit(p) for p in probs]
+    setup = time.perf_counter() - t0
+    b = cwb.Batch(fits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(args.batch_iters)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    ks = [f.trace()["k"] for f in fits]
+    b.close()
+    for f in fits:
+        f.close()
+    # the same fits one after another, each alone
+    fits = [cwb.Fit(p) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in fits:
+        f.run(args.batch_iters)
+    for f in fits:
+        f.sync()
+    t_loop = time.perf_counter() - t0
+    same = all(np.array_equal(f.trace()["k"], k) for f, k in zip(fits, ks))
+    for f in fits:
+        f.close()
+    bytes_iter = sum(2.0 * p["x"].shape[0] * p["x"].shape[1] * (1 if p["variant"] == "cwb" else 1)
+                     for p in probs)
+    return {"fits": len(probs), "iters": args.batch_iters,
+            "fits_per_s": round(len(probs) / t_batch, 3),
+            "loop_fits_per_s": round(len(probs) / t_loop, 3),
+            "speedup_vs_loop": round(t_loop / t_batch, 3),
+            "index_gbs": round(bytes_iter * args.batch_iters / t_batch / 1e9, 1),
+            "same_selections_as_alone": bool(same), "setup_s": round(setup, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--p", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--profile-iters", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batch-fits", type=int, default=64)
+    ap.add_argument("--batch-iters", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    from paper_2110_03513_amd import cwb, datagen
+    cwb.lib()
+    prob, tr, h = headline(args, torch, cwb, datagen)
+    out = {
+        "metric": METRIC, "value": round(h["iters_s"], 2), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i64",
+        "data": "synthetic",
+        "config": {"workload": (f"binned CWB, L2, n={args.n}, p={args.p}, 1000 bins, cubic "
+                                "P-splines d=24 df=5, nu=0.1 (synthetic, seed 2)"),
+                   "global_batch": args.n, "parallelism": "1 GPU"},
+        "precision": "uint16 bin indices; int64 fixed-point histograms; fp32 model state; "
+                     "fp64 merge, solves and selection",
+        "hbm_gbs": round(h["iter_gbs"], 1),
+        "hbm_frac": round(h["iter_gbs"] / HBM_PEAK_GBS, 4),
+        "roofline": h["roofline"],
+        "kernels_us": {"hist": round(h["hist_avg_us"], 2),
+                       "state": h["state_avg_us"] and round(h["state_avg_us"], 2),
+                       "select": h["select_avg_us"] and round(h["select_avg_us"], 2)},
+        "setup_s": round(h["setup_s"], 2),
+    }
+    if not args.no_cpu:
+        cb, par = cpu_baseline(args, prob, tr)
+        out["cpu_baseline"] = cb
+        out["parity"] = par
+    del prob
+    if not args.no_batch:
+        out["batched"] = batched(args, torch, cwb, datagen)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -361,6 +361,8 @@ typedef struct {
   double* f;              /* n: f^[M] on all rows */
   double* coef_f;         /* sum d: aggregated primary-model coefficients */
   double* coef_h;         /* sum d: aggregated momentum-model coefficients */
+  double* rtr;            /* M: r^T r of the signal fitted by the primary learner */
+  double* rtr_cor;        /* M: c^T c of the corrected signal (ACWB steps) */
 } orc_result;
 
 typedef struct {
@@ -457,6 +459,7 @@ int orc_sizes(const orc_problem* pr, int32_t* d_max, int32_t* sum_d) {
 typedef struct {
   int k;          /* selected learner */
   int own;        /* own argmin */
+  double rtr;     /* r^T r over the rows fitted */
   double sse;     /* SSE of the selected learner */
   double gap;     /* SSE(selected) - SSE(best) if forced, else SSE(2nd) - SSE(best) */
   double theta[64];
@@ -536,6 +539,12 @@ static void find_best(const feat_t* F, int p, int64_t n, const double* r,
   else out->gap = (second >= 0) ? sse_all[second] - sse_all[best] : INFINITY;
   out->sse = sse_all[out->k];
   for (int a = 0; a < d_max; ++a) out->theta[a] = theta_all[(size_t)out->k * d_max + a];
+  double rtr = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!all && mask && mask[i]) continue;
+    rtr += r[i] * r[i];
+  }
+  out->rtr = rtr;
 }
 
 /* f_i += step * b_k(x_i, theta) on all rows. */
@@ -743,6 +752,7 @@ int orc_fit(const orc_problem* pr, orc_result* res) {
       res->kcor[mi] = -1;
       res->own_kcor[mi] = -1;
       res->gapcor[mi] = 0.0;
+      res->rtr_cor[mi] = 0.0;
       for (int a = 0; a < d_max; ++a) res->thetacor[(size_t)mi * d_max + a] = 0.0;
     } else {
       /* ACWB step on the training rows (Algorithm 2). */
@@ -774,12 +784,14 @@ int orc_fit(const orc_problem* pr, orc_result* res) {
       res->kcor[mi] = pc.k;
       res->own_kcor[mi] = pc.own;
       res->gapcor[mi] = pc.gap;
+      res->rtr_cor[mi] = pc.rtr;
       for (int a = 0; a < d_max; ++a) res->thetacor[(size_t)mi * d_max + a] = pc.theta[a];
     }
     res->k[mi] = pk.k;
     res->own_k[mi] = pk.own;
     res->gap[mi] = pk.gap;
     res->sse[mi] = pk.sse;
+    res->rtr[mi] = pk.rtr;
     for (int a = 0; a < d_max; ++a) res->theta[(size_t)mi * d_max + a] = pk.theta[a];
     res->risk_train[m] = empirical_risk(loss, pr->y, f, n, mask, 0);
     res->risk_val[m] = mask ? empirical_risk(loss, pr->y, f, n, mask, 1) : 0.0;

@@ -1,0 +1,142 @@
+// cwb_internal.h -- device data layout shared by the host runtime and the
+// gfx950 kernels of the binned componentwise-boosting library.
+//
+// HBM layout of one fit (all inside the caller's workspace):
+//   X      p x n_pad uint16, feature-major: the index vectors of Section 3.1.1,
+//          one contiguous row of n_pad entries per learner (16-byte aligned)
+//   y, fg, h, c, r   n_pad floats each (model state, Algorithm 2 notation:
+//          fg holds f, or g while an ACWB update is pending)
+//   per-bin tables: first nonzero basis index and the (degree+1) nonzero
+//          reduced-design values of every design point (banded Z^b)
+//   per-learner d x d FP64: inverse penalised Gram (G + lambda D)^-1 and G,
+//          one set for the training rows and one for all rows (HCWB)
+//   q, theta, candidate update tables for every learner (per iteration)
+//   traces, aggregated coefficients, risk partials, control block.
+// Rows are permuted so that training rows come first: [0, n_train) train,
+// [n_train, n) validation, [n, n_pad) zero padding.
+#pragma once
+#include <cstdint>
+
+namespace cwb {
+
+constexpr int kRowsPerThread = 8;                       // one 16-byte X load
+constexpr int kStateThreads = 256;
+constexpr int kStateRows = kStateThreads * kRowsPerThread;  // rows per row-pass block
+constexpr int kSelectThreads = 256;
+constexpr int kMaxBand = 4;      // nonzero basis values per design point (cubic)
+constexpr int kMaxD = 64;        // largest basis size
+constexpr int kMaxBins = 8192;   // largest n* (one learner's histogram must fit LDS)
+constexpr int kNumSig = 2;       // signals: pseudo-residuals r, corrected residuals c
+
+// One base learner.
+struct FeatDev {
+  int32_t nb;        // design points (P-spline) or levels (ridge)
+  int32_t band;      // nonzeros per reduced-design row: degree+1, or 1 for ridge
+  int32_t d;         // basis size
+  int32_t coef_off;  // offset in the concatenated coefficient vectors
+  int64_t bin_off;   // offset into the per-bin arrays
+  int64_t mat_off;   // offset (doubles) into the d x d matrix arrays
+};
+
+// Mutable per-fit control block, written only by kernels after create.
+struct Ctl {
+  int32_t m_done;       // iterations whose selection is complete
+  int32_t pending;      // update tables of iteration m_done not yet applied
+  int32_t pend_acwb;    // iteration m_done was an ACWB step
+  int32_t k;            // learner selected in iteration m_done
+  int32_t kcor;         // correction learner of iteration m_done (-1: none)
+  int32_t switched;     // HCWB: CWB phase reached
+  int32_t switch_iter;  // HCWB: first CWB iteration (-1 until switched)
+  int32_t counter;      // HCWB: consecutive validation-risk rises
+  double eta;           // momentum step of iteration m_done
+  double rval_prev;     // HCWB: validation risk of the previous model
+  uint32_t absmax[kNumSig];  // bits of max |signal| of the current iteration
+  uint32_t sel_done;    // selection blocks finished this iteration
+  uint32_t val_done;    // validation-risk blocks finished
+  int32_t error;        // non-finite model state seen
+  int32_t pad;
+};
+
+struct FitDev {
+  int64_t n, n_pad, n_train;
+  int32_t p, nb_max, d_max, sum_d;
+  int32_t loss, variant, M, patience;
+  double nu, gamma;
+  int32_t n_row_blocks;  // row-pass blocks: ceil(n_pad / kStateRows)
+  int32_t n_val_blocks;  // validation blocks over [n_train, n)
+  int32_t nsig_max;      // 2 for ACWB / HCWB, else 1
+  int32_t pad;
+  const uint16_t* X;
+  const float* y;
+  float* fg;
+  float* h;
+  float* c;
+  float* r;
+  const FeatDev* feat;
+  const int32_t* bstart;   // per design point: first nonzero basis index
+  const double* bval;      // per design point: kMaxBand values
+  const int32_t* jr;       // per basis index: [first, last] design point in its support
+  const double* ainv[2];   // [0] training rows, [1] all rows
+  const double* gram[2];
+  double* q;               // [kNumSig][p]
+  double* theta;           // [kNumSig][p][d_max]
+  float* table;            // [kNumSig][p][nb_max] candidate update tables Z^b theta
+  int32_t* tr_k;
+  double* tr_theta;        // [M][d_max]
+  int32_t* tr_kcor;
+  double* tr_thetacor;
+  double* tr_risk;         // [M+1]
+  double* tr_val;          // [M+1]
+  double* tr_gap;          // [M]
+  double* coef_f;          // [sum_d]
+  double* coef_h;          // [sum_d]
+  double* risk_part;       // [n_row_blocks][2]
+  double* val_part;        // [n_val_blocks]
+  Ctl* ctl;
+};
+
+// Histogram schedule.  A segment is one (fit, feature group, row range)
+// whose histogram is accumulated in LDS and flushed once, as int64, to its
+// own partial slot.  Row ranges are in 8-row units of the fit's n_pad and
+// are rescaled at run time to the rows the current phase fits.
+struct Seg {
+  int32_t fit;
+  int32_t k0;      // first learner of the group
+  int32_t nf;      // learners in the group
+  int32_t pad;
+  int64_t u0, u1;  // unit range within [0, n_pad / 8)
+  int64_t slot;    // offset (int64 words) of the partial slot
+};
+
+struct GroupSegs {
+  int64_t seg_begin, seg_end;  // segments of one (fit, group), consecutive
+};
+
+struct StateItem {   // one row-pass block
+  int32_t fit;
+  int32_t blk;       // block index within the fit
+};
+
+struct SelItem {     // one learner's solve
+  int32_t fit;
+  int32_t k;
+  int64_t grp;       // index into the GroupSegs table
+};
+
+// Fixed-point exponent for the int64 histogram of a signal whose largest
+// magnitude has float bits `absmax_bits`, summed over at most n_fit rows:
+// |r| * 2^e < 2^(62 - N) with n_fit < 2^N, so no sum can overflow.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline int scale_exponent(uint32_t absmax_bits, int64_t n_fit) {
+  if (absmax_bits == 0u) return 0;
+  uint32_t ex = (absmax_bits >> 23) & 0xffu;   // biased exponent of max |r|
+  int E = (int)ex - 126;                        // max |r| < 2^E
+  if (ex == 0u) E = -125;                       // subnormal
+  int N = 0;
+  for (int64_t v = n_fit; v > 0; v >>= 1) ++N;  // n_fit < 2^N
+  return 62 - N - E;
+}
+
+}  // namespace cwb

@@ -1,0 +1,20 @@
+// kernels.h -- host launchers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "cwb_internal.h"
+
+namespace cwb {
+
+hipError_t launch_state(hipStream_t st, const FitDev* fits, const StateItem* items, int nitems,
+                        int nb_max, int final_mode);
+hipError_t launch_hist(hipStream_t st, int nt, int fmax, int blocks, size_t lds, const FitDev* fits,
+                       const Seg* segs, const int64_t* blk, long long* partials);
+hipError_t launch_select(hipStream_t st, const FitDev* fits, const SelItem* items, int nitems,
+                         int nb_max, const int64_t* grp_ptr, const int64_t* grp_seg,
+                         const Seg* segs, const long long* partials);
+hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* items, int nitems,
+                          int nb_max);
+hipError_t launch_finalize(hipStream_t st, const FitDev* fits, int nfits);
+
+}  // namespace cwb

@@ -1,0 +1,990 @@
+// runtime.cpp -- C ABI of the library: fit and batch objects, the histogram
+// schedule, the workspace layout and the per-iteration launch sequence.
+#include "runtime.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "kernels.h"
+
+namespace cwb {
+
+namespace {
+thread_local std::string g_err;
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return set_error(CWB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int device_cus(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+  return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
+}  // namespace
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
+  if (!pr) { *err = "null problem"; return CWB_E_INVALID_ARG; }
+  if (pr->n < 2 || pr->p < 1 || !pr->specs) { *err = "need n >= 2, p >= 1 and specs"; return CWB_E_INVALID_ARG; }
+  if (pr->M < 1) { *err = "M must be >= 1"; return CWB_E_INVALID_ARG; }
+  if (pr->n > (int64_t)INT32_MAX) { *err = "n above 2^31 - 1 rows is not supported"; return CWB_E_UNSUPPORTED; }
+  sh->n = pr->n;
+  sh->n_pad = (pr->n + 63) / 64 * 64;
+  int64_t nt = pr->n;
+  if (pr->val_mask) {
+    nt = 0;
+    for (int64_t i = 0; i < pr->n; ++i) nt += pr->val_mask[i] ? 0 : 1;
+  }
+  sh->n_train = nt;
+  sh->p = pr->p;
+  sh->M = pr->M;
+  sh->variant = pr->variant;
+  sh->nsig_max = (pr->variant == CWB_CWB) ? 1 : 2;
+  sh->nb_max = sh->d_max = sh->sum_d = 0;
+  sh->sum_nb = sh->sum_d2 = 0;
+  for (int j = 0; j < pr->p; ++j) {
+    const cwb_learner_spec& s = pr->specs[j];
+    int nb, d;
+    if (s.kind == CWB_RIDGE_CAT) {
+      nb = s.n_levels;
+      d = s.n_levels;
+    } else {
+      nb = s.n_bins == -1 ? (int)std::floor(std::sqrt((double)pr->n)) : s.n_bins;
+      if (nb < 2) nb = 2;
+      d = s.n_interior_knots + s.degree + 1;
+    }
+    if (nb < 1 || nb > kMaxBins || d < 1 || d > kMaxD) {
+      *err = "learner " + std::to_string(j) + ": bins must be 2..8192 and basis size 1..64";
+      return (nb > kMaxBins && nb <= 65535) ? CWB_E_UNSUPPORTED : CWB_E_INVALID_ARG;
+    }
+    sh->nb_max = std::max(sh->nb_max, nb);
+    sh->d_max = std::max(sh->d_max, d);
+    sh->sum_d += d;
+    sh->sum_nb += nb;
+    sh->sum_d2 += (int64_t)d * d;
+  }
+  sh->n_row_blocks = (int)((sh->n_pad + kStateRows - 1) / kStateRows);
+  const int64_t nv = sh->n - sh->n_train;
+  sh->n_val_blocks = (sh->variant == CWB_HCWB && nv > 0) ? (int)((nv + kStateRows - 1) / kStateRows) : 0;
+  return CWB_OK;
+}
+
+Tune make_tune(int nb_max, int nsig_max, int p_max) {
+  Tune t;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  t.cus = device_cus(dev);
+  t.nt = env_int("CWB_HIST_NT", 512);
+  if (t.nt != 256 && t.nt != 512 && t.nt != 1024) t.nt = 512;
+  t.lds_kb = std::max(8, std::min(160, env_int("CWB_HIST_LDS_KB", 64)));
+  t.blocks_per_cu = std::max(1, std::min(8, env_int("CWB_HIST_BPC", 1)));
+  t.slices = std::max(1, std::min(64, env_int("CWB_HIST_SLICES", 1)));
+  const size_t per_learner = (size_t)nsig_max * nb_max * sizeof(long long);
+  int F = (int)((size_t)t.lds_kb * 1024 / per_learner);
+  const int fenv = env_int("CWB_HIST_F", 0);
+  if (fenv > 0) F = fenv;
+  F = std::max(1, std::min(16, F));
+  F = std::min(F, std::max(1, p_max));
+  while (F > 1 && (size_t)F * per_learner > 160 * 1024) --F;
+  t.F = F;
+  t.fmax = 1;
+  while (t.fmax < F) t.fmax *= 2;
+  return t;
+}
+
+Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t) {
+  Schedule S;
+  struct Item {
+    int fit, k0, nf;
+    int64_t u0, u1;
+  };
+  std::vector<Item> items;
+  int64_t W = 0;
+  for (int fi = 0; fi < (int)fits.size(); ++fi) {
+    const FitShape& sh = *fits[fi];
+    const int64_t U = sh.n_pad / 8;
+    const int groups = (sh.p + t.F - 1) / t.F;
+    const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(t.slices, U));
+    for (int s = 0; s < slices; ++s) {
+      const int64_t u0 = U * s / slices, u1 = U * (s + 1) / slices;
+      for (int g = 0; g < groups; ++g) {
+        const int k0 = g * t.F;
+        const int nf = std::min(t.F, sh.p - k0);
+        items.push_back({fi, k0, nf, u0, u1});
+        W += (int64_t)nf * (u1 - u0);
+      }
+    }
+  }
+  const int B = std::max(1, t.cus * t.blocks_per_cu);
+  S.blocks = B;
+  std::vector<int64_t> seg_vb;
+  int64_t vb = 0, wpos = 0;
+  for (const Item& it : items) {
+    int64_t u = it.u0;
+    while (u < it.u1) {
+      const int64_t wp = wpos + (u - it.u0) * it.nf;
+      while (vb < B - 1 && ((vb + 1) * W) / B <= wp) ++vb;
+      int64_t take;
+      if (vb == B - 1) {
+        take = it.u1 - u;
+      } else {
+        const int64_t bend = ((vb + 1) * W) / B;
+        take = (bend - wp + it.nf - 1) / it.nf;
+      }
+      const int64_t ue = std::min(it.u1, u + std::max<int64_t>(1, take));
+      Seg sg;
+      sg.fit = it.fit;
+      sg.k0 = it.k0;
+      sg.nf = it.nf;
+      sg.pad = 0;
+      sg.u0 = u;
+      sg.u1 = ue;
+      sg.slot = 0;
+      S.segs.push_back(sg);
+      seg_vb.push_back(vb);
+      u = ue;
+    }
+    wpos += (int64_t)it.nf * (it.u1 - it.u0);
+  }
+  // partial slots
+  int64_t off = 0;
+  for (Seg& sg : S.segs) {
+    sg.slot = off;
+    const FitShape& sh = *fits[sg.fit];
+    off += (int64_t)sh.nsig_max * sg.nf * sh.nb_max;
+  }
+  S.partial_words = off;
+  // virtual block ranges, then XCD-aware physical mapping: consecutive
+  // virtual blocks go to the same XCD (workgroups are dealt round-robin
+  // over the 8 XCDs), so a row slice stays in one XCD's L2.
+  std::vector<int64_t> vbeg(B, 0), vend(B, 0);
+  {
+    size_t s = 0;
+    for (int v = 0; v < B; ++v) {
+      vbeg[v] = (int64_t)s;
+      while (s < S.segs.size() && seg_vb[s] == v) ++s;
+      vend[v] = (int64_t)s;
+    }
+  }
+  S.blk.assign(2 * (size_t)B, 0);
+  const int X = 8;
+  for (int b = 0; b < B; ++b) {
+    const int v = (B % X == 0) ? (b % X) * (B / X) + b / X : b;
+    S.blk[2 * b] = vbeg[v];
+    S.blk[2 * b + 1] = vend[v];
+  }
+  // group tables
+  S.grp_base.resize(fits.size() + 1);
+  int64_t ng = 0;
+  for (size_t fi = 0; fi < fits.size(); ++fi) {
+    S.grp_base[fi] = ng;
+    ng += (fits[fi]->p + t.F - 1) / t.F;
+  }
+  S.grp_base[fits.size()] = ng;
+  std::vector<std::vector<int64_t>> lists(ng);
+  for (size_t s = 0; s < S.segs.size(); ++s) {
+    const Seg& sg = S.segs[s];
+    lists[S.grp_base[sg.fit] + sg.k0 / t.F].push_back((int64_t)s);
+  }
+  S.grp_ptr.assign(ng + 1, 0);
+  for (int64_t g = 0; g < ng; ++g) {
+    S.grp_ptr[g + 1] = S.grp_ptr[g] + (int64_t)lists[g].size();
+    for (int64_t v : lists[g]) S.grp_seg.push_back(v);
+  }
+  int ns_max = 1, nb_max = 1;
+  for (const FitShape* f : fits) {
+    ns_max = std::max(ns_max, f->nsig_max);
+    nb_max = std::max(nb_max, f->nb_max);
+  }
+  S.lds = (size_t)ns_max * t.F * nb_max * sizeof(long long);
+  return S;
+}
+
+// Every (fit, group) must be covered by its segments exactly once over
+// [0, n_pad/8), slots must be disjoint and inside the partial buffer, and
+// every block range must index existing segments.  Checked on the host
+// before a schedule is uploaded.
+bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fits, const Tune& t,
+                       std::string* why) {
+  const int64_t nseg = (int64_t)S.segs.size();
+  if ((int64_t)S.blk.size() != 2 * (int64_t)S.blocks) { *why = "block table size"; return false; }
+  std::vector<int> seen(nseg, 0);
+  for (int b = 0; b < S.blocks; ++b) {
+    const int64_t a = S.blk[2 * b], e = S.blk[2 * b + 1];
+    if (a < 0 || e < a || e > nseg) { *why = "block range"; return false; }
+    for (int64_t s = a; s < e; ++s) seen[s] += 1;
+  }
+  for (int64_t s = 0; s < nseg; ++s)
+    if (seen[s] != 1) { *why = "segment not owned by exactly one block"; return false; }
+  int64_t slot_end = 0;
+  for (const Seg& sg : S.segs) {
+    if (sg.fit < 0 || sg.fit >= (int)fits.size()) { *why = "segment fit"; return false; }
+    const FitShape& sh = *fits[sg.fit];
+    if (sg.nf < 1 || sg.nf > t.F || sg.nf > t.fmax || sg.k0 < 0 || sg.k0 + sg.nf > sh.p ||
+        sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
+    if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
+    if (sg.slot != slot_end) { *why = "slot order"; return false; }
+    slot_end += (int64_t)sh.nsig_max * sg.nf * sh.nb_max;
+    if ((size_t)sh.nsig_max * sg.nf * sh.nb_max * sizeof(long long) > S.lds) { *why = "LDS size"; return false; }
+  }
+  if (slot_end != S.partial_words) { *why = "partial size"; return false; }
+  if (S.lds > 160 * 1024) { *why = "LDS above 160 KiB"; return false; }
+  const int64_t ng = (int64_t)S.grp_ptr.size() - 1;
+  for (size_t fi = 0; fi < fits.size(); ++fi) {
+    const int groups = (fits[fi]->p + t.F - 1) / t.F;
+    for (int g = 0; g < groups; ++g) {
+      const int64_t gi = S.grp_base[fi] + g;
+      if (gi >= ng) { *why = "group table"; return false; }
+      std::vector<std::pair<int64_t, int64_t>> iv;
+      for (int64_t q = S.grp_ptr[gi]; q < S.grp_ptr[gi + 1]; ++q) {
+        const Seg& sg = S.segs[S.grp_seg[q]];
+        if (sg.fit != (int)fi || sg.k0 != g * t.F) { *why = "group membership"; return false; }
+        iv.push_back({sg.u0, sg.u1});
+      }
+      std::sort(iv.begin(), iv.end());
+      int64_t pos = 0;
+      for (auto& v : iv) {
+        if (v.first != pos) { *why = "group rows not covered exactly once"; return false; }
+        pos = v.second;
+      }
+      if (pos != fits[fi]->n_pad / 8) { *why = "group rows incomplete"; return false; }
+    }
+  }
+  return true;
+}
+
+Layout make_layout(const FitShape& sh, const Schedule& s) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, 256);
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t np = (size_t)sh.n_pad;
+  const bool two = sh.nsig_max == 2;
+  // mutable state first (contiguous, for checkpoints)
+  L.state_begin = take(0);
+  L.ctl = take(sizeof(Ctl));
+  L.fg = take(np * 4);
+  L.h = take(two ? np * 4 : 0);
+  L.c = take(two ? np * 4 : 0);
+  L.q = take((size_t)kNumSig * sh.p * 8);
+  L.theta = take((size_t)kNumSig * sh.p * sh.d_max * 8);
+  L.table = take((size_t)kNumSig * sh.p * sh.nb_max * 4);
+  L.trk = take((size_t)sh.M * 4);
+  L.trth = take((size_t)sh.M * sh.d_max * 8);
+  L.trkc = take((size_t)sh.M * 4);
+  L.trthc = take((size_t)sh.M * sh.d_max * 8);
+  L.trrisk = take((size_t)(sh.M + 1) * 8);
+  L.trval = take((size_t)(sh.M + 1) * 8);
+  L.trgap = take((size_t)sh.M * 8);
+  L.coef_f = take((size_t)sh.sum_d * 8);
+  L.coef_h = take((size_t)sh.sum_d * 8);
+  L.state_end = align_up(off, 256);
+  // inputs and tables
+  L.X = take((size_t)sh.p * np * 2);
+  L.y = take(np * 4);
+  L.r = take(np * 4);
+  L.feat = take((size_t)sh.p * sizeof(FeatDev));
+  L.bstart = take((size_t)sh.sum_nb * 4);
+  L.bval = take((size_t)sh.sum_nb * kMaxBand * 8);
+  L.jr = take((size_t)sh.sum_d * 2 * 4);
+  for (int set = 0; set < 2; ++set) {
+    L.ainv[set] = take((size_t)sh.sum_d2 * 8);
+    L.gram[set] = take((size_t)sh.sum_d2 * 8);
+  }
+  L.riskpart = take((size_t)sh.n_row_blocks * 2 * 8);
+  L.valpart = take((size_t)std::max(1, sh.n_val_blocks) * 8);
+  L.fitdev = take(sizeof(FitDev));
+  // solo schedule
+  L.segs = take(s.segs.size() * sizeof(Seg));
+  L.blk = take(s.blk.size() * 8);
+  L.grp_ptr = take(s.grp_ptr.size() * 8);
+  L.grp_seg = take(s.grp_seg.size() * 8);
+  L.partials = take((size_t)s.partial_words * 8);
+  L.st_items = take((size_t)sh.n_row_blocks * sizeof(StateItem));
+  L.sel_items = take((size_t)sh.p * sizeof(SelItem));
+  L.val_items = take((size_t)std::max(1, sh.n_val_blocks) * sizeof(StateItem));
+  L.total = align_up(off, 256);
+  return L;
+}
+
+namespace {
+
+void timer_reset(KernelTimer& t) {
+  t.used = 0;
+  t.total_ms = 0.0;
+  t.launches = 0;
+}
+
+// Record a start or stop event when timing is on.
+hipError_t timer_mark(KernelTimer& t, hipStream_t st) {
+  if (t.used == t.ev.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    t.ev.push_back(e);
+  }
+  return hipEventRecord(t.ev[t.used++], st);
+}
+
+hipError_t timer_collect(KernelTimer& t) {
+  for (size_t i = 0; i + 1 < t.used; i += 2) {
+    hipError_t r = hipEventSynchronize(t.ev[i + 1]);
+    if (r != hipSuccess) return r;
+    float ms = 0.0f;
+    r = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]);
+    if (r != hipSuccess) return r;
+    t.total_ms += ms;
+    t.launches += 1;
+  }
+  t.used = 0;
+  return hipSuccess;
+}
+
+void timer_free(KernelTimer& t) {
+  for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  t.ev.clear();
+  t.used = 0;
+}
+
+// One iteration for a set of fits sharing a schedule.
+int enqueue_iteration(hipStream_t st, const FitDev* d_fits, const Schedule& S, const Tune& t,
+                      const StateItem* d_st, int n_st, const SelItem* d_sel, int n_sel,
+                      const StateItem* d_val, int n_val, int nb_max, const Seg* d_segs,
+                      const int64_t* d_blk, const int64_t* d_gp, const int64_t* d_gs,
+                      long long* d_part, cwb_fit* timed) {
+  const int tm = timed ? timed->timing : 0;
+  if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
+  HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
+  if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
+  if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
+  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+  if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
+  if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
+  HIP_TRY(launch_select(st, d_fits, d_sel, n_sel, nb_max, d_gp, d_gs, d_segs, d_part));
+  if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
+  if (n_val > 0) HIP_TRY(launch_valrisk(st, d_fits, d_val, n_val, nb_max));
+  return CWB_OK;
+}
+
+template <typename T>
+T* dptr(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+}  // namespace
+
+int finalize_fit(cwb_fit* f) {
+  HIP_TRY(hipSetDevice(f->device));
+  StateItem* d_st = dptr<StateItem>(f->ws, f->lay.st_items);
+  HIP_TRY(launch_state(f->stream, f->d_fit, d_st, f->n_st, f->shape.nb_max, 1));
+  HIP_TRY(launch_finalize(f->stream, f->d_fit, 1));
+  return CWB_OK;
+}
+
+}  // namespace cwb
+
+using namespace cwb;
+
+extern "C" {
+
+int cwb_version(int* major, int* minor) {
+  if (major) *major = CWB_VERSION_MAJOR;
+  if (minor) *minor = CWB_VERSION_MINOR;
+  return CWB_OK;
+}
+
+const char* cwb_last_error(void) { return g_err.c_str(); }
+
+int cwb_bin_feature(const double* x, int64_t n, int32_t n_bins, uint16_t* ind_out, double* z_out) {
+  try {
+    std::string err;
+    const int rc = bin_one_feature(x, n, n_bins, ind_out, z_out, &err);
+    return rc ? set_error(rc, err) : CWB_OK;
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
+}
+
+int cwb_workspace_bytes(const cwb_problem* pr, size_t* bytes) {
+  try {
+    if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
+    std::string err;
+    FitShape sh;
+    int rc = shape_from_problem(pr, &sh, &err);
+    if (rc) return set_error(rc, err);
+    Tune t = make_tune(sh.nb_max, sh.nsig_max, sh.p);
+    Schedule s = build_schedule({&sh}, t);
+    std::string why;
+    if (!schedule_is_valid(s, {&sh}, t, &why)) return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+    *bytes = make_layout(sh, s).total;
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
+}
+
+static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
+                           cwb_fit** out) {
+  if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!dev_ws) return set_error(CWB_E_INVALID_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+    return set_error(CWB_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  std::string err;
+  FitShape sh;
+  int rc = shape_from_problem(pr, &sh, &err);
+  if (rc) return set_error(rc, err);
+  HostFit hf;
+  rc = build_host_fit(pr, &hf, &err);
+  if (rc) return set_error(rc, err);
+  std::unique_ptr<cwb_fit> f(new cwb_fit());
+  f->stream = reinterpret_cast<hipStream_t>(stream);
+  f->shape = sh;
+  f->tune = make_tune(sh.nb_max, sh.nsig_max, sh.p);
+  f->sched = build_schedule({&f->shape}, f->tune);
+  {
+    std::string why;
+    if (!schedule_is_valid(f->sched, {&f->shape}, f->tune, &why))
+      return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+  }
+  f->lay = make_layout(sh, f->sched);
+  if (ws_bytes < f->lay.total)
+    return set_error(CWB_E_NO_MEMORY, "workspace too small: need " + std::to_string(f->lay.total) +
+                                          " bytes, got " + std::to_string(ws_bytes));
+  HIP_TRY(hipGetDevice(&f->device));
+  f->ws = reinterpret_cast<char*>(dev_ws);
+  f->ws_bytes = ws_bytes;
+  f->f0 = hf.f0;
+  f->perm = std::move(hf.perm);
+  const Layout& L = f->lay;
+  char* ws = f->ws;
+  hipStream_t st = f->stream;
+
+  // per-learner tables, concatenated
+  std::vector<FeatDev> feat(sh.p);
+  std::vector<int32_t> bstart;
+  std::vector<double> bval;
+  std::vector<int32_t> jr;
+  std::vector<double> ainv[2], gram[2];
+  bstart.reserve(sh.sum_nb);
+  bval.reserve(sh.sum_nb * kMaxBand);
+  int64_t bin_off = 0, mat_off = 0;
+  int coef_off = 0;
+  f->d.resize(sh.p);
+  for (int j = 0; j < sh.p; ++j) {
+    const HostLearner& hl = hf.L[j];
+    FeatDev& fd = feat[j];
+    fd.nb = hl.nb;
+    fd.band = hl.band;
+    fd.d = hl.d;
+    fd.coef_off = coef_off;
+    fd.bin_off = bin_off;
+    fd.mat_off = mat_off;
+    f->d[j] = hl.d;
+    bstart.insert(bstart.end(), hl.bstart.begin(), hl.bstart.end());
+    bval.insert(bval.end(), hl.bval.begin(), hl.bval.end());
+    jr.insert(jr.end(), hl.jr.begin(), hl.jr.end());
+    for (int set = 0; set < 2; ++set) {
+      ainv[set].insert(ainv[set].end(), hl.ainv[set].begin(), hl.ainv[set].end());
+      gram[set].insert(gram[set].end(), hl.gram[set].begin(), hl.gram[set].end());
+    }
+    bin_off += hl.nb;
+    mat_off += (int64_t)hl.d * hl.d;
+    coef_off += hl.d;
+  }
+  if (bin_off != sh.sum_nb || coef_off != sh.sum_d)
+    return set_error(CWB_E_INVALID_ARG, "learner sizes disagree with the specification");
+
+  FitDev& D = f->dev;
+  std::memset(&D, 0, sizeof(D));
+  D.n = sh.n;
+  D.n_pad = sh.n_pad;
+  D.n_train = sh.n_train;
+  D.p = sh.p;
+  D.nb_max = sh.nb_max;
+  D.d_max = sh.d_max;
+  D.sum_d = sh.sum_d;
+  D.loss = pr->loss;
+  D.variant = pr->variant;
+  D.M = pr->M;
+  D.patience = pr->patience;
+  D.nu = pr->nu;
+  D.gamma = pr->gamma;
+  D.n_row_blocks = sh.n_row_blocks;
+  D.n_val_blocks = sh.n_val_blocks;
+  D.nsig_max = sh.nsig_max;
+  D.X = dptr<uint16_t>(ws, L.X);
+  D.y = dptr<float>(ws, L.y);
+  D.fg = dptr<float>(ws, L.fg);
+  D.h = sh.nsig_max == 2 ? dptr<float>(ws, L.h) : nullptr;
+  D.c = sh.nsig_max == 2 ? dptr<float>(ws, L.c) : nullptr;
+  D.r = dptr<float>(ws, L.r);
+  D.feat = dptr<FeatDev>(ws, L.feat);
+  D.bstart = dptr<int32_t>(ws, L.bstart);
+  D.bval = dptr<double>(ws, L.bval);
+  D.jr = dptr<int32_t>(ws, L.jr);
+  for (int set = 0; set < 2; ++set) {
+    D.ainv[set] = dptr<double>(ws, L.ainv[set]);
+    D.gram[set] = dptr<double>(ws, L.gram[set]);
+  }
+  D.q = dptr<double>(ws, L.q);
+  D.theta = dptr<double>(ws, L.theta);
+  D.table = dptr<float>(ws, L.table);
+  D.tr_k = dptr<int32_t>(ws, L.trk);
+  D.tr_theta = dptr<double>(ws, L.trth);
+  D.tr_kcor = dptr<int32_t>(ws, L.trkc);
+  D.tr_thetacor = dptr<double>(ws, L.trthc);
+  D.tr_risk = dptr<double>(ws, L.trrisk);
+  D.tr_val = dptr<double>(ws, L.trval);
+  D.tr_gap = dptr<double>(ws, L.trgap);
+  D.coef_f = dptr<double>(ws, L.coef_f);
+  D.coef_h = dptr<double>(ws, L.coef_h);
+  D.risk_part = dptr<double>(ws, L.riskpart);
+  D.val_part = dptr<double>(ws, L.valpart);
+  D.ctl = dptr<Ctl>(ws, L.ctl);
+  f->d_fit = dptr<FitDev>(ws, L.fitdev);
+
+  Ctl ctl;
+  std::memset(&ctl, 0, sizeof(ctl));
+  ctl.kcor = -1;
+  ctl.switch_iter = -1;
+  if (pr->variant == CWB_HCWB && pr->patience == 0) {
+    ctl.switched = 1;
+    ctl.switch_iter = 1;
+  }
+
+  // state and inputs
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipMemsetAsync(ws + L.state_begin, 0, L.state_end - L.state_begin, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
+  std::vector<float> init((size_t)sh.n_pad, 0.0f);
+  std::fill(init.begin(), init.begin() + sh.n, (float)hf.f0);
+  HIP_TRY(hipMemcpyAsync(ws + L.fg, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+  if (sh.nsig_max == 2)
+    HIP_TRY(hipMemcpyAsync(ws + L.h, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.feat, feat.data(), feat.size() * sizeof(FeatDev), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.bval, bval.data(), bval.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.jr, jr.data(), jr.size() * 4, hipMemcpyHostToDevice, st));
+  for (int set = 0; set < 2; ++set) {
+    HIP_TRY(hipMemcpyAsync(ws + L.ainv[set], ainv[set].data(), ainv[set].size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ws + L.gram[set], gram[set].data(), gram[set].size() * 8, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(ws + L.fitdev, &D, sizeof(D), hipMemcpyHostToDevice, st));
+
+  // solo schedule and work lists
+  const Schedule& S = f->sched;
+  HIP_TRY(hipMemcpyAsync(ws + L.segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.grp_ptr, S.grp_ptr.data(), S.grp_ptr.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.grp_seg, S.grp_seg.data(), S.grp_seg.size() * 8, hipMemcpyHostToDevice, st));
+  std::vector<StateItem> st_items(sh.n_row_blocks);
+  for (int b = 0; b < sh.n_row_blocks; ++b) st_items[b] = {0, b};
+  std::vector<SelItem> sel_items(sh.p);
+  for (int k = 0; k < sh.p; ++k) sel_items[k] = {0, k, S.grp_base[0] + k / f->tune.F};
+  std::vector<StateItem> val_items(std::max(1, sh.n_val_blocks));
+  for (int b = 0; b < sh.n_val_blocks; ++b) val_items[b] = {0, b};
+  f->n_st = sh.n_row_blocks;
+  f->n_sel = sh.p;
+  f->n_val = sh.n_val_blocks;
+  HIP_TRY(hipMemcpyAsync(ws + L.st_items, st_items.data(), st_items.size() * sizeof(StateItem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.sel_items, sel_items.data(), sel_items.size() * sizeof(SelItem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.val_items, val_items.data(), val_items.size() * sizeof(StateItem), hipMemcpyHostToDevice, st));
+  // HCWB: validation risk of f^[0]
+  if (f->n_val > 0 && !ctl.switched)
+    HIP_TRY(launch_valrisk(st, f->d_fit, dptr<StateItem>(ws, L.val_items), f->n_val, sh.nb_max));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = f.release();
+  return CWB_OK;
+}
+
+int cwb_fit_create(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream, cwb_fit** out) {
+  try {
+    return fit_create_impl(pr, dev_ws, ws_bytes, stream, out);
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(CWB_E_INVALID_ARG, e.what());
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
+}
+
+int cwb_fit_run(cwb_fit* f, int32_t iters) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  if (iters < 0) return set_error(CWB_E_INVALID_ARG, "negative iteration count");
+  if ((int64_t)f->iters + iters > f->shape.M)
+    return set_error(CWB_E_STATE, "run would exceed M iterations");
+  HIP_TRY(hipSetDevice(f->device));
+  const Layout& L = f->lay;
+  char* ws = f->ws;
+  for (int i = 0; i < iters; ++i) {
+    int rc = enqueue_iteration(f->stream, f->d_fit, f->sched, f->tune, dptr<StateItem>(ws, L.st_items),
+                               f->n_st, dptr<SelItem>(ws, L.sel_items), f->n_sel,
+                               dptr<StateItem>(ws, L.val_items), f->n_val, f->shape.nb_max,
+                               dptr<Seg>(ws, L.segs), dptr<int64_t>(ws, L.blk),
+                               dptr<int64_t>(ws, L.grp_ptr), dptr<int64_t>(ws, L.grp_seg),
+                               dptr<long long>(ws, L.partials), f);
+    if (rc) return rc;
+  }
+  f->iters += iters;
+  return CWB_OK;
+}
+
+static int check_device_error(cwb_fit* f) {
+  int32_t e = 0;
+  HIP_TRY(hipMemcpy(&e, f->ws + f->lay.ctl + offsetof(Ctl, error), sizeof(e), hipMemcpyDeviceToHost));
+  if (e) return set_error(CWB_E_NUMERIC, "non-finite model state (diverged)");
+  return CWB_OK;
+}
+
+int cwb_fit_sync(cwb_fit* f) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  return check_device_error(f);
+}
+
+int cwb_fit_info(const cwb_fit* f, cwb_info* info) {
+  if (!f || !info) return set_error(CWB_E_INVALID_ARG, "null argument");
+  info->n = f->shape.n;
+  info->p = f->shape.p;
+  info->M = f->shape.M;
+  info->d_max = f->shape.d_max;
+  info->sum_d = f->shape.sum_d;
+  info->nb_max = f->shape.nb_max;
+  info->iters_done = f->iters;
+  info->n_train = f->shape.n_train;
+  info->f0 = f->f0;
+  return CWB_OK;
+}
+
+static int finalize_and_sync(cwb_fit* f) {
+  int rc = finalize_fit(f);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  return check_device_error(f);
+}
+
+int cwb_fit_get_trace(cwb_fit* f, int32_t* k, double* theta, int32_t* k_cor, double* theta_cor,
+                      double* train_risk, double* val_risk, double* crit_gap, int32_t* switch_iter) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  int rc = finalize_and_sync(f);
+  if (rc) return rc;
+  const Layout& L = f->lay;
+  const size_t m = (size_t)f->iters;
+  const size_t dm = (size_t)f->shape.d_max;
+  if (k) HIP_TRY(hipMemcpy(k, f->ws + L.trk, m * 4, hipMemcpyDeviceToHost));
+  if (theta) HIP_TRY(hipMemcpy(theta, f->ws + L.trth, m * dm * 8, hipMemcpyDeviceToHost));
+  if (k_cor) HIP_TRY(hipMemcpy(k_cor, f->ws + L.trkc, m * 4, hipMemcpyDeviceToHost));
+  if (theta_cor) HIP_TRY(hipMemcpy(theta_cor, f->ws + L.trthc, m * dm * 8, hipMemcpyDeviceToHost));
+  if (train_risk) HIP_TRY(hipMemcpy(train_risk, f->ws + L.trrisk, (m + 1) * 8, hipMemcpyDeviceToHost));
+  if (val_risk) HIP_TRY(hipMemcpy(val_risk, f->ws + L.trval, (m + 1) * 8, hipMemcpyDeviceToHost));
+  if (crit_gap) HIP_TRY(hipMemcpy(crit_gap, f->ws + L.trgap, m * 8, hipMemcpyDeviceToHost));
+  if (switch_iter) {
+    Ctl c;
+    HIP_TRY(hipMemcpy(&c, f->ws + L.ctl, sizeof(c), hipMemcpyDeviceToHost));
+    *switch_iter = c.switched ? c.switch_iter : -1;
+  }
+  return CWB_OK;
+}
+
+int cwb_fit_get_model(cwb_fit* f, double* intercept, double* coef_f, double* coef_h) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  int rc = check_device_error(f);
+  if (rc) return rc;
+  if (intercept) *intercept = f->f0;
+  const size_t sd = (size_t)f->shape.sum_d;
+  if (coef_f) HIP_TRY(hipMemcpy(coef_f, f->ws + f->lay.coef_f, sd * 8, hipMemcpyDeviceToHost));
+  if (coef_h) {
+    if (f->shape.nsig_max == 2)
+      HIP_TRY(hipMemcpy(coef_h, f->ws + f->lay.coef_h, sd * 8, hipMemcpyDeviceToHost));
+    else
+      std::memset(coef_h, 0, sd * 8);
+  }
+  return CWB_OK;
+}
+
+int cwb_fit_get_pred(cwb_fit* f, float* f_out) {
+  if (!f || !f_out) return set_error(CWB_E_INVALID_ARG, "null argument");
+  int rc = finalize_and_sync(f);
+  if (rc) return rc;
+  std::vector<float> buf((size_t)f->shape.n);
+  HIP_TRY(hipMemcpy(buf.data(), f->ws + f->lay.fg, buf.size() * 4, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < f->shape.n; ++i) f_out[f->perm[i]] = buf[i];
+  return CWB_OK;
+}
+
+int cwb_fit_state_bytes(const cwb_fit* f, size_t* bytes) {
+  if (!f || !bytes) return set_error(CWB_E_INVALID_ARG, "null argument");
+  *bytes = sizeof(int64_t) + (f->lay.state_end - f->lay.state_begin);
+  return CWB_OK;
+}
+
+int cwb_fit_save_state(cwb_fit* f, void* host_buf, size_t bytes) {
+  size_t need = 0;
+  int rc = cwb_fit_state_bytes(f, &need);
+  if (rc) return rc;
+  if (!host_buf || bytes < need) return set_error(CWB_E_INVALID_ARG, "state buffer too small");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  int64_t it = f->iters;
+  std::memcpy(host_buf, &it, sizeof(it));
+  HIP_TRY(hipMemcpy(static_cast<char*>(host_buf) + sizeof(it), f->ws + f->lay.state_begin,
+                    need - sizeof(it), hipMemcpyDeviceToHost));
+  return CWB_OK;
+}
+
+int cwb_fit_load_state(cwb_fit* f, const void* host_buf, size_t bytes) {
+  size_t need = 0;
+  int rc = cwb_fit_state_bytes(f, &need);
+  if (rc) return rc;
+  if (!host_buf || bytes != need) return set_error(CWB_E_INVALID_ARG, "state buffer has the wrong size");
+  int64_t it = 0;
+  std::memcpy(&it, host_buf, sizeof(it));
+  if (it < 0 || it > f->shape.M) return set_error(CWB_E_INVALID_ARG, "corrupt state buffer");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  HIP_TRY(hipMemcpy(f->ws + f->lay.state_begin, static_cast<const char*>(host_buf) + sizeof(it),
+                    need - sizeof(it), hipMemcpyHostToDevice));
+  f->iters = (int)it;
+  return CWB_OK;
+}
+
+int cwb_fit_set_timing(cwb_fit* f, int32_t mask) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  if (mask < 0 || mask > 7) return set_error(CWB_E_INVALID_ARG, "timing mask must be 0..7");
+  f->timing = mask;
+  timer_reset(f->t_hist);
+  timer_reset(f->t_state);
+  timer_reset(f->t_select);
+  return CWB_OK;
+}
+
+int cwb_fit_kernel_time(cwb_fit* f, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!f || !kernel) return set_error(CWB_E_INVALID_ARG, "null argument");
+  KernelTimer* t = nullptr;
+  if (!std::strcmp(kernel, "hist")) t = &f->t_hist;
+  else if (!std::strcmp(kernel, "state")) t = &f->t_state;
+  else if (!std::strcmp(kernel, "select")) t = &f->t_select;
+  if (!t) return set_error(CWB_E_INVALID_ARG, "unknown kernel name");
+  HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(timer_collect(*t));
+  if (total_ms) *total_ms = t->total_ms;
+  if (launches) *launches = t->launches;
+  return CWB_OK;
+}
+
+void cwb_fit_destroy(cwb_fit* f) {
+  if (!f) return;
+  hipSetDevice(f->device);
+  hipStreamSynchronize(f->stream);
+  timer_free(f->t_hist);
+  timer_free(f->t_state);
+  timer_free(f->t_select);
+  delete f;
+}
+
+// ---- batches ----------------------------------------------------------------
+
+namespace {
+
+struct BatchLayout {
+  size_t fits, segs, blk, grp_ptr, grp_seg, partials, st, sel, val, total;
+};
+
+BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int n_val) {
+  BatchLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    off = align_up(off, 256);
+    const size_t o = off;
+    off += b;
+    return o;
+  };
+  L.fits = take((size_t)count * sizeof(FitDev));
+  L.segs = take(S.segs.size() * sizeof(Seg));
+  L.blk = take(S.blk.size() * 8);
+  L.grp_ptr = take(S.grp_ptr.size() * 8);
+  L.grp_seg = take(S.grp_seg.size() * 8);
+  L.partials = take((size_t)S.partial_words * 8);
+  L.st = take((size_t)std::max(1, n_st) * sizeof(StateItem));
+  L.sel = take((size_t)std::max(1, n_sel) * sizeof(SelItem));
+  L.val = take((size_t)std::max(1, n_val) * sizeof(StateItem));
+  L.total = align_up(off, 256);
+  return L;
+}
+
+int batch_plan(cwb_fit* const* fits, int32_t count, Tune* t, Schedule* S, int* n_st, int* n_sel,
+               int* n_val) {
+  if (!fits || count < 1) return set_error(CWB_E_INVALID_ARG, "need at least one fit");
+  std::vector<const FitShape*> shapes;
+  int nb = 1, ns = 1, pmax = 1;
+  *n_st = *n_sel = *n_val = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!fits[i]) return set_error(CWB_E_INVALID_ARG, "null fit in batch");
+    for (int j = 0; j < i; ++j)
+      if (fits[j] == fits[i]) return set_error(CWB_E_INVALID_ARG, "fit listed twice in batch");
+    shapes.push_back(&fits[i]->shape);
+    nb = std::max(nb, fits[i]->shape.nb_max);
+    ns = std::max(ns, fits[i]->shape.nsig_max);
+    pmax = std::max(pmax, fits[i]->shape.p);
+    *n_st += fits[i]->shape.n_row_blocks;
+    *n_sel += fits[i]->shape.p;
+    *n_val += fits[i]->shape.n_val_blocks;
+  }
+  *t = make_tune(nb, ns, pmax);
+  *S = build_schedule(shapes, *t);
+  std::string why;
+  if (!schedule_is_valid(*S, shapes, *t, &why))
+    return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+  return CWB_OK;
+}
+
+}  // namespace
+
+int cwb_batch_workspace_bytes(cwb_fit* const* fits, int32_t count, size_t* bytes) {
+  try {
+    if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
+    Tune t;
+    Schedule S;
+    int n_st, n_sel, n_val;
+    int rc = batch_plan(fits, count, &t, &S, &n_st, &n_sel, &n_val);
+    if (rc) return rc;
+    *bytes = batch_layout(S, count, n_st, n_sel, n_val).total;
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  }
+}
+
+int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t ws_bytes, void* stream,
+                     cwb_batch** out) {
+  try {
+    if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+    *out = nullptr;
+    if (!dev_ws || reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+      return set_error(CWB_E_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+    std::unique_ptr<cwb_batch> b(new cwb_batch());
+    int rc = batch_plan(fits, count, &b->tune, &b->sched, &b->n_st, &b->n_sel, &b->n_val);
+    if (rc) return rc;
+    const BatchLayout L = batch_layout(b->sched, count, b->n_st, b->n_sel, b->n_val);
+    if (ws_bytes < L.total)
+      return set_error(CWB_E_NO_MEMORY, "batch workspace too small: need " + std::to_string(L.total));
+    HIP_TRY(hipGetDevice(&b->device));
+    for (int i = 0; i < count; ++i)
+      if (fits[i]->device != b->device) return set_error(CWB_E_INVALID_ARG, "fits on different devices");
+    b->stream = reinterpret_cast<hipStream_t>(stream);
+    b->ws = reinterpret_cast<char*>(dev_ws);
+    b->ws_bytes = ws_bytes;
+    b->fits.assign(fits, fits + count);
+    std::vector<FitDev> fd(count);
+    std::vector<StateItem> st;
+    std::vector<SelItem> sel;
+    std::vector<StateItem> val;
+    for (int i = 0; i < count; ++i) {
+      fd[i] = fits[i]->dev;
+      b->nb_max = std::max(b->nb_max, fits[i]->shape.nb_max);
+      if (fits[i]->shape.variant == CWB_HCWB) b->any_hcwb = true;
+      for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back({i, r});
+      for (int k = 0; k < fits[i]->shape.p; ++k)
+        sel.push_back({i, k, b->sched.grp_base[i] + k / b->tune.F});
+      for (int r = 0; r < fits[i]->shape.n_val_blocks; ++r) val.push_back({i, r});
+    }
+    char* ws = b->ws;
+    hipStream_t s = b->stream;
+    b->d_fits = dptr<FitDev>(ws, L.fits);
+    b->d_segs = dptr<Seg>(ws, L.segs);
+    b->d_blk = dptr<int64_t>(ws, L.blk);
+    b->d_grp_ptr = dptr<int64_t>(ws, L.grp_ptr);
+    b->d_grp_seg = dptr<int64_t>(ws, L.grp_seg);
+    b->d_partials = dptr<long long>(ws, L.partials);
+    b->d_st = dptr<StateItem>(ws, L.st);
+    b->d_sel = dptr<SelItem>(ws, L.sel);
+    b->d_val = dptr<StateItem>(ws, L.val);
+    const Schedule& S = b->sched;
+    HIP_TRY(hipMemcpyAsync(b->d_fits, fd.data(), fd.size() * sizeof(FitDev), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_grp_ptr, S.grp_ptr.data(), S.grp_ptr.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_grp_seg, S.grp_seg.data(), S.grp_seg.size() * 8, hipMemcpyHostToDevice, s));
+    if (!st.empty()) HIP_TRY(hipMemcpyAsync(b->d_st, st.data(), st.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
+    if (!sel.empty()) HIP_TRY(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, s));
+    if (!val.empty()) HIP_TRY(hipMemcpyAsync(b->d_val, val.data(), val.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = b.release();
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  }
+}
+
+int cwb_batch_run(cwb_batch* b, int32_t iters) {
+  if (!b) return set_error(CWB_E_INVALID_ARG, "null batch");
+  if (iters < 0) return set_error(CWB_E_INVALID_ARG, "negative iteration count");
+  HIP_TRY(hipSetDevice(b->device));
+  int most = 0;
+  for (cwb_fit* f : b->fits) most = std::max(most, std::min(iters, f->shape.M - f->iters));
+  for (int i = 0; i < most; ++i) {
+    int rc = enqueue_iteration(b->stream, b->d_fits, b->sched, b->tune, b->d_st, b->n_st, b->d_sel,
+                               b->n_sel, b->d_val, b->any_hcwb ? b->n_val : 0, b->nb_max, b->d_segs,
+                               b->d_blk, b->d_grp_ptr, b->d_grp_seg, b->d_partials, nullptr);
+    if (rc) return rc;
+  }
+  for (cwb_fit* f : b->fits) f->iters += std::min(most, f->shape.M - f->iters);
+  return CWB_OK;
+}
+
+int cwb_batch_sync(cwb_batch* b) {
+  if (!b) return set_error(CWB_E_INVALID_ARG, "null batch");
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (cwb_fit* f : b->fits) {
+    int rc = check_device_error(f);
+    if (rc) return rc;
+  }
+  return CWB_OK;
+}
+
+void cwb_batch_destroy(cwb_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// runtime.h -- host-side objects behind the C ABI (fits, batches, schedules).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cwb.h"
+#include "cwb_internal.h"
+#include "setup.h"
+
+namespace cwb {
+
+// Sizes of a fit, known before the (expensive) setup.
+struct FitShape {
+  int64_t n = 0, n_pad = 0, n_train = 0;
+  int p = 0, M = 0, variant = 0, nsig_max = 1;
+  int nb_max = 0, d_max = 0, sum_d = 0;
+  int64_t sum_nb = 0, sum_d2 = 0;
+  int n_row_blocks = 0, n_val_blocks = 0;
+};
+
+int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err);
+
+// Histogram tile shape: threads per block, learners per group (F) and the
+// compiled group capacity (fmax), blocks per CU, row slices (XCD affinity).
+struct Tune {
+  int nt = 512;
+  int F = 0;
+  int fmax = 0;
+  int blocks_per_cu = 1;
+  int slices = 1;
+  int cus = 256;
+  int lds_kb = 64;
+};
+
+Tune make_tune(int nb_max, int nsig_max, int p_max);
+
+struct Schedule {
+  std::vector<Seg> segs;         // traversal order
+  std::vector<int64_t> blk;      // 2 per physical block: segment range
+  std::vector<int64_t> grp_ptr;  // per (fit, group): range in grp_seg (+1 sentinel)
+  std::vector<int64_t> grp_seg;  // segment indices, grouped
+  std::vector<int64_t> grp_base; // per fit: first group index
+  int64_t partial_words = 0;
+  int blocks = 0;
+  size_t lds = 0;
+};
+
+Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t);
+
+// Offsets (bytes) of everything inside a fit's workspace.
+struct Layout {
+  size_t ctl, fg, h, c, q, theta, table, trk, trth, trkc, trthc, trrisk, trval, trgap, coef_f,
+      coef_h;
+  size_t state_begin, state_end;  // mutable state region (checkpoint)
+  size_t X, y, r, feat, bstart, bval, jr, ainv[2], gram[2], riskpart, valpart, fitdev;
+  size_t segs, blk, grp_ptr, grp_seg, partials, st_items, sel_items, val_items;
+  size_t total;
+};
+
+Layout make_layout(const FitShape& sh, const Schedule& s);
+
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t used = 0;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+};
+
+}  // namespace cwb
+
+struct cwb_fit {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  cwb::FitShape shape;
+  cwb::Tune tune;
+  cwb::Schedule sched;
+  cwb::Layout lay;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double f0 = 0.0;
+  std::vector<int64_t> perm;
+  std::vector<int32_t> d;      // basis size per learner
+  cwb::FitDev dev;             // host copy (device pointers)
+  cwb::FitDev* d_fit = nullptr;
+  int iters = 0;
+  int n_st = 0, n_sel = 0, n_val = 0;
+  int timing = 0;  // bit set: 1 hist, 2 state, 4 select
+  cwb::KernelTimer t_hist, t_state, t_select;
+};
+
+struct cwb_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<cwb_fit*> fits;
+  cwb::Tune tune;
+  cwb::Schedule sched;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int nb_max = 0;
+  bool any_hcwb = false;
+  cwb::FitDev* d_fits = nullptr;
+  cwb::Seg* d_segs = nullptr;
+  int64_t* d_blk = nullptr;
+  int64_t* d_grp_ptr = nullptr;
+  int64_t* d_grp_seg = nullptr;
+  long long* d_partials = nullptr;
+  cwb::StateItem* d_st = nullptr;
+  cwb::SelItem* d_sel = nullptr;
+  cwb::StateItem* d_val = nullptr;
+  int n_st = 0, n_sel = 0, n_val = 0;
+};
+
+namespace cwb {
+int set_error(int code, const std::string& msg);
+// Enqueue one finalize (apply pending updates, record the current risk).
+int finalize_fit(cwb_fit* f);
+}  // namespace cwb

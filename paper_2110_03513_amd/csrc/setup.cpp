@@ -1,0 +1,553 @@
+// setup.cpp -- one-off FP64 host setup of a fit (runs once in cwb_fit_create).
+//
+//  * equal-grid binning of every numeric feature with ties to the lower
+//    design point (Section 3.1.1), written as uint16 index vectors;
+//  * B-spline bases at the design points by de Boor's triangular scheme,
+//    kept banded (degree+1 nonzeros per design point);
+//  * bin counts and Gram matrices G = Z^bT diag(counts) Z^b (binMatMat,
+//    Algorithm 1 with unit weights), separately for the training rows and
+//    for all rows (HCWB trains on D_train, then on D; Algorithm 3);
+//  * difference penalties (Appendix A.2) and, for a requested df, the
+//    smoothing parameter from the Demmler-Reinsch orthogonalisation:
+//    with G = L L^T and L^-1 D L^-T = U diag(w) U^T, df(lambda) =
+//    sum_i 1 / (1 + lambda w_i), solved by bisection in log(lambda);
+//  * categorical ridge learners in closed form (Appendix A.3.1);
+//  * the inverse penalised Gram matrix (cached factorisation, Section 2.4).
+// Compiled with -ffp-contract=off so the binning distances are not fused.
+#include "setup.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+namespace cwb {
+
+namespace {
+
+// ---- dense FP64 helpers (row-major d x d) --------------------------------
+
+bool chol_lower(int d, const std::vector<double>& A, std::vector<double>& L) {
+  L.assign((size_t)d * d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    double s = A[(size_t)j * d + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * d + k] * L[(size_t)j * d + k];
+    if (!(s > 0.0) || !std::isfinite(s)) return false;
+    const double ljj = std::sqrt(s);
+    L[(size_t)j * d + j] = ljj;
+    for (int i = j + 1; i < d; ++i) {
+      double t = A[(size_t)i * d + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * d + k] * L[(size_t)j * d + k];
+      L[(size_t)i * d + j] = t / ljj;
+    }
+  }
+  return true;
+}
+
+// Inverse of the lower-triangular L.
+std::vector<double> tri_inverse(int d, const std::vector<double>& L) {
+  std::vector<double> X((size_t)d * d, 0.0);
+  for (int c = 0; c < d; ++c) {
+    for (int i = c; i < d; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) t -= L[(size_t)i * d + k] * X[(size_t)k * d + c];
+      X[(size_t)i * d + c] = t / L[(size_t)i * d + i];
+    }
+  }
+  return X;
+}
+
+// A^-1 for symmetric positive definite A, as L^-T L^-1.
+bool spd_inverse(int d, const std::vector<double>& A, std::vector<double>& inv) {
+  std::vector<double> L;
+  if (!chol_lower(d, A, L)) return false;
+  std::vector<double> Li = tri_inverse(d, L);
+  inv.assign((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int k = i; k < d; ++k) s += Li[(size_t)k * d + i] * Li[(size_t)k * d + j];
+      inv[(size_t)i * d + j] = s;
+      inv[(size_t)j * d + i] = s;
+    }
+  return true;
+}
+
+// Eigenvalues of a symmetric matrix by cyclic Jacobi rotations.
+std::vector<double> jacobi_eigenvalues(int d, std::vector<double> S) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        const double v = S[(size_t)i * d + j] * S[(size_t)i * d + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < d - 1; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        const double apq = S[(size_t)p * d + q];
+        if (apq == 0.0) continue;
+        const double app = S[(size_t)p * d + p], aqq = S[(size_t)q * d + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < d; ++k) {  // columns p, q
+          const double akp = S[(size_t)k * d + p], akq = S[(size_t)k * d + q];
+          S[(size_t)k * d + p] = c * akp - s * akq;
+          S[(size_t)k * d + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < d; ++k) {  // rows p, q
+          const double apk = S[(size_t)p * d + k], aqk = S[(size_t)q * d + k];
+          S[(size_t)p * d + k] = c * apk - s * aqk;
+          S[(size_t)q * d + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  std::vector<double> w(d);
+  for (int i = 0; i < d; ++i) w[i] = S[(size_t)i * d + i];
+  return w;
+}
+
+// Difference penalty Delta^T Delta of order `ord` (ord = 0: identity).
+std::vector<double> difference_penalty(int d, int ord) {
+  std::vector<double> Dm((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i) Dm[(size_t)i * d + i] = 1.0;  // rows of Delta^(0) = I
+  int rows = d;
+  for (int o = 0; o < ord; ++o) {  // Delta^(o+1)[i] = Delta^(o)[i+1] - Delta^(o)[i]
+    for (int i = 0; i < rows - 1; ++i)
+      for (int j = 0; j < d; ++j)
+        Dm[(size_t)i * d + j] = Dm[(size_t)(i + 1) * d + j] - Dm[(size_t)i * d + j];
+    --rows;
+  }
+  std::vector<double> P((size_t)d * d, 0.0);
+  for (int r = 0; r < rows; ++r)
+    for (int i = 0; i < d; ++i) {
+      const double a = Dm[(size_t)r * d + i];
+      if (a == 0.0) continue;
+      for (int j = 0; j < d; ++j) P[(size_t)i * d + j] += a * Dm[(size_t)r * d + j];
+    }
+  return P;
+}
+
+// df(lambda) = trace((G + lambda D)^-1 G), directly (fallback when G is singular).
+bool df_direct(int d, const std::vector<double>& G, const std::vector<double>& D, double lam,
+               double* out) {
+  std::vector<double> A((size_t)d * d), inv;
+  for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
+  if (!spd_inverse(d, A, inv)) return false;
+  double tr = 0.0;
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) tr += inv[(size_t)i * d + k] * G[(size_t)k * d + i];
+  *out = tr;
+  return true;
+}
+
+// lambda with df(lambda) = target by bisection in log(lambda); df decreases
+// monotonically.  Uses the Demmler-Reinsch eigenvalues when G is positive
+// definite and the direct trace otherwise.
+int lambda_for_df(int d, const std::vector<double>& G, const std::vector<double>& D, double target,
+                  double* lam_out, std::string* err) {
+  std::vector<double> L;
+  std::vector<double> w;
+  const bool dro = chol_lower(d, G, L);
+  if (dro) {
+    // S = L^-1 D L^-T
+    std::vector<double> Li = tri_inverse(d, L);
+    std::vector<double> T((size_t)d * d, 0.0), S((size_t)d * d, 0.0);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int k = 0; k <= i; ++k) s += Li[(size_t)i * d + k] * D[(size_t)k * d + j];
+        T[(size_t)i * d + j] = s;
+      }
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int k = 0; k <= j; ++k) s += T[(size_t)i * d + k] * Li[(size_t)j * d + k];
+        S[(size_t)i * d + j] = s;
+      }
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j) {
+        const double a = 0.5 * (S[(size_t)i * d + j] + S[(size_t)j * d + i]);
+        S[(size_t)i * d + j] = a;
+        S[(size_t)j * d + i] = a;
+      }
+    w = jacobi_eigenvalues(d, S);
+  }
+  auto df_at = [&](double lam, double* v) -> bool {
+    if (dro) {
+      double s = 0.0;
+      for (double wi : w) s += 1.0 / (1.0 + lam * std::max(wi, 0.0));
+      *v = s;
+      return true;
+    }
+    return df_direct(d, G, D, lam, v);
+  };
+  double trG = 0.0, trD = 0.0;
+  for (int i = 0; i < d; ++i) {
+    trG += G[(size_t)i * d + i];
+    trD += D[(size_t)i * d + i];
+  }
+  if (!(trG > 0.0) || !(trD > 0.0)) {
+    *err = "degenerate Gram or penalty matrix";
+    return -5;
+  }
+  const double s = trG / trD;
+  double lo = 1e-10 * s, hi = 1e10 * s, v = 0.0;
+  int k = 0;
+  for (; k < 40; ++k) {
+    if (!df_at(lo, &v)) { *err = "penalised Gram matrix not positive definite"; return -5; }
+    if (v > target) break;
+    lo *= 1e-3;
+  }
+  if (k == 40) { *err = "df target not reachable (too large for the basis)"; return -1; }
+  for (k = 0; k < 40; ++k) {
+    if (!df_at(hi, &v)) { *err = "penalised Gram matrix not positive definite"; return -5; }
+    if (v < target) break;
+    hi *= 1e3;
+  }
+  if (k == 40) { *err = "df target not reachable (too small for the penalty)"; return -1; }
+  for (k = 0; k < 400 && hi / lo > 1.0 + 1e-15; ++k) {
+    const double mid = std::sqrt(lo * hi);
+    df_at(mid, &v);
+    if (v > target) lo = mid; else hi = mid;
+  }
+  *lam_out = std::sqrt(lo * hi);
+  return 0;
+}
+
+// ---- binning and bases -----------------------------------------------------
+
+// Design point l of the equal grid on [xmin, xmax] with nb points.
+inline double grid_point(double xmin, double xmax, double h, int l, int nb) {
+  return (l == nb - 1) ? xmax : xmin + (double)l * h;
+}
+
+// Closest design point, ties to the lower one.  An arithmetic estimate of the
+// enclosing interval is corrected with exact comparisons against the design
+// points, then the two distances decide.
+inline int bin_of(double x, double xmin, double xmax, double h, int nb) {
+  if (x <= xmin) return 0;
+  if (x >= xmax) return nb - 1;
+  int l = (int)((x - xmin) / h);
+  if (l < 0) l = 0;
+  if (l > nb - 2) l = nb - 2;
+  while (l > 0 && grid_point(xmin, xmax, h, l, nb) > x) --l;
+  while (l < nb - 2 && grid_point(xmin, xmax, h, l + 1, nb) <= x) ++l;
+  const double dlo = x - grid_point(xmin, xmax, h, l, nb);
+  const double dhi = grid_point(xmin, xmax, h, l + 1, nb) - x;
+  return (dhi < dlo) ? l + 1 : l;
+}
+
+// Nonzero B-spline values at z (de Boor's triangular scheme).  Returns the
+// index of the first nonzero basis function; vals gets degree+1 values.
+int bspline_band(double z, const std::vector<double>& t, int deg, int d, double* vals) {
+  // knot interval mu with t[mu] <= z < t[mu+1], kept inside [deg, d-1]
+  const double h = t[deg + 1] - t[deg];
+  int mu = deg + (int)std::floor((z - t[deg]) / h);
+  if (mu < deg) mu = deg;
+  if (mu > d - 1) mu = d - 1;
+  while (mu > deg && t[mu] > z) --mu;
+  while (mu < d - 1 && t[mu + 1] <= z) ++mu;
+  double N[kMaxBand + 1], left[kMaxBand + 1], right[kMaxBand + 1];
+  N[0] = 1.0;
+  for (int j = 1; j <= deg; ++j) {
+    left[j] = z - t[mu + 1 - j];
+    right[j] = t[mu + j] - z;
+    double saved = 0.0;
+    for (int r = 0; r < j; ++r) {
+      const double temp = N[r] / (right[r + 1] + left[j - r]);
+      N[r] = saved + right[r + 1] * temp;
+      saved = left[j - r] * temp;
+    }
+    N[j] = saved;
+  }
+  for (int j = 0; j <= deg; ++j) vals[j] = N[j];
+  return mu - deg;
+}
+
+void set_error(std::string* err, const std::string& msg) {
+  if (err->empty()) *err = msg;
+}
+
+}  // namespace
+
+int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z, std::string* err) {
+  if (!x || !ind || n < 1) { *err = "null pointer or n < 1"; return CWB_E_INVALID_ARG; }
+  if (nb < 2 || nb > 65535) { *err = "n_bins must be 2..65535"; return CWB_E_INVALID_ARG; }
+  double xmin = x[0], xmax = x[0];
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i])) { *err = "non-finite x"; return CWB_E_INVALID_ARG; }
+    xmin = std::min(xmin, x[i]);
+    xmax = std::max(xmax, x[i]);
+  }
+  if (!(xmax > xmin)) { *err = "constant feature"; return CWB_E_INVALID_ARG; }
+  const double h = (xmax - xmin) / (double)(nb - 1);
+  for (int64_t i = 0; i < n; ++i) ind[i] = (uint16_t)bin_of(x[i], xmin, xmax, h, nb);
+  if (z)
+    for (int l = 0; l < nb; ++l) z[l] = grid_point(xmin, xmax, h, l, nb);
+  return CWB_OK;
+}
+
+int validate_problem(const cwb_problem* pr, std::string* err) {
+  if (!pr) { *err = "null problem"; return CWB_E_INVALID_ARG; }
+  if (pr->n < 2) { *err = "n must be >= 2"; return CWB_E_INVALID_ARG; }
+  if (pr->p < 1) { *err = "p must be >= 1"; return CWB_E_INVALID_ARG; }
+  if (!pr->x || !pr->y || !pr->specs) { *err = "null x, y or specs"; return CWB_E_INVALID_ARG; }
+  if (!(pr->nu > 0.0) || !std::isfinite(pr->nu)) { *err = "nu must be > 0"; return CWB_E_INVALID_ARG; }
+  if (pr->M < 1) { *err = "M must be >= 1"; return CWB_E_INVALID_ARG; }
+  if (pr->loss != CWB_L2 && pr->loss != CWB_BINOMIAL) { *err = "unknown loss"; return CWB_E_INVALID_ARG; }
+  if (pr->variant < CWB_CWB || pr->variant > CWB_HCWB) { *err = "unknown variant"; return CWB_E_INVALID_ARG; }
+  if (!(pr->gamma >= 0.0) || !std::isfinite(pr->gamma)) { *err = "gamma must be >= 0"; return CWB_E_INVALID_ARG; }
+  if (pr->patience < 0) { *err = "patience must be >= 0"; return CWB_E_INVALID_ARG; }
+  if (pr->n > ((int64_t)1 << 40)) { *err = "n too large"; return CWB_E_UNSUPPORTED; }
+  for (int64_t i = 0; i < pr->n; ++i) {
+    const double v = pr->y[i];
+    if (!std::isfinite(v)) { *err = "non-finite y"; return CWB_E_INVALID_ARG; }
+    if (pr->loss == CWB_BINOMIAL && v != 0.0 && v != 1.0) { *err = "binomial y must be 0/1"; return CWB_E_INVALID_ARG; }
+  }
+  if (pr->variant == CWB_HCWB && !pr->val_mask) { *err = "HCWB needs a validation mask"; return CWB_E_INVALID_ARG; }
+  if (pr->val_mask) {
+    int64_t nv = 0;
+    for (int64_t i = 0; i < pr->n; ++i) nv += pr->val_mask[i] ? 1 : 0;
+    if (nv == 0 || nv == pr->n) { *err = "empty training or validation split"; return CWB_E_INVALID_ARG; }
+  }
+  for (int j = 0; j < pr->p; ++j) {
+    const cwb_learner_spec& s = pr->specs[j];
+    if (s.kind == CWB_RIDGE_CAT) {
+      if (s.n_levels < 1 || s.n_levels > kMaxD) { *err = "level count must be 1..64"; return CWB_E_INVALID_ARG; }
+    } else if (s.kind == CWB_PSPLINE) {
+      if (s.degree < 1 || s.degree > 3) { *err = "P-spline degree must be 1..3"; return CWB_E_UNSUPPORTED; }
+      if (s.n_interior_knots < 0) { *err = "negative knot count"; return CWB_E_INVALID_ARG; }
+      const int d = s.n_interior_knots + s.degree + 1;
+      if (d > kMaxD) { *err = "basis larger than 64"; return CWB_E_UNSUPPORTED; }
+      if (s.penalty_order < 0 || s.penalty_order >= d) { *err = "bad penalty order"; return CWB_E_INVALID_ARG; }
+      if (s.n_bins == 0) { *err = "unbinned learners are not supported by the GPU path"; return CWB_E_UNSUPPORTED; }
+      if (s.n_bins != -1 && (s.n_bins < 2 || s.n_bins > 65535)) { *err = "n_bins must be 2..65535"; return CWB_E_INVALID_ARG; }
+      if (s.df > 0.0 && (s.df <= (double)s.penalty_order || s.df >= (double)d)) {
+        *err = "P-spline df must lie between the penalty order and the basis size";
+        return CWB_E_INVALID_ARG;
+      }
+    } else {
+      *err = "unknown learner kind";
+      return CWB_E_INVALID_ARG;
+    }
+    if (s.df <= 0.0 && !(s.lambda >= 0.0)) { *err = "lambda must be >= 0"; return CWB_E_INVALID_ARG; }
+  }
+  return CWB_OK;
+}
+
+int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
+  int rc = validate_problem(pr, err);
+  if (rc) return rc;
+  const int64_t n = pr->n;
+  const int p = pr->p;
+  hf->n = n;
+  hf->p = p;
+  hf->n_pad = (n + 63) / 64 * 64;
+  hf->loss = pr->loss;
+  hf->variant = pr->variant;
+  hf->M = pr->M;
+  hf->nu = pr->nu;
+  hf->gamma = pr->gamma;
+  hf->patience = pr->patience;
+
+  // Training rows first, then validation rows (stable).
+  hf->perm.resize(n);
+  int64_t nt = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (!pr->val_mask || !pr->val_mask[i]) hf->perm[nt++] = i;
+  hf->n_train = nt;
+  int64_t pos = nt;
+  for (int64_t i = 0; i < n; ++i)
+    if (pr->val_mask && pr->val_mask[i]) hf->perm[pos++] = i;
+
+  hf->y.assign(hf->n_pad, 0.0f);
+  double ysum = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double v = pr->y[hf->perm[i]];
+    hf->y[i] = (float)v;
+    if (i < nt) ysum += v;
+  }
+  const double ybar = ysum / (double)nt;
+  hf->f0 = (pr->loss == CWB_L2) ? ybar : std::log(ybar / (1.0 - ybar));
+  if (!std::isfinite(hf->f0)) {
+    *err = "training labels are all equal (binomial intercept not finite)";
+    return CWB_E_NUMERIC;
+  }
+
+  hf->X.assign((size_t)p * hf->n_pad, 0);
+  hf->L.resize(p);
+  std::vector<std::string> ferr(p);
+  std::vector<int> frc(p, 0);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    std::vector<double> t;
+    for (;;) {
+      const int j = next.fetch_add(1);
+      if (j >= p) break;
+      const cwb_learner_spec& s = pr->specs[j];
+      const double* xj = pr->x + (size_t)j * n;
+      HostLearner& L = hf->L[j];
+      uint16_t* Xj = hf->X.data() + (size_t)j * hf->n_pad;
+      L.kind = s.kind;
+      if (s.kind == CWB_RIDGE_CAT) {
+        const int c = s.n_levels;
+        L.nb = c;
+        L.band = 1;
+        L.d = c;
+        for (int64_t i = 0; i < n; ++i) {
+          const double v = xj[hf->perm[i]];
+          if (!(v >= 0.0) || v >= (double)c || v != std::floor(v)) {
+            frc[j] = CWB_E_INVALID_ARG;
+            ferr[j] = "level code out of range in feature " + std::to_string(j);
+            break;
+          }
+          Xj[i] = (uint16_t)v;
+        }
+        if (frc[j]) continue;
+        L.bstart.resize(c);
+        L.bval.assign((size_t)c * kMaxBand, 0.0);
+        for (int l = 0; l < c; ++l) {
+          L.bstart[l] = l;
+          L.bval[(size_t)l * kMaxBand] = 1.0;
+        }
+      } else {
+        double xmin = xj[0], xmax = xj[0];
+        for (int64_t i = 0; i < n; ++i) {
+          const double v = xj[i];
+          if (!std::isfinite(v)) { frc[j] = CWB_E_INVALID_ARG; ferr[j] = "non-finite x"; break; }
+          xmin = std::min(xmin, v);
+          xmax = std::max(xmax, v);
+        }
+        if (frc[j]) continue;
+        if (!(xmax > xmin)) {
+          frc[j] = CWB_E_INVALID_ARG;
+          ferr[j] = "constant feature " + std::to_string(j);
+          continue;
+        }
+        int nb = s.n_bins;
+        if (nb == -1) nb = (int)std::floor(std::sqrt((double)n));
+        if (nb < 2) nb = 2;
+        if (nb > kMaxBins) {
+          frc[j] = CWB_E_UNSUPPORTED;
+          ferr[j] = "more than 8192 bins per learner is not supported";
+          continue;
+        }
+        L.nb = nb;
+        L.xmin = xmin;
+        L.xmax = xmax;
+        const double h = (xmax - xmin) / (double)(nb - 1);
+        for (int64_t i = 0; i < n; ++i) Xj[i] = (uint16_t)bin_of(xj[hf->perm[i]], xmin, xmax, h, nb);
+        // knots and banded basis at the design points
+        const int deg = s.degree;
+        const int nint = s.n_interior_knots;
+        const int nk = nint + 2 + 2 * deg;
+        const int d = nk - deg - 1;
+        L.d = d;
+        L.band = deg + 1;
+        t.resize(nk);
+        const double hk = (xmax - xmin) / (double)(nint + 1);
+        for (int q = 0; q < nk; ++q) t[q] = xmin + (double)(q - deg) * hk;
+        L.bstart.resize(nb);
+        L.bval.assign((size_t)nb * kMaxBand, 0.0);
+        for (int l = 0; l < nb; ++l) {
+          const double z = grid_point(xmin, xmax, h, l, nb);
+          L.bstart[l] = bspline_band(z, t, deg, d, &L.bval[(size_t)l * kMaxBand]);
+        }
+      }
+      // support ranges: design points whose band covers basis index q
+      const int d = L.d;
+      L.jr.assign((size_t)2 * d, 0);
+      for (int q = 0; q < d; ++q) {
+        int lo = L.nb, hi = -1;
+        for (int l = 0; l < L.nb; ++l)
+          if (L.bstart[l] <= q && q < L.bstart[l] + L.band) {
+            lo = std::min(lo, l);
+            hi = std::max(hi, l);
+          }
+        L.jr[2 * q] = lo;
+        L.jr[2 * q + 1] = hi;
+      }
+      // counts over training rows and over all rows
+      std::vector<double> cnt_t(L.nb, 0.0), cnt_a(L.nb, 0.0);
+      for (int64_t i = 0; i < n; ++i) {
+        cnt_a[Xj[i]] += 1.0;
+        if (i < nt) cnt_t[Xj[i]] += 1.0;
+      }
+      const std::vector<double> D = (s.kind == CWB_RIDGE_CAT) ? difference_penalty(d, 0)
+                                                               : difference_penalty(d, s.penalty_order);
+      for (int set = 0; set < 2; ++set) {
+        const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
+        std::vector<double> G((size_t)d * d, 0.0);
+        for (int l = 0; l < L.nb; ++l) {
+          if (cnt[l] == 0.0) continue;
+          const int b0 = L.bstart[l];
+          const double* bv = &L.bval[(size_t)l * kMaxBand];
+          for (int a = 0; a < L.band; ++a)
+            for (int b = 0; b < L.band; ++b) G[(size_t)(b0 + a) * d + (b0 + b)] += cnt[l] * bv[a] * bv[b];
+        }
+        double lam = s.lambda;
+        if (s.df > 0.0) {
+          if (s.kind == CWB_RIDGE_CAT) {
+            if (s.df >= (double)d) {
+              lam = 0.0;
+            } else {  // sum_l n_l / (n_l + lambda) = df, bisection in log(lambda)
+              double lo = 1e-12, hi = 1e12 * (double)n;
+              for (int it = 0; it < 400 && hi / lo > 1.0 + 1e-15; ++it) {
+                const double mid = std::sqrt(lo * hi);
+                double v = 0.0;
+                for (int l = 0; l < d; ++l) v += cnt[l] / (cnt[l] + mid);
+                if (v > s.df) lo = mid; else hi = mid;
+              }
+              lam = std::sqrt(lo * hi);
+            }
+          } else {
+            std::string e;
+            const int r2 = lambda_for_df(d, G, D, s.df, &lam, &e);
+            if (r2) {
+              frc[j] = r2;
+              ferr[j] = e + " (feature " + std::to_string(j) + ")";
+              break;
+            }
+          }
+        }
+        L.lambda[set] = lam;
+        std::vector<double> A((size_t)d * d);
+        for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
+        if (!spd_inverse(d, A, L.ainv[set])) {
+          frc[j] = CWB_E_NUMERIC;
+          ferr[j] = "penalised Gram matrix is singular (feature " + std::to_string(j) + ")";
+          break;
+        }
+        L.gram[set] = G;
+      }
+    }
+  };
+  unsigned nth = std::thread::hardware_concurrency();
+  if (nth == 0) nth = 4;
+  nth = std::min<unsigned>(nth, 32);
+  nth = std::min<unsigned>(nth, (unsigned)p);
+  std::vector<std::thread> pool;
+  for (unsigned i = 1; i < nth; ++i) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  for (int j = 0; j < p; ++j)
+    if (frc[j]) {
+      set_error(err, ferr[j]);
+      return frc[j];
+    }
+  hf->nb_max = 0;
+  hf->d_max = 0;
+  hf->sum_d = 0;
+  for (int j = 0; j < p; ++j) {
+    hf->nb_max = std::max(hf->nb_max, hf->L[j].nb);
+    hf->d_max = std::max(hf->d_max, hf->L[j].d);
+    hf->sum_d += hf->L[j].d;
+  }
+  return CWB_OK;
+}
+
+}  // namespace cwb

@@ -1,0 +1,42 @@
+// setup.h -- host-side FP64 setup of a fit (see setup.cpp).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cwb.h"
+#include "cwb_internal.h"
+
+namespace cwb {
+
+struct HostLearner {
+  int kind = 0;
+  int nb = 0;      // design points or levels
+  int band = 0;    // nonzeros per reduced-design row
+  int d = 0;       // basis size
+  double xmin = 0, xmax = 0;
+  std::vector<int32_t> bstart;   // nb
+  std::vector<double> bval;      // nb x kMaxBand
+  std::vector<int32_t> jr;       // d x 2
+  std::vector<double> ainv[2];   // d x d, [0] training rows, [1] all rows
+  std::vector<double> gram[2];
+  double lambda[2] = {0, 0};
+};
+
+struct HostFit {
+  int64_t n = 0, n_pad = 0, n_train = 0;
+  int p = 0;
+  int loss = 0, variant = 0, M = 0, patience = 0;
+  double nu = 0, gamma = 0, f0 = 0;
+  int nb_max = 0, d_max = 0, sum_d = 0;
+  std::vector<int64_t> perm;     // internal row -> original row
+  std::vector<uint16_t> X;       // p x n_pad, feature-major
+  std::vector<float> y;          // n_pad
+  std::vector<HostLearner> L;
+};
+
+int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z, std::string* err);
+int validate_problem(const cwb_problem* pr, std::string* err);
+int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err);
+
+}  // namespace cwb

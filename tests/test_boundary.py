@@ -1,0 +1,150 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+symbol include/cwb.h declares, sizes workspaces (building and validating the
+histogram schedule) and rejects bad problems before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2110_03513_amd import cwb, datagen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "cwb.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(cwb_[a-z_]+)\s*\(", hdr)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = _declared_symbols()
+    assert len(syms) >= 25
+    out = subprocess.run(["nm", "-D", "--defined-only", cwb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (cwb_[a-z_]+)\b", out))
+    missing = [s for s in syms if s not in exported]
+    assert not missing, missing
+    L = cwb.lib()
+    for s in syms:
+        assert getattr(L, s) is not None
+
+
+def test_binding_names_match_header():
+    assert set(cwb._SIGNATURES) == set(_declared_symbols())
+
+
+def test_version():
+    a, b = C.c_int(), C.c_int()
+    assert cwb.lib().cwb_version(C.byref(a), C.byref(b)) == 0
+    assert (a.value, b.value) == (1, 0)
+
+
+@pytest.mark.parametrize("n,p,nb,variant", [
+    (2, 1, 2, "cwb"), (100, 3, 10, "acwb"), (1000, 7, 31, "hcwb"), (12345, 40, 1000, "cwb"),
+    (1_000_000, 200, 1000, "cwb"), (2_000_000, 160, 1000, "hcwb"), (5000, 1, 8192, "acwb"),
+    (777, 33, 2, "cwb")])
+@pytest.mark.parametrize("env", [{}, {"CWB_HIST_F": "3"}, {"CWB_HIST_SLICES": "8"},
+                                 {"CWB_HIST_BPC": "3", "CWB_HIST_NT": "256"}])
+def test_workspace_sizes_and_schedule(n, p, nb, variant, env, monkeypatch):
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    prob = _shape_only_problem(n, p, nb, variant)
+    b = cwb.workspace_bytes(prob)
+    assert b >= 2 * n * p  # at least the uint16 index matrix
+    assert b % 256 == 0
+
+
+def _shape_only_problem(n, p, nb, variant):
+    # x is never read by cwb_workspace_bytes beyond its shape
+    x = np.zeros((n, p))
+    vm = (np.arange(n) % 5 == 0).astype(np.uint8) if variant == "hcwb" else None
+    prob = {"x": x, "y": np.zeros(n), "loss": "l2", "nu": 0.1, "M": 10, "variant": variant,
+            "gamma": 0.01, "patience": 5, "val_mask": vm}
+    prob.update(datagen.learner_specs(p, nb))
+    return prob
+
+
+def _create_error(prob, ws_bytes=1 << 40):
+    pr = cwb.Problem(prob)
+    h = C.c_void_p()
+    rc = cwb.lib().cwb_fit_create(C.byref(pr.c), C.c_void_p(1 << 20), ws_bytes, None, C.byref(h))
+    return rc, cwb.lib().cwb_last_error().decode()
+
+
+def test_create_rejects_bad_problems():
+    base = datagen.tiny_problem(n=200, p=3, seed=5, n_bins=10, M=5)
+    x = base["x"].copy()
+    x[:, 1] = 3.0
+    assert _create_error(dict(base, x=x)) == (cwb.CWB_E_INVALID_ARG, "constant feature 1")
+    rc, msg = _create_error(dict(base, loss="binomial"))
+    assert rc == cwb.CWB_E_INVALID_ARG and "0/1" in msg
+    rc, msg = _create_error(dict(base, nu=0.0))
+    assert rc == cwb.CWB_E_INVALID_ARG
+    rc, msg = _create_error(dict(base, M=0))
+    assert rc == cwb.CWB_E_INVALID_ARG
+    rc, msg = _create_error(dict(base, variant="hcwb", val_mask=None))
+    assert rc == cwb.CWB_E_INVALID_ARG and "validation" in msg
+    rc, msg = _create_error(dict(base, variant="hcwb", val_mask=np.ones(200, np.uint8)))
+    assert rc == cwb.CWB_E_INVALID_ARG
+    rc, msg = _create_error(dict(base, df=np.full(3, 30.0)))
+    assert rc == cwb.CWB_E_INVALID_ARG and "df" in msg
+    rc, msg = _create_error(dict(base, df=np.full(3, 1.5)))
+    assert rc == cwb.CWB_E_INVALID_ARG
+    rc, msg = _create_error(dict(base, n_bins=np.full(3, 1)))
+    assert rc == cwb.CWB_E_INVALID_ARG
+    rc, msg = _create_error(dict(base, n_bins=np.full(3, 20000)))
+    assert rc == cwb.CWB_E_UNSUPPORTED
+    rc, msg = _create_error(dict(base, n_bins=np.zeros(3, int)))
+    assert rc == cwb.CWB_E_UNSUPPORTED and "unbinned" in msg
+    y = base["y"].copy()
+    y[3] = np.nan
+    rc, msg = _create_error(dict(base, y=y))
+    assert rc == cwb.CWB_E_INVALID_ARG
+    # categorical code out of range
+    pc = datagen.additive_problem(300, 3, seed=9, n_informative=1, n_cat=1, n_bins=10, M=3)
+    xc = pc["x"].copy()
+    xc[0, 2] = pc["n_levels"][2]
+    rc, msg = _create_error(dict(pc, x=xc))
+    assert rc == cwb.CWB_E_INVALID_ARG and "level" in msg
+
+
+def test_create_rejects_small_workspace():
+    base = datagen.tiny_problem(n=200, p=3, seed=5, n_bins=10, M=5)
+    need = cwb.workspace_bytes(base)
+    rc, msg = _create_error(base, ws_bytes=need - 256)
+    assert rc == cwb.CWB_E_NO_MEMORY and "workspace too small" in msg
+
+
+def test_null_arguments():
+    L = cwb.lib()
+    assert L.cwb_fit_run(None, 1) == cwb.CWB_E_INVALID_ARG
+    assert L.cwb_fit_sync(None) == cwb.CWB_E_INVALID_ARG
+    assert L.cwb_workspace_bytes(None, None) == cwb.CWB_E_INVALID_ARG
+    b = C.c_size_t()
+    assert L.cwb_batch_workspace_bytes(None, 0, C.byref(b)) == cwb.CWB_E_INVALID_ARG
+    L.cwb_fit_destroy(None)
+    L.cwb_batch_destroy(None)
+
+
+def test_library_binning_matches_oracle_bitwise():
+    """Library and oracle bin with different code (arithmetic estimate plus
+    correction vs binary search) but must give identical index vectors,
+    including exact midpoints, one-ulp neighbours and the endpoints."""
+    import oracle
+    rng = np.random.default_rng(17)
+    for nb in (2, 3, 10, 100, 999, 1000, 1414, 8192):
+        for lo, hi in ((0.0, 1.0), (-3.7, 12.25), (1e-3, 1e-3 + 1e-6), (-1e6, 1e6)):
+            x = rng.uniform(lo, hi, 20_000)
+            x[0], x[1] = lo, hi
+            z, _ = oracle.bin_feature(x, nb)
+            mids = 0.5 * (z[:-1] + z[1:])
+            extra = np.concatenate([mids, np.nextafter(mids, -np.inf), np.nextafter(mids, np.inf), z])
+            xx = np.concatenate([x, extra[(extra >= lo) & (extra <= hi)]])
+            zo, io = oracle.bin_feature(xx, nb)
+            zl, il = cwb.bin_feature(xx, nb)
+            np.testing.assert_array_equal(zl, zo)
+            np.testing.assert_array_equal(il.astype(np.int64), io.astype(np.int64))

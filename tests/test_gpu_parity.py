@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Sizes span several histogram segments, row blocks and a ragged tail; the
+full-size headline shape (n = 1e6, p = 200, 1,000 bins) is checked on its
+first iterations in the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+from paper_2110_03513_amd import cwb, datagen
+from tests.parity import compare, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(prob, iters=None):
+    _say(f"gpu run: n={prob['x'].shape[0]} p={prob['x'].shape[1]} variant={prob.get('variant')} "
+         f"loss={prob['loss']} M={prob['M']}")
+    return cwb.fit(prob, iters=iters)
+
+
+def test_config1_cwb_l2_full():
+    prob = datagen.config1(M=500)
+    gpu = _run(prob)
+    compare(gpu, prob)
+
+
+def test_scaled_config2_cwb_l2():
+    prob = datagen.config2(n=100_000, p=50, M=300, n_bins=1000)
+    gpu = _run(prob)
+    compare(gpu, prob)
+
+
+@pytest.mark.parametrize("loss", ["l2", "binomial"])
+def test_acwb(loss):
+    prob = datagen.additive_problem(60_000, 24, seed=11, n_informative=6, loss=loss, n_bins=300,
+                                    M=200, variant="acwb", gamma=0.0034, n_cat=3,
+                                    n_informative_cat=1)
+    gpu = _run(prob)
+    compare(gpu, prob)
+
+
+def test_scaled_config3_acwb_binomial():
+    prob = datagen.config3("acwb", n=200_000, M=150, n_num=30, n_cat=4, n_bins=1000)
+    gpu = _run(prob)
+    compare(gpu, prob)
+
+
+def test_scaled_config3_hcwb_binomial():
+    prob = datagen.config3("hcwb", n=200_000, M=200, n_num=30, n_cat=4, n_bins=1000)
+    prob["gamma"] = 0.3
+    prob["patience"] = 3
+    gpu = _run(prob)
+    d = compare(gpu, prob)
+    _say(f"hcwb switch iteration {gpu['switch_iter']}")
+
+
+def test_hcwb_forced_switch_by_mirrored_validation_labels():
+    rng = np.random.default_rng(54)
+    half, p = 20_000, 5
+    x1 = rng.uniform(0, 1, (half, p))
+    y1 = np.sin(5 * x1[:, 0]) + 2 * x1[:, 1] + rng.normal(0, 0.1, half)
+    prob = {"x": np.vstack([x1, x1]), "y": np.concatenate([y1, 2 * y1.mean() - y1]),
+            "loss": "l2", "nu": 0.1, "M": 40, "variant": "hcwb", "gamma": 0.01, "patience": 4,
+            "val_mask": np.concatenate([np.zeros(half), np.ones(half)]).astype(np.uint8)}
+    prob.update(datagen.learner_specs(p, 100))
+    gpu = _run(prob)
+    assert gpu["switch_iter"] == 5
+    compare(gpu, prob)
+
+
+@pytest.mark.parametrize("patience", [0, 1000])
+def test_hcwb_limits(patience):
+    prob = datagen.additive_problem(30_000, 8, seed=13, n_informative=3, loss="l2", n_bins=150,
+                                    M=60, variant="hcwb", gamma=0.05, patience=patience)
+    gpu = _run(prob)
+    assert gpu["switch_iter"] == (1 if patience == 0 else -1)
+    compare(gpu, prob)
+
+
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 1031, 2049, 4099])
+def test_small_and_ragged_n(n):
+    rng = np.random.default_rng(n)
+    p = 3
+    x = rng.uniform(0, 1, (n, p))
+    x[0, :] = 0.0
+    x[-1, :] = 1.0
+    y = np.sin(3 * x[:, 0]) + rng.normal(0, 0.3, n)
+    prob = {"x": x, "y": y, "loss": "l2", "nu": 0.1, "M": 15, "variant": "cwb"}
+    prob.update(datagen.learner_specs(p, max(2, min(50, n // 2))))
+    prob["df"] = np.full(p, 4.0)
+    gpu = _run(prob)
+    compare(gpu, prob)
+
+
+def test_edge_bins_degrees_and_single_learner():
+    rng = np.random.default_rng(3)
+    n = 20_000
+    x = rng.uniform(-2, 5, (n, 1))
+    y = np.cos(x[:, 0]) + rng.normal(0, 0.5, n)
+    for nb in (2, 8192):
+        prob = {"x": x, "y": y, "loss": "l2", "nu": 0.3, "M": 20, "variant": "cwb"}
+        prob.update(datagen.learner_specs(1, nb, df=4.0))
+        if nb == 2:  # two design points: a fixed smoothing parameter
+            prob["df"] = np.zeros(1)
+            prob["lambda"] = np.ones(1)
+        compare(_run(prob), prob)
+    for deg in (1, 2):
+        prob = {"x": x, "y": y, "loss": "l2", "nu": 0.3, "M": 20, "variant": "acwb",
+                "gamma": 0.1, "degree": deg}
+        prob.update(datagen.learner_specs(1, 64, df=4.0))
+        prob["degree"] = deg
+        compare(_run(prob), prob)
+
+
+def test_categorical_only_binomial():
+    prob = datagen.additive_problem(50_000, 4, seed=21, n_informative=0, loss="binomial", M=40,
+                                    n_cat=4, n_informative_cat=3, variant="acwb", gamma=0.05)
+    assert (prob["kind"] == 1).all()
+    compare(_run(prob), prob)
+
+
+def test_bitwise_repeat_resume_and_checkpoint():
+    prob = datagen.additive_problem(40_000, 12, seed=31, n_informative=4, loss="binomial",
+                                    n_bins=200, M=60, variant="acwb", gamma=0.01)
+    a = _run(prob)
+    b = _run(prob)
+    for key in ("k", "kcor", "theta", "coef_f", "coef_h", "f", "risk_train"):
+        np.testing.assert_array_equal(a[key], b[key])
+    _say("resume in three parts with a checkpoint reload")
+    f1 = cwb.Fit(prob)
+    f1.run(17)
+    f1.sync()
+    blob = f1.save_state()
+    f1.run(20)
+    f1.sync()
+    f2 = cwb.Fit(prob)
+    f2.load_state(blob)
+    f2.run(43)
+    f2.sync()
+    tr = f2.trace()
+    np.testing.assert_array_equal(tr["k"], a["k"])
+    np.testing.assert_array_equal(f2.pred(), a["f"])
+    np.testing.assert_array_equal(f2.model()["coef_h"], a["coef_h"])
+    f1.run(23)
+    f1.sync()
+    np.testing.assert_array_equal(f1.pred(), a["f"])
+    f1.close()
+    f2.close()
+
+
+def test_batch_equals_alone_bitwise():
+    probs = [
+        datagen.additive_problem(30_000, 10, seed=41, n_informative=3, n_bins=170, M=40),
+        datagen.additive_problem(55_555, 23, seed=42, n_informative=4, loss="binomial",
+                                 n_bins=235, M=30, variant="acwb", gamma=0.01),
+        datagen.additive_problem(20_000, 7, seed=43, n_informative=2, n_bins=141, M=50,
+                                 variant="hcwb", gamma=0.2, patience=2),
+        datagen.additive_problem(9_000, 5, seed=44, n_informative=2, loss="binomial", M=25,
+                                 n_cat=2, n_informative_cat=1),
+    ]
+    alone = [_run(p) for p in probs]
+    _say("batched run of 4 heterogeneous fits")
+    fits = [cwb.Fit(p) for p in probs]
+    b = cwb.Batch(fits)
+    b.run(max(p["M"] for p in probs))
+    b.sync()
+    for f, a in zip(fits, alone):
+        tr = f.trace()
+        np.testing.assert_array_equal(tr["k"], a["k"])
+        np.testing.assert_array_equal(tr["kcor"], a["kcor"])
+        assert tr["switch_iter"] == a["switch_iter"]
+        np.testing.assert_array_equal(f.pred(), a["f"])
+        np.testing.assert_array_equal(f.model()["coef_f"], a["coef_f"])
+        f.close()
+    b.close()
+
+
+def test_full_size_config2_first_iterations():
+    prob = datagen.config2(M=2000)
+    M = 25
+    _say("full-size n=1e6 p=200: 25 iterations on the GPU")
+    f = cwb.Fit(prob)
+    f.run(M)
+    f.sync()
+    gpu = f.trace()
+    gpu.update(f.model())
+    gpu["f"] = f.pred()
+    f.close()
+    compare(gpu, dict(prob, M=M))

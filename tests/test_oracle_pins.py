@@ -423,3 +423,11 @@ def test_config1_scale_run_is_sane():
     # the five informative features are selected first
     assert set(out["k"][:30]) <= set(range(5))
     assert (out["gap"] >= 0).all()
+
+
+def test_rtr_is_signal_norm():
+    """r^T r reported per iteration equals 2 n R_emp(f^[m-1]) for L2."""
+    pr = datagen.tiny_problem(n=500, p=3, seed=81, n_bins=20, M=10)
+    out = oracle.fit(pr)
+    np.testing.assert_allclose(out["rtr"], 2 * 500 * out["risk_train"][:-1], rtol=1e-12)
+    assert (out["sse"] <= out["rtr"]).all()
