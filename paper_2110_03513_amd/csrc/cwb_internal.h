@@ -27,6 +27,9 @@ constexpr int kMaxBand = 4;      // nonzero basis values per design point (cubic
 constexpr int kMaxD = 64;        // largest basis size
 constexpr int kMaxBins = 8192;   // largest n* (one learner's histogram must fit LDS)
 constexpr int kNumSig = 2;       // signals: pseudo-residuals r, corrected residuals c
+constexpr int kStageBins = 2048; // learners up to this many bins are solved from LDS
+constexpr int kMaxSlots = 512;   // segment slots staged per learner group and pass
+constexpr int kHistMaxLds = 152 * 1024;  // dynamic LDS of one histogram block
 
 // One base learner.
 struct FeatDev {
@@ -50,9 +53,6 @@ struct Ctl {
   int32_t counter;      // HCWB: consecutive validation-risk rises
   double eta;           // momentum step of iteration m_done
   double rval_prev;     // HCWB: validation risk of the previous model
-  uint32_t absmax[kNumSig];  // bits of max |signal| of the current iteration
-  uint32_t sel_done;    // selection blocks finished this iteration
-  uint32_t val_done;    // validation-risk blocks finished
   int32_t error;        // non-finite model state seen
   int32_t pad;
 };
@@ -65,7 +65,7 @@ struct FitDev {
   int32_t n_row_blocks;  // row-pass blocks: ceil(n_pad / kStateRows)
   int32_t n_val_blocks;  // validation blocks over [n_train, n)
   int32_t nsig_max;      // 2 for ACWB / HCWB, else 1
-  int32_t pad;
+  int32_t nb_stride;     // histogram stride per learner: nb_max rounded up to 4
   const uint16_t* X;
   const float* y;
   float* fg;
@@ -91,6 +91,7 @@ struct FitDev {
   double* coef_f;          // [sum_d]
   double* coef_h;          // [sum_d]
   double* risk_part;       // [n_row_blocks][2]
+  float* amax_part;        // [n_row_blocks][2] largest |r|, |c| per row-pass block
   double* val_part;        // [n_val_blocks]
   Ctl* ctl;
 };
@@ -108,32 +109,33 @@ struct Seg {
   int64_t slot;    // offset (int64 words) of the partial slot
 };
 
-struct GroupSegs {
-  int64_t seg_begin, seg_end;  // segments of one (fit, group), consecutive
-};
-
 struct StateItem {   // one row-pass block
   int32_t fit;
   int32_t blk;       // block index within the fit
 };
 
-struct SelItem {     // one learner's solve
+struct SelItem {     // one learner's solve, with everything it needs up front
   int32_t fit;
   int32_t k;
-  int64_t grp;       // index into the GroupSegs table
+  int32_t nb, band, d, coef_off;
+  int64_t bin_off, mat_off;
+  int64_t off_begin; // its partial offsets: off[off_begin + sig * n_off + i]
+  int32_t n_off;     // segments of its group
+  int32_t pad;
 };
 
 // Fixed-point exponent for the int64 histogram of a signal whose largest
-// magnitude has float bits `absmax_bits`, summed over at most n_fit rows:
-// |r| * 2^e < 2^(62 - N) with n_fit < 2^N, so no sum can overflow.
+// magnitude is `amax`, summed over at most n_fit rows: |r| * 2^e < 2^(62 - N)
+// with n_fit < 2^N, so no sum of n_fit terms can overflow.
 #if defined(__HIPCC__)
 __host__ __device__
 #endif
-inline int scale_exponent(uint32_t absmax_bits, int64_t n_fit) {
-  if (absmax_bits == 0u) return 0;
-  uint32_t ex = (absmax_bits >> 23) & 0xffu;   // biased exponent of max |r|
-  int E = (int)ex - 126;                        // max |r| < 2^E
-  if (ex == 0u) E = -125;                       // subnormal
+inline int scale_exponent(float amax, int64_t n_fit) {
+  if (!(amax > 0.0f)) return 0;
+  uint32_t bits;
+  __builtin_memcpy(&bits, &amax, 4);
+  const uint32_t ex = (bits >> 23) & 0xffu;     // biased exponent of max |r|
+  const int E = (ex == 0u) ? -125 : (int)ex - 126;  // max |r| < 2^E
   int N = 0;
   for (int64_t v = n_fit; v > 0; v >>= 1) ++N;  // n_fit < 2^N
   return 62 - N - E;

@@ -11,10 +11,11 @@ hipError_t launch_state(hipStream_t st, const FitDev* fits, const StateItem* ite
 hipError_t launch_hist(hipStream_t st, int nt, int fmax, int blocks, size_t lds, const FitDev* fits,
                        const Seg* segs, const int64_t* blk, long long* partials);
 hipError_t launch_select(hipStream_t st, const FitDev* fits, const SelItem* items, int nitems,
-                         int nb_max, const int64_t* grp_ptr, const int64_t* grp_seg,
-                         const Seg* segs, const long long* partials);
+                         int nb_max, int d_max, const int64_t* sel_off, const long long* partials);
 hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* items, int nitems,
                           int nb_max);
+hipError_t launch_pick(hipStream_t st, const FitDev* fits, int nfits);
+hipError_t launch_valdecide(hipStream_t st, const FitDev* fits, int nfits);
 hipError_t launch_finalize(hipStream_t st, const FitDev* fits, int nfits);
 
 }  // namespace cwb

@@ -6,7 +6,7 @@
 //             (f += nu b_k, h += eta b_kcor), form g = (1-theta_m) f +
 //             theta_m h (ACWB), the pseudo-residuals r = -dL/df and the
 //             error-corrected residuals c (ACWB), FP64 partial risks, and the
-//             largest |r|, |c| (fixed-point scale of the histograms).
+//             per-block largest |r|, |c| (fixed-point scale of the histograms).
 //   k_hist    histogram pass over the uint16 bin-index matrix: for every
 //             learner k and design point l, s_kl = sum of r_i over the rows
 //             with ind_ki = l (binMatVec, Algorithm 1, first stage), and the
@@ -19,11 +19,14 @@
 //             the cached inverse (Section 2.4), criterion
 //             q = theta^T G theta - 2 theta^T v, so SSE_k = r^T r + q_k
 //             (Algorithm A1's SSE), and the candidate update table Z^b theta.
-//             The last block of a fit takes argmin_k q (ties to the lowest k),
-//             records the traces, aggregates the coefficients (Section 2.3 /
-//             3.2.1) and arms the update for the next row pass.
-//   k_valrisk (HCWB, ACWB phase) validation risk of the new primary model and
-//             the patience counter that decides the switch to CWB.
+//   k_pick    one block per fit: argmin_k q (ties to the lowest k), traces,
+//             aggregated coefficients (Section 2.3 / 3.2.1), and the update
+//             armed for the next row pass.
+//   k_valrisk (HCWB, ACWB phase) validation-risk partials of the new primary
+//   k_valdecide  model, then the patience counter that decides the switch.
+// Cross-block results pass through kernel boundaries only: on this chip a
+// device-scope fence writes back the issuing XCD's L2, which is far more
+// expensive than one more launch.
 #include <hip/hip_runtime.h>
 
 #include "../../include/cwb.h"
@@ -35,6 +38,20 @@ namespace cwb {
 namespace {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Pointers read out of the fit descriptors are generic; casting them to the
+// global address space makes the compiler emit global_load/global_store
+// instead of flat accesses (flat accesses also count against the LDS
+// wait counter, which would serialise HBM loads behind LDS atomics).
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gp(T* p) {
+  return (GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* gp(const T* p) {
+  return (const GLOBAL T*)p;
+}
 
 __device__ __forceinline__ bool is_acwb_step(const FitDev& F, int switched) {
   return F.variant == CWB_ACWB || (F.variant == CWB_HCWB && !switched);
@@ -62,47 +79,78 @@ __device__ __forceinline__ double loss_value(int loss, float y, float f) {
   return sp - yd * fd;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-// Deterministic block sum: fixed butterfly per wave, then waves in order.
+// Deterministic block sum (thread 0 gets the result): every thread stores its
+// value, 16 threads add 16 consecutive chunks in order, thread 0 adds those.
+// red must hold NT + 16 doubles.
 template <int NT>
 __device__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  constexpr int kParts = 16, kPer = NT / kParts;
+  red[threadIdx.x] = v;
   __syncthreads();
-  double s = 0.0;
+  if (threadIdx.x < kParts) {
+    double a = 0.0;
+    for (int i = 0; i < kPer; ++i) a += red[threadIdx.x * kPer + i];
+    red[NT + threadIdx.x] = a;
+  }
+  __syncthreads();
+  double sum = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    for (int i = 0; i < kParts; ++i) sum += red[NT + i];
   __syncthreads();
-  return s;  // valid in thread 0
+  return sum;
 }
 
+// Block maximum of non-negative floats (every thread gets the result);
+// red must hold NT + 16 floats.
+template <int NT>
+__device__ float block_max(float v, float* red) {
+  constexpr int kParts = 16, kPer = NT / kParts;
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < kParts) {
+    float a = 0.0f;
+    for (int i = 0; i < kPer; ++i) a = fmaxf(a, red[threadIdx.x * kPer + i]);
+    red[NT + threadIdx.x] = a;
+  }
+  __syncthreads();
+  float m = 0.0f;
+  for (int i = 0; i < kParts; ++i) m = fmaxf(m, red[NT + i]);
+  __syncthreads();
+  return m;
+}
+
+// Scale exponent of signal `sig` of a fit: maximum over the row-pass blocks
+// maxima (order-free, so every block computes the same value).  red must
+// hold NT + 16 floats.
+template <int NT>
+__device__ int fit_scale_exponent(const FitDev& F, int sig, int64_t n_fit, float* red) {
+  float a = 0.0f;
+  const GLOBAL float* am = gp(F.amax_part);
+  for (int b = threadIdx.x; b < F.n_row_blocks; b += NT) a = fmaxf(a, am[2 * b + sig]);
+  return scale_exponent(block_max<NT>(a, red), n_fit);
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef long long i64x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void load8f(const float* p, float* v) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  const GLOBAL f32x4* q = (const GLOBAL f32x4*)p;
+  const f32x4 a = q[0], b = q[1];
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
   v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
 __device__ __forceinline__ void store8f(float* p, const float* v) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-  *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  GLOBAL f32x4* q = (GLOBAL f32x4*)p;
+  f32x4 a, b;
+  a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+  b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
+  q[0] = a;
+  q[1] = b;
 }
 
 __device__ __forceinline__ void load8u(const uint16_t* p, uint32_t* idx) {
-  const uint4 w = *reinterpret_cast<const uint4*>(p);
+  const u32x4 w = *(const GLOBAL u32x4*)p;
   idx[0] = w.x & 0xffffu; idx[1] = w.x >> 16;
   idx[2] = w.y & 0xffffu; idx[3] = w.y >> 16;
   idx[4] = w.z & 0xffffu; idx[5] = w.z >> 16;
@@ -117,8 +165,8 @@ __device__ __forceinline__ void load8u(const uint16_t* p, uint32_t* idx) {
 __global__ void __launch_bounds__(kStateThreads)
 k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, int final_mode) {
   extern __shared__ float s_tab[];  // [2][nb_max]
-  __shared__ double s_red[kStateThreads / 64];
-  __shared__ float s_fmax[2][kStateThreads / 64];
+  __shared__ double s_red[kStateThreads + 16];
+  __shared__ float s_fred[kStateThreads + 16];
   __shared__ int s_bad;
   const StateItem it = items[blockIdx.x];
   const FitDev& F = fits[it.fit];
@@ -142,10 +190,10 @@ k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, in
   const bool use_h = pending && pend_acwb && kc >= 0;
   const bool use_cc = acwb && m > 1 && kc >= 0;
   if (use_t)
-    for (int l = threadIdx.x; l < nb; l += kStateThreads) tf[l] = F.table[((size_t)kk) * nb + l];
+    for (int l = threadIdx.x; l < nb; l += kStateThreads) tf[l] = gp(F.table)[((size_t)kk) * nb + l];
   if (use_h || use_cc)
     for (int l = threadIdx.x; l < nb; l += kStateThreads)
-      tc[l] = F.table[((size_t)F.p + kc) * nb + l];
+      tc[l] = gp(F.table)[((size_t)F.p + kc) * nb + l];
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
 
@@ -211,26 +259,15 @@ k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, in
   if (bad) s_bad = 1;
   const double st = block_sum<kStateThreads>(risk_t, s_red);
   const double sv = block_sum<kStateThreads>(risk_v, s_red);
-  amax_r = wave_max(amax_r);
-  amax_c = wave_max(amax_c);
-  if ((threadIdx.x & 63) == 0) {
-    s_fmax[0][threadIdx.x >> 6] = amax_r;
-    s_fmax[1][threadIdx.x >> 6] = amax_c;
-  }
-  __syncthreads();
+  const float a = block_max<kStateThreads>(amax_r, s_fred);
+  const float b = block_max<kStateThreads>(amax_c, s_fred);
   if (threadIdx.x == 0) {
-    float a = 0.0f, b = 0.0f;
-    for (int w = 0; w < kStateThreads / 64; ++w) {
-      a = fmaxf(a, s_fmax[0][w]);
-      b = fmaxf(b, s_fmax[1][w]);
-    }
     F.risk_part[2 * it.blk] = st;
     F.risk_part[2 * it.blk + 1] = sv;
     if (!final_mode) {
-      // non-negative floats order like their bit patterns
       if (!isfinite(a) || !isfinite(b)) s_bad = 1;
-      if (a > 0.0f) atomicMax(&ctl->absmax[0], __float_as_uint(a));
-      if (b > 0.0f) atomicMax(&ctl->absmax[1], __float_as_uint(b));
+      F.amax_part[2 * it.blk] = a;
+      F.amax_part[2 * it.blk + 1] = b;
     }
     if (s_bad) atomicOr(&ctl->error, 1);
   }
@@ -239,6 +276,27 @@ k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, in
 // ---------------------------------------------------------------------------
 // Histogram pass.
 // ---------------------------------------------------------------------------
+template <int NSIG>
+__device__ __forceinline__ void hist_add(unsigned long long* __restrict__ h, const u32x4& x,
+                                         const long long* q) {
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    __hip_atomic_fetch_add(h + (w[j] & 0xffffu), (unsigned long long)q[2 * j], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(h + (w[j] >> 16), (unsigned long long)q[2 * j + 1], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+__device__ __forceinline__ u32x4 load_idx(const uint16_t* p) {
+  return __builtin_nontemporal_load((const GLOBAL u32x4*)p);
+}
+
+// Rows [r0, r1) of one segment.  Every thread takes 8 consecutive rows per
+// step: one 32-byte load of residuals per signal and one 16-byte load of bin
+// indices per learner of the group (all issued before any atomic), then 8
+// LDS atomics per learner and signal.
 template <int NT, int FMAX, int NSIG>
 __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
                                           unsigned long long* __restrict__ hist, int nb,
@@ -248,41 +306,24 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
   const size_t ld = (size_t)F.n_pad;
   for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
     float rv[8], cv[8];
+    u32x4 xw[FMAX];
     load8f(F.r + base, rv);
+    if (NSIG == 2) load8f(F.c + base, cv);
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f)
+      if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
     long long q0[8], q1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) q0[j] = (long long)((double)rv[j] * sc0);
     if (NSIG == 2) {
-      load8f(F.c + base, cv);
 #pragma unroll
       for (int j = 0; j < 8; ++j) q1[j] = (long long)((double)cv[j] * sc1);
     }
-    u32x4 xw[FMAX];
-#pragma unroll
-    for (int f = 0; f < FMAX; ++f)
-      if (f < nf) xw[f] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(Xg + f * ld + base));
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) {
       if (f < nf) {
-        unsigned long long* h0 = hist + (size_t)f * nb;
-        const uint32_t w[4] = {xw[f].x, xw[f].y, xw[f].z, xw[f].w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          __hip_atomic_fetch_add(h0 + (w[j] & 0xffffu), (unsigned long long)q0[2 * j],
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          __hip_atomic_fetch_add(h0 + (w[j] >> 16), (unsigned long long)q0[2 * j + 1],
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        if (NSIG == 2) {
-          unsigned long long* h1 = hist + (size_t)(nf + f) * nb;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            __hip_atomic_fetch_add(h1 + (w[j] & 0xffffu), (unsigned long long)q1[2 * j],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(h1 + (w[j] >> 16), (unsigned long long)q1[2 * j + 1],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-        }
+        hist_add<NSIG>(hist + (size_t)f * nb, xw[f], q0);
+        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb, xw[f], q1);
       }
     }
   }
@@ -293,7 +334,10 @@ __global__ void __launch_bounds__(NT)
 k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
        const int64_t* __restrict__ blk, long long* __restrict__ partials) {
   extern __shared__ unsigned long long s_hist[];
+  __shared__ float s_red[NT + 16];
   const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
+  int cached_fit = -1;
+  double sc0 = 0.0, sc1 = 0.0;
   for (int64_t s = s0; s < s1; ++s) {
     const Seg sg = segs[s];
     const FitDev& F = fits[sg.fit];
@@ -302,7 +346,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int switched = ctl->switched;
     const int nsig = is_acwb_step(F, switched) ? 2 : 1;
     const int64_t n_fit = rows_fitted(F, switched);
-    const int nb = F.nb_max;
+    const int nb = F.nb_stride;
     const int words = nsig * sg.nf * nb;
     for (int i = threadIdx.x; i < words; i += NT) s_hist[i] = 0ull;
     __syncthreads();
@@ -310,15 +354,17 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int64_t U = F.n_pad >> 3;
     const int64_t r0 = 8 * (sg.u0 * n8 / U);
     const int64_t r1 = 8 * (sg.u1 * n8 / U);
-    const double sc0 = ldexp(1.0, scale_exponent(ctl->absmax[0], n_fit));
-    if (nsig == 1) {
-      hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, sc0, 0.0);
-    } else {
-      const double sc1 = ldexp(1.0, scale_exponent(ctl->absmax[1], n_fit));
-      hist_rows<NT, FMAX, 2>(F, sg, s_hist, nb, r0, r1, sc0, sc1);
+    if (sg.fit != cached_fit) {
+      sc0 = ldexp(1.0, fit_scale_exponent<NT>(F, 0, n_fit, s_red));
+      sc1 = (nsig == 2) ? ldexp(1.0, fit_scale_exponent<NT>(F, 1, n_fit, s_red)) : 0.0;
+      cached_fit = sg.fit;
     }
+    if (nsig == 1)
+      hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, sc0, 0.0);
+    else
+      hist_rows<NT, FMAX, 2>(F, sg, s_hist, nb, r0, r1, sc0, sc1);
     __syncthreads();
-    long long* out = partials + sg.slot;
+    GLOBAL long long* out = gp(partials + sg.slot);
     for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
     __syncthreads();
   }
@@ -392,7 +438,7 @@ __device__ void pick(const FitDev& F, Ctl* ctl, int m, bool acwb, int nsig) {
   __shared__ int sk[kSelectThreads];
   __shared__ int s_k[2];
   __shared__ double s_gap[2];
-  __shared__ double s_red[kSelectThreads / 64];
+  __shared__ double s_red[kSelectThreads + 16];
   for (int sig = 0; sig < nsig; ++sig)
     block_argmin(F.q + (size_t)sig * F.p, F.p, &s_k[sig], &s_gap[sig], sq, sk, sq2);
   const int k0 = s_k[0];
@@ -436,121 +482,195 @@ __device__ void pick(const FitDev& F, Ctl* ctl, int m, bool acwb, int nsig) {
     ctl->k = k0;
     ctl->kcor = k1;
     ctl->eta = eta;
-    ctl->absmax[0] = 0u;
-    ctl->absmax[1] = 0u;
-    ctl->sel_done = 0u;
     ctl->m_done = m;
   }
 }
 
 }  // namespace
 
+constexpr int kChunks = 8;  // partial sums per output of a small contraction
+
+// out = M x for a d x d matrix in LDS, as fixed-order two-level sums.
+__device__ __forceinline__ void mat_vec(const double* M, const double* x, double* out, int d,
+                                        double* part) {
+  const int per = (d + kChunks - 1) / kChunks;
+  for (int t = threadIdx.x; t < d * kChunks; t += kSelectThreads) {
+    const int j = t / kChunks, c = t % kChunks;
+    const int i0 = c * per, i1 = (i0 + per < d) ? i0 + per : d;
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) acc += M[j * d + i] * x[i];
+    part[t] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < d) {
+    double acc = 0.0;
+    for (int c = 0; c < kChunks; ++c) acc += part[threadIdx.x * kChunks + c];
+    out[threadIdx.x] = acc;
+  }
+  __syncthreads();
+}
+
+// Loads for one learner's solve: from LDS when the learner's reduced design
+// was staged there, else from global memory.
+struct Basis {
+  const double* bval;    // [nb][kMaxBand]
+  const int32_t* bstart; // [nb]
+};
+
+template <bool STAGED>
 __global__ void __launch_bounds__(kSelectThreads)
 k_select(const FitDev* __restrict__ fits, const SelItem* __restrict__ items,
-         const int64_t* __restrict__ grp_ptr, const int64_t* __restrict__ grp_seg,
-         const Seg* __restrict__ segs, const long long* __restrict__ partials) {
-  extern __shared__ double s_bins[];  // nb_max
-  __shared__ double s_v[kMaxD], s_th[kMaxD], s_w[kMaxD];
-  __shared__ int s_last;
+         const int64_t* __restrict__ sel_off, const long long* __restrict__ partials, int nb_cap,
+         int d_cap) {
+  // dynamic LDS: s[nb_cap] | Ainv[d_cap^2] | G[d_cap^2] | (STAGED) bval[nb_cap*4] | bstart[nb_cap]
+  extern __shared__ double s_dyn[];
+  __shared__ double s_v[kMaxD], s_th[kMaxD], s_gt[kMaxD];
+  __shared__ double s_part[kMaxD * kChunks];
+  __shared__ long long s_off[kMaxSlots];
+  __shared__ int s_jr[2 * kMaxD];
+  __shared__ float s_red[kSelectThreads + 16];
+  double* s_bins = s_dyn;
+  double* s_ai = s_dyn + nb_cap;
+  double* s_g = s_ai + (size_t)d_cap * d_cap;
+  double* s_bv = s_g + (size_t)d_cap * d_cap;
+  int* s_bs = reinterpret_cast<int*>(s_bv + (size_t)nb_cap * kMaxBand);
   const SelItem it = items[blockIdx.x];
   const FitDev& F = fits[it.fit];
-  Ctl* ctl = F.ctl;
+  const Ctl* ctl = F.ctl;
   const int m_done = ctl->m_done;
-  if (m_done >= F.M) return;
   const int switched = ctl->switched;
+  const int d = it.d, nb = it.nb, band = it.band, k = it.k;
+  const double* gbval = F.bval + it.bin_off * kMaxBand;
+  const int32_t* gbs = F.bstart + it.bin_off;
+  if (m_done >= F.M) return;
   const bool acwb = is_acwb_step(F, switched);
   const int nsig = acwb ? 2 : 1;
   const int64_t n_fit = rows_fitted(F, switched);
   const int set = gram_set(F, switched);
-  const int k = it.k;
-  const FeatDev fd = F.feat[k];
-  const int d = fd.d;
-  const int64_t g0 = grp_ptr[it.grp], g1 = grp_ptr[it.grp + 1];
-  const int f_local = k - segs[grp_seg[g0]].k0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t* bstart = F.bstart + fd.bin_off;
-  const double* bval = F.bval + fd.bin_off * kMaxBand;
-  const int32_t* jr = F.jr + 2 * (size_t)fd.coef_off;
+  // stage the learner's tables: inverse penalised Gram, Gram, support
+  // ranges and (STAGED) the banded reduced design
+  {
+    const GLOBAL double* Ai = gp(F.ainv[set] + it.mat_off);
+    const GLOBAL double* G = gp(F.gram[set] + it.mat_off);
+    for (int i = threadIdx.x; i < d * d; i += kSelectThreads) {
+      s_ai[i] = Ai[i];
+      s_g[i] = G[i];
+    }
+    const GLOBAL int32_t* jr = gp(F.jr + 2 * (size_t)it.coef_off);
+    for (int i = threadIdx.x; i < 2 * d; i += kSelectThreads) s_jr[i] = jr[i];
+    if (STAGED) {
+      const GLOBAL double* bv = gp(gbval);
+      const GLOBAL int32_t* bs = gp(gbs);
+      for (int i = threadIdx.x; i < nb * kMaxBand; i += kSelectThreads) s_bv[i] = bv[i];
+      for (int i = threadIdx.x; i < nb; i += kSelectThreads) s_bs[i] = bs[i];
+    }
+  }
+  const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{gbval, gbs};
+  const int n_off = it.n_off;
   for (int sig = 0; sig < nsig; ++sig) {
-    const double isc = ldexp(1.0, -scale_exponent(ctl->absmax[sig], n_fit));
-    // bin sums s_l: exact int64 merge of the segment partials, then scaled
-    for (int l = threadIdx.x; l < fd.nb; l += kSelectThreads) {
-      long long acc = 0;
-      for (int64_t g = g0; g < g1; ++g) {
-        const Seg sg = segs[grp_seg[g]];
-        acc += partials[sg.slot + (int64_t)(sig * sg.nf + f_local) * F.nb_max + l];
+    const double isc = ldexp(1.0, -fit_scale_exponent<kSelectThreads>(F, sig, n_fit, s_red));
+    const int64_t* offs = sel_off + it.off_begin + (int64_t)sig * n_off;
+    // bin sums s_l: exact int64 merge of the group's segment partials
+    for (int l0 = 0; l0 < nb; l0 += 4 * kSelectThreads) {
+      long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      const int l = l0 + 4 * threadIdx.x;
+      for (int c0 = 0; c0 < n_off; c0 += kMaxSlots) {
+        const int cnt = (n_off - c0) < kMaxSlots ? (n_off - c0) : kMaxSlots;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kSelectThreads) s_off[i] = gp(offs)[c0 + i];
+        __syncthreads();
+        if (l < nb) {
+#pragma unroll 16
+          for (int i = 0; i < cnt; ++i) {
+            const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + s_off[i] + l);
+            const i64x2 u = src[0], w = src[1];
+            a0 += u.x;
+            a1 += u.y;
+            a2 += w.x;
+            a3 += w.y;
+          }
+        }
       }
-      s_bins[l] = (double)acc * isc;
+      if (l < nb) s_bins[l] = (double)a0 * isc;
+      if (l + 1 < nb) s_bins[l + 1] = (double)a1 * isc;
+      if (l + 2 < nb) s_bins[l + 2] = (double)a2 * isc;
+      if (l + 3 < nb) s_bins[l + 3] = (double)a3 * isc;
     }
     __syncthreads();
+    // Small FP64 contractions, each as fixed-order two-level sums: thread
+    // (j, c) adds a chunk of terms into s_part[j][c], then thread j adds its
+    // kChunks partials in order.
     // v_j = sum_l Z^b[l, j] s_l over the design points supporting basis j
-    for (int j = wave; j < d; j += kSelectThreads / 64) {
-      const int lo = jr[2 * j], hi = jr[2 * j + 1];
+    for (int t = threadIdx.x; t < d * kChunks; t += kSelectThreads) {
+      const int j = t / kChunks, c = t % kChunks;
+      const int lo = s_jr[2 * j], hi = s_jr[2 * j + 1];
       double acc = 0.0;
-      for (int l = lo + lane; l <= hi; l += 64) acc += bval[(size_t)l * kMaxBand + (j - bstart[l])] * s_bins[l];
-      acc = wave_sum(acc);
-      if (lane == 0) s_v[j] = acc;
-    }
-    __syncthreads();
-    const double* Ai = F.ainv[set] + fd.mat_off;
-    const double* G = F.gram[set] + fd.mat_off;
-    if (threadIdx.x < d) {
-      double t = 0.0;
-      for (int i = 0; i < d; ++i) t += Ai[(size_t)threadIdx.x * d + i] * s_v[i];
-      s_th[threadIdx.x] = t;
+      for (int l = lo + c; l <= hi; l += kChunks)
+        acc += B.bval[(size_t)l * kMaxBand + (j - B.bstart[l])] * s_bins[l];
+      s_part[t] = acc;
     }
     __syncthreads();
     if (threadIdx.x < d) {
-      double gt = 0.0;
-      for (int i = 0; i < d; ++i) gt += G[(size_t)threadIdx.x * d + i] * s_th[i];
-      s_w[threadIdx.x] = s_th[threadIdx.x] * (gt - 2.0 * s_v[threadIdx.x]);
+      double acc = 0.0;
+      for (int c = 0; c < kChunks; ++c) acc += s_part[threadIdx.x * kChunks + c];
+      s_v[threadIdx.x] = acc;
     }
     __syncthreads();
+    // theta = (G + lambda D)^-1 v
+    mat_vec(s_ai, s_v, s_th, d, s_part);
+    // G theta
+    mat_vec(s_g, s_th, s_gt, d, s_part);
+    // q = theta^T G theta - 2 theta^T v
     if (threadIdx.x == 0) {
-      double qq = 0.0;
-      for (int j = 0; j < d; ++j) qq += s_w[j];
-      F.q[(size_t)sig * F.p + k] = qq;
+      double w = 0.0;
+      for (int j = 0; j < d; ++j) w += s_th[j] * (s_gt[j] - 2.0 * s_v[j]);
+      F.q[(size_t)sig * F.p + k] = w;
     }
     for (int j = threadIdx.x; j < F.d_max; j += kSelectThreads)
       F.theta[((size_t)sig * F.p + k) * F.d_max + j] = (j < d) ? s_th[j] : 0.0;
-    float* tab = F.table + ((size_t)sig * F.p + k) * F.nb_max;
-    for (int l = threadIdx.x; l < fd.nb; l += kSelectThreads) {
-      const int b0 = bstart[l];
+    // candidate update table Z^b theta
+    GLOBAL float* tab = gp(F.table + ((size_t)sig * F.p + k) * F.nb_max);
+    for (int l = threadIdx.x; l < nb; l += kSelectThreads) {
+      const int b0 = B.bstart[l];
       double t = 0.0;
-      for (int b = 0; b < fd.band; ++b) t += bval[(size_t)l * kMaxBand + b] * s_th[b0 + b];
+      for (int b = 0; b < band; ++b) t += B.bval[(size_t)l * kMaxBand + b] * s_th[b0 + b];
       tab[l] = (float)t;
     }
     __syncthreads();
   }
-  // the last learner block of this fit selects: every thread fences its own
-  // writes, the barrier orders them before the counter increment
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&ctl->sel_done, 1u);
-    s_last = (prev == (unsigned)F.p - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  pick(F, ctl, m_done + 1, acwb, nsig);
+}
+
+// Selection for every fit of the batch (one block per fit).
+__global__ void __launch_bounds__(kSelectThreads) k_pick(const FitDev* __restrict__ fits) {
+  const FitDev& F = fits[blockIdx.x];
+  Ctl* ctl = F.ctl;
+  const int m_done = ctl->m_done;
+  if (m_done >= F.M) return;
+  const bool acwb = is_acwb_step(F, ctl->switched);
+  pick(F, ctl, m_done + 1, acwb, acwb ? 2 : 1);
 }
 
 // ---------------------------------------------------------------------------
 // HCWB validation risk and patience (Algorithm 3).
 // ---------------------------------------------------------------------------
+namespace {
+// The validation check runs after an ACWB step of an HCWB fit that has not
+// switched yet, and once before the first iteration (m_done = 0).
+__device__ __forceinline__ bool valcheck_due(const FitDev& F, const Ctl* ctl) {
+  if (F.variant != CWB_HCWB || ctl->switched) return false;
+  return ctl->m_done == 0 || (ctl->pending && ctl->pend_acwb);
+}
+}  // namespace
+
 __global__ void __launch_bounds__(kStateThreads)
 k_valrisk(const FitDev* __restrict__ fits, const StateItem* __restrict__ items) {
   extern __shared__ float s_tf[];
-  __shared__ double s_red[kStateThreads / 64];
-  __shared__ int s_last;
+  __shared__ double s_red[kStateThreads + 16];
   const StateItem it = items[blockIdx.x];
   const FitDev& F = fits[it.fit];
-  Ctl* ctl = F.ctl;
-  if (F.variant != CWB_HCWB || ctl->switched) return;
-  const int m_done = ctl->m_done;
-  const bool init = (m_done == 0);
-  if (!init && !(ctl->pending && ctl->pend_acwb)) return;
+  const Ctl* ctl = F.ctl;
+  if (!valcheck_due(F, ctl)) return;
+  const bool init = ctl->m_done == 0;
   const int kk = ctl->k;
   const int nb = F.nb_max;
   const float nu = (float)F.nu;
@@ -569,29 +689,29 @@ k_valrisk(const FitDev* __restrict__ fits, const StateItem* __restrict__ items) 
   }
   const double s = block_sum<kStateThreads>(acc, s_red);
   if (threadIdx.x == 0) F.val_part[it.blk] = s;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&ctl->val_done, 1u);
-    s_last = (prev == (unsigned)F.n_val_blocks - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// Patience counter of Algorithm 3: count consecutive rises of the validation
+// risk; switch to CWB on all rows once it reaches pat_0.
+__global__ void __launch_bounds__(kSelectThreads) k_valdecide(const FitDev* __restrict__ fits) {
+  __shared__ double s_red[kSelectThreads + 16];
+  const FitDev& F = fits[blockIdx.x];
+  Ctl* ctl = F.ctl;
+  if (!valcheck_due(F, ctl)) return;
+  const bool init = ctl->m_done == 0;
   double t = 0.0;
-  for (int b = threadIdx.x; b < F.n_val_blocks; b += kStateThreads) t += F.val_part[b];
-  const double tot = block_sum<kStateThreads>(t, s_red);
+  for (int b = threadIdx.x; b < F.n_val_blocks; b += kSelectThreads) t += F.val_part[b];
+  const double tot = block_sum<kSelectThreads>(t, s_red);
   if (threadIdx.x == 0) {
     const double R = tot / (double)(F.n - F.n_train);
     if (!init) {
       if (R > ctl->rval_prev) ctl->counter += 1; else ctl->counter = 0;
       if (ctl->counter >= F.patience) {
         ctl->switched = 1;
-        ctl->switch_iter = m_done + 1;
+        ctl->switch_iter = ctl->m_done + 1;
       }
     }
     ctl->rval_prev = R;
-    ctl->val_done = 0u;
   }
 }
 
@@ -599,7 +719,7 @@ k_valrisk(const FitDev* __restrict__ fits, const StateItem* __restrict__ items) 
 // Finalize: after a final-mode row pass, record the risk of f^[m_done].
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kSelectThreads) k_finalize(const FitDev* __restrict__ fits) {
-  __shared__ double s_red[kSelectThreads / 64];
+  __shared__ double s_red[kSelectThreads + 16];
   const FitDev& F = fits[blockIdx.x];
   Ctl* ctl = F.ctl;
   const int m = ctl->m_done;
@@ -622,8 +742,10 @@ hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* f
                          const int64_t* blk, long long* partials) {
   static bool attr = false;
   if (!attr) {
+    // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
+    (void)hipGetLastError();
     attr = true;
   }
   hipLaunchKernelGGL((k_hist<NT, FMAX>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk, partials);
@@ -659,18 +781,37 @@ hipError_t launch_hist(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
   switch (nt) {
     case 256: return launch_hist_nt<256>(st, fmax, blocks, lds, fits, segs, blk, partials);
     case 512: return launch_hist_nt<512>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 1024: return launch_hist_nt<1024>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 1024:  // groups wider than 4 learners spill registers at 1024 threads
+      if (fmax > 4) return hipErrorInvalidValue;
+      return launch_hist_nt<1024>(st, fmax, blocks, lds, fits, segs, blk, partials);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_select(hipStream_t st, const FitDev* fits, const SelItem* items, int nitems,
-                         int nb_max, const int64_t* grp_ptr, const int64_t* grp_seg,
-                         const Seg* segs, const long long* partials) {
+                         int nb_max, int d_max, const int64_t* sel_off, const long long* partials) {
   if (nitems <= 0) return hipSuccess;
-  const size_t lds = (size_t)nb_max * sizeof(double);
-  hipLaunchKernelGGL(k_select, dim3(nitems), dim3(kSelectThreads), lds, st, fits, items, grp_ptr,
-                     grp_seg, segs, partials);
+  // static LDS of the kernel (incl. the selection step) stays below 16 KiB
+  size_t lds = ((size_t)nb_max + 2 * (size_t)d_max * d_max) * sizeof(double);
+  const size_t extra = (size_t)nb_max * kMaxBand * sizeof(double) + (size_t)nb_max * sizeof(int);
+  const bool staged = nb_max <= kStageBins && lds + extra <= 144 * 1024;
+  if (staged) lds += extra;
+  static bool attr = false;
+  if (!attr) {
+    // 160 KiB per workgroup minus the kernel's own static LDS (< 16 KiB)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  if (staged)
+    hipLaunchKernelGGL(k_select<true>, dim3(nitems), dim3(kSelectThreads), lds, st, fits, items,
+                       sel_off, partials, nb_max, d_max);
+  else
+    hipLaunchKernelGGL(k_select<false>, dim3(nitems), dim3(kSelectThreads), lds, st, fits, items,
+                       sel_off, partials, nb_max, d_max);
   return hipGetLastError();
 }
 
@@ -679,6 +820,18 @@ hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* i
   if (nitems <= 0) return hipSuccess;
   const size_t lds = (size_t)nb_max * sizeof(float);
   hipLaunchKernelGGL(k_valrisk, dim3(nitems), dim3(kStateThreads), lds, st, fits, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_pick(hipStream_t st, const FitDev* fits, int nfits) {
+  if (nfits <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pick, dim3(nfits), dim3(kSelectThreads), 0, st, fits);
+  return hipGetLastError();
+}
+
+hipError_t launch_valdecide(hipStream_t st, const FitDev* fits, int nfits) {
+  if (nfits <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_valdecide, dim3(nfits), dim3(kSelectThreads), 0, st, fits);
   return hipGetLastError();
 }
 

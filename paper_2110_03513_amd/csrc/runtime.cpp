@@ -86,29 +86,32 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
     sh->sum_nb += nb;
     sh->sum_d2 += (int64_t)d * d;
   }
+  sh->nb_stride = (sh->nb_max + 3) / 4 * 4;
   sh->n_row_blocks = (int)((sh->n_pad + kStateRows - 1) / kStateRows);
   const int64_t nv = sh->n - sh->n_train;
   sh->n_val_blocks = (sh->variant == CWB_HCWB && nv > 0) ? (int)((nv + kStateRows - 1) / kStateRows) : 0;
   return CWB_OK;
 }
 
-Tune make_tune(int nb_max, int nsig_max, int p_max) {
+Tune make_tune(int nb_stride, int nsig_max, int p_max) {
   Tune t;
   int dev = 0;
   (void)hipGetDevice(&dev);
   t.cus = device_cus(dev);
-  t.nt = env_int("CWB_HIST_NT", 512);
+  t.nt = env_int("CWB_HIST_NT", 1024);
   if (t.nt != 256 && t.nt != 512 && t.nt != 1024) t.nt = 512;
-  t.lds_kb = std::max(8, std::min(160, env_int("CWB_HIST_LDS_KB", 64)));
+  t.lds_kb = std::max(8, std::min(152, env_int("CWB_HIST_LDS_KB", 32)));
   t.blocks_per_cu = std::max(1, std::min(8, env_int("CWB_HIST_BPC", 1)));
   t.slices = std::max(1, std::min(64, env_int("CWB_HIST_SLICES", 1)));
-  const size_t per_learner = (size_t)nsig_max * nb_max * sizeof(long long);
+  t.blocks = std::max(0, std::min(65536, env_int("CWB_HIST_BLOCKS", 0)));
+  const size_t per_learner = (size_t)nsig_max * nb_stride * sizeof(long long);
   int F = (int)((size_t)t.lds_kb * 1024 / per_learner);
   const int fenv = env_int("CWB_HIST_F", 0);
   if (fenv > 0) F = fenv;
   F = std::max(1, std::min(16, F));
   F = std::min(F, std::max(1, p_max));
-  while (F > 1 && (size_t)F * per_learner > 160 * 1024) --F;
+  while (F > 1 && (size_t)F * per_learner > (size_t)kHistMaxLds) --F;
+  if (t.nt == 1024) F = std::min(F, 4);  // wider groups spill registers at 1024 threads
   t.F = F;
   t.fmax = 1;
   while (t.fmax < F) t.fmax *= 2;
@@ -138,7 +141,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       }
     }
   }
-  const int B = std::max(1, t.cus * t.blocks_per_cu);
+  const int B = t.blocks > 0 ? t.blocks : std::max(1, t.cus * t.blocks_per_cu);
   S.blocks = B;
   std::vector<int64_t> seg_vb;
   int64_t vb = 0, wpos = 0;
@@ -174,7 +177,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   for (Seg& sg : S.segs) {
     sg.slot = off;
     const FitShape& sh = *fits[sg.fit];
-    off += (int64_t)sh.nsig_max * sg.nf * sh.nb_max;
+    off += (int64_t)sh.nsig_max * sg.nf * sh.nb_stride;
   }
   S.partial_words = off;
   // virtual block ranges, then XCD-aware physical mapping: consecutive
@@ -214,12 +217,28 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
     S.grp_ptr[g + 1] = S.grp_ptr[g] + (int64_t)lists[g].size();
     for (int64_t v : lists[g]) S.grp_seg.push_back(v);
   }
-  int ns_max = 1, nb_max = 1;
+  // per learner: word offsets of its histogram in every segment slot of its
+  // group, for each signal the fit can have
+  for (size_t fi = 0; fi < fits.size(); ++fi) {
+    const FitShape& sh = *fits[fi];
+    for (int k = 0; k < sh.p; ++k) {
+      const int64_t g = S.grp_base[fi] + k / t.F;
+      const int64_t n = S.grp_ptr[g + 1] - S.grp_ptr[g];
+      S.sel_begin.push_back((int64_t)S.sel_off.size());
+      S.sel_n.push_back((int32_t)n);
+      for (int sig = 0; sig < sh.nsig_max; ++sig)
+        for (int64_t q = S.grp_ptr[g]; q < S.grp_ptr[g + 1]; ++q) {
+          const Seg& sg = S.segs[S.grp_seg[q]];
+          S.sel_off.push_back(sg.slot + (int64_t)(sig * sg.nf + (k - sg.k0)) * sh.nb_stride);
+        }
+    }
+  }
+  int ns_max = 1, nbs_max = 4;
   for (const FitShape* f : fits) {
     ns_max = std::max(ns_max, f->nsig_max);
-    nb_max = std::max(nb_max, f->nb_max);
+    nbs_max = std::max(nbs_max, f->nb_stride);
   }
-  S.lds = (size_t)ns_max * t.F * nb_max * sizeof(long long);
+  S.lds = (size_t)ns_max * t.F * nbs_max * sizeof(long long);
   return S;
 }
 
@@ -247,11 +266,13 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
         sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
     if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
     if (sg.slot != slot_end) { *why = "slot order"; return false; }
-    slot_end += (int64_t)sh.nsig_max * sg.nf * sh.nb_max;
-    if ((size_t)sh.nsig_max * sg.nf * sh.nb_max * sizeof(long long) > S.lds) { *why = "LDS size"; return false; }
+    slot_end += (int64_t)sh.nsig_max * sg.nf * sh.nb_stride;
+    if ((size_t)sh.nsig_max * sg.nf * sh.nb_stride * sizeof(long long) > S.lds) { *why = "LDS size"; return false; }
   }
   if (slot_end != S.partial_words) { *why = "partial size"; return false; }
-  if (S.lds > 160 * 1024) { *why = "LDS above 160 KiB"; return false; }
+  for (int64_t o : S.sel_off)
+    if (o < 0 || o % 4 != 0 || o + 4 > S.partial_words) { *why = "learner offset"; return false; }
+  if (S.lds > (size_t)kHistMaxLds) { *why = "histogram LDS above its limit"; return false; }
   const int64_t ng = (int64_t)S.grp_ptr.size() - 1;
   for (size_t fi = 0; fi < fits.size(); ++fi) {
     const int groups = (fits[fi]->p + t.F - 1) / t.F;
@@ -319,13 +340,13 @@ Layout make_layout(const FitShape& sh, const Schedule& s) {
     L.gram[set] = take((size_t)sh.sum_d2 * 8);
   }
   L.riskpart = take((size_t)sh.n_row_blocks * 2 * 8);
+  L.amaxpart = take((size_t)sh.n_row_blocks * 2 * 4);
   L.valpart = take((size_t)std::max(1, sh.n_val_blocks) * 8);
   L.fitdev = take(sizeof(FitDev));
   // solo schedule
   L.segs = take(s.segs.size() * sizeof(Seg));
   L.blk = take(s.blk.size() * 8);
-  L.grp_ptr = take(s.grp_ptr.size() * 8);
-  L.grp_seg = take(s.grp_seg.size() * 8);
+  L.sel_off = take(s.sel_off.size() * 8);
   L.partials = take((size_t)s.partial_words * 8);
   L.st_items = take((size_t)sh.n_row_blocks * sizeof(StateItem));
   L.sel_items = take((size_t)sh.p * sizeof(SelItem));
@@ -374,11 +395,11 @@ void timer_free(KernelTimer& t) {
 }
 
 // One iteration for a set of fits sharing a schedule.
-int enqueue_iteration(hipStream_t st, const FitDev* d_fits, const Schedule& S, const Tune& t,
+int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Schedule& S, const Tune& t,
                       const StateItem* d_st, int n_st, const SelItem* d_sel, int n_sel,
-                      const StateItem* d_val, int n_val, int nb_max, const Seg* d_segs,
-                      const int64_t* d_blk, const int64_t* d_gp, const int64_t* d_gs,
-                      long long* d_part, cwb_fit* timed) {
+                      const StateItem* d_val, int n_val, int nb_max, int d_max, const Seg* d_segs,
+                      const int64_t* d_blk, const int64_t* d_off, long long* d_part,
+                      cwb_fit* timed) {
   const int tm = timed ? timed->timing : 0;
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
@@ -387,9 +408,13 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, const Schedule& S, c
   HIP_TRY(launch_hist(st, t.nt, t.fmax, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
-  HIP_TRY(launch_select(st, d_fits, d_sel, n_sel, nb_max, d_gp, d_gs, d_segs, d_part));
+  HIP_TRY(launch_select(st, d_fits, d_sel, n_sel, nb_max, d_max, d_off, d_part));
+  HIP_TRY(launch_pick(st, d_fits, nfits));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
-  if (n_val > 0) HIP_TRY(launch_valrisk(st, d_fits, d_val, n_val, nb_max));
+  if (n_val > 0) {
+    HIP_TRY(launch_valrisk(st, d_fits, d_val, n_val, nb_max));
+    HIP_TRY(launch_valdecide(st, d_fits, nfits));
+  }
   return CWB_OK;
 }
 
@@ -399,6 +424,22 @@ T* dptr(char* ws, size_t off) {
 }
 
 }  // namespace
+
+SelItem make_sel_item(int fit, int k, const FeatDev& fd, const Schedule& S, size_t idx) {
+  SelItem it;
+  it.fit = fit;
+  it.k = k;
+  it.nb = fd.nb;
+  it.band = fd.band;
+  it.d = fd.d;
+  it.coef_off = fd.coef_off;
+  it.bin_off = fd.bin_off;
+  it.mat_off = fd.mat_off;
+  it.off_begin = S.sel_begin[idx];
+  it.n_off = S.sel_n[idx];
+  it.pad = 0;
+  return it;
+}
 
 int finalize_fit(cwb_fit* f) {
   HIP_TRY(hipSetDevice(f->device));
@@ -439,7 +480,7 @@ int cwb_workspace_bytes(const cwb_problem* pr, size_t* bytes) {
     FitShape sh;
     int rc = shape_from_problem(pr, &sh, &err);
     if (rc) return set_error(rc, err);
-    Tune t = make_tune(sh.nb_max, sh.nsig_max, sh.p);
+    Tune t = make_tune(sh.nb_stride, sh.nsig_max, sh.p);
     Schedule s = build_schedule({&sh}, t);
     std::string why;
     if (!schedule_is_valid(s, {&sh}, t, &why)) return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
@@ -469,7 +510,7 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   std::unique_ptr<cwb_fit> f(new cwb_fit());
   f->stream = reinterpret_cast<hipStream_t>(stream);
   f->shape = sh;
-  f->tune = make_tune(sh.nb_max, sh.nsig_max, sh.p);
+  f->tune = make_tune(sh.nb_stride, sh.nsig_max, sh.p);
   f->sched = build_schedule({&f->shape}, f->tune);
   {
     std::string why;
@@ -542,6 +583,7 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   D.n_row_blocks = sh.n_row_blocks;
   D.n_val_blocks = sh.n_val_blocks;
   D.nsig_max = sh.nsig_max;
+  D.nb_stride = sh.nb_stride;
   D.X = dptr<uint16_t>(ws, L.X);
   D.y = dptr<float>(ws, L.y);
   D.fg = dptr<float>(ws, L.fg);
@@ -569,6 +611,7 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   D.coef_f = dptr<double>(ws, L.coef_f);
   D.coef_h = dptr<double>(ws, L.coef_h);
   D.risk_part = dptr<double>(ws, L.riskpart);
+  D.amax_part = dptr<float>(ws, L.amaxpart);
   D.val_part = dptr<double>(ws, L.valpart);
   D.ctl = dptr<Ctl>(ws, L.ctl);
   f->d_fit = dptr<FitDev>(ws, L.fitdev);
@@ -595,6 +638,7 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
   HIP_TRY(hipMemcpyAsync(ws + L.feat, feat.data(), feat.size() * sizeof(FeatDev), hipMemcpyHostToDevice, st));
+  f->feat = feat;
   HIP_TRY(hipMemcpyAsync(ws + L.bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.bval, bval.data(), bval.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.jr, jr.data(), jr.size() * 4, hipMemcpyHostToDevice, st));
@@ -608,12 +652,11 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   const Schedule& S = f->sched;
   HIP_TRY(hipMemcpyAsync(ws + L.segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws + L.grp_ptr, S.grp_ptr.data(), S.grp_ptr.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws + L.grp_seg, S.grp_seg.data(), S.grp_seg.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, st));
   std::vector<StateItem> st_items(sh.n_row_blocks);
   for (int b = 0; b < sh.n_row_blocks; ++b) st_items[b] = {0, b};
   std::vector<SelItem> sel_items(sh.p);
-  for (int k = 0; k < sh.p; ++k) sel_items[k] = {0, k, S.grp_base[0] + k / f->tune.F};
+  for (int k = 0; k < sh.p; ++k) sel_items[k] = make_sel_item(0, k, feat[k], S, k);
   std::vector<StateItem> val_items(std::max(1, sh.n_val_blocks));
   for (int b = 0; b < sh.n_val_blocks; ++b) val_items[b] = {0, b};
   f->n_st = sh.n_row_blocks;
@@ -623,8 +666,10 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   HIP_TRY(hipMemcpyAsync(ws + L.sel_items, sel_items.data(), sel_items.size() * sizeof(SelItem), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.val_items, val_items.data(), val_items.size() * sizeof(StateItem), hipMemcpyHostToDevice, st));
   // HCWB: validation risk of f^[0]
-  if (f->n_val > 0 && !ctl.switched)
+  if (f->n_val > 0 && !ctl.switched) {
     HIP_TRY(launch_valrisk(st, f->d_fit, dptr<StateItem>(ws, L.val_items), f->n_val, sh.nb_max));
+    HIP_TRY(launch_valdecide(st, f->d_fit, 1));
+  }
   HIP_TRY(hipStreamSynchronize(st));
   *out = f.release();
   return CWB_OK;
@@ -651,12 +696,12 @@ int cwb_fit_run(cwb_fit* f, int32_t iters) {
   const Layout& L = f->lay;
   char* ws = f->ws;
   for (int i = 0; i < iters; ++i) {
-    int rc = enqueue_iteration(f->stream, f->d_fit, f->sched, f->tune, dptr<StateItem>(ws, L.st_items),
+    int rc = enqueue_iteration(f->stream, f->d_fit, 1, f->sched, f->tune, dptr<StateItem>(ws, L.st_items),
                                f->n_st, dptr<SelItem>(ws, L.sel_items), f->n_sel,
                                dptr<StateItem>(ws, L.val_items), f->n_val, f->shape.nb_max,
+                               f->shape.d_max,
                                dptr<Seg>(ws, L.segs), dptr<int64_t>(ws, L.blk),
-                               dptr<int64_t>(ws, L.grp_ptr), dptr<int64_t>(ws, L.grp_seg),
-                               dptr<long long>(ws, L.partials), f);
+                               dptr<int64_t>(ws, L.sel_off), dptr<long long>(ws, L.partials), f);
     if (rc) return rc;
   }
   f->iters += iters;
@@ -824,7 +869,7 @@ void cwb_fit_destroy(cwb_fit* f) {
 namespace {
 
 struct BatchLayout {
-  size_t fits, segs, blk, grp_ptr, grp_seg, partials, st, sel, val, total;
+  size_t fits, segs, blk, sel_off, partials, st, sel, val, total;
 };
 
 BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int n_val) {
@@ -839,8 +884,7 @@ BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int 
   L.fits = take((size_t)count * sizeof(FitDev));
   L.segs = take(S.segs.size() * sizeof(Seg));
   L.blk = take(S.blk.size() * 8);
-  L.grp_ptr = take(S.grp_ptr.size() * 8);
-  L.grp_seg = take(S.grp_seg.size() * 8);
+  L.sel_off = take(S.sel_off.size() * 8);
   L.partials = take((size_t)S.partial_words * 8);
   L.st = take((size_t)std::max(1, n_st) * sizeof(StateItem));
   L.sel = take((size_t)std::max(1, n_sel) * sizeof(SelItem));
@@ -860,7 +904,7 @@ int batch_plan(cwb_fit* const* fits, int32_t count, Tune* t, Schedule* S, int* n
     for (int j = 0; j < i; ++j)
       if (fits[j] == fits[i]) return set_error(CWB_E_INVALID_ARG, "fit listed twice in batch");
     shapes.push_back(&fits[i]->shape);
-    nb = std::max(nb, fits[i]->shape.nb_max);
+    nb = std::max(nb, fits[i]->shape.nb_stride);
     ns = std::max(ns, fits[i]->shape.nsig_max);
     pmax = std::max(pmax, fits[i]->shape.p);
     *n_st += fits[i]->shape.n_row_blocks;
@@ -919,10 +963,11 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
     for (int i = 0; i < count; ++i) {
       fd[i] = fits[i]->dev;
       b->nb_max = std::max(b->nb_max, fits[i]->shape.nb_max);
+      b->d_max = std::max(b->d_max, fits[i]->shape.d_max);
       if (fits[i]->shape.variant == CWB_HCWB) b->any_hcwb = true;
       for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back({i, r});
       for (int k = 0; k < fits[i]->shape.p; ++k)
-        sel.push_back({i, k, b->sched.grp_base[i] + k / b->tune.F});
+        sel.push_back(make_sel_item(i, k, fits[i]->feat[k], b->sched, sel.size()));
       for (int r = 0; r < fits[i]->shape.n_val_blocks; ++r) val.push_back({i, r});
     }
     char* ws = b->ws;
@@ -930,8 +975,7 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
     b->d_fits = dptr<FitDev>(ws, L.fits);
     b->d_segs = dptr<Seg>(ws, L.segs);
     b->d_blk = dptr<int64_t>(ws, L.blk);
-    b->d_grp_ptr = dptr<int64_t>(ws, L.grp_ptr);
-    b->d_grp_seg = dptr<int64_t>(ws, L.grp_seg);
+    b->d_sel_off = dptr<int64_t>(ws, L.sel_off);
     b->d_partials = dptr<long long>(ws, L.partials);
     b->d_st = dptr<StateItem>(ws, L.st);
     b->d_sel = dptr<SelItem>(ws, L.sel);
@@ -940,8 +984,7 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
     HIP_TRY(hipMemcpyAsync(b->d_fits, fd.data(), fd.size() * sizeof(FitDev), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b->d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b->d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->d_grp_ptr, S.grp_ptr.data(), S.grp_ptr.size() * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->d_grp_seg, S.grp_seg.data(), S.grp_seg.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, s));
     if (!st.empty()) HIP_TRY(hipMemcpyAsync(b->d_st, st.data(), st.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
     if (!sel.empty()) HIP_TRY(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, s));
     if (!val.empty()) HIP_TRY(hipMemcpyAsync(b->d_val, val.data(), val.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
@@ -960,9 +1003,10 @@ int cwb_batch_run(cwb_batch* b, int32_t iters) {
   int most = 0;
   for (cwb_fit* f : b->fits) most = std::max(most, std::min(iters, f->shape.M - f->iters));
   for (int i = 0; i < most; ++i) {
-    int rc = enqueue_iteration(b->stream, b->d_fits, b->sched, b->tune, b->d_st, b->n_st, b->d_sel,
-                               b->n_sel, b->d_val, b->any_hcwb ? b->n_val : 0, b->nb_max, b->d_segs,
-                               b->d_blk, b->d_grp_ptr, b->d_grp_seg, b->d_partials, nullptr);
+    int rc = enqueue_iteration(b->stream, b->d_fits, (int)b->fits.size(), b->sched, b->tune, b->d_st, b->n_st, b->d_sel,
+                               b->n_sel, b->d_val, b->any_hcwb ? b->n_val : 0, b->nb_max,
+                               b->d_max, b->d_segs,
+                               b->d_blk, b->d_sel_off, b->d_partials, nullptr);
     if (rc) return rc;
   }
   for (cwb_fit* f : b->fits) f->iters += std::min(most, f->shape.M - f->iters);

@@ -17,6 +17,7 @@ struct FitShape {
   int64_t n = 0, n_pad = 0, n_train = 0;
   int p = 0, M = 0, variant = 0, nsig_max = 1;
   int nb_max = 0, d_max = 0, sum_d = 0;
+  int nb_stride = 0;  // nb_max rounded up to a multiple of 4
   int64_t sum_nb = 0, sum_d2 = 0;
   int n_row_blocks = 0, n_val_blocks = 0;
 };
@@ -31,6 +32,7 @@ struct Tune {
   int fmax = 0;
   int blocks_per_cu = 1;
   int slices = 1;
+  int blocks = 0;  // total histogram blocks; 0 = cus * blocks_per_cu
   int cus = 256;
   int lds_kb = 64;
 };
@@ -43,6 +45,9 @@ struct Schedule {
   std::vector<int64_t> grp_ptr;  // per (fit, group): range in grp_seg (+1 sentinel)
   std::vector<int64_t> grp_seg;  // segment indices, grouped
   std::vector<int64_t> grp_base; // per fit: first group index
+  std::vector<int64_t> sel_off;  // per learner and signal: word offsets of its histograms
+  std::vector<int64_t> sel_begin;// per (fit, learner): start in sel_off (fit-major)
+  std::vector<int32_t> sel_n;    // per (fit, learner): segments of its group
   int64_t partial_words = 0;
   int blocks = 0;
   size_t lds = 0;
@@ -55,8 +60,8 @@ struct Layout {
   size_t ctl, fg, h, c, q, theta, table, trk, trth, trkc, trthc, trrisk, trval, trgap, coef_f,
       coef_h;
   size_t state_begin, state_end;  // mutable state region (checkpoint)
-  size_t X, y, r, feat, bstart, bval, jr, ainv[2], gram[2], riskpart, valpart, fitdev;
-  size_t segs, blk, grp_ptr, grp_seg, partials, st_items, sel_items, val_items;
+  size_t X, y, r, feat, bstart, bval, jr, ainv[2], gram[2], riskpart, amaxpart, valpart, fitdev;
+  size_t segs, blk, sel_off, partials, st_items, sel_items, val_items;
   size_t total;
 };
 
@@ -83,6 +88,7 @@ struct cwb_fit {
   double f0 = 0.0;
   std::vector<int64_t> perm;
   std::vector<int32_t> d;      // basis size per learner
+  std::vector<cwb::FeatDev> feat;  // host copy of the learner table
   cwb::FitDev dev;             // host copy (device pointers)
   cwb::FitDev* d_fit = nullptr;
   int iters = 0;
@@ -100,12 +106,12 @@ struct cwb_batch {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int nb_max = 0;
+  int d_max = 0;
   bool any_hcwb = false;
   cwb::FitDev* d_fits = nullptr;
   cwb::Seg* d_segs = nullptr;
   int64_t* d_blk = nullptr;
-  int64_t* d_grp_ptr = nullptr;
-  int64_t* d_grp_seg = nullptr;
+  int64_t* d_sel_off = nullptr;
   long long* d_partials = nullptr;
   cwb::StateItem* d_st = nullptr;
   cwb::SelItem* d_sel = nullptr;
@@ -117,4 +123,5 @@ namespace cwb {
 int set_error(int code, const std::string& msg);
 // Enqueue one finalize (apply pending updates, record the current risk).
 int finalize_fit(cwb_fit* f);
+SelItem make_sel_item(int fit, int k, const FeatDev& fd, const Schedule& S, size_t idx);
 }  // namespace cwb

@@ -195,3 +195,20 @@ def test_full_size_config2_first_iterations():
     gpu["f"] = f.pred()
     f.close()
     compare(gpu, dict(prob, M=M))
+
+
+@pytest.mark.parametrize("nt,F,blocks,variant", [
+    (512, 16, 8, "cwb"), (512, 7, 13, "acwb"), (256, 3, 5, "cwb"), (1024, 4, 9, "acwb"),
+    (512, 5, 3, "hcwb"), (256, 1, 16, "cwb"), (512, 2, 7, "acwb")])
+def test_histogram_tilings_many_steps(nt, F, blocks, variant, monkeypatch):
+    """Few histogram blocks, so every thread loops over many row steps, and
+    group widths that do not divide the prefetch window or p."""
+    monkeypatch.setenv("CWB_HIST_NT", str(nt))
+    monkeypatch.setenv("CWB_HIST_F", str(F))
+    monkeypatch.setenv("CWB_HIST_BLOCKS", str(blocks))
+    prob = datagen.additive_problem(70_001, 19, seed=7 + F, n_informative=5,
+                                    loss="binomial" if variant == "acwb" else "l2", n_bins=257,
+                                    M=30, variant=variant, gamma=0.05, patience=3, n_cat=3,
+                                    n_informative_cat=1)
+    gpu = _run(prob)
+    compare(gpu, prob)
