@@ -114,14 +114,42 @@ struct StateItem {   // one row-pass block
   int32_t blk;       // block index within the fit
 };
 
-struct SelItem {     // one learner's solve, with everything it needs up front
-  int32_t fit;
-  int32_t k;
-  int32_t nb, band, d, coef_off;
-  int64_t bin_off, mat_off;
-  int64_t off_begin; // its partial offsets: off[off_begin + sig * n_off + i]
-  int32_t n_off;     // segments of its group
-  int32_t pad;
+// A row-pass block with every pointer and size it needs.
+struct RowItem {
+  Ctl* ctl;
+  const uint16_t* X;
+  const float* y;
+  float* fg;
+  float* h;
+  float* c;
+  float* r;
+  const float* table;   // candidate tables [kNumSig][p][nb_max]
+  double* risk_part;    // &risk_part[2 * blk]
+  float* amax_part;     // &amax_part[2 * blk]
+  int64_t n, n_pad, n_train, base;  // base: first row of the block
+  double nu;
+  int32_t p, nb_max, loss, variant;
+  int32_t M, two, blk, fit;          // two: the fit keeps h and c
+};
+
+// One learner's solve, with every pointer and size it needs, so that a block
+// issues all of its independent loads in one round.
+struct SelItem {
+  Ctl* ctl;
+  const float* amax_part;     // the fit's per-block signal maxima
+  const double* ainv[2];      // this learner's (G + lambda D)^-1, both row sets
+  const double* gram[2];      // this learner's G, both row sets
+  const double* bval;         // this learner's banded reduced design
+  const int32_t* bstart;
+  const int32_t* jr;
+  const int64_t* offs;        // its histogram offsets: offs[sig * n_off + i]
+  double* q;                  // &q[k] (signal 1 at + p)
+  double* theta;              // &theta[k * d_max] (signal 1 at + p * d_max)
+  float* table;               // &table[k * nb_max] (signal 1 at + p * nb_max)
+  int64_t n, n_train;
+  int32_t k, nb, band, d;
+  int32_t n_off, d_max, nb_max, p;
+  int32_t M, variant, n_row_blocks, fit;
 };
 
 // Fixed-point exponent for the int64 histogram of a signal whose largest

@@ -126,11 +126,42 @@ template <int NT>
 __device__ int fit_scale_exponent(const FitDev& F, int sig, int64_t n_fit, float* red) {
   float a = 0.0f;
   const GLOBAL float* am = gp(F.amax_part);
-  for (int b = threadIdx.x; b < F.n_row_blocks; b += NT) a = fmaxf(a, am[2 * b + sig]);
+  for (int b0 = 0; b0 < F.n_row_blocks; b0 += 4 * NT) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * NT + (int)threadIdx.x;
+      v[u] = (b < F.n_row_blocks) ? am[2 * b + sig] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a = fmaxf(a, v[u]);
+  }
   return scale_exponent(block_max<NT>(a, red), n_fit);
 }
 
+// Copy `count` elements from global memory to LDS with all of a thread's
+// loads (up to U per pass) issued before its stores, so a block pays one
+// memory round trip per pass instead of one per element it copies.
+template <int NT, int U, typename T>
+__device__ __forceinline__ void stage(T* dst, const T* src, int count) {
+  const GLOBAL T* g = gp(src);
+  for (int i0 = 0; i0 < count; i0 += NT * U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT + (int)threadIdx.x;
+      if (i < count) v[u] = g[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT + (int)threadIdx.x;
+      if (i < count) dst[i] = v[u];
+    }
+  }
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef long long i64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void load8f(const float* p, float* v) {
@@ -163,67 +194,70 @@ __device__ __forceinline__ void load8u(const uint16_t* p, uint32_t* idx) {
 // Row pass.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kStateThreads)
-k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, int final_mode) {
+k_state(const RowItem* __restrict__ items, int final_mode) {
   extern __shared__ float s_tab[];  // [2][nb_max]
   __shared__ double s_red[kStateThreads + 16];
   __shared__ float s_fred[kStateThreads + 16];
   __shared__ int s_bad;
-  const StateItem it = items[blockIdx.x];
-  const FitDev& F = fits[it.fit];
-  Ctl* ctl = F.ctl;
+  const RowItem it = items[blockIdx.x];
+  // one round: the control block and this thread's rows of the model state
+  const Ctl* ctl = it.ctl;
   const int m_done = ctl->m_done;
-  if (!final_mode && m_done >= F.M) return;
   const int pending = ctl->pending;
   const int pend_acwb = ctl->pend_acwb;
   const int kk = ctl->k;
   const int kc = ctl->kcor;
   const int switched = ctl->switched;
   const float eta = (float)ctl->eta;
-  const float nu = (float)F.nu;
+  const int64_t base = it.base + (int64_t)threadIdx.x * kRowsPerThread;
+  const bool rows = base < it.n_pad;
+  const bool two = it.two != 0;
+  float f[8], yv[8], hv[8], cv[8], rr[8], cc[8];
+  if (rows) {
+    load8f(it.fg + base, f);
+    load8f(it.y + base, yv);
+    if (two) {
+      load8f(it.h + base, hv);
+      load8f(it.c + base, cv);
+    }
+  }
+  if (!final_mode && m_done >= it.M) return;
+  const float nu = (float)it.nu;
   const int m = m_done + 1;
-  const bool acwb = !final_mode && is_acwb_step(F, switched);
-  const int64_t n_fit = rows_fitted(F, switched);
-  const int nb = F.nb_max;
+  const bool acwb =
+      !final_mode && (it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched));
+  const int64_t n_fit = (it.variant == CWB_HCWB && switched) ? it.n : it.n_train;
+  const int nb = it.nb_max;
   float* tf = s_tab;
   float* tc = s_tab + nb;
   const bool use_t = pending != 0;
   const bool use_h = pending && pend_acwb && kc >= 0;
   const bool use_cc = acwb && m > 1 && kc >= 0;
-  if (use_t)
-    for (int l = threadIdx.x; l < nb; l += kStateThreads) tf[l] = gp(F.table)[((size_t)kk) * nb + l];
-  if (use_h || use_cc)
-    for (int l = threadIdx.x; l < nb; l += kStateThreads)
-      tc[l] = gp(F.table)[((size_t)F.p + kc) * nb + l];
+  uint32_t ik[8], ic[8];
+  if (rows && use_t) load8u(it.X + (size_t)kk * it.n_pad + base, ik);
+  if (rows && (use_h || use_cc)) load8u(it.X + (size_t)kc * it.n_pad + base, ic);
+  if (use_t) stage<kStateThreads, 4>(tf, it.table + (size_t)kk * nb, nb);
+  if (use_h || use_cc) stage<kStateThreads, 4>(tc, it.table + ((size_t)it.p + kc) * nb, nb);
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
 
   double risk_t = 0.0, risk_v = 0.0;
   float amax_r = 0.0f, amax_c = 0.0f;
   bool bad = false;
-  const int64_t base = (int64_t)it.blk * kStateRows + (int64_t)threadIdx.x * kRowsPerThread;
-  if (base < F.n_pad) {
-    const bool two = F.nsig_max == 2;
-    float f[8], yv[8], hv[8], cv[8], rr[8], cc[8];
-    uint32_t ik[8], ic[8];
-    load8f(F.fg + base, f);
-    load8f(F.y + base, yv);
-    if (two) load8f(F.h + base, hv);
-    if (use_cc) load8f(F.c + base, cv);
-    if (use_t) load8u(F.X + (size_t)kk * F.n_pad + base, ik);
-    if (use_h || use_cc) load8u(F.X + (size_t)kc * F.n_pad + base, ic);
+  if (rows) {
     const float vt = 2.0f / (float)(m + 1);
     const float cw = (float)m / (float)(m + 1);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int64_t i = base + j;
-      const bool live = i < F.n;
+      const bool live = i < it.n;
       float fj = f[j];
       float hj = two ? hv[j] : 0.0f;
       if (live && use_t) fj = fj + nu * tf[ik[j]];
       if (live && use_h) hj = hj + eta * tc[ic[j]];
       if (live) {
-        const double L = loss_value(F.loss, yv[j], fj);
-        if (i < F.n_train) risk_t += L; else risk_v += L;
+        const double L = loss_value(it.loss, yv[j], fj);
+        if (i < it.n_train) risk_t += L; else risk_v += L;
         if (!isfinite(fj) || !isfinite(hj)) bad = true;
       }
       f[j] = fj;
@@ -234,7 +268,7 @@ k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, in
       const bool fitrow = i < n_fit;
       if (acwb) {
         const float g = (1.0f - vt) * fj + vt * hj;
-        const float r = neg_gradient(F.loss, yv[j], g);
+        const float r = neg_gradient(it.loss, yv[j], g);
         float c = r;
         if (use_cc) c = r + cw * (cv[j] - tc[ic[j]]);
         f[j] = g;  // the primary model update f = g + nu b_k is pending
@@ -243,17 +277,17 @@ k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, in
           cc[j] = c;
         }
       } else {
-        const float r = neg_gradient(F.loss, yv[j], fj);
+        const float r = neg_gradient(it.loss, yv[j], fj);
         if (fitrow) rr[j] = r;
       }
       amax_r = fmaxf(amax_r, fabsf(rr[j]));
       amax_c = fmaxf(amax_c, fabsf(cc[j]));
     }
-    store8f(F.fg + base, f);
-    if (two) store8f(F.h + base, hv);
+    store8f(it.fg + base, f);
+    if (two) store8f(it.h + base, hv);
     if (!final_mode) {
-      store8f(F.r + base, rr);
-      if (acwb) store8f(F.c + base, cc);
+      store8f(it.r + base, rr);
+      if (acwb) store8f(it.c + base, cc);
     }
   }
   if (bad) s_bad = 1;
@@ -262,20 +296,17 @@ k_state(const FitDev* __restrict__ fits, const StateItem* __restrict__ items, in
   const float a = block_max<kStateThreads>(amax_r, s_fred);
   const float b = block_max<kStateThreads>(amax_c, s_fred);
   if (threadIdx.x == 0) {
-    F.risk_part[2 * it.blk] = st;
-    F.risk_part[2 * it.blk + 1] = sv;
+    it.risk_part[0] = st;
+    it.risk_part[1] = sv;
     if (!final_mode) {
       if (!isfinite(a) || !isfinite(b)) s_bad = 1;
-      F.amax_part[2 * it.blk] = a;
-      F.amax_part[2 * it.blk + 1] = b;
+      it.amax_part[0] = a;
+      it.amax_part[1] = b;
     }
-    if (s_bad) atomicOr(&ctl->error, 1);
+    if (s_bad) atomicOr(&it.ctl->error, 1);
   }
 }
 
-// ---------------------------------------------------------------------------
-// Histogram pass.
-// ---------------------------------------------------------------------------
 template <int NSIG>
 __device__ __forceinline__ void hist_add(unsigned long long* __restrict__ h, const u32x4& x,
                                          const long long* q) {
@@ -293,43 +324,76 @@ __device__ __forceinline__ u32x4 load_idx(const uint16_t* p) {
   return __builtin_nontemporal_load((const GLOBAL u32x4*)p);
 }
 
+// trunc(r * 2^e) as int64, from the bits of the float: r = +-m 2^(x-150)
+// with a 24-bit integer m, so the product is m shifted by x - 150 + e.
+// Equal to casting the exact double product r * 2^e to int64.
+__device__ __forceinline__ long long fixed_point(float r, int e) {
+  const uint32_t u = __float_as_uint(r);
+  const uint32_t ex = (u >> 23) & 0xffu;
+  const uint32_t m = (u & 0x7fffffu) | (ex ? 0x800000u : 0u);
+  const int sh = (ex ? (int)ex : 1) - 150 + e;
+  unsigned long long mag;
+  if (sh >= 0) mag = (unsigned long long)m << sh;  // sh <= 62 - 24 by the choice of e
+  else mag = (sh > -32) ? (unsigned long long)(m >> (-sh)) : 0ull;
+  return (u >> 31) ? -(long long)mag : (long long)mag;
+}
+
+template <int FMAX, int NSIG>
+__device__ __forceinline__ void hist_step_load(const FitDev& F, const uint16_t* __restrict__ Xg,
+                                               size_t ld, int nf, int64_t base, float* rv, float* cv,
+                                               u32x4* xw) {
+  load8f(F.r + base, rv);
+  if (NSIG == 2) load8f(F.c + base, cv);
+#pragma unroll
+  for (int f = 0; f < FMAX; ++f)
+    if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
+}
+
 // Rows [r0, r1) of one segment.  Every thread takes 8 consecutive rows per
 // step: one 32-byte load of residuals per signal and one 16-byte load of bin
-// indices per learner of the group (all issued before any atomic), then 8
-// LDS atomics per learner and signal.
+// indices per learner of the group, then 8 LDS atomics per learner and
+// signal.  The next step's loads are issued before this step's atomics.
 template <int NT, int FMAX, int NSIG>
 __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
                                           unsigned long long* __restrict__ hist, int nb,
-                                          int64_t r0, int64_t r1, double sc0, double sc1) {
+                                          int64_t r0, int64_t r1, int e0, int e1) {
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
   const int nf = sg.nf;
   const size_t ld = (size_t)F.n_pad;
-  for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
-    float rv[8], cv[8];
-    u32x4 xw[FMAX];
-    load8f(F.r + base, rv);
-    if (NSIG == 2) load8f(F.c + base, cv);
-#pragma unroll
-    for (int f = 0; f < FMAX; ++f)
-      if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
+  int64_t base = r0 + (int64_t)threadIdx.x * 8;
+  if (base >= r1) return;
+  float rv[8], cv[8];
+  u32x4 xw[FMAX];
+  hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
+  for (;;) {
+    const int64_t nxt = base + (int64_t)NT * 8;
+    const bool more = nxt < r1;
     long long q0[8], q1[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q0[j] = (long long)((double)rv[j] * sc0);
+    for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e0);
     if (NSIG == 2) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) q1[j] = (long long)((double)cv[j] * sc1);
+      for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e1);
     }
+    u32x4 xc[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
+    if (more) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, nxt, rv, cv, xw);
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) {
       if (f < nf) {
-        hist_add<NSIG>(hist + (size_t)f * nb, xw[f], q0);
-        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb, xw[f], q1);
+        hist_add<NSIG>(hist + (size_t)f * nb, xc[f], q0);
+        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb, xc[f], q1);
       }
     }
+    if (!more) break;
+    base = nxt;
   }
 }
 
-template <int NT, int FMAX>
+// NSMAX: most signals any fit of the launch can have (1 when every fit is
+// plain CWB, so the two-signal path is not compiled in).
+template <int NT, int FMAX, int NSMAX>
 __global__ void __launch_bounds__(NT)
 k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
        const int64_t* __restrict__ blk, long long* __restrict__ partials) {
@@ -337,7 +401,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
   __shared__ float s_red[NT + 16];
   const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
   int cached_fit = -1;
-  double sc0 = 0.0, sc1 = 0.0;
+  int e0 = 0, e1 = 0;
   for (int64_t s = s0; s < s1; ++s) {
     const Seg sg = segs[s];
     const FitDev& F = fits[sg.fit];
@@ -355,14 +419,14 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int64_t r0 = 8 * (sg.u0 * n8 / U);
     const int64_t r1 = 8 * (sg.u1 * n8 / U);
     if (sg.fit != cached_fit) {
-      sc0 = ldexp(1.0, fit_scale_exponent<NT>(F, 0, n_fit, s_red));
-      sc1 = (nsig == 2) ? ldexp(1.0, fit_scale_exponent<NT>(F, 1, n_fit, s_red)) : 0.0;
+      e0 = fit_scale_exponent<NT>(F, 0, n_fit, s_red);
+      e1 = (nsig == 2) ? fit_scale_exponent<NT>(F, 1, n_fit, s_red) : 0;
       cached_fit = sg.fit;
     }
-    if (nsig == 1)
-      hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, sc0, 0.0);
+    if (NSMAX == 1 || nsig == 1)
+      hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
     else
-      hist_rows<NT, FMAX, 2>(F, sg, s_hist, nb, r0, r1, sc0, sc1);
+      hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
     __syncthreads();
     GLOBAL long long* out = gp(partials + sg.slot);
     for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
@@ -428,8 +492,18 @@ __device__ void block_argmin(const double* q, int p, int* k_out, double* gap_out
 // Deterministic sum of risk partials of the row-pass blocks.
 __device__ double sum_partials(const double* part, int count, int stride, int offset,
                                double* red) {
+  const GLOBAL double* g = gp(part);
   double s = 0.0;
-  for (int b = threadIdx.x; b < count; b += kSelectThreads) s += part[(size_t)b * stride + offset];
+  for (int b0 = 0; b0 < count; b0 += 4 * kSelectThreads) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kSelectThreads + (int)threadIdx.x;
+      v[u] = (b < count) ? g[(size_t)b * stride + offset] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u];
+  }
   return block_sum<kSelectThreads>(s, red);
 }
 
@@ -519,14 +593,13 @@ struct Basis {
 
 template <bool STAGED>
 __global__ void __launch_bounds__(kSelectThreads)
-k_select(const FitDev* __restrict__ fits, const SelItem* __restrict__ items,
-         const int64_t* __restrict__ sel_off, const long long* __restrict__ partials, int nb_cap,
+k_select(const SelItem* __restrict__ items, const long long* __restrict__ partials, int nb_cap,
          int d_cap) {
   // dynamic LDS: s[nb_cap] | Ainv[d_cap^2] | G[d_cap^2] | (STAGED) bval[nb_cap*4] | bstart[nb_cap]
   extern __shared__ double s_dyn[];
   __shared__ double s_v[kMaxD], s_th[kMaxD], s_gt[kMaxD];
   __shared__ double s_part[kMaxD * kChunks];
-  __shared__ long long s_off[kMaxSlots];
+  __shared__ long long s_off[kNumSig][kMaxSlots];
   __shared__ int s_jr[2 * kMaxD];
   __shared__ float s_red[kSelectThreads + 16];
   double* s_bins = s_dyn;
@@ -535,54 +608,71 @@ k_select(const FitDev* __restrict__ fits, const SelItem* __restrict__ items,
   double* s_bv = s_g + (size_t)d_cap * d_cap;
   int* s_bs = reinterpret_cast<int*>(s_bv + (size_t)nb_cap * kMaxBand);
   const SelItem it = items[blockIdx.x];
-  const FitDev& F = fits[it.fit];
-  const Ctl* ctl = F.ctl;
-  const int m_done = ctl->m_done;
-  const int switched = ctl->switched;
-  const int d = it.d, nb = it.nb, band = it.band, k = it.k;
-  const double* gbval = F.bval + it.bin_off * kMaxBand;
-  const int32_t* gbs = F.bstart + it.bin_off;
-  if (m_done >= F.M) return;
-  const bool acwb = is_acwb_step(F, switched);
-  const int nsig = acwb ? 2 : 1;
-  const int64_t n_fit = rows_fitted(F, switched);
-  const int set = gram_set(F, switched);
-  // stage the learner's tables: inverse penalised Gram, Gram, support
-  // ranges and (STAGED) the banded reduced design
+  const int d = it.d, nb = it.nb, band = it.band, n_off = it.n_off;
+  // one round of independent loads: control block, signal maxima, offsets,
+  // the learner's tables for the training-row Gram set
+  const int m_done = it.ctl->m_done;
+  const int switched = it.ctl->switched;
+  float am0 = 0.0f, am1 = 0.0f;
   {
-    const GLOBAL double* Ai = gp(F.ainv[set] + it.mat_off);
-    const GLOBAL double* G = gp(F.gram[set] + it.mat_off);
-    for (int i = threadIdx.x; i < d * d; i += kSelectThreads) {
-      s_ai[i] = Ai[i];
-      s_g[i] = G[i];
-    }
-    const GLOBAL int32_t* jr = gp(F.jr + 2 * (size_t)it.coef_off);
-    for (int i = threadIdx.x; i < 2 * d; i += kSelectThreads) s_jr[i] = jr[i];
-    if (STAGED) {
-      const GLOBAL double* bv = gp(gbval);
-      const GLOBAL int32_t* bs = gp(gbs);
-      for (int i = threadIdx.x; i < nb * kMaxBand; i += kSelectThreads) s_bv[i] = bv[i];
-      for (int i = threadIdx.x; i < nb; i += kSelectThreads) s_bs[i] = bs[i];
+    const GLOBAL f32x2* am = (const GLOBAL f32x2*)it.amax_part;
+    for (int b0 = 0; b0 < it.n_row_blocks; b0 += 4 * kSelectThreads) {
+      f32x2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u * kSelectThreads + (int)threadIdx.x;
+        if (b < it.n_row_blocks) v[u] = am[b];
+        else v[u].x = v[u].y = 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        am0 = fmaxf(am0, v[u].x);
+        am1 = fmaxf(am1, v[u].y);
+      }
     }
   }
-  const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{gbval, gbs};
-  const int n_off = it.n_off;
+  const int n_stage = n_off < kMaxSlots ? n_off : kMaxSlots;
+  {
+    stage<kSelectThreads, 2>(s_off[0], (const long long*)it.offs, n_stage);
+    if (it.variant != CWB_CWB) stage<kSelectThreads, 2>(s_off[1], (const long long*)it.offs + n_off, n_stage);
+    stage<kSelectThreads, 4>(s_ai, it.ainv[0], d * d);
+    stage<kSelectThreads, 4>(s_g, it.gram[0], d * d);
+    stage<kSelectThreads, 1>(s_jr, it.jr, 2 * d);
+    if (STAGED) {
+      stage<kSelectThreads, 16>(s_bv, it.bval, nb * kMaxBand);
+      stage<kSelectThreads, 4>(s_bs, it.bstart, nb);
+    }
+  }
+  if (m_done >= it.M) return;
+  const bool hcwb_all = it.variant == CWB_HCWB && switched;
+  const bool acwb = it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched);
+  const int nsig = acwb ? 2 : 1;
+  const int64_t n_fit = hcwb_all ? it.n : it.n_train;
+  if (hcwb_all) {  // HCWB after the switch: Grams over all rows
+    __syncthreads();
+    stage<kSelectThreads, 4>(s_ai, it.ainv[1], d * d);
+    stage<kSelectThreads, 4>(s_g, it.gram[1], d * d);
+  }
+  const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{it.bval, it.bstart};
+  const float amax[2] = {block_max<kSelectThreads>(am0, s_red), block_max<kSelectThreads>(am1, s_red)};
   for (int sig = 0; sig < nsig; ++sig) {
-    const double isc = ldexp(1.0, -fit_scale_exponent<kSelectThreads>(F, sig, n_fit, s_red));
-    const int64_t* offs = sel_off + it.off_begin + (int64_t)sig * n_off;
+    const double isc = ldexp(1.0, -scale_exponent(amax[sig], n_fit));
     // bin sums s_l: exact int64 merge of the group's segment partials
     for (int l0 = 0; l0 < nb; l0 += 4 * kSelectThreads) {
       long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
       const int l = l0 + 4 * threadIdx.x;
       for (int c0 = 0; c0 < n_off; c0 += kMaxSlots) {
         const int cnt = (n_off - c0) < kMaxSlots ? (n_off - c0) : kMaxSlots;
-        __syncthreads();
-        for (int i = threadIdx.x; i < cnt; i += kSelectThreads) s_off[i] = gp(offs)[c0 + i];
-        __syncthreads();
+        const long long* so = s_off[sig];
+        if (n_off > kMaxSlots) {  // more segments than the staged list holds
+          __syncthreads();
+          stage<kSelectThreads, 2>(s_off[sig], (const long long*)(it.offs + (int64_t)sig * n_off + c0), cnt);
+          __syncthreads();
+        }
         if (l < nb) {
 #pragma unroll 16
           for (int i = 0; i < cnt; ++i) {
-            const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + s_off[i] + l);
+            const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + so[i] + l);
             const i64x2 u = src[0], w = src[1];
             a0 += u.x;
             a1 += u.y;
@@ -624,12 +714,12 @@ k_select(const FitDev* __restrict__ fits, const SelItem* __restrict__ items,
     if (threadIdx.x == 0) {
       double w = 0.0;
       for (int j = 0; j < d; ++j) w += s_th[j] * (s_gt[j] - 2.0 * s_v[j]);
-      F.q[(size_t)sig * F.p + k] = w;
+      it.q[(size_t)sig * it.p] = w;
     }
-    for (int j = threadIdx.x; j < F.d_max; j += kSelectThreads)
-      F.theta[((size_t)sig * F.p + k) * F.d_max + j] = (j < d) ? s_th[j] : 0.0;
+    GLOBAL double* th = gp(it.theta + (size_t)sig * it.p * it.d_max);
+    for (int j = threadIdx.x; j < it.d_max; j += kSelectThreads) th[j] = (j < d) ? s_th[j] : 0.0;
     // candidate update table Z^b theta
-    GLOBAL float* tab = gp(F.table + ((size_t)sig * F.p + k) * F.nb_max);
+    GLOBAL float* tab = gp(it.table + (size_t)sig * it.p * it.nb_max);
     for (int l = threadIdx.x; l < nb; l += kSelectThreads) {
       const int b0 = B.bstart[l];
       double t = 0.0;
@@ -737,59 +827,66 @@ __global__ void __launch_bounds__(kSelectThreads) k_finalize(const FitDev* __res
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int NT, int FMAX>
+template <int NT, int FMAX, int NSMAX>
 hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                          const int64_t* blk, long long* partials) {
   static bool attr = false;
   if (!attr) {
     // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL((k_hist<NT, FMAX>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk, partials);
+  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
+                     partials);
   return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, int NSMAX>
 hipError_t launch_hist_nt(hipStream_t st, int fmax, int blocks, size_t lds, const FitDev* fits,
                           const Seg* segs, const int64_t* blk, long long* partials) {
   switch (fmax) {
-    case 1: return launch_hist_t<NT, 1>(st, blocks, lds, fits, segs, blk, partials);
-    case 2: return launch_hist_t<NT, 2>(st, blocks, lds, fits, segs, blk, partials);
-    case 4: return launch_hist_t<NT, 4>(st, blocks, lds, fits, segs, blk, partials);
-    case 8: return launch_hist_t<NT, 8>(st, blocks, lds, fits, segs, blk, partials);
-    case 16: return launch_hist_t<NT, 16>(st, blocks, lds, fits, segs, blk, partials);
+    case 1: return launch_hist_t<NT, 1, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
+    case 2: return launch_hist_t<NT, 2, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
+    case 4: return launch_hist_t<NT, 4, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
+    case 8: return launch_hist_t<NT, 8, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
+    case 16: return launch_hist_t<NT, 16, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NSMAX>
+hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
+                          const FitDev* fits, const Seg* segs, const int64_t* blk,
+                          long long* partials) {
+  switch (nt) {
+    case 256: return launch_hist_nt<256, NSMAX>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 512: return launch_hist_nt<512, NSMAX>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 1024: return launch_hist_nt<1024, NSMAX>(st, fmax, blocks, lds, fits, segs, blk, partials);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-hipError_t launch_state(hipStream_t st, const FitDev* fits, const StateItem* items, int nitems,
-                        int nb_max, int final_mode) {
+hipError_t launch_state(hipStream_t st, const RowItem* items, int nitems, int nb_max,
+                        int final_mode) {
   if (nitems <= 0) return hipSuccess;
   const size_t lds = (size_t)2 * nb_max * sizeof(float);
-  hipLaunchKernelGGL(k_state, dim3(nitems), dim3(kStateThreads), lds, st, fits, items, final_mode);
+  hipLaunchKernelGGL(k_state, dim3(nitems), dim3(kStateThreads), lds, st, items, final_mode);
   return hipGetLastError();
 }
 
-hipError_t launch_hist(hipStream_t st, int nt, int fmax, int blocks, size_t lds, const FitDev* fits,
-                       const Seg* segs, const int64_t* blk, long long* partials) {
+hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, int blocks, size_t lds,
+                       const FitDev* fits, const Seg* segs, const int64_t* blk, long long* partials) {
   if (blocks <= 0) return hipSuccess;
-  switch (nt) {
-    case 256: return launch_hist_nt<256>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 512: return launch_hist_nt<512>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 1024:  // groups wider than 4 learners spill registers at 1024 threads
-      if (fmax > 4) return hipErrorInvalidValue;
-      return launch_hist_nt<1024>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    default: return hipErrorInvalidValue;
-  }
+  if (nsmax == 1) return launch_hist_ns<1>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_ns<2>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
 }
 
-hipError_t launch_select(hipStream_t st, const FitDev* fits, const SelItem* items, int nitems,
-                         int nb_max, int d_max, const int64_t* sel_off, const long long* partials) {
+hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nb_max, int d_max,
+                         const long long* partials) {
   if (nitems <= 0) return hipSuccess;
   // static LDS of the kernel (incl. the selection step) stays below 16 KiB
   size_t lds = ((size_t)nb_max + 2 * (size_t)d_max * d_max) * sizeof(double);
@@ -807,11 +904,11 @@ hipError_t launch_select(hipStream_t st, const FitDev* fits, const SelItem* item
     attr = true;
   }
   if (staged)
-    hipLaunchKernelGGL(k_select<true>, dim3(nitems), dim3(kSelectThreads), lds, st, fits, items,
-                       sel_off, partials, nb_max, d_max);
+    hipLaunchKernelGGL(k_select<true>, dim3(nitems), dim3(kSelectThreads), lds, st, items,
+                       partials, nb_max, d_max);
   else
-    hipLaunchKernelGGL(k_select<false>, dim3(nitems), dim3(kSelectThreads), lds, st, fits, items,
-                       sel_off, partials, nb_max, d_max);
+    hipLaunchKernelGGL(k_select<false>, dim3(nitems), dim3(kSelectThreads), lds, st, items,
+                       partials, nb_max, d_max);
   return hipGetLastError();
 }
 

@@ -111,7 +111,9 @@ Tune make_tune(int nb_stride, int nsig_max, int p_max) {
   F = std::max(1, std::min(16, F));
   F = std::min(F, std::max(1, p_max));
   while (F > 1 && (size_t)F * per_learner > (size_t)kHistMaxLds) --F;
-  if (t.nt == 1024) F = std::min(F, 4);  // wider groups spill registers at 1024 threads
+  // register budget at 1024 threads: groups of at most 8 learners (one
+  // signal) or 2 learners (two signals); wider groups would spill
+  if (t.nt == 1024) F = std::min(F, nsig_max == 1 ? 8 : 2);
   t.F = F;
   t.fmax = 1;
   while (t.fmax < F) t.fmax *= 2;
@@ -239,6 +241,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
     nbs_max = std::max(nbs_max, f->nb_stride);
   }
   S.lds = (size_t)ns_max * t.F * nbs_max * sizeof(long long);
+  S.nsig_max = ns_max;
   return S;
 }
 
@@ -348,7 +351,7 @@ Layout make_layout(const FitShape& sh, const Schedule& s) {
   L.blk = take(s.blk.size() * 8);
   L.sel_off = take(s.sel_off.size() * 8);
   L.partials = take((size_t)s.partial_words * 8);
-  L.st_items = take((size_t)sh.n_row_blocks * sizeof(StateItem));
+  L.st_items = take((size_t)sh.n_row_blocks * sizeof(RowItem));
   L.sel_items = take((size_t)sh.p * sizeof(SelItem));
   L.val_items = take((size_t)std::max(1, sh.n_val_blocks) * sizeof(StateItem));
   L.total = align_up(off, 256);
@@ -396,19 +399,19 @@ void timer_free(KernelTimer& t) {
 
 // One iteration for a set of fits sharing a schedule.
 int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Schedule& S, const Tune& t,
-                      const StateItem* d_st, int n_st, const SelItem* d_sel, int n_sel,
+                      const RowItem* d_st, int n_st, const SelItem* d_sel, int n_sel,
                       const StateItem* d_val, int n_val, int nb_max, int d_max, const Seg* d_segs,
                       const int64_t* d_blk, const int64_t* d_off, long long* d_part,
                       cwb_fit* timed) {
   const int tm = timed ? timed->timing : 0;
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
-  HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
+  HIP_TRY(launch_state(st, d_st, n_st, nb_max, 0));
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
-  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
-  HIP_TRY(launch_select(st, d_fits, d_sel, n_sel, nb_max, d_max, d_off, d_part));
+  HIP_TRY(launch_select(st, d_sel, n_sel, nb_max, d_max, d_part));
   HIP_TRY(launch_pick(st, d_fits, nfits));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   if (n_val > 0) {
@@ -425,26 +428,73 @@ T* dptr(char* ws, size_t off) {
 
 }  // namespace
 
-SelItem make_sel_item(int fit, int k, const FeatDev& fd, const Schedule& S, size_t idx) {
-  SelItem it;
+RowItem make_row_item(int fit, int blk, const FitDev& D) {
+  RowItem it;
+  std::memset(&it, 0, sizeof(it));
+  it.ctl = D.ctl;
+  it.X = D.X;
+  it.y = D.y;
+  it.fg = D.fg;
+  it.h = D.h;
+  it.c = D.c;
+  it.r = D.r;
+  it.table = D.table;
+  it.risk_part = D.risk_part + 2 * (int64_t)blk;
+  it.amax_part = D.amax_part + 2 * (int64_t)blk;
+  it.n = D.n;
+  it.n_pad = D.n_pad;
+  it.n_train = D.n_train;
+  it.base = (int64_t)blk * kStateRows;
+  it.nu = D.nu;
+  it.p = D.p;
+  it.nb_max = D.nb_max;
+  it.loss = D.loss;
+  it.variant = D.variant;
+  it.M = D.M;
+  it.two = D.nsig_max == 2 ? 1 : 0;
+  it.blk = blk;
   it.fit = fit;
+  return it;
+}
+
+SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const Schedule& S,
+                      const int64_t* d_sel_off, size_t idx) {
+  SelItem it;
+  std::memset(&it, 0, sizeof(it));
+  it.ctl = D.ctl;
+  it.amax_part = D.amax_part;
+  for (int set = 0; set < 2; ++set) {
+    it.ainv[set] = D.ainv[set] + fd.mat_off;
+    it.gram[set] = D.gram[set] + fd.mat_off;
+  }
+  it.bval = D.bval + fd.bin_off * kMaxBand;
+  it.bstart = D.bstart + fd.bin_off;
+  it.jr = D.jr + 2 * (int64_t)fd.coef_off;
+  it.offs = d_sel_off + S.sel_begin[idx];
+  it.q = D.q + k;
+  it.theta = D.theta + (int64_t)k * D.d_max;
+  it.table = D.table + (int64_t)k * D.nb_max;
+  it.n = D.n;
+  it.n_train = D.n_train;
   it.k = k;
   it.nb = fd.nb;
   it.band = fd.band;
   it.d = fd.d;
-  it.coef_off = fd.coef_off;
-  it.bin_off = fd.bin_off;
-  it.mat_off = fd.mat_off;
-  it.off_begin = S.sel_begin[idx];
   it.n_off = S.sel_n[idx];
-  it.pad = 0;
+  it.d_max = D.d_max;
+  it.nb_max = D.nb_max;
+  it.p = D.p;
+  it.M = D.M;
+  it.variant = D.variant;
+  it.n_row_blocks = D.n_row_blocks;
+  it.fit = fit;
   return it;
 }
 
 int finalize_fit(cwb_fit* f) {
   HIP_TRY(hipSetDevice(f->device));
-  StateItem* d_st = dptr<StateItem>(f->ws, f->lay.st_items);
-  HIP_TRY(launch_state(f->stream, f->d_fit, d_st, f->n_st, f->shape.nb_max, 1));
+  RowItem* d_st = dptr<RowItem>(f->ws, f->lay.st_items);
+  HIP_TRY(launch_state(f->stream, d_st, f->n_st, f->shape.nb_max, 1));
   HIP_TRY(launch_finalize(f->stream, f->d_fit, 1));
   return CWB_OK;
 }
@@ -653,16 +703,17 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   HIP_TRY(hipMemcpyAsync(ws + L.segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, st));
-  std::vector<StateItem> st_items(sh.n_row_blocks);
-  for (int b = 0; b < sh.n_row_blocks; ++b) st_items[b] = {0, b};
+  std::vector<RowItem> st_items(sh.n_row_blocks);
+  for (int b = 0; b < sh.n_row_blocks; ++b) st_items[b] = make_row_item(0, b, D);
   std::vector<SelItem> sel_items(sh.p);
-  for (int k = 0; k < sh.p; ++k) sel_items[k] = make_sel_item(0, k, feat[k], S, k);
+  for (int k = 0; k < sh.p; ++k)
+    sel_items[k] = make_sel_item(0, k, feat[k], D, S, dptr<int64_t>(ws, L.sel_off), k);
   std::vector<StateItem> val_items(std::max(1, sh.n_val_blocks));
   for (int b = 0; b < sh.n_val_blocks; ++b) val_items[b] = {0, b};
   f->n_st = sh.n_row_blocks;
   f->n_sel = sh.p;
   f->n_val = sh.n_val_blocks;
-  HIP_TRY(hipMemcpyAsync(ws + L.st_items, st_items.data(), st_items.size() * sizeof(StateItem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.st_items, st_items.data(), st_items.size() * sizeof(RowItem), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.sel_items, sel_items.data(), sel_items.size() * sizeof(SelItem), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.val_items, val_items.data(), val_items.size() * sizeof(StateItem), hipMemcpyHostToDevice, st));
   // HCWB: validation risk of f^[0]
@@ -696,7 +747,7 @@ int cwb_fit_run(cwb_fit* f, int32_t iters) {
   const Layout& L = f->lay;
   char* ws = f->ws;
   for (int i = 0; i < iters; ++i) {
-    int rc = enqueue_iteration(f->stream, f->d_fit, 1, f->sched, f->tune, dptr<StateItem>(ws, L.st_items),
+    int rc = enqueue_iteration(f->stream, f->d_fit, 1, f->sched, f->tune, dptr<RowItem>(ws, L.st_items),
                                f->n_st, dptr<SelItem>(ws, L.sel_items), f->n_sel,
                                dptr<StateItem>(ws, L.val_items), f->n_val, f->shape.nb_max,
                                f->shape.d_max,
@@ -886,7 +937,7 @@ BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int 
   L.blk = take(S.blk.size() * 8);
   L.sel_off = take(S.sel_off.size() * 8);
   L.partials = take((size_t)S.partial_words * 8);
-  L.st = take((size_t)std::max(1, n_st) * sizeof(StateItem));
+  L.st = take((size_t)std::max(1, n_st) * sizeof(RowItem));
   L.sel = take((size_t)std::max(1, n_sel) * sizeof(SelItem));
   L.val = take((size_t)std::max(1, n_val) * sizeof(StateItem));
   L.total = align_up(off, 256);
@@ -957,7 +1008,7 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
     b->ws_bytes = ws_bytes;
     b->fits.assign(fits, fits + count);
     std::vector<FitDev> fd(count);
-    std::vector<StateItem> st;
+    std::vector<RowItem> st;
     std::vector<SelItem> sel;
     std::vector<StateItem> val;
     for (int i = 0; i < count; ++i) {
@@ -965,9 +1016,10 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
       b->nb_max = std::max(b->nb_max, fits[i]->shape.nb_max);
       b->d_max = std::max(b->d_max, fits[i]->shape.d_max);
       if (fits[i]->shape.variant == CWB_HCWB) b->any_hcwb = true;
-      for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back({i, r});
+      for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back(make_row_item(i, r, fits[i]->dev));
       for (int k = 0; k < fits[i]->shape.p; ++k)
-        sel.push_back(make_sel_item(i, k, fits[i]->feat[k], b->sched, sel.size()));
+        sel.push_back(make_sel_item(i, k, fits[i]->feat[k], fits[i]->dev, b->sched,
+                                    dptr<int64_t>(b->ws, L.sel_off), sel.size()));
       for (int r = 0; r < fits[i]->shape.n_val_blocks; ++r) val.push_back({i, r});
     }
     char* ws = b->ws;
@@ -977,7 +1029,7 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
     b->d_blk = dptr<int64_t>(ws, L.blk);
     b->d_sel_off = dptr<int64_t>(ws, L.sel_off);
     b->d_partials = dptr<long long>(ws, L.partials);
-    b->d_st = dptr<StateItem>(ws, L.st);
+    b->d_st = dptr<RowItem>(ws, L.st);
     b->d_sel = dptr<SelItem>(ws, L.sel);
     b->d_val = dptr<StateItem>(ws, L.val);
     const Schedule& S = b->sched;
@@ -985,7 +1037,7 @@ int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t w
     HIP_TRY(hipMemcpyAsync(b->d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b->d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b->d_sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, s));
-    if (!st.empty()) HIP_TRY(hipMemcpyAsync(b->d_st, st.data(), st.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
+    if (!st.empty()) HIP_TRY(hipMemcpyAsync(b->d_st, st.data(), st.size() * sizeof(RowItem), hipMemcpyHostToDevice, s));
     if (!sel.empty()) HIP_TRY(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, s));
     if (!val.empty()) HIP_TRY(hipMemcpyAsync(b->d_val, val.data(), val.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -50,6 +50,7 @@ struct Schedule {
   std::vector<int32_t> sel_n;    // per (fit, learner): segments of its group
   int64_t partial_words = 0;
   int blocks = 0;
+  int nsig_max = 1;  // most signals of any fit in the schedule
   size_t lds = 0;
 };
 
@@ -113,7 +114,7 @@ struct cwb_batch {
   int64_t* d_blk = nullptr;
   int64_t* d_sel_off = nullptr;
   long long* d_partials = nullptr;
-  cwb::StateItem* d_st = nullptr;
+  cwb::RowItem* d_st = nullptr;
   cwb::SelItem* d_sel = nullptr;
   cwb::StateItem* d_val = nullptr;
   int n_st = 0, n_sel = 0, n_val = 0;
@@ -123,5 +124,7 @@ namespace cwb {
 int set_error(int code, const std::string& msg);
 // Enqueue one finalize (apply pending updates, record the current risk).
 int finalize_fit(cwb_fit* f);
-SelItem make_sel_item(int fit, int k, const FeatDev& fd, const Schedule& S, size_t idx);
+RowItem make_row_item(int fit, int blk, const FitDev& D);
+SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const Schedule& S,
+                      const int64_t* d_sel_off, size_t idx);
 }  // namespace cwb
