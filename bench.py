@@ -122,13 +122,17 @@ def cpu_baseline(args, prob, gpu_trace):
     t_all = time.perf_counter() - t0
     per_iter = max((t_all - t_setup) / iters, 1e-9)
     m = min(len(gpu_trace["k"]), 1 + iters)
-    match = int(np.sum(gpu_trace["k"][:m] == o["k"][:m]))
+    eq = gpu_trace["k"][:m] == o["k"][:m]
+    match = int(np.sum(eq))
+    first = int(np.argmin(eq)) if not eq.all() else -1
+    gap = float(o["gap"][first]) if first >= 0 else None
     del o1
     return {
         "value": round(1.0 / per_iter, 4), "unit": "iters/s", "cores": cores, "kind": "oracle",
         "sample": (f"FP64 C oracle, iterations 2..{1 + iters} of the same n={prob['x'].shape[0]} "
                    f"p={prob['x'].shape[1]} input (setup excluded, {t_setup:.1f}s)"),
-    }, {"iterations_compared": m, "k_match": match}
+    }, {"iterations_compared": m, "k_match": match, "first_mismatch": first,
+        "oracle_gap_at_mismatch": gap}
 
 
 def batched(args, torch, cwb, datagen):
@@ -170,6 +174,20 @@ def batched(args, torch, cwb, datagen):
             "same_selections_as_alone": bool(same), "setup_s": round(setup, 2)}
 
 
+def copy_probe(torch, mib):
+    """A plain streaming copy of known size (reads and writes `mib` MiB per
+    launch), profiled beside the histogram pass so that the HBM byte counters
+    can be scaled by what they read for a known amount of traffic."""
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,13 +195,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=1200)
     ap.add_argument("--profile-iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-fits", type=int, default=64)
     ap.add_argument("--batch-iters", type=int, default=1000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain streaming copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
@@ -193,6 +213,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if args.copy_probe_mib > 0:
+        copy_probe(torch, args.copy_probe_mib)
+        return
     from paper_2110_03513_amd import cwb, datagen
     cwb.lib()
     prob, tr, h = headline(args, torch, cwb, datagen)
@@ -203,7 +226,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"binned CWB, L2, n={args.n}, p={args.p}, 1000 bins, cubic "
                                 "P-splines d=24 df=5, nu=0.1 (synthetic, seed 2)"),
-                   "global_batch": args.n, "parallelism": "1 GPU"},
+                   "n": args.n, "p": args.p, "n_bins": 1000, "variant": "cwb", "loss": "l2",
+                   "iterations_in_fit": args.warmup + args.steps + args.profile_iters},
         "precision": "uint16 bin indices; int64 fixed-point histograms; fp32 model state; "
                      "fp64 merge, solves and selection",
         "hbm_gbs": round(h["iter_gbs"], 1),
