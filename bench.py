@@ -43,15 +43,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch: float):
+def measured_traffic(tile: dict):
     """HBM bytes per hist launch from the committed rocprofv3 counter summary,
-    or None if it is missing or was taken on a different kernel source."""
+    or None if it is missing, was taken on a different kernel source or on a
+    different tile shape than the one this run uses."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("kernel_hash") != kernel_source_hash():
+        return None
+    want = t.get("tile", {})
+    if any(want.get(k) != tile.get(k) for k in ("threads", "learners", "blocks")):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -64,7 +68,8 @@ def headline(args, torch, cwb, datagen):
     t0 = time.perf_counter()
     fit = cwb.Fit(prob)
     setup_s = time.perf_counter() - t0
-    log(f"[bench] setup {setup_s:.2f}s; warmup {args.warmup} iterations")
+    tile = fit.tile()
+    log(f"[bench] setup {setup_s:.2f}s (tile {tile}); warmup {args.warmup} iterations")
     fit.run(args.warmup)
     fit.sync()
     # timed region: exactly `steps` iterations, HIP events around every
@@ -96,7 +101,7 @@ def headline(args, torch, cwb, datagen):
     hist_bytes = 2.0 * n * p + 4.0 * n
     hist_avg_s = hist_ms / 1e3 / max(hist_n, 1)
     achieved = hist_bytes / hist_avg_s / 1e9
-    traffic = measured_traffic(hist_bytes)
+    traffic = measured_traffic(tile)
     return prob, tr, {
         "iters_s": iters_s, "ms_per_step": per_iter * 1e3, "setup_s": setup_s,
         "iter_gbs": alg_iter_bytes * iters_s / 1e9,
@@ -105,8 +110,43 @@ def headline(args, torch, cwb, datagen):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
-        "alg_iter_bytes": alg_iter_bytes, "hist_bytes_per_launch": hist_bytes,
+        "alg_iter_bytes": alg_iter_bytes, "hist_bytes_per_launch": hist_bytes, "tile": tile,
     }
+
+
+def momentum_legs(args, torch, cwb, datagen):
+    """ACWB and HCWB, binomial, at the full n = 2e6 (150 numeric + 10
+    categorical learners): iterations per second of each phase."""
+    out = {}
+    for variant in ("acwb", "hcwb"):
+        M = args.momentum_iters
+        log(f"[bench] {variant}: n=2e6 p=160, {M} iterations")
+        prob = datagen.config3(variant, M=M)
+        n, p = prob["x"].shape
+        fit = cwb.Fit(prob)
+        del prob
+        fit.run(10)
+        fit.sync()
+        fit.set_timing(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fit.run(M - 10)
+        fit.sync()
+        wall = time.perf_counter() - t0
+        hist_ms, hist_n = fit.kernel_time("hist")
+        tr = fit.trace()
+        sw = tr["switch_iter"]
+        fit.close()
+        two = 2.0 * n * p + 8.0 * n
+        rec = {"iters_s": round((M - 10) / wall, 2), "hist_avg_us": round(hist_ms * 1e3 / max(hist_n, 1), 2),
+               "hist_alg_gbs": round(two / (hist_ms / 1e3 / max(hist_n, 1)) / 1e9, 1),
+               "iterations": M}
+        if variant == "hcwb":
+            rec["switch_iter"] = sw
+            if sw != -1:  # the CWB phase streams one signal: no single byte count
+                rec.pop("hist_alg_gbs")
+        out[variant] = rec
+    return out
 
 
 def cpu_baseline(args, prob, gpu_trace):
@@ -139,19 +179,25 @@ def batched(args, torch, cwb, datagen):
     specs = datagen.config4_specs(count=args.batch_fits, M=args.batch_iters)
     log(f"[bench] batched: {len(specs)} fits, M={args.batch_iters}")
     probs = [datagen.config4_problem(s) for s in specs]
-    t0 = time.perf_counter()
-    fits = [cwb.Fit(p) for p in probs]
-    setup = time.perf_counter() - t0
-    b = cwb.Batch(fits)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.run(args.batch_iters)
-    b.sync()
-    t_batch = time.perf_counter() - t0
-    ks = [f.trace()["k"] for f in fits]
-    b.close()
-    for f in fits:
-        f.close()
+    stream = torch.cuda.Stream()
+    t_batch = {}
+    for graphs in ("1", "0"):
+        os.environ["CWB_GRAPH"] = graphs
+        t0 = time.perf_counter()
+        fits = [cwb.Fit(p) for p in probs]
+        setup = time.perf_counter() - t0
+        b = cwb.Batch(fits, stream=stream)
+        tile = b.tile()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(args.batch_iters)
+        b.sync()
+        t_batch[graphs] = time.perf_counter() - t0
+        ks = [f.trace()["k"] for f in fits]
+        b.close()
+        for f in fits:
+            f.close()
+    os.environ.pop("CWB_GRAPH")
     # the same fits one after another, each alone
     fits = [cwb.Fit(p) for p in probs]
     torch.cuda.synchronize()
@@ -164,14 +210,112 @@ def batched(args, torch, cwb, datagen):
     same = all(np.array_equal(f.trace()["k"], k) for f, k in zip(fits, ks))
     for f in fits:
         f.close()
-    bytes_iter = sum(2.0 * p["x"].shape[0] * p["x"].shape[1] * (1 if p["variant"] == "cwb" else 1)
-                     for p in probs)
+    bytes_iter = sum(2.0 * p["x"].shape[0] * p["x"].shape[1] for p in probs)
+    tb = t_batch["1"]
     return {"fits": len(probs), "iters": args.batch_iters,
-            "fits_per_s": round(len(probs) / t_batch, 3),
+            "fits_per_s": round(len(probs) / tb, 3),
+            "fits_per_s_without_graphs": round(len(probs) / t_batch["0"], 3),
             "loop_fits_per_s": round(len(probs) / t_loop, 3),
-            "speedup_vs_loop": round(t_loop / t_batch, 3),
-            "index_gbs": round(bytes_iter * args.batch_iters / t_batch / 1e9, 1),
+            "speedup_vs_loop": round(t_loop / tb, 3),
+            "index_gbs": round(bytes_iter * args.batch_iters / tb / 1e9, 1),
+            "tile": tile,
             "same_selections_as_alone": bool(same), "setup_s": round(setup, 2)}
+
+
+def served(args, torch, cwb, datagen):
+    """Poisson request stream through the fit server, then the same stream
+    served one fit at a time (max_slots = 1) on the same GPU."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = datagen.config5_stream(count=args.serve_requests)
+    n_max = max(s["n"] for s in specs)
+    p_max = max(s["p"] for s in specs)
+    log(f"[bench] served: {len(specs)} requests, feature pool {n_max} x {p_max}")
+    pool = datagen.FeaturePool(n_max, p_max)
+    # requests whose results are also computed alone (the smallest few)
+    sample = sorted(range(len(specs)), key=lambda i: specs[i]["n"] * specs[i]["p"] * specs[i]["M"])[:8]
+    index_bytes = sum(2.0 * s["n"] * s["p"] * s["M"] for s in specs)
+
+    def one_stream(max_slots):
+        srv = cwb.Server(arena_bytes=int(args.serve_arena_gb * (1 << 30)), max_slots=max_slots,
+                         quantum=args.serve_quantum)
+        ex = ThreadPoolExecutor(max_workers=4)
+        futs = {}
+        ahead = 8
+        for i in range(min(ahead, len(specs))):
+            futs[i] = ex.submit(datagen.config5_problem_pooled, specs[i], pool)
+        tickets = []
+        lateness = []
+        t0 = time.perf_counter()
+        for i, s in enumerate(specs):
+            prob = futs.pop(i).result()
+            if i + ahead < len(specs):
+                futs[i + ahead] = ex.submit(datagen.config5_problem_pooled, specs[i + ahead], pool)
+            wait = t0 + s["arrival"] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(prob))
+            lateness.append(time.perf_counter() - (t0 + s["arrival"]))
+            del prob
+        ex.shutdown()
+        results = {}
+        pending = set(range(len(tickets)))
+        last = time.perf_counter()
+        while pending:
+            for i in list(pending):
+                r = srv.poll(tickets[i])
+                if r is not None:
+                    pending.discard(i)
+                    results[i] = r if i in sample else {"status": r["status"], "latency_s": r["latency_s"]}
+                    last = time.perf_counter()
+            if time.perf_counter() - last > 300:
+                raise RuntimeError("served stream made no progress for 300 s")
+            time.sleep(0.005)
+        st = srv.stats()
+        srv.close()
+        # latency from the scheduled arrival (submit lateness included)
+        lat = np.sort([lateness[i] + results[i]["latency_s"] for i in range(len(tickets))])
+        st["arrival_p50_s"] = float(np.percentile(lat, 50))
+        st["arrival_p99_s"] = float(np.percentile(lat, 99))
+        st["late_submit_s"] = float(max(lateness))
+        st["wall_s"] = time.perf_counter() - t0
+        st["failed"] = sum(1 for r in results.values() if r["status"] != 0)
+        return st, results
+
+    log("[bench] served: continuous batching")
+    st, res = one_stream(args.serve_slots)
+    log("[bench] served: one fit at a time")
+    st1, _ = one_stream(1)
+    # alone vs in the mix
+    bitwise = 0
+    worst = 0.0
+    for i in sample:
+        a = cwb.fit(datagen.config5_problem_pooled(specs[i], pool))
+        r = res[i]
+        same = np.array_equal(a["k"], r["k"]) and np.array_equal(a["f"], r["f"])
+        bitwise += int(same)
+        den = max(float(np.max(np.abs(a["f"]))), 1e-30)
+        worst = max(worst, float(np.max(np.abs(a["f"] - r["f"]))) / den)
+    span = max(s["arrival"] for s in specs)
+
+    def summary(x):
+        return {"fits_per_s": round(x["fits_per_s"], 3), "p50_latency_s": round(x["arrival_p50_s"], 4),
+                "p99_latency_s": round(x["arrival_p99_s"], 4),
+                "p50_from_submit_s": round(x["p50_latency_s"], 4),
+                "p99_from_submit_s": round(x["p99_latency_s"], 4),
+                "mean_setup_s": round(x["mean_setup_s"], 4), "mean_queue_s": round(x["mean_queue_s"], 4),
+                "completed": x["completed"],
+                "rejected": x["rejected"], "failed": x["failed"],
+                "arena_peak_gb": round(x["arena_peak"] / 2**30, 3), "wall_s": round(x["wall_s"], 2),
+                "late_submit_s": round(x["late_submit_s"], 3)}
+
+    return {"requests": len(specs), "rate_per_s": 20.0, "arrival_span_s": round(span, 2),
+            "max_slots": args.serve_slots, "quantum": args.serve_quantum,
+            "arena_gb": args.serve_arena_gb,
+            "continuous_batching": summary(st), "one_at_a_time": summary(st1),
+            "speedup_fits_per_s": round(st["fits_per_s"] / max(st1["fits_per_s"], 1e-12), 3),
+            "index_gbs": round(index_bytes / max(st["wall_s"], 1e-9) / 1e9, 1),
+            "alone_vs_mix": {"requests": len(sample), "bitwise_equal": bitwise,
+                             "max_rel_err_f": worst}}
 
 
 def copy_probe(torch, mib):
@@ -202,9 +346,22 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-fits", type=int, default=64)
     ap.add_argument("--batch-iters", type=int, default=1000)
+    ap.add_argument("--momentum-iters", type=int, default=300)
+    ap.add_argument("--no-momentum", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-quantum", type=int, default=50)
+    ap.add_argument("--serve-arena-gb", type=float, default=64.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain streaming copy of this many MiB (counter calibration)")
+    ap.add_argument("--tile", default="",
+                    help="threads,lds_kib,blocks_per_cu: force one histogram tile shape "
+                         "instead of autotuning (used for counter runs)")
     args = ap.parse_args()
+    if args.tile:
+        nt, kb, bpc = (int(v) for v in args.tile.split(","))
+        os.environ.update({"CWB_HIST_NT": str(nt), "CWB_HIST_LDS_KB": str(kb),
+                           "CWB_HIST_BPC": str(bpc)})
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(multi-GPU sharding is a design note only)"}))
@@ -237,14 +394,19 @@ def main():
                        "state": h["state_avg_us"] and round(h["state_avg_us"], 2),
                        "select": h["select_avg_us"] and round(h["select_avg_us"], 2)},
         "setup_s": round(h["setup_s"], 2),
+        "hist_tile": h["tile"],
     }
     if not args.no_cpu:
         cb, par = cpu_baseline(args, prob, tr)
         out["cpu_baseline"] = cb
         out["parity"] = par
     del prob
+    if not args.no_momentum:
+        out["momentum"] = momentum_legs(args, torch, cwb, datagen)
     if not args.no_batch:
         out["batched"] = batched(args, torch, cwb, datagen)
+    if not args.no_serve:
+        out["served"] = served(args, torch, cwb, datagen)
     print(json.dumps(out), flush=True)
 
 

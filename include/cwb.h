@@ -83,7 +83,7 @@ typedef struct {
 typedef struct {
   int64_t n;                     /* rows, >= 2 */
   int32_t p;                     /* features = base learners, >= 1 */
-  const double* x;               /* n x p, COLUMN-major: x[j*n + i].  Ridge
+  const double* x;               /* n x p, COLUMN-major: x[j*ldx + i].  Ridge
                                     columns hold integer level codes 0..c_j-1. */
   const double* y;               /* n targets (binomial: 0 or 1) */
   int32_t loss;                  /* CWB_L2 or CWB_BINOMIAL */
@@ -96,6 +96,8 @@ typedef struct {
   const uint8_t* val_mask;       /* NULL, or n bytes with 1 = validation row.
                                     Required for HCWB.  CWB / ACWB then fit on
                                     the other rows and report validation risk. */
+  int64_t ldx;                   /* column stride of x in elements: column j
+                                    starts at x + j*ldx; 0 means n; else >= n */
 } cwb_problem;
 
 /* Sizes of a created fit (for sizing getter buffers). */
@@ -140,7 +142,11 @@ typedef struct cwb_fit cwb_fit;
  * orthogonalisation, App. A.2; the inverse penalised Gram matrix, Sec. 2.4)
  * and copy everything to `dev_ws` on `stream`.  The library copies what it
  * needs, so the caller may free the host arrays on return.  `dev_ws` stays
- * owned by the caller and must outlive the fit.
+ * owned by the caller and must outlive the fit.  Create then times the
+ * histogram pass under each candidate tile shape on the fit's own data and
+ * keeps the fastest (see cwb_tile; the environment variable CWB_AUTOTUNE=0
+ * keeps the default shape).  Histograms are exact integer sums, so the
+ * choice never changes a result.
  * Errors: INVALID_ARG (n < 2, p < 1, bins outside 2..65535, constant
  * feature, df <= 2 or df >= basis size for a P-spline, binomial y not 0/1,
  * nu <= 0, M < 1, NULL pointer, level code out of range, HCWB without a
@@ -202,6 +208,18 @@ int cwb_fit_load_state(cwb_fit* f, const void* host_buf, size_t bytes);
 int cwb_fit_set_timing(cwb_fit* f, int32_t mask);
 int cwb_fit_kernel_time(cwb_fit* f, const char* kernel, double* total_ms, int64_t* launches);
 
+/* Histogram tile shape a fit or batch uses (Section 3.1.2's first stage:
+ * each block accumulates the bin sums of `learners` learners over its rows
+ * in LDS). */
+typedef struct {
+  int32_t threads;     /* threads per histogram block */
+  int32_t learners;    /* learners per LDS histogram group */
+  int32_t blocks;      /* histogram blocks per launch */
+  int32_t candidates;  /* tile shapes timed at create (1: not tuned) */
+  double tuned_us;     /* measured pass time of the chosen shape (0: not tuned) */
+} cwb_tile;
+int cwb_fit_tile(const cwb_fit* f, cwb_tile* out);
+
 /* Free host-side objects; never frees the caller's device workspace. */
 void cwb_fit_destroy(cwb_fit* f);
 
@@ -214,8 +232,11 @@ void cwb_fit_destroy(cwb_fit* f);
  * the batch enqueues on `stream`. */
 typedef struct cwb_batch cwb_batch;
 int cwb_batch_workspace_bytes(cwb_fit* const* fits, int32_t count, size_t* bytes);
+/* Creates the combined schedule and autotunes its histogram tiles like
+ * cwb_fit_create (the workspace is sized for every candidate shape). */
 int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t ws_bytes,
                      void* stream, cwb_batch** out);
+int cwb_batch_tile(const cwb_batch* b, cwb_tile* out);
 /* Advance every fit by up to `iters` iterations (fits stop at their own M). */
 int cwb_batch_run(cwb_batch* b, int32_t iters);
 int cwb_batch_sync(cwb_batch* b);
@@ -227,7 +248,10 @@ void cwb_batch_destroy(cwb_batch* b);
  * advance together in batched iterations; requests that arrive while others
  * run join at the next scheduling quantum, and finished fits retire and free
  * their arena space.  submit never blocks; poll returns CWB_E_AGAIN until
- * the result is ready. */
+ * the result is ready, then hands it over once (a second poll of the same
+ * ticket is INVALID_ARG).  Requests that can never fit the arena finish
+ * with status NO_MEMORY.  Destroy cancels requests not yet admitted
+ * (status STATE) and finishes the admitted ones. */
 typedef struct cwb_server cwb_server;
 typedef struct {
   void* arena;          /* device memory for fit workspaces (caller-owned) */
@@ -252,10 +276,15 @@ typedef struct {
   double fits_per_s;    /* completed / seconds since the first submit */
   double p50_latency_s, p99_latency_s;
   size_t arena_in_use, arena_peak;
+  double mean_setup_s;  /* host setup time per completed request */
+  double mean_queue_s;  /* submit -> admitted, per completed request */
 } cwb_stats;
 
 int cwb_server_create(const cwb_server_cfg* cfg, cwb_server** out);
-/* Queue a request; the problem is copied.  `ticket` identifies it. */
+/* Queue a request and return at once; `ticket` identifies it.  The learner
+ * specifications are copied; the arrays x, y and val_mask are read later by
+ * the server's setup threads, so the caller keeps them valid and unchanged
+ * until poll has returned the request's result. */
 int cwb_server_submit(cwb_server* s, const cwb_problem* pr, uint64_t* ticket);
 /* CWB_E_AGAIN while pending; else fills `res` and, if the pointers are not
  * NULL, the training predictions (n floats) and k trace (M ints). */

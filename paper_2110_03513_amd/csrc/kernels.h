@@ -17,5 +17,7 @@ hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* i
 hipError_t launch_pick(hipStream_t st, const FitDev* fits, int nfits);
 hipError_t launch_valdecide(hipStream_t st, const FitDev* fits, int nfits);
 hipError_t launch_finalize(hipStream_t st, const FitDev* fits, int nfits);
+// Aggregated coefficients of one fit (sum_d of them) from its traces.
+hipError_t launch_coef(hipStream_t st, const FitDev* fit, int sum_d);
 
 }  // namespace cwb

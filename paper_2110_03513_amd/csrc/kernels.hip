@@ -448,13 +448,11 @@ __device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
   return qa < qb || (qa == qb && ka < kb);
 }
 
-// argmin_k q[k] over the fit's learners (ties: lowest k) and the runner-up value.
-__device__ void block_argmin(const double* q, int p, int* k_out, double* gap_out,
-                             double* sq, int* sk, double* sq2) {
-  double b1 = INFINITY, b2 = INFINITY;
-  int k1 = p;
-  for (int k = threadIdx.x; k < p; k += kSelectThreads) {
-    const double v = q[k];
+// Running argmin (ties: lowest k) with the runner-up value.
+struct Arg2 {
+  double b1, b2;
+  int k1;
+  __device__ __forceinline__ void add(double v, int k) {
     if (better(v, k, b1, k1)) {
       b2 = b1;
       b1 = v;
@@ -463,31 +461,16 @@ __device__ void block_argmin(const double* q, int p, int* k_out, double* gap_out
       b2 = v;
     }
   }
-  sq[threadIdx.x] = b1;
-  sk[threadIdx.x] = k1;
-  sq2[threadIdx.x] = b2;
-  __syncthreads();
-  for (int stride = kSelectThreads / 2; stride > 0; stride >>= 1) {
-    if (threadIdx.x < stride) {
-      const int o = threadIdx.x + stride;
-      const double a1 = sq[threadIdx.x], a2 = sq2[threadIdx.x], c1 = sq[o], c2 = sq2[o];
-      const int ka = sk[threadIdx.x], kb = sk[o];
-      if (better(c1, kb, a1, ka)) {
-        sq[threadIdx.x] = c1;
-        sk[threadIdx.x] = kb;
-        sq2[threadIdx.x] = fmin(a1, c2);
-      } else {
-        sq2[threadIdx.x] = fmin(a2, c1);
-      }
+  __device__ __forceinline__ void merge(double c1, double c2, int kc) {
+    if (better(c1, kc, b1, k1)) {
+      b2 = fmin(b1, c2);
+      b1 = c1;
+      k1 = kc;
+    } else {
+      b2 = fmin(b2, c1);
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    *k_out = sk[0];
-    *gap_out = sq2[0] - sq[0];
-  }
-  __syncthreads();
-}
+};
 
 // Deterministic sum of risk partials of the row-pass blocks.
 __device__ double sum_partials(const double* part, int count, int stride, int offset,
@@ -507,50 +490,88 @@ __device__ double sum_partials(const double* part, int count, int stride, int of
   return block_sum<kSelectThreads>(s, red);
 }
 
+// Selection of iteration m (Algorithm A1's argmin; with `nsig` = 2 also the
+// ACWB correction fit of Algorithm 2): argmin of the criteria, the traces,
+// and the update armed for the next row pass.  Two rounds of global loads:
+// the criteria of both signals with the risk partials, then the winners'
+// coefficients.  The aggregated coefficients are formed from the traces
+// when the model is read (k_coef).
 __device__ void pick(const FitDev& F, Ctl* ctl, int m, bool acwb, int nsig) {
-  __shared__ double sq[kSelectThreads], sq2[kSelectThreads];
-  __shared__ int sk[kSelectThreads];
-  __shared__ int s_k[2];
-  __shared__ double s_gap[2];
+  __shared__ double s_b1[2][kSelectThreads], s_b2[2][kSelectThreads];
+  __shared__ int s_k[2][kSelectThreads];
   __shared__ double s_red[kSelectThreads + 16];
-  for (int sig = 0; sig < nsig; ++sig)
-    block_argmin(F.q + (size_t)sig * F.p, F.p, &s_k[sig], &s_gap[sig], sq, sk, sq2);
-  const int k0 = s_k[0];
-  const int k1 = (nsig == 2) ? s_k[1] : -1;
+  const int p = F.p;
+  const GLOBAL double* q = gp(F.q);
+  const GLOBAL double* rp = gp(F.risk_part);
+  Arg2 a0{INFINITY, INFINITY, p}, a1{INFINITY, INFINITY, p};
+  double rt = 0.0, rv = 0.0;
+  const int n = p > F.n_row_blocks ? p : F.n_row_blocks;
+  for (int t = threadIdx.x; t < n; t += kSelectThreads) {
+    double v0 = INFINITY, v1 = INFINITY, r0 = 0.0, r1 = 0.0;
+    if (t < p) {
+      v0 = q[t];
+      if (nsig == 2) v1 = q[p + t];
+    }
+    if (t < F.n_row_blocks) {
+      r0 = rp[2 * (size_t)t];
+      r1 = rp[2 * (size_t)t + 1];
+    }
+    if (t < p) {
+      a0.add(v0, t);
+      if (nsig == 2) a1.add(v1, t);
+    }
+    rt += r0;
+    rv += r1;
+  }
+  s_b1[0][threadIdx.x] = a0.b1;
+  s_b2[0][threadIdx.x] = a0.b2;
+  s_k[0][threadIdx.x] = a0.k1;
+  s_b1[1][threadIdx.x] = a1.b1;
+  s_b2[1][threadIdx.x] = a1.b2;
+  s_k[1][threadIdx.x] = a1.k1;
+  __syncthreads();
+  for (int stride = kSelectThreads / 2; stride > 0; stride >>= 1) {
+    if (threadIdx.x < stride) {
+      const int o = threadIdx.x + stride;
+#pragma unroll
+      for (int sig = 0; sig < 2; ++sig) {
+        Arg2 a{s_b1[sig][threadIdx.x], s_b2[sig][threadIdx.x], s_k[sig][threadIdx.x]};
+        a.merge(s_b1[sig][o], s_b2[sig][o], s_k[sig][o]);
+        s_b1[sig][threadIdx.x] = a.b1;
+        s_b2[sig][threadIdx.x] = a.b2;
+        s_k[sig][threadIdx.x] = a.k1;
+      }
+    }
+    __syncthreads();
+  }
+  const double sum_t = block_sum<kSelectThreads>(rt, s_red);
+  const double sum_v = block_sum<kSelectThreads>(rv, s_red);
+  int k0 = s_k[0][0];
+  int k1 = (nsig == 2) ? s_k[1][0] : -1;
+  // criteria that are all non-finite select nothing: flag the fit
+  const bool bad = k0 >= p || (nsig == 2 && k1 >= p);
+  if (bad) {
+    k0 = 0;
+    k1 = (nsig == 2) ? 0 : -1;
+  }
   const int mi = m - 1;
   const int dmax = F.d_max;
+  const double vt = 2.0 / ((double)m + 1.0);
+  const double eta = acwb ? F.gamma * F.nu / vt : 0.0;
+  const GLOBAL double* th = gp(F.theta);
   for (int j = threadIdx.x; j < dmax; j += kSelectThreads) {
-    F.tr_theta[(size_t)mi * dmax + j] = F.theta[(size_t)k0 * dmax + j];
-    F.tr_thetacor[(size_t)mi * dmax + j] =
-        (k1 >= 0) ? F.theta[((size_t)F.p + k1) * dmax + j] : 0.0;
+    const double t0 = th[(size_t)k0 * dmax + j];
+    const double t1 = (k1 >= 0) ? th[((size_t)p + k1) * dmax + j] : 0.0;
+    F.tr_theta[(size_t)mi * dmax + j] = t0;
+    F.tr_thetacor[(size_t)mi * dmax + j] = t1;
   }
-  // aggregated coefficients (Section 2.3; ACWB bookkeeping of Section 3.2.1)
-  const FeatDev f0 = F.feat[k0];
-  double eta = 0.0;
-  if (!acwb) {
-    for (int j = threadIdx.x; j < f0.d; j += kSelectThreads)
-      F.coef_f[f0.coef_off + j] += F.nu * F.theta[(size_t)k0 * dmax + j];
-  } else {
-    const double vt = 2.0 / ((double)m + 1.0);
-    eta = F.gamma * F.nu / vt;
-    for (int a = threadIdx.x; a < F.sum_d; a += kSelectThreads)
-      F.coef_f[a] = (1.0 - vt) * F.coef_f[a] + vt * F.coef_h[a];
-    __syncthreads();
-    for (int j = threadIdx.x; j < f0.d; j += kSelectThreads)
-      F.coef_f[f0.coef_off + j] += F.nu * F.theta[(size_t)k0 * dmax + j];
-    const FeatDev f1 = F.feat[k1];
-    for (int j = threadIdx.x; j < f1.d; j += kSelectThreads)
-      F.coef_h[f1.coef_off + j] += eta * F.theta[((size_t)F.p + k1) * dmax + j];
-  }
-  // risk of f^[m-1], from the row pass of this iteration
-  const double rt = sum_partials(F.risk_part, F.n_row_blocks, 2, 0, s_red);
-  const double rv = sum_partials(F.risk_part, F.n_row_blocks, 2, 1, s_red);
   if (threadIdx.x == 0) {
     F.tr_k[mi] = k0;
     F.tr_kcor[mi] = k1;
-    F.tr_gap[mi] = s_gap[0];
-    F.tr_risk[mi] = rt / (double)F.n_train;
-    F.tr_val[mi] = (F.n > F.n_train) ? rv / (double)(F.n - F.n_train) : 0.0;
+    F.tr_gap[mi] = s_b2[0][0] - s_b1[0][0];
+    F.tr_risk[mi] = sum_t / (double)F.n_train;  // risk of f^[m-1]
+    F.tr_val[mi] = (F.n > F.n_train) ? sum_v / (double)(F.n - F.n_train) : 0.0;
+    if (bad) ctl->error = 1;
     ctl->pending = 1;
     ctl->pend_acwb = acwb ? 1 : 0;
     ctl->k = k0;
@@ -822,6 +843,53 @@ __global__ void __launch_bounds__(kSelectThreads) k_finalize(const FitDev* __res
   }
 }
 
+// Aggregated coefficients of the primary and momentum models from the
+// traces (Section 2.3; the ACWB parameter recurrences of Section 3.2.1):
+// thread a owns coefficient a of both models and replays the iterations in
+// order.  An iteration with a correction learner (k_cor >= 0) is an ACWB
+// step: theta_f = (1 - t_m) theta_f + t_m theta_h + nu e_k theta and
+// theta_h += eta_m e_kcor theta_cor with t_m = 2/(m+1), eta_m = gamma nu / t_m;
+// otherwise theta_f += nu e_k theta.
+constexpr int kCoefChunk = 256;
+__global__ void __launch_bounds__(kSelectThreads) k_coef(const FitDev* __restrict__ fits) {
+  __shared__ int s_off[kCoefChunk], s_d[kCoefChunk], s_offc[kCoefChunk], s_dc[kCoefChunk];
+  const FitDev& F = fits[blockIdx.y];
+  const int a = blockIdx.x * kSelectThreads + threadIdx.x;
+  const int m_done = F.ctl->m_done;
+  const int dmax = F.d_max;
+  double cf = 0.0, ch = 0.0;
+  for (int m0 = 0; m0 < m_done; m0 += kCoefChunk) {
+    const int cnt = (m_done - m0 < kCoefChunk) ? m_done - m0 : kCoefChunk;
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += kSelectThreads) {
+      const int k = F.tr_k[m0 + t], kc = F.tr_kcor[m0 + t];
+      s_off[t] = F.feat[k].coef_off;
+      s_d[t] = F.feat[k].d;
+      s_offc[t] = kc >= 0 ? F.feat[kc].coef_off : -1;
+      s_dc[t] = kc >= 0 ? F.feat[kc].d : 0;
+    }
+    __syncthreads();
+    if (a < F.sum_d) {
+      for (int t = 0; t < cnt; ++t) {
+        const int mi = m0 + t;
+        if (s_offc[t] >= 0) {
+          const double vt = 2.0 / ((double)(mi + 1) + 1.0);
+          const double eta = F.gamma * F.nu / vt;
+          cf = (1.0 - vt) * cf + vt * ch;
+          if (a >= s_offc[t] && a < s_offc[t] + s_dc[t])
+            ch += eta * F.tr_thetacor[(size_t)mi * dmax + (a - s_offc[t])];
+        }
+        if (a >= s_off[t] && a < s_off[t] + s_d[t])
+          cf += F.nu * F.tr_theta[(size_t)mi * dmax + (a - s_off[t])];
+      }
+    }
+  }
+  if (a < F.sum_d) {
+    F.coef_f[a] = cf;
+    F.coef_h[a] = ch;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
@@ -830,14 +898,15 @@ namespace {
 template <int NT, int FMAX, int NSMAX>
 hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                          const int64_t* blk, long long* partials) {
-  static bool attr = false;
-  if (!attr) {
-    // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB)
+  // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB);
+  // set once (thread-safe static initialisation), before any graph capture
+  static const bool attr = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
     (void)hipGetLastError();
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
                      partials);
   return hipGetLastError();
@@ -893,16 +962,16 @@ hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int n
   const size_t extra = (size_t)nb_max * kMaxBand * sizeof(double) + (size_t)nb_max * sizeof(int);
   const bool staged = nb_max <= kStageBins && lds + extra <= 144 * 1024;
   if (staged) lds += extra;
-  static bool attr = false;
-  if (!attr) {
-    // 160 KiB per workgroup minus the kernel's own static LDS (< 16 KiB)
+  // 160 KiB per workgroup minus the kernel's own static LDS (< 16 KiB)
+  static const bool attr = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select<false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
     (void)hipGetLastError();
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   if (staged)
     hipLaunchKernelGGL(k_select<true>, dim3(nitems), dim3(kSelectThreads), lds, st, items,
                        partials, nb_max, d_max);
@@ -929,6 +998,13 @@ hipError_t launch_pick(hipStream_t st, const FitDev* fits, int nfits) {
 hipError_t launch_valdecide(hipStream_t st, const FitDev* fits, int nfits) {
   if (nfits <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_valdecide, dim3(nfits), dim3(kSelectThreads), 0, st, fits);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef(hipStream_t st, const FitDev* fits, int sum_d) {
+  if (sum_d <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coef, dim3((sum_d + kSelectThreads - 1) / kSelectThreads, 1), dim3(kSelectThreads),
+                     0, st, fits);
   return hipGetLastError();
 }
 

@@ -93,21 +93,29 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
   return CWB_OK;
 }
 
-Tune make_tune(int nb_stride, int nsig_max, int p_max) {
+namespace {
+
+bool hist_env_set() {
+  for (const char* v : {"CWB_HIST_NT", "CWB_HIST_LDS_KB", "CWB_HIST_BPC", "CWB_HIST_SLICES",
+                        "CWB_HIST_BLOCKS", "CWB_HIST_F"}) {
+    const char* e = std::getenv(v);
+    if (e && *e) return true;
+  }
+  return false;
+}
+
+Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, int nb_stride,
+               int nsig_max, int p_max, int cus) {
   Tune t;
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  t.cus = device_cus(dev);
-  t.nt = env_int("CWB_HIST_NT", 1024);
-  if (t.nt != 256 && t.nt != 512 && t.nt != 1024) t.nt = 512;
-  t.lds_kb = std::max(8, std::min(152, env_int("CWB_HIST_LDS_KB", 32)));
-  t.blocks_per_cu = std::max(1, std::min(8, env_int("CWB_HIST_BPC", 1)));
-  t.slices = std::max(1, std::min(64, env_int("CWB_HIST_SLICES", 1)));
-  t.blocks = std::max(0, std::min(65536, env_int("CWB_HIST_BLOCKS", 0)));
+  t.cus = cus;
+  t.nt = (nt == 256 || nt == 512 || nt == 1024) ? nt : 512;
+  t.lds_kb = std::max(8, std::min(152, lds_kb));
+  t.blocks_per_cu = std::max(1, std::min(8, bpc));
+  t.slices = std::max(1, std::min(64, slices));
+  t.blocks = std::max(0, std::min(65536, blocks));
   const size_t per_learner = (size_t)nsig_max * nb_stride * sizeof(long long);
   int F = (int)((size_t)t.lds_kb * 1024 / per_learner);
-  const int fenv = env_int("CWB_HIST_F", 0);
-  if (fenv > 0) F = fenv;
+  if (fset > 0) F = fset;
   F = std::max(1, std::min(16, F));
   F = std::min(F, std::max(1, p_max));
   while (F > 1 && (size_t)F * per_learner > (size_t)kHistMaxLds) --F;
@@ -118,6 +126,44 @@ Tune make_tune(int nb_stride, int nsig_max, int p_max) {
   t.fmax = 1;
   while (t.fmax < F) t.fmax *= 2;
   return t;
+}
+
+}  // namespace
+
+Tune make_tune(int nb_stride, int nsig_max, int p_max) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return tune_with(env_int("CWB_HIST_NT", 1024), env_int("CWB_HIST_LDS_KB", 32),
+                   env_int("CWB_HIST_BPC", 1), env_int("CWB_HIST_SLICES", 1),
+                   env_int("CWB_HIST_BLOCKS", 0), env_int("CWB_HIST_F", 0), nb_stride, nsig_max,
+                   p_max, device_cus(dev));
+}
+
+// Tile shapes the autotuner tries: the default first, then threads x LDS
+// budget x blocks per CU.  Explicit CWB_HIST_* settings, or CWB_AUTOTUNE=0,
+// leave the default alone.
+std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool all) {
+  std::vector<Tune> out{make_tune(nb_stride, nsig_max, p_max)};
+  if (!all || hist_env_set() || env_int("CWB_AUTOTUNE", 1) == 0) return out;
+  const int cus = out[0].cus;
+  for (int nt : {1024, 512, 256})
+    for (int kb : {32, 64, 128})
+      for (int bpc : {1, 2}) {
+        const Tune t = tune_with(nt, kb, bpc, 1, 0, 0, nb_stride, nsig_max, p_max, cus);
+        bool dup = false;
+        for (const Tune& u : out)
+          dup = dup || (u.nt == t.nt && u.F == t.F && u.blocks_per_cu == t.blocks_per_cu &&
+                        u.slices == t.slices && u.blocks == t.blocks);
+        if (!dup) out.push_back(t);
+      }
+  return out;
+}
+
+void SchedCap::add(const Schedule& S) {
+  segs = std::max(segs, S.segs.size());
+  blk = std::max(blk, S.blk.size());
+  sel_off = std::max(sel_off, S.sel_off.size());
+  partial_words = std::max(partial_words, S.partial_words);
 }
 
 Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t) {
@@ -300,7 +346,7 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
   return true;
 }
 
-Layout make_layout(const FitShape& sh, const Schedule& s) {
+Layout make_layout(const FitShape& sh, const SchedCap& s) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -347,9 +393,9 @@ Layout make_layout(const FitShape& sh, const Schedule& s) {
   L.valpart = take((size_t)std::max(1, sh.n_val_blocks) * 8);
   L.fitdev = take(sizeof(FitDev));
   // solo schedule
-  L.segs = take(s.segs.size() * sizeof(Seg));
-  L.blk = take(s.blk.size() * 8);
-  L.sel_off = take(s.sel_off.size() * 8);
+  L.segs = take(s.segs * sizeof(Seg));
+  L.blk = take(s.blk * 8);
+  L.sel_off = take(s.sel_off * 8);
   L.partials = take((size_t)s.partial_words * 8);
   L.st_items = take((size_t)sh.n_row_blocks * sizeof(RowItem));
   L.sel_items = take((size_t)sh.p * sizeof(SelItem));
@@ -499,75 +545,119 @@ int finalize_fit(cwb_fit* f) {
   return CWB_OK;
 }
 
-}  // namespace cwb
-
-using namespace cwb;
-
-extern "C" {
-
-int cwb_version(int* major, int* minor) {
-  if (major) *major = CWB_VERSION_MAJOR;
-  if (minor) *minor = CWB_VERSION_MINOR;
+int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::vector<Tune>* cands,
+                    SchedCap* cap, Schedule* first) {
+  int nb = 1, ns = 1, pmax = 1;
+  for (const FitShape* sh : shapes) {
+    nb = std::max(nb, sh->nb_stride);
+    ns = std::max(ns, sh->nsig_max);
+    pmax = std::max(pmax, sh->p);
+  }
+  *cands = tune_candidates(nb, ns, pmax, all);
+  *cap = SchedCap();
+  for (size_t i = 0; i < cands->size(); ++i) {
+    Schedule S = build_schedule(shapes, (*cands)[i]);
+    std::string why;
+    if (!schedule_is_valid(S, shapes, (*cands)[i], &why))
+      return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+    cap->add(S);
+    if (i == 0 && first) *first = std::move(S);
+  }
   return CWB_OK;
 }
 
-const char* cwb_last_error(void) { return g_err.c_str(); }
+namespace {
 
-int cwb_bin_feature(const double* x, int64_t n, int32_t n_bins, uint16_t* ind_out, double* z_out) {
-  try {
-    std::string err;
-    const int rc = bin_one_feature(x, n, n_bins, ind_out, z_out, &err);
-    return rc ? set_error(rc, err) : CWB_OK;
-  } catch (...) {
-    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
   }
+};
+
+}  // namespace
+
+int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const FitShape*>& shapes,
+                  const std::vector<Tune>& cands, const SchedCap& cap, Seg* d_segs, int64_t* d_blk,
+                  long long* d_part, int* best, double* best_us) {
+  *best = 0;
+  *best_us = 0.0;
+  if (cands.size() < 2) return CWB_OK;
+  constexpr int kWarm = 2, kTimed = 5;
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.a));
+  HIP_TRY(hipEventCreate(&ev.b));
+  double best_t = 0.0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    const Tune& t = cands[i];
+    Schedule S = build_schedule(shapes, t);
+    if (S.segs.size() > cap.segs || S.blk.size() > cap.blk || S.partial_words > cap.partial_words)
+      continue;
+    HIP_TRY(hipMemcpyAsync(d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
+    for (int w = 0; w < kWarm; ++w)
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+    HIP_TRY(hipEventRecord(ev.a, st));
+    for (int r = 0; r < kTimed; ++r)
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+    HIP_TRY(hipEventRecord(ev.b, st));
+    HIP_TRY(hipEventSynchronize(ev.b));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+    const double us = (double)ms * 1e3 / kTimed;
+    if (*best_us == 0.0 || us < best_t) {
+      best_t = us;
+      *best = (int)i;
+      *best_us = us;
+    }
+  }
+  return CWB_OK;
 }
 
-int cwb_workspace_bytes(const cwb_problem* pr, size_t* bytes) {
-  try {
-    if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
-    std::string err;
-    FitShape sh;
-    int rc = shape_from_problem(pr, &sh, &err);
-    if (rc) return set_error(rc, err);
-    Tune t = make_tune(sh.nb_stride, sh.nsig_max, sh.p);
-    Schedule s = build_schedule({&sh}, t);
-    std::string why;
-    if (!schedule_is_valid(s, {&sh}, t, &why)) return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
-    *bytes = make_layout(sh, s).total;
-    return CWB_OK;
-  } catch (const std::bad_alloc&) {
-    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
-  } catch (...) {
-    return set_error(CWB_E_INVALID_ARG, "unexpected error");
-  }
+int fit_footprint(const FitShape& sh, size_t* bytes, bool all) {
+  std::vector<Tune> cands;
+  SchedCap cap;
+  int rc = plan_candidates({&sh}, all, &cands, &cap, nullptr);
+  if (rc) return rc;
+  *bytes = make_layout(sh, cap).total;
+  return CWB_OK;
 }
 
-static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
-                           cwb_fit** out) {
-  if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+// Upload a schedule and the select work list that indexes its partials.
+static int fit_install(cwb_fit* f, const Tune& t, Schedule&& S) {
+  const Layout& L = f->lay;
+  char* ws = f->ws;
+  hipStream_t st = f->stream;
+  std::vector<SelItem> sel_items(f->shape.p);
+  for (int k = 0; k < f->shape.p; ++k)
+    sel_items[k] = make_sel_item(0, k, f->feat[k], f->dev, S, dptr<int64_t>(ws, L.sel_off), k);
+  HIP_TRY(hipMemcpyAsync(ws + L.segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L.sel_items, sel_items.data(), sel_items.size() * sizeof(SelItem),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  f->tune = t;
+  f->sched = std::move(S);
+  return CWB_OK;
+}
+
+int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
+               bool autotune, cwb_fit** out) {
   *out = nullptr;
-  if (!dev_ws) return set_error(CWB_E_INVALID_ARG, "null workspace");
-  if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
-    return set_error(CWB_E_INVALID_ARG, "workspace must be 256-byte aligned");
-  std::string err;
-  FitShape sh;
-  int rc = shape_from_problem(pr, &sh, &err);
-  if (rc) return set_error(rc, err);
-  HostFit hf;
-  rc = build_host_fit(pr, &hf, &err);
-  if (rc) return set_error(rc, err);
   std::unique_ptr<cwb_fit> f(new cwb_fit());
-  f->stream = reinterpret_cast<hipStream_t>(stream);
+  f->stream = stream;
   f->shape = sh;
-  f->tune = make_tune(sh.nb_stride, sh.nsig_max, sh.p);
-  f->sched = build_schedule({&f->shape}, f->tune);
+  std::vector<Tune> cands;
+  SchedCap cap;
   {
-    std::string why;
-    if (!schedule_is_valid(f->sched, {&f->shape}, f->tune, &why))
-      return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+    int rc = plan_candidates({&f->shape}, autotune, &cands, &cap, &f->sched);
+    if (rc) return rc;
   }
-  f->lay = make_layout(sh, f->sched);
+  f->tune = cands[0];
+  f->n_cands = (int)cands.size();
+  f->lay = make_layout(sh, cap);
   if (ws_bytes < f->lay.total)
     return set_error(CWB_E_NO_MEMORY, "workspace too small: need " + std::to_string(f->lay.total) +
                                           " bytes, got " + std::to_string(ws_bytes));
@@ -624,12 +714,12 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   D.nb_max = sh.nb_max;
   D.d_max = sh.d_max;
   D.sum_d = sh.sum_d;
-  D.loss = pr->loss;
-  D.variant = pr->variant;
-  D.M = pr->M;
-  D.patience = pr->patience;
-  D.nu = pr->nu;
-  D.gamma = pr->gamma;
+  D.loss = hf.loss;
+  D.variant = hf.variant;
+  D.M = hf.M;
+  D.patience = hf.patience;
+  D.nu = hf.nu;
+  D.gamma = hf.gamma;
   D.n_row_blocks = sh.n_row_blocks;
   D.n_val_blocks = sh.n_val_blocks;
   D.nsig_max = sh.nsig_max;
@@ -670,7 +760,7 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   std::memset(&ctl, 0, sizeof(ctl));
   ctl.kcor = -1;
   ctl.switch_iter = -1;
-  if (pr->variant == CWB_HCWB && pr->patience == 0) {
+  if (hf.variant == CWB_HCWB && hf.patience == 0) {
     ctl.switched = 1;
     ctl.switch_iter = 1;
   }
@@ -722,8 +812,74 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
     HIP_TRY(launch_valdecide(st, f->d_fit, 1));
   }
   HIP_TRY(hipStreamSynchronize(st));
+  if (cands.size() > 1) {
+    int best = 0;
+    int rc = autotune_hist(st, f->d_fit, {&f->shape}, cands, cap, dptr<Seg>(ws, L.segs),
+                           dptr<int64_t>(ws, L.blk), dptr<long long>(ws, L.partials), &best,
+                           &f->tuned_us);
+    if (rc) return rc;
+    Schedule S = build_schedule({&f->shape}, cands[best]);
+    rc = fit_install(f.get(), cands[best], std::move(S));
+    if (rc) return rc;
+  }
   *out = f.release();
   return CWB_OK;
+}
+
+}  // namespace cwb
+
+using namespace cwb;
+
+extern "C" {
+
+int cwb_version(int* major, int* minor) {
+  if (major) *major = CWB_VERSION_MAJOR;
+  if (minor) *minor = CWB_VERSION_MINOR;
+  return CWB_OK;
+}
+
+const char* cwb_last_error(void) { return g_err.c_str(); }
+
+int cwb_bin_feature(const double* x, int64_t n, int32_t n_bins, uint16_t* ind_out, double* z_out) {
+  try {
+    std::string err;
+    const int rc = bin_one_feature(x, n, n_bins, ind_out, z_out, &err);
+    return rc ? set_error(rc, err) : CWB_OK;
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
+}
+
+int cwb_workspace_bytes(const cwb_problem* pr, size_t* bytes) {
+  try {
+    if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
+    std::string err;
+    FitShape sh;
+    int rc = shape_from_problem(pr, &sh, &err);
+    if (rc) return set_error(rc, err);
+    return fit_footprint(sh, bytes, true);
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
+}
+
+static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
+                           cwb_fit** out) {
+  if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!dev_ws) return set_error(CWB_E_INVALID_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+    return set_error(CWB_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  std::string err;
+  FitShape sh;
+  int rc = shape_from_problem(pr, &sh, &err);
+  if (rc) return set_error(rc, err);
+  HostFit hf;
+  rc = build_host_fit(pr, &hf, &err);
+  if (rc) return set_error(rc, err);
+  return fit_upload(sh, hf, dev_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), true, out);
 }
 
 int cwb_fit_create(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream, cwb_fit** out) {
@@ -820,6 +976,7 @@ int cwb_fit_get_trace(cwb_fit* f, int32_t* k, double* theta, int32_t* k_cor, dou
 int cwb_fit_get_model(cwb_fit* f, double* intercept, double* coef_f, double* coef_h) {
   if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
   HIP_TRY(hipSetDevice(f->device));
+  HIP_TRY(launch_coef(f->stream, f->d_fit, f->shape.sum_d));
   HIP_TRY(hipStreamSynchronize(f->stream));
   int rc = check_device_error(f);
   if (rc) return rc;
@@ -905,6 +1062,16 @@ int cwb_fit_kernel_time(cwb_fit* f, const char* kernel, double* total_ms, int64_
   return CWB_OK;
 }
 
+int cwb_fit_tile(const cwb_fit* f, cwb_tile* out) {
+  if (!f || !out) return set_error(CWB_E_INVALID_ARG, "null argument");
+  out->threads = f->tune.nt;
+  out->learners = f->tune.F;
+  out->blocks = f->sched.blocks;
+  out->candidates = f->n_cands;
+  out->tuned_us = f->tuned_us;
+  return CWB_OK;
+}
+
 void cwb_fit_destroy(cwb_fit* f) {
   if (!f) return;
   hipSetDevice(f->device);
@@ -915,15 +1082,18 @@ void cwb_fit_destroy(cwb_fit* f) {
   delete f;
 }
 
+}  // extern "C"
+
 // ---- batches ----------------------------------------------------------------
 
+namespace cwb {
 namespace {
 
 struct BatchLayout {
   size_t fits, segs, blk, sel_off, partials, st, sel, val, total;
 };
 
-BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int n_val) {
+BatchLayout batch_layout(const SchedCap& S, int count, int n_st, int n_sel, int n_val) {
   BatchLayout L;
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -933,9 +1103,9 @@ BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int 
     return o;
   };
   L.fits = take((size_t)count * sizeof(FitDev));
-  L.segs = take(S.segs.size() * sizeof(Seg));
-  L.blk = take(S.blk.size() * 8);
-  L.sel_off = take(S.sel_off.size() * 8);
+  L.segs = take(S.segs * sizeof(Seg));
+  L.blk = take(S.blk * 8);
+  L.sel_off = take(S.sel_off * 8);
   L.partials = take((size_t)S.partial_words * 8);
   L.st = take((size_t)std::max(1, n_st) * sizeof(RowItem));
   L.sel = take((size_t)std::max(1, n_sel) * sizeof(SelItem));
@@ -944,44 +1114,139 @@ BatchLayout batch_layout(const Schedule& S, int count, int n_st, int n_sel, int 
   return L;
 }
 
-int batch_plan(cwb_fit* const* fits, int32_t count, Tune* t, Schedule* S, int* n_st, int* n_sel,
-               int* n_val) {
-  if (!fits || count < 1) return set_error(CWB_E_INVALID_ARG, "need at least one fit");
-  std::vector<const FitShape*> shapes;
-  int nb = 1, ns = 1, pmax = 1;
+void work_counts(const std::vector<const FitShape*>& shapes, int* n_st, int* n_sel, int* n_val) {
   *n_st = *n_sel = *n_val = 0;
+  for (const FitShape* sh : shapes) {
+    *n_st += sh->n_row_blocks;
+    *n_sel += sh->p;
+    *n_val += sh->n_val_blocks;
+  }
+}
+
+int batch_shapes(cwb_fit* const* fits, int32_t count, std::vector<const FitShape*>* shapes) {
+  if (!fits || count < 1) return set_error(CWB_E_INVALID_ARG, "need at least one fit");
   for (int i = 0; i < count; ++i) {
     if (!fits[i]) return set_error(CWB_E_INVALID_ARG, "null fit in batch");
     for (int j = 0; j < i; ++j)
       if (fits[j] == fits[i]) return set_error(CWB_E_INVALID_ARG, "fit listed twice in batch");
-    shapes.push_back(&fits[i]->shape);
-    nb = std::max(nb, fits[i]->shape.nb_stride);
-    ns = std::max(ns, fits[i]->shape.nsig_max);
-    pmax = std::max(pmax, fits[i]->shape.p);
-    *n_st += fits[i]->shape.n_row_blocks;
-    *n_sel += fits[i]->shape.p;
-    *n_val += fits[i]->shape.n_val_blocks;
+    shapes->push_back(&fits[i]->shape);
   }
-  *t = make_tune(nb, ns, pmax);
-  *S = build_schedule(shapes, *t);
-  std::string why;
-  if (!schedule_is_valid(*S, shapes, *t, &why))
-    return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+  return CWB_OK;
+}
+
+// Upload a schedule and the select work list that indexes its partials.
+int batch_install(cwb_batch* b, const Tune& t, Schedule&& S) {
+  std::vector<SelItem> sel;
+  for (size_t i = 0; i < b->fits.size(); ++i) {
+    cwb_fit* f = b->fits[i];
+    for (int k = 0; k < f->shape.p; ++k)
+      sel.push_back(make_sel_item((int)i, k, f->feat[k], f->dev, S, b->d_sel_off, sel.size()));
+  }
+  hipStream_t s = b->stream;
+  HIP_TRY(hipMemcpyAsync(b->d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->d_sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, s));
+  if (!sel.empty())
+    HIP_TRY(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  b->tune = t;
+  b->sched = std::move(S);
   return CWB_OK;
 }
 
 }  // namespace
 
+int batch_footprint(const std::vector<const FitShape*>& shapes, size_t* bytes, bool all) {
+  if (shapes.empty()) {
+    *bytes = 0;
+    return CWB_OK;
+  }
+  std::vector<Tune> cands;
+  SchedCap cap;
+  int rc = plan_candidates(shapes, all, &cands, &cap, nullptr);
+  if (rc) return rc;
+  int n_st, n_sel, n_val;
+  work_counts(shapes, &n_st, &n_sel, &n_val);
+  *bytes = batch_layout(cap, (int)shapes.size(), n_st, n_sel, n_val).total;
+  return CWB_OK;
+}
+
+int batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t ws_bytes, hipStream_t stream,
+                 bool autotune, cwb_batch** out) {
+  if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!dev_ws || reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+    return set_error(CWB_E_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+  std::vector<const FitShape*> shapes;
+  int rc = batch_shapes(fits, count, &shapes);
+  if (rc) return rc;
+  std::unique_ptr<cwb_batch> b(new cwb_batch());
+  std::vector<Tune> cands;
+  SchedCap cap;
+  Schedule first;
+  rc = plan_candidates(shapes, autotune, &cands, &cap, &first);
+  if (rc) return rc;
+  work_counts(shapes, &b->n_st, &b->n_sel, &b->n_val);
+  const BatchLayout L = batch_layout(cap, count, b->n_st, b->n_sel, b->n_val);
+  if (ws_bytes < L.total)
+    return set_error(CWB_E_NO_MEMORY, "batch workspace too small: need " + std::to_string(L.total));
+  HIP_TRY(hipGetDevice(&b->device));
+  for (int i = 0; i < count; ++i)
+    if (fits[i]->device != b->device) return set_error(CWB_E_INVALID_ARG, "fits on different devices");
+  b->stream = stream;
+  b->ws = reinterpret_cast<char*>(dev_ws);
+  b->ws_bytes = ws_bytes;
+  b->fits.assign(fits, fits + count);
+  b->n_cands = (int)cands.size();
+  std::vector<FitDev> fd(count);
+  std::vector<RowItem> st;
+  std::vector<StateItem> val;
+  for (int i = 0; i < count; ++i) {
+    fd[i] = fits[i]->dev;
+    b->nb_max = std::max(b->nb_max, fits[i]->shape.nb_max);
+    b->d_max = std::max(b->d_max, fits[i]->shape.d_max);
+    if (fits[i]->shape.variant == CWB_HCWB) b->any_hcwb = true;
+    for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back(make_row_item(i, r, fits[i]->dev));
+    for (int r = 0; r < fits[i]->shape.n_val_blocks; ++r) val.push_back({i, r});
+  }
+  char* ws = b->ws;
+  hipStream_t s = b->stream;
+  b->d_fits = dptr<FitDev>(ws, L.fits);
+  b->d_segs = dptr<Seg>(ws, L.segs);
+  b->d_blk = dptr<int64_t>(ws, L.blk);
+  b->d_sel_off = dptr<int64_t>(ws, L.sel_off);
+  b->d_partials = dptr<long long>(ws, L.partials);
+  b->d_st = dptr<RowItem>(ws, L.st);
+  b->d_sel = dptr<SelItem>(ws, L.sel);
+  b->d_val = dptr<StateItem>(ws, L.val);
+  HIP_TRY(hipMemcpyAsync(b->d_fits, fd.data(), fd.size() * sizeof(FitDev), hipMemcpyHostToDevice, s));
+  if (!st.empty()) HIP_TRY(hipMemcpyAsync(b->d_st, st.data(), st.size() * sizeof(RowItem), hipMemcpyHostToDevice, s));
+  if (!val.empty()) HIP_TRY(hipMemcpyAsync(b->d_val, val.data(), val.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
+  rc = batch_install(b.get(), cands[0], std::move(first));
+  if (rc) return rc;
+  if (cands.size() > 1) {
+    int best = 0;
+    rc = autotune_hist(s, b->d_fits, shapes, cands, cap, b->d_segs, b->d_blk, b->d_partials, &best,
+                       &b->tuned_us);
+    if (rc) return rc;
+    rc = batch_install(b.get(), cands[best], build_schedule(shapes, cands[best]));
+    if (rc) return rc;
+  }
+  *out = b.release();
+  return CWB_OK;
+}
+
+}  // namespace cwb
+
+extern "C" {
+
 int cwb_batch_workspace_bytes(cwb_fit* const* fits, int32_t count, size_t* bytes) {
   try {
     if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
-    Tune t;
-    Schedule S;
-    int n_st, n_sel, n_val;
-    int rc = batch_plan(fits, count, &t, &S, &n_st, &n_sel, &n_val);
+    std::vector<const FitShape*> shapes;
+    int rc = batch_shapes(fits, count, &shapes);
     if (rc) return rc;
-    *bytes = batch_layout(S, count, n_st, n_sel, n_val).total;
-    return CWB_OK;
+    return batch_footprint(shapes, bytes, true);
   } catch (const std::bad_alloc&) {
     return set_error(CWB_E_NO_MEMORY, "host allocation failed");
   }
@@ -990,59 +1255,7 @@ int cwb_batch_workspace_bytes(cwb_fit* const* fits, int32_t count, size_t* bytes
 int cwb_batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t ws_bytes, void* stream,
                      cwb_batch** out) {
   try {
-    if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
-    *out = nullptr;
-    if (!dev_ws || reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
-      return set_error(CWB_E_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
-    std::unique_ptr<cwb_batch> b(new cwb_batch());
-    int rc = batch_plan(fits, count, &b->tune, &b->sched, &b->n_st, &b->n_sel, &b->n_val);
-    if (rc) return rc;
-    const BatchLayout L = batch_layout(b->sched, count, b->n_st, b->n_sel, b->n_val);
-    if (ws_bytes < L.total)
-      return set_error(CWB_E_NO_MEMORY, "batch workspace too small: need " + std::to_string(L.total));
-    HIP_TRY(hipGetDevice(&b->device));
-    for (int i = 0; i < count; ++i)
-      if (fits[i]->device != b->device) return set_error(CWB_E_INVALID_ARG, "fits on different devices");
-    b->stream = reinterpret_cast<hipStream_t>(stream);
-    b->ws = reinterpret_cast<char*>(dev_ws);
-    b->ws_bytes = ws_bytes;
-    b->fits.assign(fits, fits + count);
-    std::vector<FitDev> fd(count);
-    std::vector<RowItem> st;
-    std::vector<SelItem> sel;
-    std::vector<StateItem> val;
-    for (int i = 0; i < count; ++i) {
-      fd[i] = fits[i]->dev;
-      b->nb_max = std::max(b->nb_max, fits[i]->shape.nb_max);
-      b->d_max = std::max(b->d_max, fits[i]->shape.d_max);
-      if (fits[i]->shape.variant == CWB_HCWB) b->any_hcwb = true;
-      for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back(make_row_item(i, r, fits[i]->dev));
-      for (int k = 0; k < fits[i]->shape.p; ++k)
-        sel.push_back(make_sel_item(i, k, fits[i]->feat[k], fits[i]->dev, b->sched,
-                                    dptr<int64_t>(b->ws, L.sel_off), sel.size()));
-      for (int r = 0; r < fits[i]->shape.n_val_blocks; ++r) val.push_back({i, r});
-    }
-    char* ws = b->ws;
-    hipStream_t s = b->stream;
-    b->d_fits = dptr<FitDev>(ws, L.fits);
-    b->d_segs = dptr<Seg>(ws, L.segs);
-    b->d_blk = dptr<int64_t>(ws, L.blk);
-    b->d_sel_off = dptr<int64_t>(ws, L.sel_off);
-    b->d_partials = dptr<long long>(ws, L.partials);
-    b->d_st = dptr<RowItem>(ws, L.st);
-    b->d_sel = dptr<SelItem>(ws, L.sel);
-    b->d_val = dptr<StateItem>(ws, L.val);
-    const Schedule& S = b->sched;
-    HIP_TRY(hipMemcpyAsync(b->d_fits, fd.data(), fd.size() * sizeof(FitDev), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->d_sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, s));
-    if (!st.empty()) HIP_TRY(hipMemcpyAsync(b->d_st, st.data(), st.size() * sizeof(RowItem), hipMemcpyHostToDevice, s));
-    if (!sel.empty()) HIP_TRY(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, s));
-    if (!val.empty()) HIP_TRY(hipMemcpyAsync(b->d_val, val.data(), val.size() * sizeof(StateItem), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    *out = b.release();
-    return CWB_OK;
+    return batch_create(fits, count, dev_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), true, out);
   } catch (const std::bad_alloc&) {
     return set_error(CWB_E_NO_MEMORY, "host allocation failed");
   }
@@ -1054,14 +1267,62 @@ int cwb_batch_run(cwb_batch* b, int32_t iters) {
   HIP_TRY(hipSetDevice(b->device));
   int most = 0;
   for (cwb_fit* f : b->fits) most = std::max(most, std::min(iters, f->shape.M - f->iters));
-  for (int i = 0; i < most; ++i) {
-    int rc = enqueue_iteration(b->stream, b->d_fits, (int)b->fits.size(), b->sched, b->tune, b->d_st, b->n_st, b->d_sel,
-                               b->n_sel, b->d_val, b->any_hcwb ? b->n_val : 0, b->nb_max,
-                               b->d_max, b->d_segs,
-                               b->d_blk, b->d_sel_off, b->d_partials, nullptr);
+  auto eager = [&]() {
+    return enqueue_iteration(b->stream, b->d_fits, (int)b->fits.size(), b->sched, b->tune, b->d_st,
+                             b->n_st, b->d_sel, b->n_sel, b->d_val, b->any_hcwb ? b->n_val : 0,
+                             b->nb_max, b->d_max, b->d_segs, b->d_blk, b->d_sel_off,
+                             b->d_partials, nullptr);
+  };
+  int i = 0;
+  // The first iteration runs eagerly; after it, chunks of kGraphIters
+  // iterations replay one captured graph.  Every kernel reads its iteration
+  // from the fits' control blocks, so one graph serves every chunk.
+  const bool graphs = b->stream != nullptr && env_int("CWB_GRAPH", 1) != 0;
+  if (graphs && !b->graph_exec && most > kGraphIters && b->eager_iters == 0) {
+    int rc = eager();
     if (rc) return rc;
+    ++i;
+    ++b->eager_iters;
+  }
+  while (graphs && most - i >= kGraphIters && b->eager_iters > 0) {
+    if (!b->graph_exec) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+      int rc = CWB_OK;
+      for (int c = 0; c < kGraphIters && !rc; ++c) rc = eager();
+      const hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return set_error(CWB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      const hipError_t e2 = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) {
+        b->graph_exec = nullptr;
+        return set_error(CWB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+      }
+    }
+    HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
+    i += kGraphIters;
+    b->graph_launches += 1;
+  }
+  for (; i < most; ++i) {
+    int rc = eager();
+    if (rc) return rc;
+    ++b->eager_iters;
   }
   for (cwb_fit* f : b->fits) f->iters += std::min(most, f->shape.M - f->iters);
+  return CWB_OK;
+}
+
+int cwb_batch_tile(const cwb_batch* b, cwb_tile* out) {
+  if (!b || !out) return set_error(CWB_E_INVALID_ARG, "null argument");
+  out->threads = b->tune.nt;
+  out->learners = b->tune.F;
+  out->blocks = b->sched.blocks;
+  out->candidates = b->n_cands;
+  out->tuned_us = b->tuned_us;
   return CWB_OK;
 }
 
@@ -1080,6 +1341,7 @@ void cwb_batch_destroy(cwb_batch* b) {
   if (!b) return;
   hipSetDevice(b->device);
   hipStreamSynchronize(b->stream);
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
   delete b;
 }
 

@@ -12,6 +12,8 @@
 
 namespace cwb {
 
+constexpr int kGraphIters = 8;  // iterations per captured batch graph
+
 // Sizes of a fit, known before the (expensive) setup.
 struct FitShape {
   int64_t n = 0, n_pad = 0, n_train = 0;
@@ -66,7 +68,17 @@ struct Layout {
   size_t total;
 };
 
-Layout make_layout(const FitShape& sh, const Schedule& s);
+// Largest schedule arrays over the tile shapes a fit or batch may use: the
+// workspace is sized for all of them, so the autotuner can try each.
+struct SchedCap {
+  size_t segs = 0, blk = 0, sel_off = 0;
+  int64_t partial_words = 0;
+  void add(const Schedule& S);
+};
+
+std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool all);
+
+Layout make_layout(const FitShape& sh, const SchedCap& s);
 
 struct KernelTimer {
   std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -96,6 +108,8 @@ struct cwb_fit {
   int n_st = 0, n_sel = 0, n_val = 0;
   int timing = 0;  // bit set: 1 hist, 2 state, 4 select
   cwb::KernelTimer t_hist, t_state, t_select;
+  int n_cands = 1;        // tile shapes considered
+  double tuned_us = 0.0;  // histogram pass time of the chosen shape (0: not tuned)
 };
 
 struct cwb_batch {
@@ -118,6 +132,10 @@ struct cwb_batch {
   cwb::SelItem* d_sel = nullptr;
   cwb::StateItem* d_val = nullptr;
   int n_st = 0, n_sel = 0, n_val = 0;
+  int n_cands = 1;
+  double tuned_us = 0.0;
+  hipGraphExec_t graph_exec = nullptr;  // kGraphIters captured iterations
+  int64_t eager_iters = 0, graph_launches = 0;
 };
 
 namespace cwb {
@@ -127,4 +145,29 @@ int finalize_fit(cwb_fit* f);
 RowItem make_row_item(int fit, int blk, const FitDev& D);
 SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const Schedule& S,
                       const int64_t* d_sel_off, size_t idx);
+// Every candidate tile shape for these fits (only the default unless `all`),
+// its schedules validated; `cap` receives the largest schedule arrays and
+// `first` (if not null) the default schedule.
+int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::vector<Tune>* cands,
+                    SchedCap* cap, Schedule* first);
+// Time the histogram pass of each candidate on the fits' current data and
+// return the index of the fastest.  The pass only reads the model state and
+// writes the histogram partials (exact integer sums), so trying candidates
+// changes no result.
+int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const FitShape*>& shapes,
+                  const std::vector<Tune>& cands, const SchedCap& cap, Seg* d_segs, int64_t* d_blk,
+                  long long* d_part, int* best, double* best_us);
+// Device bytes of a fit of this shape (its workspace layout, sized for every
+// candidate tile shape when `all`).
+int fit_footprint(const FitShape& sh, size_t* bytes, bool all);
+// Upload a fit whose host setup is done into `dev_ws` on `stream`, autotune
+// its histogram tiles if asked, and wait; the new fit enqueues its
+// iterations on the same stream.
+int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
+               bool autotune, cwb_fit** out);
+// Device bytes of the batch workspace (combined schedule, partials, work
+// lists) for fits of these shapes; 0 for none.
+int batch_footprint(const std::vector<const FitShape*>& shapes, size_t* bytes, bool all);
+int batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t ws_bytes, hipStream_t stream,
+                 bool autotune, cwb_batch** out);
 }  // namespace cwb

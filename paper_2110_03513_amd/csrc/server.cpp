@@ -1,21 +1,579 @@
-// server.cpp -- continuous-batching fit server (see cwb.h).
+// server.cpp -- continuous-batching fit server.
+//
+// Requests flow through four stages:
+//   submit    the request is queued for setup (the caller's arrays are read
+//             in place, so they stay valid until its result is polled);
+//   setup     host threads run the FP64 setup (binning, bases, Grams,
+//             smoothing parameters) and compute the device footprint;
+//   admission the device thread admits set-up requests in arrival order while
+//             the arena holds their workspace and the batch workspace of the
+//             grown set, and a slot is free;
+//   run       all admitted fits advance together, `quantum` iterations per
+//             round (one launch per kernel per iteration covers every fit);
+//             finished fits retire at the end of a round: their results are
+//             copied to the host and their arena space is released.
+// Uploads of newly admitted fits go through a second stream, so they overlap
+// the round that is running; the fits join the batch in the next round.
+// A fit's result does not depend on which other fits share its rounds: the
+// histograms are exact integer sums and every selection is per fit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+
 #include "runtime.h"
+
+namespace cwb {
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) in 256-byte units; neighbouring free
+// ranges are merged on release.
+class Arena {
+ public:
+  void reset(size_t bytes) {
+    free_.clear();
+    size_ = bytes / 256 * 256;
+    if (size_) free_[0] = size_;
+    in_use = peak = 0;
+  }
+  size_t size() const { return size_; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = std::max<size_t>(256, (bytes + 255) / 256 * 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      in_use += bytes;
+      peak = std::max(peak, in_use);
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = std::max<size_t>(256, (bytes + 255) / 256 * 256);
+    in_use -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t in_use = 0, peak = 0;
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0;
+};
+
+enum class Stage { kQueued, kSetup, kReady, kAdmitted, kRunning, kDone };
+
+struct Request {
+  uint64_t ticket = 0;
+  Stage stage = Stage::kQueued;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  // the problem (caller-owned arrays, copied specifications)
+  cwb_problem pr;
+  std::vector<cwb_learner_spec> specs;
+  double setup_s = 0;
+  // setup result, dropped after upload
+  FitShape shape;
+  HostFit hf;
+  size_t footprint = 0;
+  // device residency
+  cwb_fit* fit = nullptr;
+  size_t off = 0;
+  // result
+  int status = CWB_OK;
+  std::string err;
+  int M = 0;
+  double intercept = 0;
+  std::vector<float> pred;
+  std::vector<int32_t> k;
+};
+
+}  // namespace
+}  // namespace cwb
 
 using namespace cwb;
 
+struct cwb_server {
+  cwb_server_cfg cfg;
+  int device = 0;
+  hipStream_t stream = nullptr;   // rounds
+  hipStream_t upload = nullptr;   // uploads of admitted fits
+  char* base = nullptr;
+
+  std::mutex mu;
+  std::condition_variable cv_setup, cv_dev;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;  // every request not yet polled
+  std::deque<Request*> setup_q;
+  std::deque<Request*> ready_q;
+  Arena arena;
+  int64_t submitted = 0, completed = 0, rejected = 0;
+  int32_t in_flight = 0;
+  double t_first = -1.0, t_last_done = 0.0;
+  double sum_setup_s = 0.0, sum_queue_s = 0.0;
+  std::vector<double> latencies;
+
+  // device thread only
+  std::vector<Request*> active;
+  cwb_batch* batch = nullptr;
+  size_t batch_off = 0, batch_bytes = 0;
+
+  std::vector<std::thread> workers;
+  std::thread dev;
+};
+
+namespace {
+
+// Mark a request finished (lock held).
+void finish_locked(cwb_server* s, Request* r, int status, const std::string& err) {
+  r->status = status;
+  r->err = err;
+  r->stage = Stage::kDone;
+  r->t_done = now_s();
+  r->hf = HostFit();
+  if (status == CWB_OK) {
+    s->completed += 1;
+    s->latencies.push_back(r->t_done - r->t_submit);
+    s->t_last_done = r->t_done;
+    s->sum_setup_s += r->setup_s;
+    s->sum_queue_s += r->t_admit > 0 ? r->t_admit - r->t_submit : 0.0;
+  } else {
+    s->rejected += 1;
+  }
+}
+
+void setup_worker(cwb_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_setup.wait(lk, [&] { return s->stop || !s->setup_q.empty(); });
+      if (s->setup_q.empty()) return;  // stopping
+      r = s->setup_q.front();
+      s->setup_q.pop_front();
+      r->stage = Stage::kSetup;
+    }
+    std::string err;
+    int rc = CWB_OK;
+    size_t fp = 0;
+    const double t0 = now_s();
+    try {
+      rc = shape_from_problem(&r->pr, &r->shape, &err);
+      if (!rc) rc = build_host_fit(&r->pr, &r->hf, &err);
+      if (!rc) {
+        rc = fit_footprint(r->shape, &fp, false);
+        if (rc) err = cwb_last_error();
+      }
+    } catch (const std::bad_alloc&) {
+      rc = CWB_E_NO_MEMORY;
+      err = "host allocation failed during setup";
+    } catch (...) {
+      rc = CWB_E_INVALID_ARG;
+      err = "unexpected error during setup";
+    }
+    r->setup_s = now_s() - t0;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!rc) {
+      size_t bb = 0;
+      std::vector<const FitShape*> one{&r->shape};
+      if (batch_footprint(one, &bb, false) || fp + bb + 512 > s->arena.size()) {
+        rc = CWB_E_NO_MEMORY;
+        err = "request needs " + std::to_string(fp + bb) + " device bytes, arena holds " +
+              std::to_string(s->arena.size());
+      }
+    }
+    if (rc) {
+      finish_locked(s, r, rc, err);
+      continue;
+    }
+    r->footprint = fp;
+    r->stage = Stage::kReady;
+    s->ready_q.push_back(r);
+    s->cv_dev.notify_one();
+  }
+}
+
+// Retire a fit whose iterations are done (device thread; the round's stream
+// is idle).  Returns the request's status.
+int retire(cwb_server* s, Request* r) {
+  cwb_fit* f = r->fit;
+  std::string err;
+  int rc = cwb_fit_sync(f);
+  if (!rc) {
+    r->M = f->shape.M;
+    r->k.resize((size_t)r->M);
+    rc = cwb_fit_get_trace(f, r->k.data(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr);
+  }
+  if (!rc) {
+    r->pred.resize((size_t)f->shape.n);
+    rc = cwb_fit_get_pred(f, r->pred.data());
+  }
+  if (rc) err = cwb_last_error();
+  r->intercept = f->f0;
+  cwb_fit_destroy(f);
+  r->fit = nullptr;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->arena.release(r->off, r->footprint);
+  s->in_flight -= 1;
+  finish_locked(s, r, rc, err);
+  return rc;
+}
+
+// Drop a fit from the device after an error (device thread).
+void fail_fit(cwb_server* s, Request* r, int status, const std::string& err) {
+  if (r->fit) cwb_fit_destroy(r->fit);
+  r->fit = nullptr;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->arena.release(r->off, r->footprint);
+  s->in_flight -= 1;
+  finish_locked(s, r, status, err);
+}
+
+// Replace the batch by one over the active fits.  The old batch is never run
+// again once a fit it covers has retired, so it is destroyed first.  The new
+// batch workspace comes from `reserved` when the admission step set space
+// aside, else from a fresh allocation.
+void rebuild_batch(cwb_server* s, bool have_res, size_t res_off, size_t res_bytes) {
+  if (s->batch) {
+    cwb_batch_destroy(s->batch);
+    s->batch = nullptr;
+  }
+  std::vector<const FitShape*> shapes;
+  std::vector<cwb_fit*> fits;
+  for (Request* r : s->active) {
+    shapes.push_back(&r->fit->shape);
+    fits.push_back(r->fit);
+  }
+  size_t need = 0;
+  int rc = fits.empty() ? CWB_OK : batch_footprint(shapes, &need, false);
+  size_t off = 0;
+  bool ok = false;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->batch_bytes) s->arena.release(s->batch_off, s->batch_bytes);
+    s->batch_bytes = 0;
+    if (have_res && (rc || fits.empty() || need > res_bytes)) {
+      s->arena.release(res_off, res_bytes);
+      have_res = false;
+    }
+    if (!rc && !fits.empty()) {
+      if (have_res) {
+        off = res_off;
+        need = res_bytes;
+        ok = true;
+      } else {
+        ok = s->arena.alloc(need, &off);
+      }
+      if (ok) {
+        s->batch_off = off;
+        s->batch_bytes = need;
+      }
+    }
+  }
+  if (fits.empty()) return;
+  std::string err;
+  if (rc) {
+    err = cwb_last_error();
+  } else if (!ok) {
+    rc = CWB_E_NO_MEMORY;
+    err = "no arena space for the batch workspace";
+  } else {
+    rc = batch_create(fits.data(), (int32_t)fits.size(), s->base + off, need, s->stream, false, &s->batch);
+    if (rc) err = cwb_last_error();
+  }
+  if (rc) {  // the active fits cannot run: report the failure on each
+    for (Request* r : s->active) fail_fit(s, r, rc, err);
+    s->active.clear();
+  }
+}
+
+void device_loop(cwb_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    // 1. admission, in arrival order, while slots and arena space last; the
+    //    batch workspace of the grown set is reserved at the same time
+    std::vector<Request*> admit;
+    size_t res_off = 0, res_bytes = 0;
+    bool have_res = false;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_dev.wait(lk, [&] { return s->stop || !s->ready_q.empty() || !s->active.empty(); });
+      if (s->stop && s->active.empty()) break;
+      std::vector<const FitShape*> shapes;
+      for (Request* r : s->active) shapes.push_back(&r->fit->shape);
+      while (!s->stop && !s->ready_q.empty() &&
+             (int)(s->active.size() + admit.size()) < s->cfg.max_slots) {
+        Request* r = s->ready_q.front();
+        shapes.push_back(&r->shape);
+        size_t bb = 0, off = 0, boff = 0;
+        bool ok = !batch_footprint(shapes, &bb, false) && s->arena.alloc(r->footprint, &off);
+        if (ok && !s->arena.alloc(bb, &boff)) {
+          s->arena.release(off, r->footprint);
+          ok = false;
+        }
+        if (!ok) {
+          shapes.pop_back();
+          break;  // first come, first served: later requests wait too
+        }
+        if (have_res) s->arena.release(res_off, res_bytes);
+        res_off = boff;
+        res_bytes = bb;
+        have_res = true;
+        r->off = off;
+        r->stage = Stage::kAdmitted;
+        r->t_admit = now_s();
+        s->in_flight += 1;
+        s->ready_q.pop_front();
+        admit.push_back(r);
+      }
+    }
+    // 2. one round of the current batch, enqueued before the uploads so
+    //    that the copies overlap it
+    int32_t q = 0;
+    if (s->batch && !s->active.empty()) {
+      q = s->cfg.quantum;
+      for (Request* r : s->active) q = std::min(q, r->fit->shape.M - r->fit->iters);
+      q = std::max(q, 1);
+      if (cwb_batch_run(s->batch, q)) {
+        const std::string e = cwb_last_error();
+        for (Request* r : s->active) r->status = CWB_E_DEVICE, r->err = e;
+      }
+    }
+    // 3. uploads of the admitted fits
+    std::vector<Request*> joined;
+    for (Request* r : admit) {
+      cwb_fit* f = nullptr;
+      int rc = CWB_OK;
+      try {
+        rc = fit_upload(r->shape, r->hf, s->base + r->off, r->footprint, s->upload, false, &f);
+      } catch (const std::bad_alloc&) {
+        rc = set_error(CWB_E_NO_MEMORY, "host allocation failed during upload");
+      }
+      r->hf = HostFit();
+      if (rc) {
+        fail_fit(s, r, rc, cwb_last_error());
+        continue;
+      }
+      f->stream = s->stream;
+      r->fit = f;
+      std::lock_guard<std::mutex> lk(s->mu);
+      r->stage = Stage::kRunning;
+      joined.push_back(r);
+    }
+    // 4. end of the round: retire finished or failed fits
+    if (q > 0) (void)hipStreamSynchronize(s->stream);
+    bool changed = !joined.empty();
+    std::vector<Request*> keep;
+    for (Request* r : s->active) {
+      if (r->status != CWB_OK) {
+        fail_fit(s, r, r->status, r->err);
+        changed = true;
+      } else if (r->fit->iters >= r->fit->shape.M) {
+        retire(s, r);
+        changed = true;
+      } else {
+        keep.push_back(r);
+      }
+    }
+    s->active.swap(keep);
+    for (Request* r : joined) s->active.push_back(r);
+    // 5. a new batch whenever the membership changed
+    if (changed) {
+      rebuild_batch(s, have_res, res_off, res_bytes);
+    } else if (have_res) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->arena.release(res_off, res_bytes);
+    }
+  }
+  if (s->batch) {
+    cwb_batch_destroy(s->batch);
+    s->batch = nullptr;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->batch_bytes) s->arena.release(s->batch_off, s->batch_bytes);
+  s->batch_bytes = 0;
+}
+
+}  // namespace
+
 extern "C" {
-int cwb_server_create(const cwb_server_cfg*, cwb_server** out) {
-  if (out) *out = nullptr;
-  return set_error(CWB_E_UNSUPPORTED, "server not built yet");
+
+int cwb_server_create(const cwb_server_cfg* cfg, cwb_server** out) {
+  if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!cfg) return set_error(CWB_E_INVALID_ARG, "null configuration");
+  if (!cfg->arena || reinterpret_cast<uintptr_t>(cfg->arena) % 256 != 0)
+    return set_error(CWB_E_INVALID_ARG, "arena must be non-null and 256-byte aligned");
+  if (cfg->arena_bytes < (1u << 20)) return set_error(CWB_E_INVALID_ARG, "arena below 1 MiB");
+  if (cfg->max_slots < 1 || cfg->max_slots > 4096)
+    return set_error(CWB_E_INVALID_ARG, "max_slots must be 1..4096");
+  if (cfg->quantum < 1) return set_error(CWB_E_INVALID_ARG, "quantum must be >= 1");
+  if (cfg->setup_threads < 0 || cfg->setup_threads > 64)
+    return set_error(CWB_E_INVALID_ARG, "setup_threads must be 0..64");
+  try {
+    std::unique_ptr<cwb_server> s(new cwb_server());
+    s->cfg = *cfg;
+    s->base = static_cast<char*>(cfg->arena);
+    s->stream = static_cast<hipStream_t>(cfg->stream);
+    s->arena.reset(cfg->arena_bytes);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking);
+    if (e != hipSuccess) return set_error(CWB_E_DEVICE, std::string("server streams: ") + hipGetErrorString(e));
+    const int nw = cfg->setup_threads > 0 ? cfg->setup_threads : 4;
+    cwb_server* sp = s.get();
+    for (int i = 0; i < nw; ++i) s->workers.emplace_back(setup_worker, sp);
+    s->dev = std::thread(device_loop, sp);
+    *out = s.release();
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return set_error(CWB_E_INVALID_ARG, ex.what());
+  }
 }
-int cwb_server_submit(cwb_server*, const cwb_problem*, uint64_t*) {
-  return set_error(CWB_E_UNSUPPORTED, "server not built yet");
+
+int cwb_server_submit(cwb_server* s, const cwb_problem* pr, uint64_t* ticket) {
+  if (!s || !pr || !ticket) return set_error(CWB_E_INVALID_ARG, "null argument");
+  if (!pr->x || !pr->y || !pr->specs) return set_error(CWB_E_INVALID_ARG, "null problem array");
+  FitShape sh;
+  std::string err;
+  int rc = shape_from_problem(pr, &sh, &err);
+  if (rc) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->rejected += 1;
+    return set_error(rc, err);
+  }
+  try {
+    std::unique_ptr<Request> r(new Request());
+    r->specs.assign(pr->specs, pr->specs + pr->p);
+    r->pr = *pr;  // x, y and val_mask stay the caller's until the result is polled
+    r->pr.specs = r->specs.data();
+    r->t_submit = now_s();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return set_error(CWB_E_STATE, "server is stopping");
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    if (s->t_first < 0) s->t_first = r->t_submit;
+    s->submitted += 1;
+    s->setup_q.push_back(r.get());
+    s->reqs.emplace(r->ticket, std::move(r));
+    s->cv_setup.notify_one();
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed copying the request");
+  }
 }
-int cwb_server_poll(cwb_server*, uint64_t, cwb_result*, float*, int32_t*) {
-  return set_error(CWB_E_UNSUPPORTED, "server not built yet");
+
+int cwb_server_poll(cwb_server* s, uint64_t ticket, cwb_result* res, float* pred_out, int32_t* k_out) {
+  if (!s || !res) return set_error(CWB_E_INVALID_ARG, "null argument");
+  std::unique_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return set_error(CWB_E_INVALID_ARG, "unknown ticket (or already collected)");
+    if (it->second->stage != Stage::kDone) return CWB_E_AGAIN;
+    r = std::move(it->second);
+    s->reqs.erase(it);
+  }
+  std::memset(res, 0, sizeof(*res));
+  res->status = r->status;
+  res->M = r->M;
+  res->latency_s = r->t_done - r->t_submit;
+  res->queue_s = r->t_admit > 0 ? r->t_admit - r->t_submit : 0.0;
+  res->intercept = r->intercept;
+  if (r->status == CWB_OK) {
+    if (pred_out && !r->pred.empty()) std::memcpy(pred_out, r->pred.data(), r->pred.size() * 4);
+    if (k_out && !r->k.empty()) std::memcpy(k_out, r->k.data(), r->k.size() * 4);
+    return CWB_OK;
+  }
+  set_error(r->status, r->err);
+  return CWB_OK;
 }
-int cwb_server_stats(cwb_server*, cwb_stats*) {
-  return set_error(CWB_E_UNSUPPORTED, "server not built yet");
+
+int cwb_server_stats(cwb_server* s, cwb_stats* st) {
+  if (!s || !st) return set_error(CWB_E_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(st, 0, sizeof(*st));
+  st->submitted = s->submitted;
+  st->completed = s->completed;
+  st->rejected = s->rejected;
+  st->in_flight = s->in_flight;
+  st->queued = (int32_t)(s->setup_q.size() + s->ready_q.size());
+  const double span = s->t_last_done - s->t_first;
+  st->fits_per_s = (s->completed > 0 && span > 0) ? (double)s->completed / span : 0.0;
+  if (!s->latencies.empty()) {
+    std::vector<double> v = s->latencies;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double q) {
+      const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::ceil(q * v.size()) - 1);
+      return v[i];
+    };
+    st->p50_latency_s = pct(0.50);
+    st->p99_latency_s = pct(0.99);
+  }
+  st->arena_in_use = s->arena.in_use;
+  st->arena_peak = s->arena.peak;
+  if (s->completed > 0) {
+    st->mean_setup_s = s->sum_setup_s / (double)s->completed;
+    st->mean_queue_s = s->sum_queue_s / (double)s->completed;
+  }
+  return CWB_OK;
 }
-void cwb_server_destroy(cwb_server*) {}
+
+void cwb_server_destroy(cwb_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    // requests not yet admitted are cancelled
+    for (Request* r : s->setup_q) finish_locked(s, r, CWB_E_STATE, "server stopped");
+    s->setup_q.clear();
+    for (Request* r : s->ready_q) finish_locked(s, r, CWB_E_STATE, "server stopped");
+    s->ready_q.clear();
+  }
+  s->cv_setup.notify_all();
+  s->cv_dev.notify_all();
+  for (auto& t : s->workers) t.join();
+  // a worker may have queued a request after the cancellation above
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Request* r : s->ready_q) finish_locked(s, r, CWB_E_STATE, "server stopped");
+    s->ready_q.clear();
+  }
+  s->cv_dev.notify_all();
+  if (s->dev.joinable()) s->dev.join();
+  if (s->upload) (void)hipStreamDestroy(s->upload);
+  delete s;
 }
+
+}  // extern "C"

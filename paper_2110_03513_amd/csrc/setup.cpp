@@ -296,6 +296,7 @@ int validate_problem(const cwb_problem* pr, std::string* err) {
   if (pr->n < 2) { *err = "n must be >= 2"; return CWB_E_INVALID_ARG; }
   if (pr->p < 1) { *err = "p must be >= 1"; return CWB_E_INVALID_ARG; }
   if (!pr->x || !pr->y || !pr->specs) { *err = "null x, y or specs"; return CWB_E_INVALID_ARG; }
+  if (pr->ldx != 0 && pr->ldx < pr->n) { *err = "ldx must be 0 or at least n"; return CWB_E_INVALID_ARG; }
   if (!(pr->nu > 0.0) || !std::isfinite(pr->nu)) { *err = "nu must be > 0"; return CWB_E_INVALID_ARG; }
   if (pr->M < 1) { *err = "M must be >= 1"; return CWB_E_INVALID_ARG; }
   if (pr->loss != CWB_L2 && pr->loss != CWB_BINOMIAL) { *err = "unknown loss"; return CWB_E_INVALID_ARG; }
@@ -389,7 +390,7 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
       const int j = next.fetch_add(1);
       if (j >= p) break;
       const cwb_learner_spec& s = pr->specs[j];
-      const double* xj = pr->x + (size_t)j * n;
+      const double* xj = pr->x + (size_t)j * (size_t)(pr->ldx ? pr->ldx : n);
       HostLearner& L = hf->L[j];
       uint16_t* Xj = hf->X.data() + (size_t)j * hf->n_pad;
       L.kind = s.kind;

@@ -38,13 +38,18 @@ class cwb_problem(C.Structure):
                 ("y", C.POINTER(C.c_double)), ("loss", C.c_int32),
                 ("specs", C.POINTER(cwb_learner_spec)), ("nu", C.c_double), ("M", C.c_int32),
                 ("variant", C.c_int32), ("gamma", C.c_double), ("patience", C.c_int32),
-                ("val_mask", C.POINTER(C.c_uint8))]
+                ("val_mask", C.POINTER(C.c_uint8)), ("ldx", C.c_int64)]
 
 
 class cwb_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("p", C.c_int32), ("M", C.c_int32), ("d_max", C.c_int32),
                 ("sum_d", C.c_int32), ("nb_max", C.c_int32), ("iters_done", C.c_int32),
                 ("n_train", C.c_int64), ("f0", C.c_double)]
+
+
+class cwb_tile(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("learners", C.c_int32), ("blocks", C.c_int32),
+                ("candidates", C.c_int32), ("tuned_us", C.c_double)]
 
 
 class cwb_server_cfg(C.Structure):
@@ -61,7 +66,8 @@ class cwb_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
                 ("in_flight", C.c_int32), ("queued", C.c_int32), ("fits_per_s", C.c_double),
                 ("p50_latency_s", C.c_double), ("p99_latency_s", C.c_double),
-                ("arena_in_use", C.c_size_t), ("arena_peak", C.c_size_t)]
+                ("arena_in_use", C.c_size_t), ("arena_peak", C.c_size_t),
+                ("mean_setup_s", C.c_double), ("mean_queue_s", C.c_double)]
 
 
 _P = C.c_void_p
@@ -88,6 +94,8 @@ _SIGNATURES = {
     "cwb_batch_run": [_P, C.c_int32],
     "cwb_batch_sync": [_P],
     "cwb_batch_destroy": [_P],
+    "cwb_fit_tile": [_P, C.POINTER(cwb_tile)],
+    "cwb_batch_tile": [_P, C.POINTER(cwb_tile)],
     "cwb_server_create": [C.POINTER(cwb_server_cfg), C.POINTER(_P)],
     "cwb_server_submit": [_P, C.POINTER(cwb_problem), C.POINTER(C.c_uint64)],
     "cwb_server_poll": [_P, C.c_uint64, C.POINTER(cwb_result), _P, _P],
@@ -136,7 +144,12 @@ class Problem:
     def __init__(self, prob: dict):
         x = np.asarray(prob["x"], dtype=np.float64)
         n, p = x.shape
-        self.x = np.asfortranarray(x)
+        # column-major views with a column stride (e.g. leading rows and
+        # columns of a larger column-major matrix) are passed without a copy
+        if x.strides[0] == 8 and x.strides[1] % 8 == 0 and x.strides[1] // 8 >= n:
+            self.x, ldx = x, x.strides[1] // 8
+        else:
+            self.x, ldx = np.asfortranarray(x), n
         self.y = np.ascontiguousarray(prob["y"], dtype=np.float64)
         vm = prob.get("val_mask")
         self.vm = None if vm is None else np.ascontiguousarray(vm, dtype=np.uint8)
@@ -159,7 +172,8 @@ class Problem:
             specs=C.cast(specs, C.POINTER(cwb_learner_spec)), nu=float(prob["nu"]),
             M=int(prob["M"]), variant=VARIANTS[prob.get("variant", "cwb")],
             gamma=float(prob.get("gamma", 0.0)), patience=int(prob.get("patience", 5)),
-            val_mask=None if self.vm is None else self.vm.ctypes.data_as(C.POINTER(C.c_uint8)))
+            val_mask=None if self.vm is None else self.vm.ctypes.data_as(C.POINTER(C.c_uint8)),
+            ldx=ldx)
         self.n, self.p, self.M = n, p, int(prob["M"])
 
 
@@ -263,6 +277,11 @@ class Fit:
         buf = (C.c_char * len(blob)).from_buffer_copy(blob)
         check(lib().cwb_fit_load_state(self.h, buf, len(blob)))
 
+    def tile(self) -> dict:
+        t = cwb_tile()
+        check(lib().cwb_fit_tile(self.h, C.byref(t)))
+        return {name: getattr(t, name) for name, _ in cwb_tile._fields_}
+
     def set_timing(self, mask):
         """mask: bit set 1 = hist, 2 = state, 4 = select (True = all, False = off)."""
         if mask is True:
@@ -308,6 +327,11 @@ class Batch:
     def run(self, iters: int):
         check(lib().cwb_batch_run(self.h, int(iters)))
 
+    def tile(self) -> dict:
+        t = cwb_tile()
+        check(lib().cwb_batch_tile(self.h, C.byref(t)))
+        return {name: getattr(t, name) for name, _ in cwb_tile._fields_}
+
     def sync(self):
         check(lib().cwb_batch_sync(self.h))
 
@@ -335,3 +359,67 @@ def fit(prob: dict, iters: int | None = None, stream=None) -> dict:
     out["n_train"] = f.info.n_train
     f.close()
     return out
+
+
+class Server:
+    """Continuous-batching fit server: requests are set up on host threads,
+    admitted while the device arena (a torch uint8 tensor) holds them, and
+    advanced together in rounds of `quantum` iterations on `stream`."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 64, quantum: int = 50,
+                 setup_threads: int = 0, stream=None):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        torch.cuda.synchronize()
+        cfg = cwb_server_cfg(arena=C.c_void_p(self.arena.data_ptr()), arena_bytes=int(arena_bytes),
+                             max_slots=int(max_slots), quantum=int(quantum),
+                             stream=C.c_void_p(self.stream.cuda_stream),
+                             setup_threads=int(setup_threads))
+        h = C.c_void_p()
+        check(lib().cwb_server_create(C.byref(cfg), C.byref(h)))
+        self.h = h
+        self._pending = {}
+
+    def submit(self, prob: dict) -> int:
+        pr = Problem(prob)
+        t = C.c_uint64()
+        check(lib().cwb_server_submit(self.h, C.byref(pr.c), C.byref(t)))
+        # the server reads the problem's arrays in place until the result is polled
+        self._pending[t.value] = (pr, np.zeros(pr.n, np.float32), np.zeros(pr.M, np.int32))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while the request is pending, else a dict with its status,
+        latency, intercept, training predictions and selection trace."""
+        _, pred, k = self._pending[ticket]
+        res = cwb_result()
+        rc = lib().cwb_server_poll(self.h, C.c_uint64(ticket), C.byref(res), _ptr(pred), _ptr(k))
+        if rc == CWB_E_AGAIN:
+            return None
+        check(rc)
+        del self._pending[ticket]
+        out = {"status": res.status, "M": res.M, "latency_s": res.latency_s,
+               "queue_s": res.queue_s, "f0": res.intercept}
+        if res.status == CWB_OK:
+            out["f"] = pred
+            out["k"] = k
+        else:
+            out["error"] = lib().cwb_last_error().decode()
+        return out
+
+    def stats(self) -> dict:
+        st = cwb_stats()
+        check(lib().cwb_server_stats(self.h, C.byref(st)))
+        return {name: getattr(st, name) for name, _ in cwb_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cwb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

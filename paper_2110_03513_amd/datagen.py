@@ -203,6 +203,43 @@ def config5_problem(spec: dict) -> dict:
                             val_frac=0.2 if spec["variant"] == "hcwb" else 0.0)
 
 
+class FeaturePool:
+    """One column-major Uniform[0, 1] matrix shared by a request stream: a
+    request of n rows and p features uses its leading n x p block, a view
+    with column stride n_max that the library reads without a copy."""
+
+    def __init__(self, n_max: int, p_max: int, seed: int = 4999):
+        rng = _rng(seed)
+        self.x = np.empty((n_max, p_max), dtype=np.float64, order="F")
+        for j in range(p_max):
+            self.x[:, j] = rng.random(n_max)
+
+
+def config5_problem_pooled(spec: dict, pool: FeaturePool) -> dict:
+    """A served request on the pool's leading block: the first min(5, p)
+    columns carry the additive signal, targets and validation split are
+    drawn from the request's own seed."""
+    n, p = spec["n"], spec["p"]
+    x = pool.x[:n, :p]
+    rng = _rng(spec["seed"])
+    eta = np.zeros(n)
+    for j in range(min(5, p)):
+        eta += (1.0 + j / 19.0) * _effect(j, x[:, j])
+    if spec["loss"] == "l2":
+        y = eta + rng.normal(0.0, math.sqrt(max(eta.var(), 1e-300)), size=n)
+    else:
+        s = eta.std()
+        z = eta / s if s > 0 else eta
+        y = (rng.random(n) < 1.0 / (1.0 + np.exp(-z))).astype(np.float64)
+    variant = spec["variant"]
+    val_mask = (rng.random(n) < 0.2).astype(np.uint8) if variant == "hcwb" else None
+    prob = {"x": x, "y": y, "loss": spec["loss"], "nu": 0.1, "M": spec["M"], "variant": variant,
+            "gamma": GAMMA_HCWB if variant == "hcwb" else GAMMA_ACWB, "patience": 5,
+            "val_mask": val_mask}
+    prob.update(learner_specs(p, int(math.floor(math.sqrt(n)))))
+    return prob
+
+
 def tiny_problem(n: int = 400, p: int = 4, seed: int = 7, n_bins: int = 20, M: int = 20,
                  loss: str = "l2", variant: str = "cwb", **kw) -> dict:
     """Small problem for brute-force checks."""

@@ -148,3 +148,43 @@ def test_library_binning_matches_oracle_bitwise():
             zl, il = cwb.bin_feature(xx, nb)
             np.testing.assert_array_equal(zl, zo)
             np.testing.assert_array_equal(il.astype(np.int64), io.astype(np.int64))
+
+
+def test_server_rejects_bad_configurations():
+    """Configuration checks happen before any device call."""
+    L = cwb.lib()
+    h = C.c_void_p()
+    assert L.cwb_server_create(None, C.byref(h)) == cwb.CWB_E_INVALID_ARG
+    base = dict(arena=C.c_void_p(1 << 20), arena_bytes=64 << 20, max_slots=4, quantum=10,
+                stream=None, setup_threads=1)
+    for bad in ({"arena": None}, {"arena": C.c_void_p((1 << 20) + 8)}, {"arena_bytes": 1000},
+                {"max_slots": 0}, {"quantum": 0}, {"setup_threads": -1}):
+        cfg = cwb.cwb_server_cfg(**dict(base, **bad))
+        rc = L.cwb_server_create(C.byref(cfg), C.byref(h))
+        assert rc == cwb.CWB_E_INVALID_ARG, bad
+        assert L.cwb_last_error()
+    t = C.c_uint64()
+    res = cwb.cwb_result()
+    st = cwb.cwb_stats()
+    assert L.cwb_server_submit(None, None, C.byref(t)) == cwb.CWB_E_INVALID_ARG
+    assert L.cwb_server_poll(None, 1, C.byref(res), None, None) == cwb.CWB_E_INVALID_ARG
+    assert L.cwb_server_stats(None, C.byref(st)) == cwb.CWB_E_INVALID_ARG
+    L.cwb_server_destroy(None)
+
+
+def test_column_stride_of_x():
+    """x may be the leading rows and columns of a larger column-major matrix
+    (ldx = its column stride); setup then reads exactly those entries."""
+    base = datagen.tiny_problem(n=200, p=3, seed=5, n_bins=10, M=5)
+    pool = np.asfortranarray(np.random.default_rng(1).random((500, 5)))
+    pool[:200, :3] = base["x"]
+    pool[:200, 1] = 3.0  # constant inside the view only
+    view = pool[:200, :3]
+    pr = cwb.Problem(dict(base, x=view))
+    assert pr.c.ldx == 500 and pr.x is view
+    assert _create_error(dict(base, x=view)) == (cwb.CWB_E_INVALID_ARG, "constant feature 1")
+    pr = cwb.Problem(base)
+    pr.c.ldx = 199
+    h = C.c_void_p()
+    rc = cwb.lib().cwb_fit_create(C.byref(pr.c), C.c_void_p(1 << 20), 1 << 40, None, C.byref(h))
+    assert rc == cwb.CWB_E_INVALID_ARG and "ldx" in cwb.lib().cwb_last_error().decode()

@@ -212,3 +212,71 @@ def test_histogram_tilings_many_steps(nt, F, blocks, variant, monkeypatch):
                                     n_informative_cat=1)
     gpu = _run(prob)
     compare(gpu, prob)
+
+
+def test_autotuned_tiles_do_not_change_results(monkeypatch):
+    """The autotuner picks a histogram tile shape by timing; the histograms
+    are exact integer sums, so every shape gives bitwise the same fit."""
+    prob = datagen.additive_problem(80_000, 30, seed=77, n_informative=5, loss="binomial",
+                                    n_bins=300, M=40, variant="acwb", gamma=0.01)
+    runs = []
+    for env in ({}, {"CWB_AUTOTUNE": "0"}, {"CWB_HIST_NT": "256", "CWB_HIST_F": "3"}):
+        for k in ("CWB_AUTOTUNE", "CWB_HIST_NT", "CWB_HIST_F"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        f = cwb.Fit(prob)
+        tile = f.tile()
+        _say(f"tile {env}: {tile}")
+        assert (tile["candidates"] > 1 and tile["tuned_us"] > 0) if not env else tile["candidates"] == 1
+        f.run(40)
+        f.sync()
+        runs.append((f.trace(), f.pred(), f.model()))
+        f.close()
+    for tr, pred, model in runs[1:]:
+        np.testing.assert_array_equal(tr["k"], runs[0][0]["k"])
+        np.testing.assert_array_equal(tr["kcor"], runs[0][0]["kcor"])
+        np.testing.assert_array_equal(pred, runs[0][1])
+        np.testing.assert_array_equal(model["coef_h"], runs[0][2]["coef_h"])
+
+
+def test_batch_graph_replays_match_alone():
+    """Batched iterations replay a captured graph (on a non-default stream);
+    runs in several chunks with eager work and synchronisations between the
+    replays must equal the stand-alone runs bitwise after every chunk."""
+    import torch
+    probs = [
+        datagen.additive_problem(25_000, 9, seed=51, n_informative=3, n_bins=150, M=70),
+        datagen.additive_problem(40_000, 14, seed=52, n_informative=4, loss="binomial",
+                                 n_bins=200, M=60, variant="acwb", gamma=0.02),
+        datagen.additive_problem(18_000, 6, seed=53, n_informative=2, n_bins=120, M=70,
+                                 variant="hcwb", gamma=0.2, patience=2),
+    ]
+    alone = []
+    for p in probs:
+        f = cwb.Fit(p)
+        snaps = []
+        for chunk in (13, 20, 37):
+            f.run(min(chunk, p["M"] - f.iters_done))
+            f.sync()
+            snaps.append(f.pred().copy())
+        alone.append((f.trace(), snaps))
+        f.close()
+    stream = torch.cuda.Stream()
+    fits = [cwb.Fit(p) for p in probs]
+    b = cwb.Batch(fits, stream=stream)
+    junk = torch.randn(1 << 20, device="cuda")
+    for ci, chunk in enumerate((13, 20, 37)):
+        b.run(chunk)
+        b.sync()
+        junk = junk * 1.0001 + 1.0  # eager work between replays
+        torch.cuda.synchronize()
+        for f, (tr, snaps) in zip(fits, alone):
+            np.testing.assert_array_equal(f.pred(), snaps[ci])
+    for f, (tr, _) in zip(fits, alone):
+        t = f.trace()
+        np.testing.assert_array_equal(t["k"], tr["k"])
+        np.testing.assert_array_equal(t["kcor"], tr["kcor"])
+        assert t["switch_iter"] == tr["switch_iter"]
+        f.close()
+    b.close()
