@@ -73,8 +73,8 @@ def headline(args, torch, cwb, datagen):
     fit.run(args.warmup)
     fit.sync()
     # timed region: exactly `steps` iterations, HIP events around every
-    # histogram-pass launch on the fit's stream
-    fit.set_timing(1)
+    # `timing_period`-th histogram-pass launch on the fit's stream
+    fit.set_timing(1, args.timing_period)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fit.run(args.steps)
@@ -106,12 +106,40 @@ def headline(args, torch, cwb, datagen):
         "iters_s": iters_s, "ms_per_step": per_iter * 1e3, "setup_s": setup_s,
         "iter_gbs": alg_iter_bytes * iters_s / 1e9,
         "hist_avg_us": hist_avg_s * 1e6, "state_avg_us": st_us, "select_avg_us": sel_us,
-        "hist_launches": hist_n,
+        "hist_launches": hist_n, "hist_timed_every": args.timing_period,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "alg_iter_bytes": alg_iter_bytes, "hist_bytes_per_launch": hist_bytes, "tile": tile,
     }
+
+
+def unbinned_leg(args, torch, cwb, datagen):
+    """The headline workload with unbinned learners (each row's own cubic
+    basis, no binning), timed beside the binned path."""
+    n, p, M = args.n, args.p, args.unbinned_iters
+    log(f"[bench] unbinned: n={n} p={p}, {M} iterations")
+    prob = datagen.config2(n=n, p=p, M=M + 10, n_bins=0)
+    t0 = time.perf_counter()
+    fit = cwb.Fit(prob)
+    setup = time.perf_counter() - t0
+    del prob
+    tile = fit.tile()
+    fit.run(10)
+    fit.sync()
+    fit.set_timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit.run(M)
+    fit.sync()
+    wall = time.perf_counter() - t0
+    hist_ms, hist_n = fit.kernel_time("hist")
+    fit.close()
+    hist_s = hist_ms / 1e3 / max(hist_n, 1)
+    alg = 4.0 * n * p + 4.0 * n  # 32-bit knot-interval code per (row, learner) + residuals
+    return {"iters_s": round(M / wall, 2), "hist_avg_us": round(hist_s * 1e6, 2),
+            "hist_alg_gbs": round(alg / hist_s / 1e9, 1), "iterations": M, "tile": tile,
+            "setup_s": round(setup, 2)}
 
 
 def momentum_legs(args, torch, cwb, datagen):
@@ -125,6 +153,7 @@ def momentum_legs(args, torch, cwb, datagen):
         n, p = prob["x"].shape
         fit = cwb.Fit(prob)
         del prob
+        tile = fit.tile()
         fit.run(10)
         fit.sync()
         fit.set_timing(1)
@@ -140,7 +169,7 @@ def momentum_legs(args, torch, cwb, datagen):
         two = 2.0 * n * p + 8.0 * n
         rec = {"iters_s": round((M - 10) / wall, 2), "hist_avg_us": round(hist_ms * 1e3 / max(hist_n, 1), 2),
                "hist_alg_gbs": round(two / (hist_ms / 1e3 / max(hist_n, 1)) / 1e9, 1),
-               "iterations": M}
+               "iterations": M, "tile": tile}
         if variant == "hcwb":
             rec["switch_iter"] = sw
             if sw != -1:  # the CWB phase streams one signal: no single byte count
@@ -346,6 +375,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-fits", type=int, default=64)
     ap.add_argument("--batch-iters", type=int, default=1000)
+    ap.add_argument("--timing-period", type=int, default=8,
+                    help="time every k-th histogram launch in the timed region")
+    ap.add_argument("--unbinned-iters", type=int, default=200)
+    ap.add_argument("--no-unbinned", action="store_true")
     ap.add_argument("--momentum-iters", type=int, default=300)
     ap.add_argument("--no-momentum", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -395,12 +428,17 @@ def main():
                        "select": h["select_avg_us"] and round(h["select_avg_us"], 2)},
         "setup_s": round(h["setup_s"], 2),
         "hist_tile": h["tile"],
+        "hist_timing": {"launches_timed": h["hist_launches"], "every": args.timing_period,
+                        "method": "HIP events on the fit's stream around every k-th histogram "
+                                  "launch of the timed region"},
     }
     if not args.no_cpu:
         cb, par = cpu_baseline(args, prob, tr)
         out["cpu_baseline"] = cb
         out["parity"] = par
     del prob
+    if not args.no_unbinned:
+        out["unbinned"] = unbinned_leg(args, torch, cwb, datagen)
     if not args.no_momentum:
         out["momentum"] = momentum_legs(args, torch, cwb, datagen)
     if not args.no_batch:

@@ -75,7 +75,10 @@ typedef struct {
                                equals df (App. A.2); <= 0: use `lambda` */
   double lambda;            /* smoothing parameter when df <= 0 (>= 0) */
   int32_t n_bins;           /* P-spline design points n* (Sec. 3.1.1), 2..65535;
-                               -1 selects floor(sqrt(n)) */
+                               -1 selects floor(sqrt(n)); 0 selects an unbinned
+                               learner (each row's own basis, Sec. 2.2; cubic
+                               only, and then every learner of the fit must be
+                               unbinned: no categorical learners; not served) */
   int32_t n_levels;         /* CWB_RIDGE_CAT: number of levels c_j (1..64) */
 } cwb_learner_spec;
 
@@ -206,6 +209,10 @@ int cwb_fit_load_state(cwb_fit* f, const void* host_buf, size_t bytes);
  * the query synchronises and returns the summed milliseconds and the number
  * of timed launches of the named kernel. */
 int cwb_fit_set_timing(cwb_fit* f, int32_t mask);
+/* The same, timing only every `period`-th iteration (period >= 1): each
+ * event pair costs a few microseconds of queue time, so sampling keeps the
+ * timed run close to an untimed one. */
+int cwb_fit_set_timing_period(cwb_fit* f, int32_t mask, int32_t period);
 int cwb_fit_kernel_time(cwb_fit* f, const char* kernel, double* total_ms, int64_t* launches);
 
 /* Histogram tile shape a fit or batch uses (Section 3.1.2's first stage:

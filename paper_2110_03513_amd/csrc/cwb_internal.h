@@ -3,7 +3,8 @@
 //
 // HBM layout of one fit (all inside the caller's workspace):
 //   X      p x n_pad uint16, feature-major: the index vectors of Section 3.1.1,
-//          one contiguous row of n_pad entries per learner (16-byte aligned)
+//          one contiguous row of n_pad entries per learner (16-byte aligned);
+//          for unbinned learners p x n_pad uint32 knot-interval codes
 //   y, fg, h, c, r   n_pad floats each (model state, Algorithm 2 notation:
 //          fg holds f, or g while an ACWB update is pending)
 //   per-bin tables: first nonzero basis index and the (degree+1) nonzero
@@ -30,6 +31,17 @@ constexpr int kNumSig = 2;       // signals: pseudo-residuals r, corrected resid
 constexpr int kStageBins = 2048; // learners up to this many bins are solved from LDS
 constexpr int kMaxSlots = 512;   // segment slots staged per learner group and pass
 constexpr int kHistMaxLds = 152 * 1024;  // dynamic LDS of one histogram block
+
+// Unbinned cubic P-spline learners.  Knots are equally spaced, so the four
+// nonzero basis functions at x are those of its knot interval j, and their
+// values are fixed cubic polynomials of the position t in [0, 1] inside the
+// interval.  Each (learner, row) is stored as one 32-bit code
+// (j << 24) | round(t * kUnbFracMax).  Their per-iteration sums go into
+// kUnbCopies interleaved LDS copies of each learner's basis sums (one per
+// lane mod kUnbCopies), which spreads the lanes of a wave over more
+// addresses.
+constexpr uint32_t kUnbFracMax = 0xffffffu;
+constexpr int kUnbCopies = 4;
 
 // One base learner.
 struct FeatDev {
@@ -65,7 +77,9 @@ struct FitDev {
   int32_t n_row_blocks;  // row-pass blocks: ceil(n_pad / kStateRows)
   int32_t n_val_blocks;  // validation blocks over [n_train, n)
   int32_t nsig_max;      // 2 for ACWB / HCWB, else 1
-  int32_t nb_stride;     // histogram stride per learner: nb_max rounded up to 4
+  int32_t nb_stride;     // histogram words per learner and signal (a multiple of 4)
+  int32_t unbinned;      // learners are unbinned cubic P-splines (X holds 32-bit codes)
+  int32_t pad_;
   const uint16_t* X;
   const float* y;
   float* fg;
@@ -130,6 +144,7 @@ struct RowItem {
   double nu;
   int32_t p, nb_max, loss, variant;
   int32_t M, two, blk, fit;          // two: the fit keeps h and c
+  int32_t unbinned, pad_;            // X holds 32-bit unbinned codes
 };
 
 // One learner's solve, with every pointer and size it needs, so that a block

@@ -188,6 +188,39 @@ __device__ __forceinline__ void load8u(const uint16_t* p, uint32_t* idx) {
   idx[6] = w.w & 0xffffu; idx[7] = w.w >> 16;
 }
 
+// 8 unbinned codes (32-bit) of consecutive rows.
+__device__ __forceinline__ void load8c(const uint32_t* p, uint32_t* c) {
+  const u32x4 a = *(const GLOBAL u32x4*)p;
+  const u32x4 b = *(const GLOBAL u32x4*)(p + 4);
+  c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+  c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+}
+
+// The four nonzero cubic B-spline values at position t of a knot interval
+// (equally spaced knots: the uniform cubic segments).
+__device__ __forceinline__ void cubic4(uint32_t code, float* b) {
+  const float t = (float)(code & kUnbFracMax) * (1.0f / (float)kUnbFracMax);
+  const float s = 1.0f - t, t2 = t * t, t3 = t2 * t;
+  b[0] = s * s * s * (1.0f / 6.0f);
+  b[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+  b[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+  b[3] = t3 * (1.0f / 6.0f);
+}
+
+// (Z theta)_i of an unbinned learner: its basis at the row's code against
+// the coefficient table.
+__device__ __forceinline__ float unb_eval(uint32_t code, const float* tab) {
+  float b[4];
+  cubic4(code, b);
+  const int iv = (int)(code >> 24);
+  return b[0] * tab[iv] + b[1] * tab[iv + 1] + b[2] * tab[iv + 2] + b[3] * tab[iv + 3];
+}
+
+// Update-table lookup of one row: the bin's entry, or the basis expansion.
+__device__ __forceinline__ float table_at(bool unb, uint32_t idx, const float* tab) {
+  return unb ? unb_eval(idx, tab) : tab[idx];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -234,8 +267,15 @@ k_state(const RowItem* __restrict__ items, int final_mode) {
   const bool use_h = pending && pend_acwb && kc >= 0;
   const bool use_cc = acwb && m > 1 && kc >= 0;
   uint32_t ik[8], ic[8];
-  if (rows && use_t) load8u(it.X + (size_t)kk * it.n_pad + base, ik);
-  if (rows && (use_h || use_cc)) load8u(it.X + (size_t)kc * it.n_pad + base, ic);
+  const bool unb = it.unbinned != 0;
+  if (unb) {
+    const uint32_t* XU = reinterpret_cast<const uint32_t*>(it.X);
+    if (rows && use_t) load8c(XU + (size_t)kk * it.n_pad + base, ik);
+    if (rows && (use_h || use_cc)) load8c(XU + (size_t)kc * it.n_pad + base, ic);
+  } else {
+    if (rows && use_t) load8u(it.X + (size_t)kk * it.n_pad + base, ik);
+    if (rows && (use_h || use_cc)) load8u(it.X + (size_t)kc * it.n_pad + base, ic);
+  }
   if (use_t) stage<kStateThreads, 4>(tf, it.table + (size_t)kk * nb, nb);
   if (use_h || use_cc) stage<kStateThreads, 4>(tc, it.table + ((size_t)it.p + kc) * nb, nb);
   if (threadIdx.x == 0) s_bad = 0;
@@ -253,8 +293,8 @@ k_state(const RowItem* __restrict__ items, int final_mode) {
       const bool live = i < it.n;
       float fj = f[j];
       float hj = two ? hv[j] : 0.0f;
-      if (live && use_t) fj = fj + nu * tf[ik[j]];
-      if (live && use_h) hj = hj + eta * tc[ic[j]];
+      if (live && use_t) fj = fj + nu * table_at(unb, ik[j], tf);
+      if (live && use_h) hj = hj + eta * table_at(unb, ic[j], tc);
       if (live) {
         const double L = loss_value(it.loss, yv[j], fj);
         if (i < it.n_train) risk_t += L; else risk_v += L;
@@ -270,7 +310,7 @@ k_state(const RowItem* __restrict__ items, int final_mode) {
         const float g = (1.0f - vt) * fj + vt * hj;
         const float r = neg_gradient(it.loss, yv[j], g);
         float c = r;
-        if (use_cc) c = r + cw * (cv[j] - tc[ic[j]]);
+        if (use_cc) c = r + cw * (cv[j] - table_at(unb, ic[j], tc));
         f[j] = g;  // the primary model update f = g + nu b_k is pending
         if (fitrow) {
           rr[j] = r;
@@ -391,9 +431,57 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
   }
 }
 
+// Rows [r0, r1) of one segment of unbinned learners: per row and learner,
+// the four basis values at the row's code times r (and c), as int64 fixed
+// point, into the learner's basis sums (copy lane mod kUnbCopies, stride
+// d_max words).  |B r| <= |r|, and each basis sum gets at most one term per
+// row, so the exponent of the binned pass is safe here too.
+template <int NT, int FMAX, int NSIG>
+__device__ __forceinline__ void uhist_rows(const FitDev& F, const Seg& sg,
+                                           unsigned long long* __restrict__ hist, int nb,
+                                           int64_t r0, int64_t r1, int e0, int e1) {
+  const uint32_t* __restrict__ Xg =
+      reinterpret_cast<const uint32_t*>(F.X) + (size_t)sg.k0 * F.n_pad;
+  const int nf = sg.nf;
+  const size_t ld = (size_t)F.n_pad;
+  const int copy = ((int)threadIdx.x & (kUnbCopies - 1)) * F.d_max;
+  for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
+    float rv[8], cv[8];
+    load8f(F.r + base, rv);
+    if (NSIG == 2) load8f(F.c + base, cv);
+    uint32_t code[FMAX][8];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f)
+      if (f < nf) load8c(Xg + f * ld + base, code[f]);
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) {
+      if (f >= nf) continue;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        float b[4];
+        cubic4(code[f][j], b);
+        const int iv = (int)(code[f][j] >> 24);
+        unsigned long long* h0 = hist + (size_t)f * nb + copy + iv;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          __hip_atomic_fetch_add(h0 + a, (unsigned long long)fixed_point(b[a] * rv[j], e0),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (NSIG == 2) {
+          unsigned long long* h1 = hist + (size_t)(nf + f) * nb + copy + iv;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            __hip_atomic_fetch_add(h1 + a, (unsigned long long)fixed_point(b[a] * cv[j], e1),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+  }
+}
+
 // NSMAX: most signals any fit of the launch can have (1 when every fit is
-// plain CWB, so the two-signal path is not compiled in).
-template <int NT, int FMAX, int NSMAX>
+// plain CWB, so the two-signal path is not compiled in).  UNB: every fit of
+// the launch has unbinned learners.
+template <int NT, int FMAX, int NSMAX, bool UNB>
 __global__ void __launch_bounds__(NT)
 k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
        const int64_t* __restrict__ blk, long long* __restrict__ partials) {
@@ -423,13 +511,31 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
       e1 = (nsig == 2) ? fit_scale_exponent<NT>(F, 1, n_fit, s_red) : 0;
       cached_fit = sg.fit;
     }
-    if (NSMAX == 1 || nsig == 1)
-      hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
-    else
-      hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
+    if (UNB) {
+      if (NSMAX == 1 || nsig == 1)
+        uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
+      else
+        uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
+    } else {
+      if (NSMAX == 1 || nsig == 1)
+        hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
+      else
+        hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
+    }
     __syncthreads();
     GLOBAL long long* out = gp(partials + sg.slot);
-    for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
+    if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
+      const int d = F.d_max;
+      for (int i = threadIdx.x; i < nsig * sg.nf * d; i += NT) {
+        const int lf = i / d, b = i - lf * d;
+        long long acc = 0;
+#pragma unroll
+        for (int c = 0; c < kUnbCopies; ++c) acc += (long long)s_hist[(size_t)lf * nb + c * d + b];
+        out[(size_t)lf * nb + b] = acc;
+      }
+    } else {
+      for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
+    }
     __syncthreads();
   }
 }
@@ -794,7 +900,12 @@ k_valrisk(const FitDev* __restrict__ fits, const StateItem* __restrict__ items) 
     const int64_t i = start + (int64_t)j * kStateThreads + threadIdx.x;
     if (i < F.n) {
       float f = F.fg[i];
-      if (!init) f = f + nu * s_tf[F.X[(size_t)kk * F.n_pad + i]];
+      if (!init) {
+        const uint32_t idx = F.unbinned
+            ? reinterpret_cast<const uint32_t*>(F.X)[(size_t)kk * F.n_pad + i]
+            : (uint32_t)F.X[(size_t)kk * F.n_pad + i];
+        f = f + nu * table_at(F.unbinned != 0, idx, s_tf);
+      }
       acc += loss_value(F.loss, F.y[i], f);
     }
   }
@@ -895,44 +1006,46 @@ __global__ void __launch_bounds__(kSelectThreads) k_coef(const FitDev* __restric
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int NT, int FMAX, int NSMAX>
+template <int NT, int FMAX, int NSMAX, bool UNB>
 hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                          const int64_t* blk, long long* partials) {
   // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB);
   // set once (thread-safe static initialisation), before any graph capture
   static const bool attr = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, UNB>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
     (void)hipGetLastError();
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
+  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, UNB>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
                      partials);
   return hipGetLastError();
 }
 
-template <int NT, int NSMAX>
+template <int NT, int NSMAX, bool UNB>
 hipError_t launch_hist_nt(hipStream_t st, int fmax, int blocks, size_t lds, const FitDev* fits,
                           const Seg* segs, const int64_t* blk, long long* partials) {
   switch (fmax) {
-    case 1: return launch_hist_t<NT, 1, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
-    case 2: return launch_hist_t<NT, 2, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
-    case 4: return launch_hist_t<NT, 4, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
-    case 8: return launch_hist_t<NT, 8, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
-    case 16: return launch_hist_t<NT, 16, NSMAX>(st, blocks, lds, fits, segs, blk, partials);
+    case 1: return launch_hist_t<NT, 1, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 2: return launch_hist_t<NT, 2, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 4: return launch_hist_t<NT, 4, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 8: return launch_hist_t<NT, 8, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 16:
+      if (!UNB) return launch_hist_t<NT, 16, NSMAX, false>(st, blocks, lds, fits, segs, blk, partials);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int NSMAX>
+template <int NSMAX, bool UNB>
 hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
                           const FitDev* fits, const Seg* segs, const int64_t* blk,
                           long long* partials) {
   switch (nt) {
-    case 256: return launch_hist_nt<256, NSMAX>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 512: return launch_hist_nt<512, NSMAX>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 1024: return launch_hist_nt<1024, NSMAX>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 256: return launch_hist_nt<256, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 512: return launch_hist_nt<512, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 1024: return launch_hist_nt<1024, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
     default: return hipErrorInvalidValue;
   }
 }
@@ -947,11 +1060,16 @@ hipError_t launch_state(hipStream_t st, const RowItem* items, int nitems, int nb
   return hipGetLastError();
 }
 
-hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, int blocks, size_t lds,
-                       const FitDev* fits, const Seg* segs, const int64_t* blk, long long* partials) {
+hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, int blocks,
+                       size_t lds, const FitDev* fits, const Seg* segs, const int64_t* blk,
+                       long long* partials) {
   if (blocks <= 0) return hipSuccess;
-  if (nsmax == 1) return launch_hist_ns<1>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-  return launch_hist_ns<2>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  if (unbinned) {
+    if (nsmax == 1) return launch_hist_ns<1, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+    return launch_hist_ns<2, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  }
+  if (nsmax == 1) return launch_hist_ns<1, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_ns<2, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
 }
 
 hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nb_max, int d_max,

@@ -65,12 +65,17 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
   sh->nsig_max = (pr->variant == CWB_CWB) ? 1 : 2;
   sh->nb_max = sh->d_max = sh->sum_d = 0;
   sh->sum_nb = sh->sum_d2 = 0;
+  sh->unbinned = false;
   for (int j = 0; j < pr->p; ++j) {
     const cwb_learner_spec& s = pr->specs[j];
     int nb, d;
     if (s.kind == CWB_RIDGE_CAT) {
       nb = s.n_levels;
       d = s.n_levels;
+    } else if (s.n_bins == 0) {  // unbinned: the basis functions take the place of bins
+      d = s.n_interior_knots + s.degree + 1;
+      nb = d;
+      sh->unbinned = true;
     } else {
       nb = s.n_bins == -1 ? (int)std::floor(std::sqrt((double)pr->n)) : s.n_bins;
       if (nb < 2) nb = 2;
@@ -87,6 +92,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
     sh->sum_d2 += (int64_t)d * d;
   }
   sh->nb_stride = (sh->nb_max + 3) / 4 * 4;
+  if (sh->unbinned) sh->nb_stride = (kUnbCopies * sh->d_max + 3) / 4 * 4;
   sh->n_row_blocks = (int)((sh->n_pad + kStateRows - 1) / kStateRows);
   const int64_t nv = sh->n - sh->n_train;
   sh->n_val_blocks = (sh->variant == CWB_HCWB && nv > 0) ? (int)((nv + kStateRows - 1) / kStateRows) : 0;
@@ -105,7 +111,7 @@ bool hist_env_set() {
 }
 
 Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, int nb_stride,
-               int nsig_max, int p_max, int cus) {
+               int nsig_max, int p_max, bool unbinned, int cus) {
   Tune t;
   t.cus = cus;
   t.nt = (nt == 256 || nt == 512 || nt == 1024) ? nt : 512;
@@ -122,6 +128,8 @@ Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, in
   // register budget at 1024 threads: groups of at most 8 learners (one
   // signal) or 2 learners (two signals); wider groups would spill
   if (t.nt == 1024) F = std::min(F, nsig_max == 1 ? 8 : 2);
+  // unbinned groups hold 32 bytes of codes per learner and thread
+  if (unbinned) F = std::min(F, t.nt == 1024 ? (nsig_max == 1 ? 4 : 2) : 8);
   t.F = F;
   t.fmax = 1;
   while (t.fmax < F) t.fmax *= 2;
@@ -130,26 +138,31 @@ Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, in
 
 }  // namespace
 
-Tune make_tune(int nb_stride, int nsig_max, int p_max) {
+// Default tile shape (measured on the headline and momentum workloads): one
+// signal, 1,024 threads with 32 KiB of histograms; two signals, 512 threads
+// with 128 KiB, since 1,024-thread blocks can hold only two learners of two
+// signals in registers.
+Tune make_tune(int nb_stride, int nsig_max, int p_max, bool unbinned) {
   int dev = 0;
   (void)hipGetDevice(&dev);
-  return tune_with(env_int("CWB_HIST_NT", 1024), env_int("CWB_HIST_LDS_KB", 32),
+  const bool two = nsig_max == 2;
+  return tune_with(env_int("CWB_HIST_NT", two ? 512 : 1024), env_int("CWB_HIST_LDS_KB", two ? 128 : 32),
                    env_int("CWB_HIST_BPC", 1), env_int("CWB_HIST_SLICES", 1),
                    env_int("CWB_HIST_BLOCKS", 0), env_int("CWB_HIST_F", 0), nb_stride, nsig_max,
-                   p_max, device_cus(dev));
+                   p_max, unbinned, device_cus(dev));
 }
 
 // Tile shapes the autotuner tries: the default first, then threads x LDS
 // budget x blocks per CU.  Explicit CWB_HIST_* settings, or CWB_AUTOTUNE=0,
 // leave the default alone.
-std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool all) {
-  std::vector<Tune> out{make_tune(nb_stride, nsig_max, p_max)};
+std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all) {
+  std::vector<Tune> out{make_tune(nb_stride, nsig_max, p_max, unbinned)};
   if (!all || hist_env_set() || env_int("CWB_AUTOTUNE", 1) == 0) return out;
   const int cus = out[0].cus;
   for (int nt : {1024, 512, 256})
     for (int kb : {32, 64, 128})
       for (int bpc : {1, 2}) {
-        const Tune t = tune_with(nt, kb, bpc, 1, 0, 0, nb_stride, nsig_max, p_max, cus);
+        const Tune t = tune_with(nt, kb, bpc, 1, 0, 0, nb_stride, nsig_max, p_max, unbinned, cus);
         bool dup = false;
         for (const Tune& u : out)
           dup = dup || (u.nt == t.nt && u.F == t.F && u.blocks_per_cu == t.blocks_per_cu &&
@@ -288,6 +301,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   }
   S.lds = (size_t)ns_max * t.F * nbs_max * sizeof(long long);
   S.nsig_max = ns_max;
+  S.unbinned = !fits.empty() && fits[0]->unbinned;
   return S;
 }
 
@@ -377,7 +391,7 @@ Layout make_layout(const FitShape& sh, const SchedCap& s) {
   L.coef_h = take((size_t)sh.sum_d * 8);
   L.state_end = align_up(off, 256);
   // inputs and tables
-  L.X = take((size_t)sh.p * np * 2);
+  L.X = take((size_t)sh.p * np * (sh.unbinned ? 4 : 2));
   L.y = take(np * 4);
   L.r = take(np * 4);
   L.feat = take((size_t)sh.p * sizeof(FeatDev));
@@ -449,12 +463,14 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Sch
                       const StateItem* d_val, int n_val, int nb_max, int d_max, const Seg* d_segs,
                       const int64_t* d_blk, const int64_t* d_off, long long* d_part,
                       cwb_fit* timed) {
-  const int tm = timed ? timed->timing : 0;
+  // timed launches: every timing_period-th iteration of a timed fit
+  int tm = timed ? timed->timing : 0;
+  if (tm && (timed->timing_counter++ % timed->timing_period) != 0) tm = 0;
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   HIP_TRY(launch_state(st, d_st, n_st, nb_max, 0));
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
-  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   HIP_TRY(launch_select(st, d_sel, n_sel, nb_max, d_max, d_part));
@@ -500,6 +516,7 @@ RowItem make_row_item(int fit, int blk, const FitDev& D) {
   it.two = D.nsig_max == 2 ? 1 : 0;
   it.blk = blk;
   it.fit = fit;
+  it.unbinned = D.unbinned;
   return it;
 }
 
@@ -552,8 +569,10 @@ int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::v
     nb = std::max(nb, sh->nb_stride);
     ns = std::max(ns, sh->nsig_max);
     pmax = std::max(pmax, sh->p);
+    if (sh->unbinned != shapes[0]->unbinned)
+      return set_error(CWB_E_UNSUPPORTED, "binned and unbinned fits cannot share a batch");
   }
-  *cands = tune_candidates(nb, ns, pmax, all);
+  *cands = tune_candidates(nb, ns, pmax, shapes[0]->unbinned, all);
   *cap = SchedCap();
   for (size_t i = 0; i < cands->size(); ++i) {
     Schedule S = build_schedule(shapes, (*cands)[i]);
@@ -597,10 +616,10 @@ int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const 
     HIP_TRY(hipMemcpyAsync(d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
     for (int w = 0; w < kWarm; ++w)
-      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
     HIP_TRY(hipEventRecord(ev.a, st));
     for (int r = 0; r < kTimed; ++r)
-      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
     HIP_TRY(hipEventRecord(ev.b, st));
     HIP_TRY(hipEventSynchronize(ev.b));
     float ms = 0.0f;
@@ -724,6 +743,9 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   D.n_val_blocks = sh.n_val_blocks;
   D.nsig_max = sh.nsig_max;
   D.nb_stride = sh.nb_stride;
+  D.unbinned = sh.unbinned ? 1 : 0;
+  if (sh.unbinned != hf.unbinned)
+    return set_error(CWB_E_INVALID_ARG, "learner kinds disagree with the specification");
   D.X = dptr<uint16_t>(ws, L.X);
   D.y = dptr<float>(ws, L.y);
   D.fg = dptr<float>(ws, L.fg);
@@ -774,7 +796,10 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   HIP_TRY(hipMemcpyAsync(ws + L.fg, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
   if (sh.nsig_max == 2)
     HIP_TRY(hipMemcpyAsync(ws + L.h, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
+  if (sh.unbinned)
+    HIP_TRY(hipMemcpyAsync(ws + L.X, hf.XU.data(), hf.XU.size() * 4, hipMemcpyHostToDevice, st));
+  else
+    HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
   HIP_TRY(hipMemcpyAsync(ws + L.feat, feat.data(), feat.size() * sizeof(FeatDev), hipMemcpyHostToDevice, st));
@@ -1039,9 +1064,16 @@ int cwb_fit_load_state(cwb_fit* f, const void* host_buf, size_t bytes) {
 }
 
 int cwb_fit_set_timing(cwb_fit* f, int32_t mask) {
+  return cwb_fit_set_timing_period(f, mask, 1);
+}
+
+int cwb_fit_set_timing_period(cwb_fit* f, int32_t mask, int32_t period) {
   if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
   if (mask < 0 || mask > 7) return set_error(CWB_E_INVALID_ARG, "timing mask must be 0..7");
+  if (period < 1) return set_error(CWB_E_INVALID_ARG, "timing period must be >= 1");
   f->timing = mask;
+  f->timing_period = period;
+  f->timing_counter = 0;
   timer_reset(f->t_hist);
   timer_reset(f->t_state);
   timer_reset(f->t_select);

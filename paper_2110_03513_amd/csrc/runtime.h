@@ -22,6 +22,7 @@ struct FitShape {
   int nb_stride = 0;  // nb_max rounded up to a multiple of 4
   int64_t sum_nb = 0, sum_d2 = 0;
   int n_row_blocks = 0, n_val_blocks = 0;
+  bool unbinned = false;  // learners are unbinned cubic P-splines
 };
 
 int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err);
@@ -39,7 +40,7 @@ struct Tune {
   int lds_kb = 64;
 };
 
-Tune make_tune(int nb_max, int nsig_max, int p_max);
+Tune make_tune(int nb_stride, int nsig_max, int p_max, bool unbinned);
 
 struct Schedule {
   std::vector<Seg> segs;         // traversal order
@@ -53,6 +54,7 @@ struct Schedule {
   int64_t partial_words = 0;
   int blocks = 0;
   int nsig_max = 1;  // most signals of any fit in the schedule
+  bool unbinned = false;  // the fits' learners are unbinned (one kind per schedule)
   size_t lds = 0;
 };
 
@@ -76,7 +78,7 @@ struct SchedCap {
   void add(const Schedule& S);
 };
 
-std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool all);
+std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all);
 
 Layout make_layout(const FitShape& sh, const SchedCap& s);
 
@@ -107,6 +109,8 @@ struct cwb_fit {
   int iters = 0;
   int n_st = 0, n_sel = 0, n_val = 0;
   int timing = 0;  // bit set: 1 hist, 2 state, 4 select
+  int timing_period = 1;  // time every period-th iteration
+  int64_t timing_counter = 0;
   cwb::KernelTimer t_hist, t_state, t_select;
   int n_cands = 1;        // tile shapes considered
   double tuned_us = 0.0;  // histogram pass time of the chosen shape (0: not tuned)

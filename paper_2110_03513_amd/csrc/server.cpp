@@ -468,6 +468,10 @@ int cwb_server_submit(cwb_server* s, const cwb_problem* pr, uint64_t* ticket) {
   FitShape sh;
   std::string err;
   int rc = shape_from_problem(pr, &sh, &err);
+  if (!rc && sh.unbinned) {
+    rc = CWB_E_UNSUPPORTED;
+    err = "the server batches binned fits only";
+  }
   if (rc) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->rejected += 1;

@@ -325,8 +325,11 @@ int validate_problem(const cwb_problem* pr, std::string* err) {
       const int d = s.n_interior_knots + s.degree + 1;
       if (d > kMaxD) { *err = "basis larger than 64"; return CWB_E_UNSUPPORTED; }
       if (s.penalty_order < 0 || s.penalty_order >= d) { *err = "bad penalty order"; return CWB_E_INVALID_ARG; }
-      if (s.n_bins == 0) { *err = "unbinned learners are not supported by the GPU path"; return CWB_E_UNSUPPORTED; }
-      if (s.n_bins != -1 && (s.n_bins < 2 || s.n_bins > 65535)) { *err = "n_bins must be 2..65535"; return CWB_E_INVALID_ARG; }
+      if (s.n_bins == 0 && s.degree != 3) { *err = "unbinned learners must be cubic"; return CWB_E_UNSUPPORTED; }
+      if (s.n_bins != -1 && s.n_bins != 0 && (s.n_bins < 2 || s.n_bins > 65535)) {
+        *err = "n_bins must be 2..65535 (or 0: unbinned, -1: floor(sqrt(n)))";
+        return CWB_E_INVALID_ARG;
+      }
       if (s.df > 0.0 && (s.df <= (double)s.penalty_order || s.df >= (double)d)) {
         *err = "P-spline df must lie between the penalty order and the basis size";
         return CWB_E_INVALID_ARG;
@@ -337,8 +340,29 @@ int validate_problem(const cwb_problem* pr, std::string* err) {
     }
     if (s.df <= 0.0 && !(s.lambda >= 0.0)) { *err = "lambda must be >= 0"; return CWB_E_INVALID_ARG; }
   }
+  int n_unb = 0;
+  for (int j = 0; j < pr->p; ++j)
+    n_unb += (pr->specs[j].kind == CWB_PSPLINE && pr->specs[j].n_bins == 0) ? 1 : 0;
+  if (n_unb > 0 && n_unb < pr->p) {
+    *err = "a fit's learners must be all binned or all unbinned P-splines";
+    return CWB_E_UNSUPPORTED;
+  }
   return CWB_OK;
 }
+
+namespace {
+
+// The four nonzero cubic B-spline values on an interval of equally spaced
+// knots, at position t in [0, 1] inside it (the uniform cubic segments).
+void uniform_cubic(double t, double* b) {
+  const double s = 1.0 - t, t2 = t * t, t3 = t2 * t;
+  b[0] = s * s * s / 6.0;
+  b[1] = (3.0 * t3 - 6.0 * t2 + 4.0) / 6.0;
+  b[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) / 6.0;
+  b[3] = t3 / 6.0;
+}
+
+}  // namespace
 
 int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
   int rc = validate_problem(pr, err);
@@ -379,7 +403,11 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
     return CWB_E_NUMERIC;
   }
 
-  hf->X.assign((size_t)p * hf->n_pad, 0);
+  hf->unbinned = pr->specs[0].kind == CWB_PSPLINE && pr->specs[0].n_bins == 0;
+  if (hf->unbinned)
+    hf->XU.assign((size_t)p * hf->n_pad, 0u);
+  else
+    hf->X.assign((size_t)p * hf->n_pad, 0);
   hf->L.resize(p);
   std::vector<std::string> ferr(p);
   std::vector<int> frc(p, 0);
@@ -392,7 +420,8 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
       const cwb_learner_spec& s = pr->specs[j];
       const double* xj = pr->x + (size_t)j * (size_t)(pr->ldx ? pr->ldx : n);
       HostLearner& L = hf->L[j];
-      uint16_t* Xj = hf->X.data() + (size_t)j * hf->n_pad;
+      uint16_t* Xj = hf->unbinned ? nullptr : hf->X.data() + (size_t)j * hf->n_pad;
+      uint32_t* XUj = hf->unbinned ? hf->XU.data() + (size_t)j * hf->n_pad : nullptr;
       L.kind = s.kind;
       if (s.kind == CWB_RIDGE_CAT) {
         const int c = s.n_levels;
@@ -429,6 +458,31 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
           ferr[j] = "constant feature " + std::to_string(j);
           continue;
         }
+        if (hf->unbinned) {
+          // unbinned cubic P-spline: knot-interval codes and an identity
+          // reduced design (its "bins" are the basis functions)
+          const int nint = s.n_interior_knots;
+          const int d = nint + 4;
+          const double hk = (xmax - xmin) / (double)(nint + 1);
+          L.xmin = xmin;
+          L.xmax = xmax;
+          L.nb = d;
+          L.d = d;
+          L.band = 1;
+          for (int64_t i = 0; i < n; ++i) {
+            const double u = (xj[hf->perm[i]] - xmin) / hk;
+            int iv = (int)std::floor(u);
+            iv = std::max(0, std::min(nint, iv));
+            const double tt = std::max(0.0, std::min(1.0, u - (double)iv));
+            XUj[i] = ((uint32_t)iv << 24) | (uint32_t)std::llround(tt * (double)kUnbFracMax);
+          }
+          L.bstart.resize(d);
+          L.bval.assign((size_t)d * kMaxBand, 0.0);
+          for (int l = 0; l < d; ++l) {
+            L.bstart[l] = l;
+            L.bval[(size_t)l * kMaxBand] = 1.0;
+          }
+        } else {
         int nb = s.n_bins;
         if (nb == -1) nb = (int)std::floor(std::sqrt((double)n));
         if (nb < 2) nb = 2;
@@ -458,6 +512,7 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
           const double z = grid_point(xmin, xmax, h, l, nb);
           L.bstart[l] = bspline_band(z, t, deg, d, &L.bval[(size_t)l * kMaxBand]);
         }
+        }
       }
       // support ranges: design points whose band covers basis index q
       const int d = L.d;
@@ -472,23 +527,47 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
         L.jr[2 * q] = lo;
         L.jr[2 * q + 1] = hi;
       }
-      // counts over training rows and over all rows
-      std::vector<double> cnt_t(L.nb, 0.0), cnt_a(L.nb, 0.0);
-      for (int64_t i = 0; i < n; ++i) {
-        cnt_a[Xj[i]] += 1.0;
-        if (i < nt) cnt_t[Xj[i]] += 1.0;
+      // Gram matrices over the training rows and over all rows: from the bin
+      // counts (binMatMat, Algorithm 1), or row by row for unbinned learners
+      // (with the basis at the stored interval positions)
+      std::vector<double> cnt_t, cnt_a, G_unb[2];
+      if (hf->unbinned) {
+        for (int set = 0; set < 2; ++set) G_unb[set].assign((size_t)d * d, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+          const uint32_t code = XUj[i];
+          const int b0 = (int)(code >> 24);
+          double bv[4];
+          uniform_cubic((double)(code & kUnbFracMax) / (double)kUnbFracMax, bv);
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+              const double v = bv[a] * bv[b];
+              G_unb[1][(size_t)(b0 + a) * d + (b0 + b)] += v;
+              if (i < nt) G_unb[0][(size_t)(b0 + a) * d + (b0 + b)] += v;
+            }
+        }
+      } else {
+        cnt_t.assign(L.nb, 0.0);
+        cnt_a.assign(L.nb, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+          cnt_a[Xj[i]] += 1.0;
+          if (i < nt) cnt_t[Xj[i]] += 1.0;
+        }
       }
       const std::vector<double> D = (s.kind == CWB_RIDGE_CAT) ? difference_penalty(d, 0)
                                                                : difference_penalty(d, s.penalty_order);
       for (int set = 0; set < 2; ++set) {
-        const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
         std::vector<double> G((size_t)d * d, 0.0);
-        for (int l = 0; l < L.nb; ++l) {
-          if (cnt[l] == 0.0) continue;
-          const int b0 = L.bstart[l];
-          const double* bv = &L.bval[(size_t)l * kMaxBand];
-          for (int a = 0; a < L.band; ++a)
-            for (int b = 0; b < L.band; ++b) G[(size_t)(b0 + a) * d + (b0 + b)] += cnt[l] * bv[a] * bv[b];
+        if (hf->unbinned) {
+          G = G_unb[set];
+        } else {
+          const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
+          for (int l = 0; l < L.nb; ++l) {
+            if (cnt[l] == 0.0) continue;
+            const int b0 = L.bstart[l];
+            const double* bv = &L.bval[(size_t)l * kMaxBand];
+            for (int a = 0; a < L.band; ++a)
+              for (int b = 0; b < L.band; ++b) G[(size_t)(b0 + a) * d + (b0 + b)] += cnt[l] * bv[a] * bv[b];
+          }
         }
         double lam = s.lambda;
         if (s.df > 0.0) {
@@ -500,6 +579,7 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
               for (int it = 0; it < 400 && hi / lo > 1.0 + 1e-15; ++it) {
                 const double mid = std::sqrt(lo * hi);
                 double v = 0.0;
+                const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
                 for (int l = 0; l < d; ++l) v += cnt[l] / (cnt[l] + mid);
                 if (v > s.df) lo = mid; else hi = mid;
               }

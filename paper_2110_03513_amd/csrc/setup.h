@@ -30,7 +30,9 @@ struct HostFit {
   double nu = 0, gamma = 0, f0 = 0;
   int nb_max = 0, d_max = 0, sum_d = 0;
   std::vector<int64_t> perm;     // internal row -> original row
-  std::vector<uint16_t> X;       // p x n_pad, feature-major
+  std::vector<uint16_t> X;       // p x n_pad, feature-major (binned learners)
+  bool unbinned = false;         // every learner is an unbinned cubic P-spline
+  std::vector<uint32_t> XU;      // p x n_pad knot-interval codes (unbinned)
   std::vector<float> y;          // n_pad
   std::vector<HostLearner> L;
 };

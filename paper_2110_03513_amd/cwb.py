@@ -95,6 +95,7 @@ _SIGNATURES = {
     "cwb_batch_sync": [_P],
     "cwb_batch_destroy": [_P],
     "cwb_fit_tile": [_P, C.POINTER(cwb_tile)],
+    "cwb_fit_set_timing_period": [_P, C.c_int32, C.c_int32],
     "cwb_batch_tile": [_P, C.POINTER(cwb_tile)],
     "cwb_server_create": [C.POINTER(cwb_server_cfg), C.POINTER(_P)],
     "cwb_server_submit": [_P, C.POINTER(cwb_problem), C.POINTER(C.c_uint64)],
@@ -282,11 +283,12 @@ class Fit:
         check(lib().cwb_fit_tile(self.h, C.byref(t)))
         return {name: getattr(t, name) for name, _ in cwb_tile._fields_}
 
-    def set_timing(self, mask):
-        """mask: bit set 1 = hist, 2 = state, 4 = select (True = all, False = off)."""
+    def set_timing(self, mask, period: int = 1):
+        """mask: bit set 1 = hist, 2 = state, 4 = select (True = all, False =
+        off); only every `period`-th iteration is timed."""
         if mask is True:
             mask = 7
-        check(lib().cwb_fit_set_timing(self.h, int(mask)))
+        check(lib().cwb_fit_set_timing_period(self.h, int(mask), int(period)))
 
     def kernel_time(self, name: str):
         ms = C.c_double()

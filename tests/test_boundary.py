@@ -98,8 +98,6 @@ def test_create_rejects_bad_problems():
     assert rc == cwb.CWB_E_INVALID_ARG
     rc, msg = _create_error(dict(base, n_bins=np.full(3, 20000)))
     assert rc == cwb.CWB_E_UNSUPPORTED
-    rc, msg = _create_error(dict(base, n_bins=np.zeros(3, int)))
-    assert rc == cwb.CWB_E_UNSUPPORTED and "unbinned" in msg
     y = base["y"].copy()
     y[3] = np.nan
     rc, msg = _create_error(dict(base, y=y))
@@ -188,3 +186,18 @@ def test_column_stride_of_x():
     h = C.c_void_p()
     rc = cwb.lib().cwb_fit_create(C.byref(pr.c), C.c_void_p(1 << 20), 1 << 40, None, C.byref(h))
     assert rc == cwb.CWB_E_INVALID_ARG and "ldx" in cwb.lib().cwb_last_error().decode()
+
+
+def test_unbinned_learners_shape_and_rules():
+    """n_bins = 0 selects unbinned cubic P-splines: the workspace holds 32-bit
+    knot-interval codes; a fit mixes no binned and unbinned learners."""
+    base = datagen.tiny_problem(n=3000, p=4, seed=9, n_bins=0, M=5)
+    binned = datagen.tiny_problem(n=3000, p=4, seed=9, n_bins=50, M=5)
+    assert cwb.workspace_bytes(base) >= 4 * 3000 * 4
+    assert cwb.workspace_bytes(base) > cwb.workspace_bytes(binned) - 2 * 3000 * 4 * 1
+    mixed = dict(base, n_bins=np.array([0, 50, 0, 0], np.int32))
+    rc, msg = _create_error(mixed)
+    assert rc == cwb.CWB_E_UNSUPPORTED and "unbinned" in msg
+    quad = dict(base, degree=2)
+    rc, msg = _create_error(quad)
+    assert rc == cwb.CWB_E_UNSUPPORTED and "cubic" in msg

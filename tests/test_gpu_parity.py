@@ -280,3 +280,28 @@ def test_batch_graph_replays_match_alone():
         assert t["switch_iter"] == tr["switch_iter"]
         f.close()
     b.close()
+
+
+@pytest.mark.parametrize("variant,loss", [("cwb", "l2"), ("acwb", "binomial"), ("hcwb", "l2")])
+def test_unbinned_against_oracle(variant, loss):
+    """Unbinned cubic P-splines (each row's exact basis, Section 2.2) against
+    the oracle's unbinned FP64 fit."""
+    prob = datagen.additive_problem(40_000, 10, seed=61, n_informative=4, loss=loss, n_bins=0,
+                                    M=80, variant=variant, gamma=0.05 if variant == "acwb" else 0.3,
+                                    patience=3)
+    compare(_run(prob), prob)
+
+
+def test_unbinned_full_size_first_iterations():
+    prob = datagen.config2(M=2000, n_bins=0)
+    M = 6
+    _say("full-size unbinned n=1e6 p=200: 6 iterations on the GPU")
+    f = cwb.Fit(prob)
+    _say(f"tile {f.tile()}")
+    f.run(M)
+    f.sync()
+    gpu = f.trace()
+    gpu.update(f.model())
+    gpu["f"] = f.pred()
+    f.close()
+    compare(gpu, dict(prob, M=M))
