@@ -30,6 +30,7 @@ constexpr int kMaxBins = 8192;   // largest n* (one learner's histogram must fit
 constexpr int kNumSig = 2;       // signals: pseudo-residuals r, corrected residuals c
 constexpr int kStageBins = 2048; // learners up to this many bins are solved from LDS
 constexpr int kMaxSlots = 512;   // segment slots staged per learner group and pass
+constexpr int kInlineOffs = 8;   // segment offsets carried in a select item (signal 0)
 constexpr int kHistMaxLds = 152 * 1024;  // dynamic LDS of one histogram block
 
 // Unbinned cubic P-spline learners.  Knots are equally spaced, so the four
@@ -54,19 +55,22 @@ struct FeatDev {
 };
 
 // Mutable per-fit control block, written only by kernels after create.
+// Each field has one writing kernel, and no block of that kernel reads it,
+// so no kernel races with itself:
+//   sel_done, sel_acwb      written by k_select (learner 0's block)
+//   pick_done               written by k_state (block 0) and k_finalize
+//   fin_done                written by k_finalize
+//   switched, switch_iter, counter, rval_prev   written by k_valdecide
 struct Ctl {
-  int32_t m_done;       // iterations whose selection is complete
-  int32_t pending;      // update tables of iteration m_done not yet applied
-  int32_t pend_acwb;    // iteration m_done was an ACWB step
-  int32_t k;            // learner selected in iteration m_done
-  int32_t kcor;         // correction learner of iteration m_done (-1: none)
+  int32_t sel_done;     // selections made (iterations whose criteria are in q)
+  int32_t pick_done;    // selections recorded in the traces and applied
+  int32_t fin_done;     // sel_done at the last finalize (which applied it)
+  int32_t sel_acwb;     // selection sel_done was an ACWB step (two signals)
   int32_t switched;     // HCWB: CWB phase reached
   int32_t switch_iter;  // HCWB: first CWB iteration (-1 until switched)
   int32_t counter;      // HCWB: consecutive validation-risk rises
-  double eta;           // momentum step of iteration m_done
-  double rval_prev;     // HCWB: validation risk of the previous model
   int32_t error;        // non-finite model state seen
-  int32_t pad;
+  double rval_prev;     // HCWB: validation risk of the previous model
 };
 
 struct FitDev {
@@ -131,6 +135,7 @@ struct StateItem {   // one row-pass block
 // A row-pass block with every pointer and size it needs.
 struct RowItem {
   Ctl* ctl;
+  const double* q;      // the fit's criteria [kNumSig][p] of the last selection
   const uint16_t* X;
   const float* y;
   float* fg;
@@ -141,7 +146,7 @@ struct RowItem {
   double* risk_part;    // &risk_part[2 * blk]
   float* amax_part;     // &amax_part[2 * blk]
   int64_t n, n_pad, n_train, base;  // base: first row of the block
-  double nu;
+  double nu, gamma;
   int32_t p, nb_max, loss, variant;
   int32_t M, two, blk, fit;          // two: the fit keeps h and c
   int32_t unbinned, pad_;            // X holds 32-bit unbinned codes
@@ -158,9 +163,13 @@ struct SelItem {
   const int32_t* bstart;
   const int32_t* jr;
   const int64_t* offs;        // its histogram offsets: offs[sig * n_off + i]
+  int64_t off0[kInlineOffs];  // the first offsets of signal 0, inline
   double* q;                  // &q[k] (signal 1 at + p)
   double* theta;              // &theta[k * d_max] (signal 1 at + p * d_max)
   float* table;               // &table[k * nb_max] (signal 1 at + p * nb_max)
+  double* tr_risk;            // the fit's risk traces (written by learner 0's block)
+  double* tr_val;
+  const double* risk_part;    // the fit's row-pass risk partials
   int64_t n, n_train;
   int32_t k, nb, band, d;
   int32_t n_off, d_max, nb_max, p;

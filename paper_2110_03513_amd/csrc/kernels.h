@@ -6,8 +6,8 @@
 
 namespace cwb {
 
-hipError_t launch_state(hipStream_t st, const RowItem* items, int nitems, int nb_max,
-                        int final_mode);
+hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items, int nitems,
+                        int nb_max, int final_mode);
 hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, int blocks,
                        size_t lds, const FitDev* fits, const Seg* segs, const int64_t* blk,
                        long long* partials);
@@ -15,7 +15,6 @@ hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int n
                          const long long* partials);
 hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* items, int nitems,
                           int nb_max);
-hipError_t launch_pick(hipStream_t st, const FitDev* fits, int nfits);
 hipError_t launch_valdecide(hipStream_t st, const FitDev* fits, int nfits);
 hipError_t launch_finalize(hipStream_t st, const FitDev* fits, int nfits);
 // Aggregated coefficients of one fit (sum_d of them) from its traces.

@@ -2,7 +2,9 @@
 //
 // Per iteration m (Algorithm A1 for CWB, Algorithm 2 for ACWB, Algorithm 3
 // for HCWB) the host enqueues, for every fit of a batch at once:
-//   k_state   row pass: apply the update tables selected in iteration m-1
+//   k_state   row pass: take over the selection of iteration m-1 (every block
+//             computes the chosen learners from the criteria; the fit's first
+//             block records them in the traces), apply its update
 //             (f += nu b_k, h += eta b_kcor), form g = (1-theta_m) f +
 //             theta_m h (ACWB), the pseudo-residuals r = -dL/df and the
 //             error-corrected residuals c (ACWB), FP64 partial risks, and the
@@ -18,12 +20,13 @@
 //             (second stage of binMatVec), theta = (G + lambda D)^-1 v with
 //             the cached inverse (Section 2.4), criterion
 //             q = theta^T G theta - 2 theta^T v, so SSE_k = r^T r + q_k
-//             (Algorithm A1's SSE), and the candidate update table Z^b theta.
-//   k_pick    one block per fit: argmin_k q (ties to the lowest k), traces,
-//             aggregated coefficients (Section 2.3 / 3.2.1), and the update
-//             armed for the next row pass.
+//             (Algorithm A1's SSE), and the candidate update table Z^b theta;
+//             learner 0's block also records the risk of f^[m-1].
 //   k_valrisk (HCWB, ACWB phase) validation-risk partials of the new primary
 //   k_valdecide  model, then the patience counter that decides the switch.
+// The argmin over q needs every learner's criterion, so it cannot run in
+// k_select; instead each block of the next kernel that needs the chosen
+// learners computes it from q (p values).
 // Cross-block results pass through kernel boundaries only: on this chip a
 // device-scope fence writes back the issuing XCD's L2, which is far more
 // expensive than one more launch.
@@ -119,24 +122,91 @@ __device__ float block_max(float v, float* red) {
   return m;
 }
 
-// Scale exponent of signal `sig` of a fit: maximum over the row-pass blocks
-// maxima (order-free, so every block computes the same value).  red must
-// hold NT + 16 floats.
+// Two FP64 sums and two float maxima of a block in one pass: butterfly
+// shuffles within each wavefront (every lane gets the same, fixed-order
+// result), then thread 0 combines the wavefronts in order.  `red` holds
+// 4 * (NT / 64) doubles.  Results are valid in thread 0.
 template <int NT>
-__device__ int fit_scale_exponent(const FitDev& F, int sig, int64_t n_fit, float* red) {
-  float a = 0.0f;
+__device__ __forceinline__ void block_sum2_max2(double& s0, double& s1, float& m0, float& m1,
+                                                double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+    m0 = fmaxf(m0, __shfl_xor(m0, off, 64));
+    m1 = fmaxf(m1, __shfl_xor(m1, off, 64));
+  }
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    red[4 * w] = s0;
+    red[4 * w + 1] = s1;
+    red[4 * w + 2] = (double)m0;
+    red[4 * w + 3] = (double)m1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s0 = red[0];
+    s1 = red[1];
+    m0 = (float)red[2];
+    m1 = (float)red[3];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) {
+      s0 += red[4 * i];
+      s1 += red[4 * i + 1];
+      m0 = fmaxf(m0, (float)red[4 * i + 2]);
+      m1 = fmaxf(m1, (float)red[4 * i + 3]);
+    }
+  }
+}
+
+// Block maxima of two non-negative floats (every thread gets both).  `red`
+// holds 2 * (NT / 64) floats.
+template <int NT>
+__device__ __forceinline__ void block_max2(float& m0, float& m1, float* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    m0 = fmaxf(m0, __shfl_xor(m0, off, 64));
+    m1 = fmaxf(m1, __shfl_xor(m1, off, 64));
+  }
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = m0;
+    red[2 * w + 1] = m1;
+  }
+  __syncthreads();
+  m0 = red[0];
+  m1 = red[1];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {
+    m0 = fmaxf(m0, red[2 * i]);
+    m1 = fmaxf(m1, red[2 * i + 1]);
+  }
+  __syncthreads();
+}
+
+// Scale exponents of both signals of a fit: maxima over the row-pass
+// blocks' maxima (order-free, so every block computes the same values).
+template <int NT>
+__device__ void fit_scale_exponents(const FitDev& F, int64_t n_fit, int* e0, int* e1, float* red) {
+  float a = 0.0f, b = 0.0f;
   const GLOBAL float* am = gp(F.amax_part);
   for (int b0 = 0; b0 < F.n_row_blocks; b0 += 4 * NT) {
-    float v[4];
+    float v[4], w[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int b = b0 + u * NT + (int)threadIdx.x;
-      v[u] = (b < F.n_row_blocks) ? am[2 * b + sig] : 0.0f;
+      const int k = b0 + u * NT + (int)threadIdx.x;
+      v[u] = (k < F.n_row_blocks) ? am[2 * k] : 0.0f;
+      w[u] = (k < F.n_row_blocks) ? am[2 * k + 1] : 0.0f;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a = fmaxf(a, v[u]);
+    for (int u = 0; u < 4; ++u) {
+      a = fmaxf(a, v[u]);
+      b = fmaxf(b, w[u]);
+    }
   }
-  return scale_exponent(block_max<NT>(a, red), n_fit);
+  block_max2<NT>(a, b, red);
+  *e0 = scale_exponent(a, n_fit);
+  *e1 = scale_exponent(b, n_fit);
 }
 
 // Copy `count` elements from global memory to LDS with all of a thread's
@@ -221,27 +291,130 @@ __device__ __forceinline__ float table_at(bool unb, uint32_t idx, const float* t
   return unb ? unb_eval(idx, tab) : tab[idx];
 }
 
+__device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
+  return qa < qb || (qa == qb && ka < kb);
+}
+
+// Running argmin (ties: lowest k) with the runner-up value.
+struct Arg2 {
+  double b1, b2;
+  int k1;
+  __device__ __forceinline__ void add(double v, int k) {
+    if (better(v, k, b1, k1)) {
+      b2 = b1;
+      b1 = v;
+      k1 = k;
+    } else if (v < b2) {
+      b2 = v;
+    }
+  }
+  __device__ __forceinline__ void merge(double c1, double c2, int kc) {
+    if (better(c1, kc, b1, k1)) {
+      b2 = fmin(b1, c2);
+      b1 = c1;
+      k1 = kc;
+    } else {
+      b2 = fmin(b2, c1);
+    }
+  }
+};
+
+// The learners chosen by the last selection (Algorithm A1's argmin over the
+// criteria q, ties to the lowest k; with nsig = 2 also the ACWB correction
+// fit of Algorithm 2), computed by every block that needs them from q
+// itself, so that no kernel publishes them to the blocks of the next one.
+// `gap` is the runner-up minus the best criterion of signal 0; `bad` flags
+// criteria that are all non-finite (the learners are then 0).
+struct Picked {
+  int k0, k1;
+  double gap;
+  bool bad;
+};
+
+// Argmin of one signal within a wavefront (64 lanes) by butterfly shuffles;
+// every lane ends with the wavefront's result.
+__device__ __forceinline__ void wave_arg2(Arg2& a) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double c1 = __shfl_xor(a.b1, off, 64);
+    const double c2 = __shfl_xor(a.b2, off, 64);
+    const int kc = __shfl_xor(a.k1, off, 64);
+    a.merge(c1, c2, kc);
+  }
+}
+
+// `v0`, `v1`: this thread's criteria q[t], q[p + t] for t = threadIdx.x,
+// loaded early by the caller (INFINITY past p); the rest is loaded here.
+template <int NT>
+__device__ Picked block_pick(const double* q_, int p, int nsig, double v0, double v1,
+                             Arg2 (*s_w)[NT / 64]) {
+  const GLOBAL double* q = gp(q_);
+  Arg2 a0{INFINITY, INFINITY, p}, a1{INFINITY, INFINITY, p};
+  if ((int)threadIdx.x < p) {
+    a0.add(v0, threadIdx.x);
+    if (nsig == 2) a1.add(v1, threadIdx.x);
+  }
+  for (int t = threadIdx.x + NT; t < p; t += NT) {
+    a0.add(q[t], t);
+    if (nsig == 2) a1.add(q[p + t], t);
+  }
+  wave_arg2(a0);
+  if (nsig == 2) wave_arg2(a1);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    s_w[0][w] = a0;
+    s_w[1][w] = a1;
+  }
+  __syncthreads();
+  Arg2 r0 = s_w[0][0], r1 = s_w[1][0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {  // fixed order: the same result in every block
+    r0.merge(s_w[0][i].b1, s_w[0][i].b2, s_w[0][i].k1);
+    r1.merge(s_w[1][i].b1, s_w[1][i].b2, s_w[1][i].k1);
+  }
+  __syncthreads();
+  Picked r;
+  r.k0 = r0.k1;
+  r.k1 = (nsig == 2) ? r1.k1 : -1;
+  r.gap = r0.b2 - r0.b1;
+  r.bad = r.k0 >= p || (nsig == 2 && r.k1 >= p);
+  if (r.bad) {
+    r.k0 = 0;
+    r.k1 = (nsig == 2) ? 0 : -1;
+  }
+  return r;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Row pass.
 // ---------------------------------------------------------------------------
+// Row pass of iteration m = sel_done + 1 (in final mode: no new
+// iteration).  It first takes over the selection made by the last k_select,
+// unless a finalize already did: every block computes the chosen learners
+// from q, block 0 records them in the traces, and every block applies the
+// update to its rows (f = g + nu b_k; ACWB: h += eta b_kcor with
+// eta = gamma nu (S + 1) / 2 for selection S).
 __global__ void __launch_bounds__(kStateThreads)
-k_state(const RowItem* __restrict__ items, int final_mode) {
+k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int final_mode) {
   extern __shared__ float s_tab[];  // [2][nb_max]
   __shared__ double s_red[kStateThreads + 16];
-  __shared__ float s_fred[kStateThreads + 16];
+  __shared__ Arg2 s_w[2][kStateThreads / 64];
   __shared__ int s_bad;
   const RowItem it = items[blockIdx.x];
-  // one round: the control block and this thread's rows of the model state
-  const Ctl* ctl = it.ctl;
-  const int m_done = ctl->m_done;
-  const int pending = ctl->pending;
-  const int pend_acwb = ctl->pend_acwb;
-  const int kk = ctl->k;
-  const int kc = ctl->kcor;
+  // one round: the control block, the criteria of the last selection and
+  // this thread's rows of the model state
+  double qv0 = INFINITY, qv1 = INFINITY;
+  if ((int)threadIdx.x < it.p) {
+    qv0 = gp(it.q)[threadIdx.x];
+    qv1 = gp(it.q)[it.p + threadIdx.x];  // used only after an ACWB selection
+  }
+  Ctl* ctl = it.ctl;
+  const int S = ctl->sel_done;
+  const int fin = ctl->fin_done;
+  const int sel_acwb = ctl->sel_acwb;
   const int switched = ctl->switched;
-  const float eta = (float)ctl->eta;
   const int64_t base = it.base + (int64_t)threadIdx.x * kRowsPerThread;
   const bool rows = base < it.n_pad;
   const bool two = it.two != 0;
@@ -254,18 +427,49 @@ k_state(const RowItem* __restrict__ items, int final_mode) {
       load8f(it.c + base, cv);
     }
   }
-  if (!final_mode && m_done >= it.M) return;
+  if (!final_mode && S >= it.M) {
+    // all M selections made (a batch runs on for other fits): mark the fit
+    // done for the histogram and select passes; finalize records the last
+    // selection
+    if (it.blk == 0 && threadIdx.x == 0) ctl->pick_done = it.M;
+    return;
+  }
   const float nu = (float)it.nu;
-  const int m = m_done + 1;
+  const int m = S + 1;
   const bool acwb =
       !final_mode && (it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched));
   const int64_t n_fit = (it.variant == CWB_HCWB && switched) ? it.n : it.n_train;
   const int nb = it.nb_max;
   float* tf = s_tab;
   float* tc = s_tab + nb;
-  const bool use_t = pending != 0;
-  const bool use_h = pending && pend_acwb && kc >= 0;
-  const bool use_cc = acwb && m > 1 && kc >= 0;
+  // the last selection: its learners, and whether its update is still to apply
+  const bool have_sel = S >= 1;
+  const bool do_pick = have_sel && fin != S;
+  Picked pk{0, -1, 0.0, false};
+  if (have_sel) pk = block_pick<kStateThreads>(it.q, it.p, sel_acwb ? 2 : 1, qv0, qv1, s_w);
+  const int kk = pk.k0;
+  const int kc = pk.k1;
+  const float eta = (float)(it.gamma * it.nu / (2.0 / ((double)S + 1.0)));
+  if (do_pick && it.blk == 0) {  // the fit's first row block records the selection
+    const FitDev& F = fits[it.fit];
+    const int mi = S - 1;
+    const int dmax = F.d_max;
+    const GLOBAL double* th = gp(F.theta);
+    for (int j = threadIdx.x; j < dmax; j += kStateThreads) {
+      F.tr_theta[(size_t)mi * dmax + j] = th[(size_t)kk * dmax + j];
+      F.tr_thetacor[(size_t)mi * dmax + j] = (kc >= 0) ? th[((size_t)F.p + kc) * dmax + j] : 0.0;
+    }
+    if (threadIdx.x == 0) {
+      F.tr_k[mi] = kk;
+      F.tr_kcor[mi] = kc;
+      F.tr_gap[mi] = pk.gap;
+      ctl->pick_done = S;
+    }
+  }
+  if (pk.bad && threadIdx.x == 0) atomicOr(&ctl->error, 1);
+  const bool use_t = do_pick;
+  const bool use_h = do_pick && sel_acwb && kc >= 0;
+  const bool use_cc = acwb && have_sel && sel_acwb && kc >= 0;
   uint32_t ik[8], ic[8];
   const bool unb = it.unbinned != 0;
   if (unb) {
@@ -331,10 +535,9 @@ k_state(const RowItem* __restrict__ items, int final_mode) {
     }
   }
   if (bad) s_bad = 1;
-  const double st = block_sum<kStateThreads>(risk_t, s_red);
-  const double sv = block_sum<kStateThreads>(risk_v, s_red);
-  const float a = block_max<kStateThreads>(amax_r, s_fred);
-  const float b = block_max<kStateThreads>(amax_c, s_fred);
+  double st = risk_t, sv = risk_v;
+  float a = amax_r, b = amax_c;
+  block_sum2_max2<kStateThreads>(st, sv, a, b, s_red);
   if (threadIdx.x == 0) {
     it.risk_part[0] = st;
     it.risk_part[1] = sv;
@@ -393,18 +596,23 @@ __device__ __forceinline__ void hist_step_load(const FitDev& F, const uint16_t* 
 // step: one 32-byte load of residuals per signal and one 16-byte load of bin
 // indices per learner of the group, then 8 LDS atomics per learner and
 // signal.  The next step's loads are issued before this step's atomics.
+// With `need_e`, the fit's scale exponents are computed (by all threads)
+// while the first step's loads are in flight.
 template <int NT, int FMAX, int NSIG>
 __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
                                           unsigned long long* __restrict__ hist, int nb,
-                                          int64_t r0, int64_t r1, int e0, int e1) {
+                                          int64_t r0, int64_t r1, int& e0, int& e1, bool need_e,
+                                          int64_t n_fit, float* red) {
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
   const int nf = sg.nf;
   const size_t ld = (size_t)F.n_pad;
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
-  if (base >= r1) return;
+  const bool any = base < r1;
   float rv[8], cv[8];
   u32x4 xw[FMAX];
-  hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
+  if (any) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
+  if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, red);
+  if (!any) return;
   for (;;) {
     const int64_t nxt = base + (int64_t)NT * 8;
     const bool more = nxt < r1;
@@ -494,7 +702,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const Seg sg = segs[s];
     const FitDev& F = fits[sg.fit];
     const Ctl* ctl = F.ctl;
-    if (ctl->m_done >= F.M) continue;
+    if (ctl->pick_done >= F.M) continue;
     const int switched = ctl->switched;
     const int nsig = is_acwb_step(F, switched) ? 2 : 1;
     const int64_t n_fit = rows_fitted(F, switched);
@@ -506,21 +714,19 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int64_t U = F.n_pad >> 3;
     const int64_t r0 = 8 * (sg.u0 * n8 / U);
     const int64_t r1 = 8 * (sg.u1 * n8 / U);
-    if (sg.fit != cached_fit) {
-      e0 = fit_scale_exponent<NT>(F, 0, n_fit, s_red);
-      e1 = (nsig == 2) ? fit_scale_exponent<NT>(F, 1, n_fit, s_red) : 0;
-      cached_fit = sg.fit;
-    }
+    const bool need_e = sg.fit != cached_fit;
+    cached_fit = sg.fit;
     if (UNB) {
+      if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, s_red);
       if (NSMAX == 1 || nsig == 1)
         uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
       else
         uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
     } else {
       if (NSMAX == 1 || nsig == 1)
-        hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
+        hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
       else
-        hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
+        hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
     }
     __syncthreads();
     GLOBAL long long* out = gp(partials + sg.slot);
@@ -545,39 +751,6 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
 // ---------------------------------------------------------------------------
 namespace {
 
-struct Best {
-  double q;
-  int k;
-};
-
-__device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
-  return qa < qb || (qa == qb && ka < kb);
-}
-
-// Running argmin (ties: lowest k) with the runner-up value.
-struct Arg2 {
-  double b1, b2;
-  int k1;
-  __device__ __forceinline__ void add(double v, int k) {
-    if (better(v, k, b1, k1)) {
-      b2 = b1;
-      b1 = v;
-      k1 = k;
-    } else if (v < b2) {
-      b2 = v;
-    }
-  }
-  __device__ __forceinline__ void merge(double c1, double c2, int kc) {
-    if (better(c1, kc, b1, k1)) {
-      b2 = fmin(b1, c2);
-      b1 = c1;
-      k1 = kc;
-    } else {
-      b2 = fmin(b2, c1);
-    }
-  }
-};
-
 // Deterministic sum of risk partials of the row-pass blocks.
 __device__ double sum_partials(const double* part, int count, int stride, int offset,
                                double* red) {
@@ -594,97 +767,6 @@ __device__ double sum_partials(const double* part, int count, int stride, int of
     for (int u = 0; u < 4; ++u) s += v[u];
   }
   return block_sum<kSelectThreads>(s, red);
-}
-
-// Selection of iteration m (Algorithm A1's argmin; with `nsig` = 2 also the
-// ACWB correction fit of Algorithm 2): argmin of the criteria, the traces,
-// and the update armed for the next row pass.  Two rounds of global loads:
-// the criteria of both signals with the risk partials, then the winners'
-// coefficients.  The aggregated coefficients are formed from the traces
-// when the model is read (k_coef).
-__device__ void pick(const FitDev& F, Ctl* ctl, int m, bool acwb, int nsig) {
-  __shared__ double s_b1[2][kSelectThreads], s_b2[2][kSelectThreads];
-  __shared__ int s_k[2][kSelectThreads];
-  __shared__ double s_red[kSelectThreads + 16];
-  const int p = F.p;
-  const GLOBAL double* q = gp(F.q);
-  const GLOBAL double* rp = gp(F.risk_part);
-  Arg2 a0{INFINITY, INFINITY, p}, a1{INFINITY, INFINITY, p};
-  double rt = 0.0, rv = 0.0;
-  const int n = p > F.n_row_blocks ? p : F.n_row_blocks;
-  for (int t = threadIdx.x; t < n; t += kSelectThreads) {
-    double v0 = INFINITY, v1 = INFINITY, r0 = 0.0, r1 = 0.0;
-    if (t < p) {
-      v0 = q[t];
-      if (nsig == 2) v1 = q[p + t];
-    }
-    if (t < F.n_row_blocks) {
-      r0 = rp[2 * (size_t)t];
-      r1 = rp[2 * (size_t)t + 1];
-    }
-    if (t < p) {
-      a0.add(v0, t);
-      if (nsig == 2) a1.add(v1, t);
-    }
-    rt += r0;
-    rv += r1;
-  }
-  s_b1[0][threadIdx.x] = a0.b1;
-  s_b2[0][threadIdx.x] = a0.b2;
-  s_k[0][threadIdx.x] = a0.k1;
-  s_b1[1][threadIdx.x] = a1.b1;
-  s_b2[1][threadIdx.x] = a1.b2;
-  s_k[1][threadIdx.x] = a1.k1;
-  __syncthreads();
-  for (int stride = kSelectThreads / 2; stride > 0; stride >>= 1) {
-    if (threadIdx.x < stride) {
-      const int o = threadIdx.x + stride;
-#pragma unroll
-      for (int sig = 0; sig < 2; ++sig) {
-        Arg2 a{s_b1[sig][threadIdx.x], s_b2[sig][threadIdx.x], s_k[sig][threadIdx.x]};
-        a.merge(s_b1[sig][o], s_b2[sig][o], s_k[sig][o]);
-        s_b1[sig][threadIdx.x] = a.b1;
-        s_b2[sig][threadIdx.x] = a.b2;
-        s_k[sig][threadIdx.x] = a.k1;
-      }
-    }
-    __syncthreads();
-  }
-  const double sum_t = block_sum<kSelectThreads>(rt, s_red);
-  const double sum_v = block_sum<kSelectThreads>(rv, s_red);
-  int k0 = s_k[0][0];
-  int k1 = (nsig == 2) ? s_k[1][0] : -1;
-  // criteria that are all non-finite select nothing: flag the fit
-  const bool bad = k0 >= p || (nsig == 2 && k1 >= p);
-  if (bad) {
-    k0 = 0;
-    k1 = (nsig == 2) ? 0 : -1;
-  }
-  const int mi = m - 1;
-  const int dmax = F.d_max;
-  const double vt = 2.0 / ((double)m + 1.0);
-  const double eta = acwb ? F.gamma * F.nu / vt : 0.0;
-  const GLOBAL double* th = gp(F.theta);
-  for (int j = threadIdx.x; j < dmax; j += kSelectThreads) {
-    const double t0 = th[(size_t)k0 * dmax + j];
-    const double t1 = (k1 >= 0) ? th[((size_t)p + k1) * dmax + j] : 0.0;
-    F.tr_theta[(size_t)mi * dmax + j] = t0;
-    F.tr_thetacor[(size_t)mi * dmax + j] = t1;
-  }
-  if (threadIdx.x == 0) {
-    F.tr_k[mi] = k0;
-    F.tr_kcor[mi] = k1;
-    F.tr_gap[mi] = s_b2[0][0] - s_b1[0][0];
-    F.tr_risk[mi] = sum_t / (double)F.n_train;  // risk of f^[m-1]
-    F.tr_val[mi] = (F.n > F.n_train) ? sum_v / (double)(F.n - F.n_train) : 0.0;
-    if (bad) ctl->error = 1;
-    ctl->pending = 1;
-    ctl->pend_acwb = acwb ? 1 : 0;
-    ctl->k = k0;
-    ctl->kcor = k1;
-    ctl->eta = eta;
-    ctl->m_done = m;
-  }
 }
 
 }  // namespace
@@ -736,9 +818,23 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   int* s_bs = reinterpret_cast<int*>(s_bv + (size_t)nb_cap * kMaxBand);
   const SelItem it = items[blockIdx.x];
   const int d = it.d, nb = it.nb, band = it.band, n_off = it.n_off;
+  // the first chunk of signal 0's partials, loaded in the first round when
+  // its offsets are inline (bins 4t .. 4t+3 of every segment)
+  const bool pre = n_off <= kInlineOffs && nb <= 4 * kSelectThreads;
+  i64x2 pv[kInlineOffs][2];
+  if (pre && 4 * (int)threadIdx.x < nb) {
+#pragma unroll
+    for (int i = 0; i < kInlineOffs; ++i) {
+      if (i < n_off) {
+        const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + it.off0[i] + 4 * threadIdx.x);
+        pv[i][0] = src[0];
+        pv[i][1] = src[1];
+      }
+    }
+  }
   // one round of independent loads: control block, signal maxima, offsets,
   // the learner's tables for the training-row Gram set
-  const int m_done = it.ctl->m_done;
+  const int P = it.ctl->pick_done;  // = iterations before this selection
   const int switched = it.ctl->switched;
   float am0 = 0.0f, am1 = 0.0f;
   {
@@ -770,24 +866,50 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       stage<kSelectThreads, 4>(s_bs, it.bstart, nb);
     }
   }
-  if (m_done >= it.M) return;
+  if (P >= it.M) return;
   const bool hcwb_all = it.variant == CWB_HCWB && switched;
   const bool acwb = it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched);
   const int nsig = acwb ? 2 : 1;
   const int64_t n_fit = hcwb_all ? it.n : it.n_train;
+  if (it.k == 0) {
+    // learner 0's block: the risk of f^[P] from this iteration's row pass,
+    // and the count and kind of this selection for the next row pass
+    const double rt = sum_partials(it.risk_part, it.n_row_blocks, 2, 0, s_part);
+    const double rv = sum_partials(it.risk_part, it.n_row_blocks, 2, 1, s_part);
+    if (threadIdx.x == 0) {
+      it.tr_risk[P] = rt / (double)it.n_train;
+      it.tr_val[P] = (it.n > it.n_train) ? rv / (double)(it.n - it.n_train) : 0.0;
+      it.ctl->sel_done = P + 1;
+      it.ctl->sel_acwb = acwb ? 1 : 0;
+    }
+  }
   if (hcwb_all) {  // HCWB after the switch: Grams over all rows
     __syncthreads();
     stage<kSelectThreads, 4>(s_ai, it.ainv[1], d * d);
     stage<kSelectThreads, 4>(s_g, it.gram[1], d * d);
   }
   const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{it.bval, it.bstart};
-  const float amax[2] = {block_max<kSelectThreads>(am0, s_red), block_max<kSelectThreads>(am1, s_red)};
+  block_max2<kSelectThreads>(am0, am1, s_red);
+  const float amax[2] = {am0, am1};
   for (int sig = 0; sig < nsig; ++sig) {
     const double isc = ldexp(1.0, -scale_exponent(amax[sig], n_fit));
     // bin sums s_l: exact int64 merge of the group's segment partials
     for (int l0 = 0; l0 < nb; l0 += 4 * kSelectThreads) {
       long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
       const int l = l0 + 4 * threadIdx.x;
+      if (pre && sig == 0) {  // l0 == 0: the preloaded chunk
+        if (l < nb) {
+#pragma unroll
+          for (int i = 0; i < kInlineOffs; ++i) {
+            if (i < n_off) {
+              a0 += pv[i][0].x;
+              a1 += pv[i][0].y;
+              a2 += pv[i][1].x;
+              a3 += pv[i][1].y;
+            }
+          }
+        }
+      } else
       for (int c0 = 0; c0 < n_off; c0 += kMaxSlots) {
         const int cnt = (n_off - c0) < kMaxSlots ? (n_off - c0) : kMaxSlots;
         const long long* so = s_off[sig];
@@ -857,38 +979,36 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   }
 }
 
-// Selection for every fit of the batch (one block per fit).
-__global__ void __launch_bounds__(kSelectThreads) k_pick(const FitDev* __restrict__ fits) {
-  const FitDev& F = fits[blockIdx.x];
-  Ctl* ctl = F.ctl;
-  const int m_done = ctl->m_done;
-  if (m_done >= F.M) return;
-  const bool acwb = is_acwb_step(F, ctl->switched);
-  pick(F, ctl, m_done + 1, acwb, acwb ? 2 : 1);
-}
-
 // ---------------------------------------------------------------------------
 // HCWB validation risk and patience (Algorithm 3).
 // ---------------------------------------------------------------------------
 namespace {
-// The validation check runs after an ACWB step of an HCWB fit that has not
-// switched yet, and once before the first iteration (m_done = 0).
+// The validation check runs after an ACWB selection of an HCWB fit that has
+// not switched yet, and once before the first iteration (no selection yet).
 __device__ __forceinline__ bool valcheck_due(const FitDev& F, const Ctl* ctl) {
   if (F.variant != CWB_HCWB || ctl->switched) return false;
-  return ctl->m_done == 0 || (ctl->pending && ctl->pend_acwb);
+  const int S = ctl->sel_done;
+  return S == 0 || (ctl->sel_acwb && S == ctl->pick_done + 1);  // a new ACWB selection
 }
 }  // namespace
 
+// Validation risk of the new primary model f^[m] = g + nu b_k (the
+// selection's update applied to the validation rows), or of f^[0].
 __global__ void __launch_bounds__(kStateThreads)
 k_valrisk(const FitDev* __restrict__ fits, const StateItem* __restrict__ items) {
   extern __shared__ float s_tf[];
   __shared__ double s_red[kStateThreads + 16];
+  __shared__ Arg2 s_w[2][kStateThreads / 64];
   const StateItem it = items[blockIdx.x];
   const FitDev& F = fits[it.fit];
   const Ctl* ctl = F.ctl;
   if (!valcheck_due(F, ctl)) return;
-  const bool init = ctl->m_done == 0;
-  const int kk = ctl->k;
+  const bool init = ctl->sel_done == 0;
+  int kk = 0;
+  if (!init) {
+    const double v0 = ((int)threadIdx.x < F.p) ? gp(F.q)[threadIdx.x] : INFINITY;
+    kk = block_pick<kStateThreads>(F.q, F.p, 1, v0, INFINITY, s_w).k0;
+  }
   const int nb = F.nb_max;
   const float nu = (float)F.nu;
   if (!init)
@@ -920,7 +1040,7 @@ __global__ void __launch_bounds__(kSelectThreads) k_valdecide(const FitDev* __re
   const FitDev& F = fits[blockIdx.x];
   Ctl* ctl = F.ctl;
   if (!valcheck_due(F, ctl)) return;
-  const bool init = ctl->m_done == 0;
+  const bool init = ctl->sel_done == 0;
   double t = 0.0;
   for (int b = threadIdx.x; b < F.n_val_blocks; b += kSelectThreads) t += F.val_part[b];
   const double tot = block_sum<kSelectThreads>(t, s_red);
@@ -930,7 +1050,7 @@ __global__ void __launch_bounds__(kSelectThreads) k_valdecide(const FitDev* __re
       if (R > ctl->rval_prev) ctl->counter += 1; else ctl->counter = 0;
       if (ctl->counter >= F.patience) {
         ctl->switched = 1;
-        ctl->switch_iter = ctl->m_done + 1;
+        ctl->switch_iter = ctl->sel_done + 1;
       }
     }
     ctl->rval_prev = R;
@@ -938,19 +1058,21 @@ __global__ void __launch_bounds__(kSelectThreads) k_valdecide(const FitDev* __re
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: after a final-mode row pass, record the risk of f^[m_done].
+// Finalize: after a final-mode row pass (which applied the last selection),
+// record the risk of f^[S] for the S selections made, and mark S applied.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kSelectThreads) k_finalize(const FitDev* __restrict__ fits) {
   __shared__ double s_red[kSelectThreads + 16];
   const FitDev& F = fits[blockIdx.x];
   Ctl* ctl = F.ctl;
-  const int m = ctl->m_done;
+  const int S = ctl->sel_done;
   const double rt = sum_partials(F.risk_part, F.n_row_blocks, 2, 0, s_red);
   const double rv = sum_partials(F.risk_part, F.n_row_blocks, 2, 1, s_red);
   if (threadIdx.x == 0) {
-    F.tr_risk[m] = rt / (double)F.n_train;
-    F.tr_val[m] = (F.n > F.n_train) ? rv / (double)(F.n - F.n_train) : 0.0;
-    ctl->pending = 0;
+    F.tr_risk[S] = rt / (double)F.n_train;
+    F.tr_val[S] = (F.n > F.n_train) ? rv / (double)(F.n - F.n_train) : 0.0;
+    ctl->pick_done = S;
+    ctl->fin_done = S;
   }
 }
 
@@ -966,7 +1088,7 @@ __global__ void __launch_bounds__(kSelectThreads) k_coef(const FitDev* __restric
   __shared__ int s_off[kCoefChunk], s_d[kCoefChunk], s_offc[kCoefChunk], s_dc[kCoefChunk];
   const FitDev& F = fits[blockIdx.y];
   const int a = blockIdx.x * kSelectThreads + threadIdx.x;
-  const int m_done = F.ctl->m_done;
+  const int m_done = F.ctl->pick_done;
   const int dmax = F.d_max;
   double cf = 0.0, ch = 0.0;
   for (int m0 = 0; m0 < m_done; m0 += kCoefChunk) {
@@ -1052,11 +1174,11 @@ hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t l
 
 }  // namespace
 
-hipError_t launch_state(hipStream_t st, const RowItem* items, int nitems, int nb_max,
-                        int final_mode) {
+hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items, int nitems,
+                        int nb_max, int final_mode) {
   if (nitems <= 0) return hipSuccess;
   const size_t lds = (size_t)2 * nb_max * sizeof(float);
-  hipLaunchKernelGGL(k_state, dim3(nitems), dim3(kStateThreads), lds, st, items, final_mode);
+  hipLaunchKernelGGL(k_state, dim3(nitems), dim3(kStateThreads), lds, st, fits, items, final_mode);
   return hipGetLastError();
 }
 
@@ -1104,12 +1226,6 @@ hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* i
   if (nitems <= 0) return hipSuccess;
   const size_t lds = (size_t)nb_max * sizeof(float);
   hipLaunchKernelGGL(k_valrisk, dim3(nitems), dim3(kStateThreads), lds, st, fits, items);
-  return hipGetLastError();
-}
-
-hipError_t launch_pick(hipStream_t st, const FitDev* fits, int nfits) {
-  if (nfits <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pick, dim3(nfits), dim3(kSelectThreads), 0, st, fits);
   return hipGetLastError();
 }
 

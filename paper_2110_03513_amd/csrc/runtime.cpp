@@ -467,14 +467,13 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Sch
   int tm = timed ? timed->timing : 0;
   if (tm && (timed->timing_counter++ % timed->timing_period) != 0) tm = 0;
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
-  HIP_TRY(launch_state(st, d_st, n_st, nb_max, 0));
+  HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   HIP_TRY(launch_select(st, d_sel, n_sel, nb_max, d_max, d_part));
-  HIP_TRY(launch_pick(st, d_fits, nfits));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   if (n_val > 0) {
     HIP_TRY(launch_valrisk(st, d_fits, d_val, n_val, nb_max));
@@ -494,6 +493,7 @@ RowItem make_row_item(int fit, int blk, const FitDev& D) {
   RowItem it;
   std::memset(&it, 0, sizeof(it));
   it.ctl = D.ctl;
+  it.q = D.q;
   it.X = D.X;
   it.y = D.y;
   it.fg = D.fg;
@@ -508,6 +508,7 @@ RowItem make_row_item(int fit, int blk, const FitDev& D) {
   it.n_train = D.n_train;
   it.base = (int64_t)blk * kStateRows;
   it.nu = D.nu;
+  it.gamma = D.gamma;
   it.p = D.p;
   it.nb_max = D.nb_max;
   it.loss = D.loss;
@@ -534,9 +535,13 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
   it.bstart = D.bstart + fd.bin_off;
   it.jr = D.jr + 2 * (int64_t)fd.coef_off;
   it.offs = d_sel_off + S.sel_begin[idx];
+  for (int i = 0; i < kInlineOffs && i < S.sel_n[idx]; ++i) it.off0[i] = S.sel_off[S.sel_begin[idx] + i];
   it.q = D.q + k;
   it.theta = D.theta + (int64_t)k * D.d_max;
   it.table = D.table + (int64_t)k * D.nb_max;
+  it.tr_risk = D.tr_risk;
+  it.tr_val = D.tr_val;
+  it.risk_part = D.risk_part;
   it.n = D.n;
   it.n_train = D.n_train;
   it.k = k;
@@ -557,7 +562,7 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
 int finalize_fit(cwb_fit* f) {
   HIP_TRY(hipSetDevice(f->device));
   RowItem* d_st = dptr<RowItem>(f->ws, f->lay.st_items);
-  HIP_TRY(launch_state(f->stream, d_st, f->n_st, f->shape.nb_max, 1));
+  HIP_TRY(launch_state(f->stream, f->d_fit, d_st, f->n_st, f->shape.nb_max, 1));
   HIP_TRY(launch_finalize(f->stream, f->d_fit, 1));
   return CWB_OK;
 }
@@ -780,7 +785,6 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
 
   Ctl ctl;
   std::memset(&ctl, 0, sizeof(ctl));
-  ctl.kcor = -1;
   ctl.switch_iter = -1;
   if (hf.variant == CWB_HCWB && hf.patience == 0) {
     ctl.switched = 1;
@@ -1001,6 +1005,8 @@ int cwb_fit_get_trace(cwb_fit* f, int32_t* k, double* theta, int32_t* k_cor, dou
 int cwb_fit_get_model(cwb_fit* f, double* intercept, double* coef_f, double* coef_h) {
   if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
   HIP_TRY(hipSetDevice(f->device));
+  int rc0 = finalize_fit(f);  // records the last selection
+  if (rc0) return rc0;
   HIP_TRY(launch_coef(f->stream, f->d_fit, f->shape.sum_d));
   HIP_TRY(hipStreamSynchronize(f->stream));
   int rc = check_device_error(f);
