@@ -36,10 +36,13 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the histogram pass's sources: the
+    kernel file, the device helpers it includes and the data layout."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2110_03513_amd", "csrc", "kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in ("hist.hip", "device_common.h", "cwb_internal.h"):
+        with open(os.path.join(ROOT, "paper_2110_03513_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

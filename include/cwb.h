@@ -195,6 +195,21 @@ int cwb_fit_get_model(cwb_fit* f, double* intercept, double* coef_f, double* coe
  * iterations done so far.  Synchronises the stream. */
 int cwb_fit_get_pred(cwb_fit* f, float* f_out);
 
+/* The fitted primary model at new rows (Section 2.3: f0 plus every
+ * learner's fitted function), enqueued on the fit's stream (the caller
+ * synchronises, e.g. with cwb_fit_sync).  x: DEVICE array of n x p doubles,
+ * column-major with column stride ldx >= n, raw feature values: P-spline
+ * values are clamped to the learner's training range and evaluated with the
+ * exact B-spline basis (not binned); categorical columns hold level codes
+ * (an invalid code gives NaN).  out: DEVICE array of n doubles.  Both stay
+ * owned by the caller.  INVALID_ARG for n < 0, ldx < n or NULL arrays. */
+int cwb_fit_predict(cwb_fit* f, const double* x, int64_t n, int64_t ldx, double* out);
+
+/* Partial effect of learner k (its fitted function alone, without f0) at n
+ * values: x and out are DEVICE arrays of n doubles; otherwise as
+ * cwb_fit_predict.  INVALID_ARG for k outside 0..p-1. */
+int cwb_fit_partial_effect(cwb_fit* f, int32_t k, const double* x, int64_t n, double* out);
+
 /* Checkpoint / resume: bytes of the mutable fit state (model vectors,
  * control block, traces, aggregated coefficients); save copies it to a host
  * buffer, load restores it into a fit created from the same problem. */

@@ -257,3 +257,30 @@ def max_threads() -> int:
 
 def set_threads(t: int) -> None:
     _load().orc_set_threads(int(t))
+
+
+def predict(problem: dict, result: dict, x_new) -> np.ndarray:
+    """The fitted primary model at new feature values (Section 2.3: the
+    intercept plus each learner's fitted function): each P-spline learner's
+    basis at x by the Cox-de Boor recursion on the knots of its training
+    range, with x clamped to that range; a categorical learner adds the
+    coefficient of the level.  ``result`` is an oracle fit of ``problem``."""
+    x = np.asarray(problem["x"], dtype=np.float64)
+    xn = np.atleast_2d(np.asarray(x_new, dtype=np.float64))
+    p = x.shape[1]
+    kind = _arr(problem["kind"], np.int32, p)
+    degree = int(problem.get("degree", 3))
+    n_knots = int(problem.get("n_knots", 20))
+    f = np.full(xn.shape[0], float(result["f0"]))
+    off = 0
+    for k in range(p):
+        d = int(result["d"][k])
+        c = result["coef_f"][off:off + d]
+        if kind[k] == 1:
+            f += c[xn[:, k].astype(np.int64)]
+        else:
+            lo, hi = float(x[:, k].min()), float(x[:, k].max())
+            t = knots(lo, hi, n_knots, degree)
+            f += bspline(np.clip(xn[:, k], lo, hi), t, degree) @ c
+        off += d
+    return f

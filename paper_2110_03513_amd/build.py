@@ -25,6 +25,7 @@ HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 
 SOURCES = [
     ("kernels.hip", DEVICE),
+    ("hist.hip", DEVICE),
     ("runtime.cpp", HOST),
     ("server.cpp", HOST + ["-pthread"]),
     ("setup.cpp", HOST + ["-ffp-contract=off", "-pthread"]),

@@ -52,6 +52,11 @@ struct FeatDev {
   int32_t coef_off;  // offset in the concatenated coefficient vectors
   int64_t bin_off;   // offset into the per-bin arrays
   int64_t mat_off;   // offset (doubles) into the d x d matrix arrays
+  double xmin, xmax; // P-spline: training range (knots equally spaced on it)
+  int32_t kind;      // CWB_PSPLINE or CWB_RIDGE_CAT
+  int32_t degree;    // P-spline degree
+  int32_t n_int;     // P-spline interior knots
+  int32_t pad;
 };
 
 // Mutable per-fit control block, written only by kernels after create.

@@ -1,0 +1,257 @@
+// hist.hip -- the histogram pass over the bin-index matrix (binMatVec,
+// Algorithm 1, first stage): for every learner k and design point l,
+// s_kl = sum of r_i over the rows with ind_ki = l, and the same for the
+// ACWB corrected residuals c.  Each block accumulates int64 fixed-point
+// sums in LDS and flushes them once per segment; int64 addition is exact,
+// so the result does not depend on the order of the atomics or on the
+// schedule.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace cwb {
+
+template <int NSIG>
+__device__ __forceinline__ void hist_add(unsigned long long* __restrict__ h, const u32x4& x,
+                                         const long long* q) {
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    __hip_atomic_fetch_add(h + (w[j] & 0xffffu), (unsigned long long)q[2 * j], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(h + (w[j] >> 16), (unsigned long long)q[2 * j + 1], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+__device__ __forceinline__ u32x4 load_idx(const uint16_t* p) {
+  return __builtin_nontemporal_load((const GLOBAL u32x4*)p);
+}
+
+
+template <int FMAX, int NSIG>
+__device__ __forceinline__ void hist_step_load(const FitDev& F, const uint16_t* __restrict__ Xg,
+                                               size_t ld, int nf, int64_t base, float* rv, float* cv,
+                                               u32x4* xw) {
+  load8f(F.r + base, rv);
+  if (NSIG == 2) load8f(F.c + base, cv);
+#pragma unroll
+  for (int f = 0; f < FMAX; ++f)
+    if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
+}
+
+// Rows [r0, r1) of one segment.  Every thread takes 8 consecutive rows per
+// step: one 32-byte load of residuals per signal and one 16-byte load of bin
+// indices per learner of the group, then 8 LDS atomics per learner and
+// signal.  The next step's loads are issued before this step's atomics.
+// With `need_e`, the fit's scale exponents are computed (by all threads)
+// while the first step's loads are in flight.
+template <int NT, int FMAX, int NSIG>
+__device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
+                                          unsigned long long* __restrict__ hist, int nb,
+                                          int64_t r0, int64_t r1, int& e0, int& e1, bool need_e,
+                                          int64_t n_fit, float* red) {
+  const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
+  const int nf = sg.nf;
+  const size_t ld = (size_t)F.n_pad;
+  int64_t base = r0 + (int64_t)threadIdx.x * 8;
+  const bool any = base < r1;
+  float rv[8], cv[8];
+  u32x4 xw[FMAX];
+  if (any) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
+  if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, red);
+  if (!any) return;
+  for (;;) {
+    const int64_t nxt = base + (int64_t)NT * 8;
+    const bool more = nxt < r1;
+    long long q0[8], q1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e0);
+    if (NSIG == 2) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e1);
+    }
+    u32x4 xc[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
+    if (more) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, nxt, rv, cv, xw);
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) {
+      if (f < nf) {
+        hist_add<NSIG>(hist + (size_t)f * nb, xc[f], q0);
+        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb, xc[f], q1);
+      }
+    }
+    if (!more) break;
+    base = nxt;
+  }
+}
+
+// Rows [r0, r1) of one segment of unbinned learners: per row and learner,
+// the four basis values at the row's code times r (and c), as int64 fixed
+// point, into the learner's basis sums (copy lane mod kUnbCopies, stride
+// d_max words).  |B r| <= |r|, and each basis sum gets at most one term per
+// row, so the exponent of the binned pass is safe here too.
+template <int NT, int FMAX, int NSIG>
+__device__ __forceinline__ void uhist_rows(const FitDev& F, const Seg& sg,
+                                           unsigned long long* __restrict__ hist, int nb,
+                                           int64_t r0, int64_t r1, int e0, int e1) {
+  const uint32_t* __restrict__ Xg =
+      reinterpret_cast<const uint32_t*>(F.X) + (size_t)sg.k0 * F.n_pad;
+  const int nf = sg.nf;
+  const size_t ld = (size_t)F.n_pad;
+  const int copy = ((int)threadIdx.x & (kUnbCopies - 1)) * F.d_max;
+  for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
+    float rv[8], cv[8];
+    load8f(F.r + base, rv);
+    if (NSIG == 2) load8f(F.c + base, cv);
+    uint32_t code[FMAX][8];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f)
+      if (f < nf) load8c(Xg + f * ld + base, code[f]);
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) {
+      if (f >= nf) continue;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        float b[4];
+        cubic4(code[f][j], b);
+        const int iv = (int)(code[f][j] >> 24);
+        unsigned long long* h0 = hist + (size_t)f * nb + copy + iv;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          __hip_atomic_fetch_add(h0 + a, (unsigned long long)fixed_point(b[a] * rv[j], e0),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (NSIG == 2) {
+          unsigned long long* h1 = hist + (size_t)(nf + f) * nb + copy + iv;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            __hip_atomic_fetch_add(h1 + a, (unsigned long long)fixed_point(b[a] * cv[j], e1),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+  }
+}
+
+// NSMAX: most signals any fit of the launch can have (1 when every fit is
+// plain CWB, so the two-signal path is not compiled in).  UNB: every fit of
+// the launch has unbinned learners.
+template <int NT, int FMAX, int NSMAX, bool UNB>
+__global__ void __launch_bounds__(NT)
+k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
+       const int64_t* __restrict__ blk, long long* __restrict__ partials) {
+  extern __shared__ unsigned long long s_hist[];
+  __shared__ float s_red[NT + 16];
+  const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
+  int cached_fit = -1;
+  int e0 = 0, e1 = 0;
+  for (int64_t s = s0; s < s1; ++s) {
+    const Seg sg = segs[s];
+    const FitDev& F = fits[sg.fit];
+    const Ctl* ctl = F.ctl;
+    if (ctl->pick_done >= F.M) continue;
+    const int switched = ctl->switched;
+    const int nsig = is_acwb_step(F, switched) ? 2 : 1;
+    const int64_t n_fit = rows_fitted(F, switched);
+    const int nb = F.nb_stride;
+    const int words = nsig * sg.nf * nb;
+    for (int i = threadIdx.x; i < words; i += NT) s_hist[i] = 0ull;
+    __syncthreads();
+    const int64_t n8 = (n_fit + 7) >> 3;
+    const int64_t U = F.n_pad >> 3;
+    const int64_t r0 = 8 * (sg.u0 * n8 / U);
+    const int64_t r1 = 8 * (sg.u1 * n8 / U);
+    const bool need_e = sg.fit != cached_fit;
+    cached_fit = sg.fit;
+    if (UNB) {
+      if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, s_red);
+      if (NSMAX == 1 || nsig == 1)
+        uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
+      else
+        uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
+    } else {
+      if (NSMAX == 1 || nsig == 1)
+        hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
+      else
+        hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
+    }
+    __syncthreads();
+    GLOBAL long long* out = gp(partials + sg.slot);
+    if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
+      const int d = F.d_max;
+      for (int i = threadIdx.x; i < nsig * sg.nf * d; i += NT) {
+        const int lf = i / d, b = i - lf * d;
+        long long acc = 0;
+#pragma unroll
+        for (int c = 0; c < kUnbCopies; ++c) acc += (long long)s_hist[(size_t)lf * nb + c * d + b];
+        out[(size_t)lf * nb + b] = acc;
+      }
+    } else {
+      for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
+    }
+    __syncthreads();
+  }
+}
+
+
+namespace {
+
+template <int NT, int FMAX, int NSMAX, bool UNB>
+hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
+                         const int64_t* blk, long long* partials) {
+  // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB);
+  // set once (thread-safe static initialisation), before any graph capture
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, UNB>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, UNB>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
+                     partials);
+  return hipGetLastError();
+}
+
+template <int NT, int NSMAX, bool UNB>
+hipError_t launch_hist_nt(hipStream_t st, int fmax, int blocks, size_t lds, const FitDev* fits,
+                          const Seg* segs, const int64_t* blk, long long* partials) {
+  switch (fmax) {
+    case 1: return launch_hist_t<NT, 1, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 2: return launch_hist_t<NT, 2, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 4: return launch_hist_t<NT, 4, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 8: return launch_hist_t<NT, 8, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
+    case 16:
+      if (!UNB) return launch_hist_t<NT, 16, NSMAX, false>(st, blocks, lds, fits, segs, blk, partials);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NSMAX, bool UNB>
+hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
+                          const FitDev* fits, const Seg* segs, const int64_t* blk,
+                          long long* partials) {
+  switch (nt) {
+    case 256: return launch_hist_nt<256, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 512: return launch_hist_nt<512, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 1024: return launch_hist_nt<1024, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, int blocks,
+                       size_t lds, const FitDev* fits, const Seg* segs, const int64_t* blk,
+                       long long* partials) {
+  if (blocks <= 0) return hipSuccess;
+  if (unbinned) {
+    if (nsmax == 1) return launch_hist_ns<1, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+    return launch_hist_ns<2, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  }
+  if (nsmax == 1) return launch_hist_ns<1, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_ns<2, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+}
+
+}  // namespace cwb

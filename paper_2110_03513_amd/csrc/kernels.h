@@ -17,6 +17,10 @@ hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* i
                           int nb_max);
 hipError_t launch_valdecide(hipStream_t st, const FitDev* fits, int nfits);
 hipError_t launch_finalize(hipStream_t st, const FitDev* fits, int nfits);
+// The fit's primary model (learners [k0, k1) plus f0) at n new rows of the
+// column-major device array x (column j: learner k0 + j).
+hipError_t launch_predict(hipStream_t st, const FitDev* fit, const double* x, int64_t n, int64_t ldx,
+                          double f0, int k0, int k1, double* out);
 // Aggregated coefficients of one fit (sum_d of them) from its traces.
 hipError_t launch_coef(hipStream_t st, const FitDev* fit, int sum_d);
 

@@ -1,4 +1,5 @@
-// kernels.hip -- gfx950 kernels of one boosting iteration.
+// kernels.hip -- gfx950 kernels of one boosting iteration (the histogram
+// pass is in hist.hip) and of model evaluation.
 //
 // Per iteration m (Algorithm A1 for CWB, Algorithm 2 for ACWB, Algorithm 3
 // for HCWB) the host enqueues, for every fit of a batch at once:
@@ -9,13 +10,10 @@
 //             theta_m h (ACWB), the pseudo-residuals r = -dL/df and the
 //             error-corrected residuals c (ACWB), FP64 partial risks, and the
 //             per-block largest |r|, |c| (fixed-point scale of the histograms).
-//   k_hist    histogram pass over the uint16 bin-index matrix: for every
-//             learner k and design point l, s_kl = sum of r_i over the rows
-//             with ind_ki = l (binMatVec, Algorithm 1, first stage), and the
-//             same for c.  Each block accumulates int64 fixed-point sums in
-//             LDS and flushes them once per segment; int64 addition is exact,
-//             so the result does not depend on the order of the atomics or on
-//             the schedule.
+//   k_hist    histogram pass over the uint16 bin-index matrix (hist.hip):
+//             for every learner k and design point l, s_kl = sum of r_i over
+//             the rows with ind_ki = l (binMatVec, Algorithm 1, first stage),
+//             and the same for c, as exact int64 fixed-point sums.
 //   k_select  one block per learner: merge the segment partials, v = Z^bT s
 //             (second stage of binMatVec), theta = (G + lambda D)^-1 v with
 //             the cached inverse (Section 2.4), criterion
@@ -30,362 +28,11 @@
 // Cross-block results pass through kernel boundaries only: on this chip a
 // device-scope fence writes back the issuing XCD's L2, which is far more
 // expensive than one more launch.
-#include <hip/hip_runtime.h>
-
-#include "../../include/cwb.h"
-#include "cwb_internal.h"
+#include "device_common.h"
 #include "kernels.h"
 
 namespace cwb {
 
-namespace {
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// Pointers read out of the fit descriptors are generic; casting them to the
-// global address space makes the compiler emit global_load/global_store
-// instead of flat accesses (flat accesses also count against the LDS
-// wait counter, which would serialise HBM loads behind LDS atomics).
-#define GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ GLOBAL T* gp(T* p) {
-  return (GLOBAL T*)p;
-}
-template <typename T>
-__device__ __forceinline__ const GLOBAL T* gp(const T* p) {
-  return (const GLOBAL T*)p;
-}
-
-__device__ __forceinline__ bool is_acwb_step(const FitDev& F, int switched) {
-  return F.variant == CWB_ACWB || (F.variant == CWB_HCWB && !switched);
-}
-__device__ __forceinline__ int64_t rows_fitted(const FitDev& F, int switched) {
-  return (F.variant == CWB_HCWB && switched) ? F.n : F.n_train;
-}
-__device__ __forceinline__ int gram_set(const FitDev& F, int switched) {
-  return (F.variant == CWB_HCWB && switched) ? 1 : 0;
-}
-
-// Pseudo-residual -dL/df (L2: (y-f)^2/2; binomial: log(1+e^f) - y f).
-__device__ __forceinline__ float neg_gradient(int loss, float y, float f) {
-  if (loss == CWB_L2) return y - f;
-  return y - 1.0f / (1.0f + expf(-f));
-}
-
-__device__ __forceinline__ double loss_value(int loss, float y, float f) {
-  const double fd = (double)f, yd = (double)y;
-  if (loss == CWB_L2) {
-    const double e = yd - fd;
-    return 0.5 * e * e;
-  }
-  const double sp = fd > 0.0 ? fd + log1p(exp(-fd)) : log1p(exp(fd));
-  return sp - yd * fd;
-}
-
-// Deterministic block sum (thread 0 gets the result): every thread stores its
-// value, 16 threads add 16 consecutive chunks in order, thread 0 adds those.
-// red must hold NT + 16 doubles.
-template <int NT>
-__device__ double block_sum(double v, double* red) {
-  constexpr int kParts = 16, kPer = NT / kParts;
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x < kParts) {
-    double a = 0.0;
-    for (int i = 0; i < kPer; ++i) a += red[threadIdx.x * kPer + i];
-    red[NT + threadIdx.x] = a;
-  }
-  __syncthreads();
-  double sum = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kParts; ++i) sum += red[NT + i];
-  __syncthreads();
-  return sum;
-}
-
-// Block maximum of non-negative floats (every thread gets the result);
-// red must hold NT + 16 floats.
-template <int NT>
-__device__ float block_max(float v, float* red) {
-  constexpr int kParts = 16, kPer = NT / kParts;
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x < kParts) {
-    float a = 0.0f;
-    for (int i = 0; i < kPer; ++i) a = fmaxf(a, red[threadIdx.x * kPer + i]);
-    red[NT + threadIdx.x] = a;
-  }
-  __syncthreads();
-  float m = 0.0f;
-  for (int i = 0; i < kParts; ++i) m = fmaxf(m, red[NT + i]);
-  __syncthreads();
-  return m;
-}
-
-// Two FP64 sums and two float maxima of a block in one pass: butterfly
-// shuffles within each wavefront (every lane gets the same, fixed-order
-// result), then thread 0 combines the wavefronts in order.  `red` holds
-// 4 * (NT / 64) doubles.  Results are valid in thread 0.
-template <int NT>
-__device__ __forceinline__ void block_sum2_max2(double& s0, double& s1, float& m0, float& m1,
-                                                double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off, 64);
-    s1 += __shfl_xor(s1, off, 64);
-    m0 = fmaxf(m0, __shfl_xor(m0, off, 64));
-    m1 = fmaxf(m1, __shfl_xor(m1, off, 64));
-  }
-  const int w = threadIdx.x / 64;
-  if ((threadIdx.x & 63) == 0) {
-    red[4 * w] = s0;
-    red[4 * w + 1] = s1;
-    red[4 * w + 2] = (double)m0;
-    red[4 * w + 3] = (double)m1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    s0 = red[0];
-    s1 = red[1];
-    m0 = (float)red[2];
-    m1 = (float)red[3];
-#pragma unroll
-    for (int i = 1; i < NT / 64; ++i) {
-      s0 += red[4 * i];
-      s1 += red[4 * i + 1];
-      m0 = fmaxf(m0, (float)red[4 * i + 2]);
-      m1 = fmaxf(m1, (float)red[4 * i + 3]);
-    }
-  }
-}
-
-// Block maxima of two non-negative floats (every thread gets both).  `red`
-// holds 2 * (NT / 64) floats.
-template <int NT>
-__device__ __forceinline__ void block_max2(float& m0, float& m1, float* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    m0 = fmaxf(m0, __shfl_xor(m0, off, 64));
-    m1 = fmaxf(m1, __shfl_xor(m1, off, 64));
-  }
-  const int w = threadIdx.x / 64;
-  if ((threadIdx.x & 63) == 0) {
-    red[2 * w] = m0;
-    red[2 * w + 1] = m1;
-  }
-  __syncthreads();
-  m0 = red[0];
-  m1 = red[1];
-#pragma unroll
-  for (int i = 1; i < NT / 64; ++i) {
-    m0 = fmaxf(m0, red[2 * i]);
-    m1 = fmaxf(m1, red[2 * i + 1]);
-  }
-  __syncthreads();
-}
-
-// Scale exponents of both signals of a fit: maxima over the row-pass
-// blocks' maxima (order-free, so every block computes the same values).
-template <int NT>
-__device__ void fit_scale_exponents(const FitDev& F, int64_t n_fit, int* e0, int* e1, float* red) {
-  float a = 0.0f, b = 0.0f;
-  const GLOBAL float* am = gp(F.amax_part);
-  for (int b0 = 0; b0 < F.n_row_blocks; b0 += 4 * NT) {
-    float v[4], w[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = b0 + u * NT + (int)threadIdx.x;
-      v[u] = (k < F.n_row_blocks) ? am[2 * k] : 0.0f;
-      w[u] = (k < F.n_row_blocks) ? am[2 * k + 1] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a = fmaxf(a, v[u]);
-      b = fmaxf(b, w[u]);
-    }
-  }
-  block_max2<NT>(a, b, red);
-  *e0 = scale_exponent(a, n_fit);
-  *e1 = scale_exponent(b, n_fit);
-}
-
-// Copy `count` elements from global memory to LDS with all of a thread's
-// loads (up to U per pass) issued before its stores, so a block pays one
-// memory round trip per pass instead of one per element it copies.
-template <int NT, int U, typename T>
-__device__ __forceinline__ void stage(T* dst, const T* src, int count) {
-  const GLOBAL T* g = gp(src);
-  for (int i0 = 0; i0 < count; i0 += NT * U) {
-    T v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * NT + (int)threadIdx.x;
-      if (i < count) v[u] = g[i];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * NT + (int)threadIdx.x;
-      if (i < count) dst[i] = v[u];
-    }
-  }
-}
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef long long i64x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void load8f(const float* p, float* v) {
-  const GLOBAL f32x4* q = (const GLOBAL f32x4*)p;
-  const f32x4 a = q[0], b = q[1];
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-
-__device__ __forceinline__ void store8f(float* p, const float* v) {
-  GLOBAL f32x4* q = (GLOBAL f32x4*)p;
-  f32x4 a, b;
-  a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
-  b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
-  q[0] = a;
-  q[1] = b;
-}
-
-__device__ __forceinline__ void load8u(const uint16_t* p, uint32_t* idx) {
-  const u32x4 w = *(const GLOBAL u32x4*)p;
-  idx[0] = w.x & 0xffffu; idx[1] = w.x >> 16;
-  idx[2] = w.y & 0xffffu; idx[3] = w.y >> 16;
-  idx[4] = w.z & 0xffffu; idx[5] = w.z >> 16;
-  idx[6] = w.w & 0xffffu; idx[7] = w.w >> 16;
-}
-
-// 8 unbinned codes (32-bit) of consecutive rows.
-__device__ __forceinline__ void load8c(const uint32_t* p, uint32_t* c) {
-  const u32x4 a = *(const GLOBAL u32x4*)p;
-  const u32x4 b = *(const GLOBAL u32x4*)(p + 4);
-  c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
-  c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
-}
-
-// The four nonzero cubic B-spline values at position t of a knot interval
-// (equally spaced knots: the uniform cubic segments).
-__device__ __forceinline__ void cubic4(uint32_t code, float* b) {
-  const float t = (float)(code & kUnbFracMax) * (1.0f / (float)kUnbFracMax);
-  const float s = 1.0f - t, t2 = t * t, t3 = t2 * t;
-  b[0] = s * s * s * (1.0f / 6.0f);
-  b[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
-  b[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
-  b[3] = t3 * (1.0f / 6.0f);
-}
-
-// (Z theta)_i of an unbinned learner: its basis at the row's code against
-// the coefficient table.
-__device__ __forceinline__ float unb_eval(uint32_t code, const float* tab) {
-  float b[4];
-  cubic4(code, b);
-  const int iv = (int)(code >> 24);
-  return b[0] * tab[iv] + b[1] * tab[iv + 1] + b[2] * tab[iv + 2] + b[3] * tab[iv + 3];
-}
-
-// Update-table lookup of one row: the bin's entry, or the basis expansion.
-__device__ __forceinline__ float table_at(bool unb, uint32_t idx, const float* tab) {
-  return unb ? unb_eval(idx, tab) : tab[idx];
-}
-
-__device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
-  return qa < qb || (qa == qb && ka < kb);
-}
-
-// Running argmin (ties: lowest k) with the runner-up value.
-struct Arg2 {
-  double b1, b2;
-  int k1;
-  __device__ __forceinline__ void add(double v, int k) {
-    if (better(v, k, b1, k1)) {
-      b2 = b1;
-      b1 = v;
-      k1 = k;
-    } else if (v < b2) {
-      b2 = v;
-    }
-  }
-  __device__ __forceinline__ void merge(double c1, double c2, int kc) {
-    if (better(c1, kc, b1, k1)) {
-      b2 = fmin(b1, c2);
-      b1 = c1;
-      k1 = kc;
-    } else {
-      b2 = fmin(b2, c1);
-    }
-  }
-};
-
-// The learners chosen by the last selection (Algorithm A1's argmin over the
-// criteria q, ties to the lowest k; with nsig = 2 also the ACWB correction
-// fit of Algorithm 2), computed by every block that needs them from q
-// itself, so that no kernel publishes them to the blocks of the next one.
-// `gap` is the runner-up minus the best criterion of signal 0; `bad` flags
-// criteria that are all non-finite (the learners are then 0).
-struct Picked {
-  int k0, k1;
-  double gap;
-  bool bad;
-};
-
-// Argmin of one signal within a wavefront (64 lanes) by butterfly shuffles;
-// every lane ends with the wavefront's result.
-__device__ __forceinline__ void wave_arg2(Arg2& a) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double c1 = __shfl_xor(a.b1, off, 64);
-    const double c2 = __shfl_xor(a.b2, off, 64);
-    const int kc = __shfl_xor(a.k1, off, 64);
-    a.merge(c1, c2, kc);
-  }
-}
-
-// `v0`, `v1`: this thread's criteria q[t], q[p + t] for t = threadIdx.x,
-// loaded early by the caller (INFINITY past p); the rest is loaded here.
-template <int NT>
-__device__ Picked block_pick(const double* q_, int p, int nsig, double v0, double v1,
-                             Arg2 (*s_w)[NT / 64]) {
-  const GLOBAL double* q = gp(q_);
-  Arg2 a0{INFINITY, INFINITY, p}, a1{INFINITY, INFINITY, p};
-  if ((int)threadIdx.x < p) {
-    a0.add(v0, threadIdx.x);
-    if (nsig == 2) a1.add(v1, threadIdx.x);
-  }
-  for (int t = threadIdx.x + NT; t < p; t += NT) {
-    a0.add(q[t], t);
-    if (nsig == 2) a1.add(q[p + t], t);
-  }
-  wave_arg2(a0);
-  if (nsig == 2) wave_arg2(a1);
-  const int w = threadIdx.x / 64;
-  if ((threadIdx.x & 63) == 0) {
-    s_w[0][w] = a0;
-    s_w[1][w] = a1;
-  }
-  __syncthreads();
-  Arg2 r0 = s_w[0][0], r1 = s_w[1][0];
-#pragma unroll
-  for (int i = 1; i < NT / 64; ++i) {  // fixed order: the same result in every block
-    r0.merge(s_w[0][i].b1, s_w[0][i].b2, s_w[0][i].k1);
-    r1.merge(s_w[1][i].b1, s_w[1][i].b2, s_w[1][i].k1);
-  }
-  __syncthreads();
-  Picked r;
-  r.k0 = r0.k1;
-  r.k1 = (nsig == 2) ? r1.k1 : -1;
-  r.gap = r0.b2 - r0.b1;
-  r.bad = r.k0 >= p || (nsig == 2 && r.k1 >= p);
-  if (r.bad) {
-    r.k0 = 0;
-    r.k1 = (nsig == 2) ? 0 : -1;
-  }
-  return r;
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // Row pass.
@@ -547,202 +194,6 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
       it.amax_part[1] = b;
     }
     if (s_bad) atomicOr(&it.ctl->error, 1);
-  }
-}
-
-template <int NSIG>
-__device__ __forceinline__ void hist_add(unsigned long long* __restrict__ h, const u32x4& x,
-                                         const long long* q) {
-  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    __hip_atomic_fetch_add(h + (w[j] & 0xffffu), (unsigned long long)q[2 * j], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(h + (w[j] >> 16), (unsigned long long)q[2 * j + 1], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
-}
-
-__device__ __forceinline__ u32x4 load_idx(const uint16_t* p) {
-  return __builtin_nontemporal_load((const GLOBAL u32x4*)p);
-}
-
-// trunc(r * 2^e) as int64, from the bits of the float: r = +-m 2^(x-150)
-// with a 24-bit integer m, so the product is m shifted by x - 150 + e.
-// Equal to casting the exact double product r * 2^e to int64.
-__device__ __forceinline__ long long fixed_point(float r, int e) {
-  const uint32_t u = __float_as_uint(r);
-  const uint32_t ex = (u >> 23) & 0xffu;
-  const uint32_t m = (u & 0x7fffffu) | (ex ? 0x800000u : 0u);
-  const int sh = (ex ? (int)ex : 1) - 150 + e;
-  unsigned long long mag;
-  if (sh >= 0) mag = (unsigned long long)m << sh;  // sh <= 62 - 24 by the choice of e
-  else mag = (sh > -32) ? (unsigned long long)(m >> (-sh)) : 0ull;
-  return (u >> 31) ? -(long long)mag : (long long)mag;
-}
-
-template <int FMAX, int NSIG>
-__device__ __forceinline__ void hist_step_load(const FitDev& F, const uint16_t* __restrict__ Xg,
-                                               size_t ld, int nf, int64_t base, float* rv, float* cv,
-                                               u32x4* xw) {
-  load8f(F.r + base, rv);
-  if (NSIG == 2) load8f(F.c + base, cv);
-#pragma unroll
-  for (int f = 0; f < FMAX; ++f)
-    if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
-}
-
-// Rows [r0, r1) of one segment.  Every thread takes 8 consecutive rows per
-// step: one 32-byte load of residuals per signal and one 16-byte load of bin
-// indices per learner of the group, then 8 LDS atomics per learner and
-// signal.  The next step's loads are issued before this step's atomics.
-// With `need_e`, the fit's scale exponents are computed (by all threads)
-// while the first step's loads are in flight.
-template <int NT, int FMAX, int NSIG>
-__device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
-                                          unsigned long long* __restrict__ hist, int nb,
-                                          int64_t r0, int64_t r1, int& e0, int& e1, bool need_e,
-                                          int64_t n_fit, float* red) {
-  const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
-  const int nf = sg.nf;
-  const size_t ld = (size_t)F.n_pad;
-  int64_t base = r0 + (int64_t)threadIdx.x * 8;
-  const bool any = base < r1;
-  float rv[8], cv[8];
-  u32x4 xw[FMAX];
-  if (any) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
-  if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, red);
-  if (!any) return;
-  for (;;) {
-    const int64_t nxt = base + (int64_t)NT * 8;
-    const bool more = nxt < r1;
-    long long q0[8], q1[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e0);
-    if (NSIG == 2) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e1);
-    }
-    u32x4 xc[FMAX];
-#pragma unroll
-    for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
-    if (more) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, nxt, rv, cv, xw);
-#pragma unroll
-    for (int f = 0; f < FMAX; ++f) {
-      if (f < nf) {
-        hist_add<NSIG>(hist + (size_t)f * nb, xc[f], q0);
-        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb, xc[f], q1);
-      }
-    }
-    if (!more) break;
-    base = nxt;
-  }
-}
-
-// Rows [r0, r1) of one segment of unbinned learners: per row and learner,
-// the four basis values at the row's code times r (and c), as int64 fixed
-// point, into the learner's basis sums (copy lane mod kUnbCopies, stride
-// d_max words).  |B r| <= |r|, and each basis sum gets at most one term per
-// row, so the exponent of the binned pass is safe here too.
-template <int NT, int FMAX, int NSIG>
-__device__ __forceinline__ void uhist_rows(const FitDev& F, const Seg& sg,
-                                           unsigned long long* __restrict__ hist, int nb,
-                                           int64_t r0, int64_t r1, int e0, int e1) {
-  const uint32_t* __restrict__ Xg =
-      reinterpret_cast<const uint32_t*>(F.X) + (size_t)sg.k0 * F.n_pad;
-  const int nf = sg.nf;
-  const size_t ld = (size_t)F.n_pad;
-  const int copy = ((int)threadIdx.x & (kUnbCopies - 1)) * F.d_max;
-  for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
-    float rv[8], cv[8];
-    load8f(F.r + base, rv);
-    if (NSIG == 2) load8f(F.c + base, cv);
-    uint32_t code[FMAX][8];
-#pragma unroll
-    for (int f = 0; f < FMAX; ++f)
-      if (f < nf) load8c(Xg + f * ld + base, code[f]);
-#pragma unroll
-    for (int f = 0; f < FMAX; ++f) {
-      if (f >= nf) continue;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        float b[4];
-        cubic4(code[f][j], b);
-        const int iv = (int)(code[f][j] >> 24);
-        unsigned long long* h0 = hist + (size_t)f * nb + copy + iv;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-          __hip_atomic_fetch_add(h0 + a, (unsigned long long)fixed_point(b[a] * rv[j], e0),
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (NSIG == 2) {
-          unsigned long long* h1 = hist + (size_t)(nf + f) * nb + copy + iv;
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-            __hip_atomic_fetch_add(h1 + a, (unsigned long long)fixed_point(b[a] * cv[j], e1),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-      }
-    }
-  }
-}
-
-// NSMAX: most signals any fit of the launch can have (1 when every fit is
-// plain CWB, so the two-signal path is not compiled in).  UNB: every fit of
-// the launch has unbinned learners.
-template <int NT, int FMAX, int NSMAX, bool UNB>
-__global__ void __launch_bounds__(NT)
-k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
-       const int64_t* __restrict__ blk, long long* __restrict__ partials) {
-  extern __shared__ unsigned long long s_hist[];
-  __shared__ float s_red[NT + 16];
-  const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
-  int cached_fit = -1;
-  int e0 = 0, e1 = 0;
-  for (int64_t s = s0; s < s1; ++s) {
-    const Seg sg = segs[s];
-    const FitDev& F = fits[sg.fit];
-    const Ctl* ctl = F.ctl;
-    if (ctl->pick_done >= F.M) continue;
-    const int switched = ctl->switched;
-    const int nsig = is_acwb_step(F, switched) ? 2 : 1;
-    const int64_t n_fit = rows_fitted(F, switched);
-    const int nb = F.nb_stride;
-    const int words = nsig * sg.nf * nb;
-    for (int i = threadIdx.x; i < words; i += NT) s_hist[i] = 0ull;
-    __syncthreads();
-    const int64_t n8 = (n_fit + 7) >> 3;
-    const int64_t U = F.n_pad >> 3;
-    const int64_t r0 = 8 * (sg.u0 * n8 / U);
-    const int64_t r1 = 8 * (sg.u1 * n8 / U);
-    const bool need_e = sg.fit != cached_fit;
-    cached_fit = sg.fit;
-    if (UNB) {
-      if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, s_red);
-      if (NSMAX == 1 || nsig == 1)
-        uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
-      else
-        uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
-    } else {
-      if (NSMAX == 1 || nsig == 1)
-        hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
-      else
-        hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
-    }
-    __syncthreads();
-    GLOBAL long long* out = gp(partials + sg.slot);
-    if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
-      const int d = F.d_max;
-      for (int i = threadIdx.x; i < nsig * sg.nf * d; i += NT) {
-        const int lf = i / d, b = i - lf * d;
-        long long acc = 0;
-#pragma unroll
-        for (int c = 0; c < kUnbCopies; ++c) acc += (long long)s_hist[(size_t)lf * nb + c * d + b];
-        out[(size_t)lf * nb + b] = acc;
-      }
-    } else {
-      for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
-    }
-    __syncthreads();
   }
 }
 
@@ -1123,56 +574,67 @@ __global__ void __launch_bounds__(kSelectThreads) k_coef(const FitDev* __restric
   }
 }
 
+// The fitted primary model at new feature values (Section 2.3: the
+// intercept plus every learner's fitted function).  Thread i takes row i of
+// the column-major x (column stride ldx) and adds, per learner, the B-spline
+// basis of degree 1..3 at x (clamped to the training range; equally spaced
+// knots, so the degree+1 nonzero values are the uniform segment polynomials
+// of the position t inside the knot interval) against the learner's
+// aggregated coefficients, or the coefficient of a categorical level (an
+// invalid level gives NaN).  FP64 throughout.
+__device__ __forceinline__ void uniform_basis(int degree, double t, double* b) {
+  const double s = 1.0 - t;
+  if (degree == 1) {
+    b[0] = s;
+    b[1] = t;
+  } else if (degree == 2) {
+    b[0] = 0.5 * s * s;
+    b[1] = 0.5 * (-2.0 * t * t + 2.0 * t + 1.0);
+    b[2] = 0.5 * t * t;
+  } else {
+    const double t2 = t * t, t3 = t2 * t;
+    b[0] = s * s * s / 6.0;
+    b[1] = (3.0 * t3 - 6.0 * t2 + 4.0) / 6.0;
+    b[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) / 6.0;
+    b[3] = t3 / 6.0;
+  }
+}
+
+// Learners [k0, k1) only: column k - k0 of x holds learner k's values (a
+// partial effect is one learner with f0 = 0).
+__global__ void __launch_bounds__(kStateThreads)
+k_predict(const FitDev* __restrict__ fits, const double* __restrict__ x, int64_t n, int64_t ldx,
+          double f0, int k0, int k1, double* __restrict__ out) {
+  const FitDev& F = fits[0];
+  const int64_t i = (int64_t)blockIdx.x * kStateThreads + threadIdx.x;
+  if (i >= n) return;
+  const GLOBAL double* xg = gp(x);
+  const GLOBAL double* cf = gp(F.coef_f);
+  double acc = f0;
+  for (int k = k0; k < k1; ++k) {
+    const FeatDev fd = F.feat[k];
+    const double v = xg[(size_t)(k - k0) * ldx + i];
+    if (fd.kind == CWB_RIDGE_CAT) {
+      const int lev = (int)v;
+      acc += (v >= 0.0 && lev < fd.d && (double)lev == v) ? cf[fd.coef_off + lev] : NAN;
+      continue;
+    }
+    const double xv = fmin(fmax(v, fd.xmin), fd.xmax);
+    const double hk = (fd.xmax - fd.xmin) / (double)(fd.n_int + 1);
+    const double u = (xv - fd.xmin) / hk;
+    int j = (int)floor(u);
+    j = j < 0 ? 0 : (j > fd.n_int ? fd.n_int : j);
+    const double t = fmin(fmax(u - (double)j, 0.0), 1.0);
+    double b[4];
+    uniform_basis(fd.degree, t, b);
+    for (int a = 0; a <= fd.degree; ++a) acc += b[a] * cf[fd.coef_off + j + a];
+  }
+  out[i] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-namespace {
-
-template <int NT, int FMAX, int NSMAX, bool UNB>
-hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
-                         const int64_t* blk, long long* partials) {
-  // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB);
-  // set once (thread-safe static initialisation), before any graph capture
-  static const bool attr = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, UNB>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
-    (void)hipGetLastError();
-    return true;
-  }();
-  (void)attr;
-  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, UNB>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
-                     partials);
-  return hipGetLastError();
-}
-
-template <int NT, int NSMAX, bool UNB>
-hipError_t launch_hist_nt(hipStream_t st, int fmax, int blocks, size_t lds, const FitDev* fits,
-                          const Seg* segs, const int64_t* blk, long long* partials) {
-  switch (fmax) {
-    case 1: return launch_hist_t<NT, 1, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 2: return launch_hist_t<NT, 2, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 4: return launch_hist_t<NT, 4, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 8: return launch_hist_t<NT, 8, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 16:
-      if (!UNB) return launch_hist_t<NT, 16, NSMAX, false>(st, blocks, lds, fits, segs, blk, partials);
-      return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int NSMAX, bool UNB>
-hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
-                          const FitDev* fits, const Seg* segs, const int64_t* blk,
-                          long long* partials) {
-  switch (nt) {
-    case 256: return launch_hist_nt<256, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 512: return launch_hist_nt<512, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 1024: return launch_hist_nt<1024, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-}  // namespace
 
 hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items, int nitems,
                         int nb_max, int final_mode) {
@@ -1182,17 +644,6 @@ hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items
   return hipGetLastError();
 }
 
-hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, int blocks,
-                       size_t lds, const FitDev* fits, const Seg* segs, const int64_t* blk,
-                       long long* partials) {
-  if (blocks <= 0) return hipSuccess;
-  if (unbinned) {
-    if (nsmax == 1) return launch_hist_ns<1, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-    return launch_hist_ns<2, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-  }
-  if (nsmax == 1) return launch_hist_ns<1, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-  return launch_hist_ns<2, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-}
 
 hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nb_max, int d_max,
                          const long long* partials) {
@@ -1239,6 +690,15 @@ hipError_t launch_coef(hipStream_t st, const FitDev* fits, int sum_d) {
   if (sum_d <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_coef, dim3((sum_d + kSelectThreads - 1) / kSelectThreads, 1), dim3(kSelectThreads),
                      0, st, fits);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(hipStream_t st, const FitDev* fit, const double* x, int64_t n, int64_t ldx,
+                          double f0, int k0, int k1, double* out) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kStateThreads - 1) / kStateThreads;
+  hipLaunchKernelGGL(k_predict, dim3((unsigned)blocks), dim3(kStateThreads), 0, st, fit, x, n, ldx,
+                     f0, k0, k1, out);
   return hipGetLastError();
 }
 

@@ -714,6 +714,12 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
     fd.coef_off = coef_off;
     fd.bin_off = bin_off;
     fd.mat_off = mat_off;
+    fd.xmin = hl.xmin;
+    fd.xmax = hl.xmax;
+    fd.kind = hl.kind;
+    fd.degree = hl.degree;
+    fd.n_int = hl.n_int;
+    fd.pad = 0;
     f->d[j] = hl.d;
     bstart.insert(bstart.end(), hl.bstart.begin(), hl.bstart.end());
     bval.insert(bval.end(), hl.bval.begin(), hl.bval.end());
@@ -1020,6 +1026,30 @@ int cwb_fit_get_model(cwb_fit* f, double* intercept, double* coef_f, double* coe
     else
       std::memset(coef_h, 0, sd * 8);
   }
+  return CWB_OK;
+}
+
+int cwb_fit_predict(cwb_fit* f, const double* x, int64_t n, int64_t ldx, double* out) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  if (n < 0 || (n > 0 && (!x || !out))) return set_error(CWB_E_INVALID_ARG, "null x or out");
+  if (ldx < n) return set_error(CWB_E_INVALID_ARG, "ldx must be at least n");
+  HIP_TRY(hipSetDevice(f->device));
+  int rc = finalize_fit(f);
+  if (rc) return rc;
+  HIP_TRY(launch_coef(f->stream, f->d_fit, f->shape.sum_d));
+  HIP_TRY(launch_predict(f->stream, f->d_fit, x, n, ldx, f->f0, 0, f->shape.p, out));
+  return CWB_OK;
+}
+
+int cwb_fit_partial_effect(cwb_fit* f, int32_t k, const double* x, int64_t n, double* out) {
+  if (!f) return set_error(CWB_E_INVALID_ARG, "null fit");
+  if (k < 0 || k >= f->shape.p) return set_error(CWB_E_INVALID_ARG, "learner index out of range");
+  if (n < 0 || (n > 0 && (!x || !out))) return set_error(CWB_E_INVALID_ARG, "null x or out");
+  HIP_TRY(hipSetDevice(f->device));
+  int rc = finalize_fit(f);
+  if (rc) return rc;
+  HIP_TRY(launch_coef(f->stream, f->d_fit, f->shape.sum_d));
+  HIP_TRY(launch_predict(f->stream, f->d_fit, x, n, n, 0.0, k, k + 1, out));
   return CWB_OK;
 }
 

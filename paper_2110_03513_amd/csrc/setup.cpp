@@ -420,6 +420,8 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
       const cwb_learner_spec& s = pr->specs[j];
       const double* xj = pr->x + (size_t)j * (size_t)(pr->ldx ? pr->ldx : n);
       HostLearner& L = hf->L[j];
+      L.degree = s.degree;
+      L.n_int = s.n_interior_knots;
       uint16_t* Xj = hf->unbinned ? nullptr : hf->X.data() + (size_t)j * hf->n_pad;
       uint32_t* XUj = hf->unbinned ? hf->XU.data() + (size_t)j * hf->n_pad : nullptr;
       L.kind = s.kind;

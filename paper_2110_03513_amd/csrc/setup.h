@@ -15,6 +15,7 @@ struct HostLearner {
   int band = 0;    // nonzeros per reduced-design row
   int d = 0;       // basis size
   double xmin = 0, xmax = 0;
+  int degree = 0, n_int = 0;     // P-spline degree and interior knots
   std::vector<int32_t> bstart;   // nb
   std::vector<double> bval;      // nb x kMaxBand
   std::vector<int32_t> jr;       // d x 2

@@ -95,6 +95,8 @@ _SIGNATURES = {
     "cwb_batch_sync": [_P],
     "cwb_batch_destroy": [_P],
     "cwb_fit_tile": [_P, C.POINTER(cwb_tile)],
+    "cwb_fit_predict": [_P, _P, C.c_int64, C.c_int64, _P],
+    "cwb_fit_partial_effect": [_P, C.c_int32, _P, C.c_int64, _P],
     "cwb_fit_set_timing_period": [_P, C.c_int32, C.c_int32],
     "cwb_batch_tile": [_P, C.POINTER(cwb_tile)],
     "cwb_server_create": [C.POINTER(cwb_server_cfg), C.POINTER(_P)],
@@ -266,6 +268,33 @@ class Fit:
         out = np.zeros(self.info.n, np.float32)
         check(lib().cwb_fit_get_pred(self.h, _ptr(out)))
         return out
+
+    def predict(self, x_new) -> np.ndarray:
+        """The fitted model at new rows (n x p raw feature values), on the GPU."""
+        torch = _torch()
+        xn = np.atleast_2d(np.asarray(x_new, dtype=np.float64))
+        n = xn.shape[0]
+        with torch.cuda.device(self.device):
+            xd = torch.from_numpy(np.ascontiguousarray(xn.T)).to(self.device)  # (p, n): column-major x
+            out = torch.empty(n, dtype=torch.float64, device=self.device)
+            torch.cuda.current_stream().synchronize()
+            check(lib().cwb_fit_predict(self.h, C.c_void_p(xd.data_ptr()), n, n,
+                                        C.c_void_p(out.data_ptr())))
+            check(lib().cwb_fit_sync(self.h))
+            return out.cpu().numpy()
+
+    def partial_effect(self, k: int, values) -> np.ndarray:
+        """Learner k's fitted function (without the intercept) at the given values."""
+        torch = _torch()
+        v = np.ascontiguousarray(np.asarray(values, dtype=np.float64).ravel())
+        with torch.cuda.device(self.device):
+            xd = torch.from_numpy(v).to(self.device)
+            out = torch.empty(v.shape[0], dtype=torch.float64, device=self.device)
+            torch.cuda.current_stream().synchronize()
+            check(lib().cwb_fit_partial_effect(self.h, int(k), C.c_void_p(xd.data_ptr()), v.shape[0],
+                                               C.c_void_p(out.data_ptr())))
+            check(lib().cwb_fit_sync(self.h))
+            return out.cpu().numpy()
 
     def save_state(self) -> bytes:
         n = C.c_size_t()

@@ -305,3 +305,41 @@ def test_unbinned_full_size_first_iterations():
     gpu["f"] = f.pred()
     f.close()
     compare(gpu, dict(prob, M=M))
+
+
+def test_predict_new_rows():
+    """The fitted model at new rows (values beyond the training range are
+    clamped): the GPU kernel against the oracle's Cox-de Boor evaluation of
+    the same coefficients (FP64, tight), and against the oracle's own fit."""
+    import oracle
+    prob = datagen.additive_problem(30_000, 8, seed=71, n_informative=4, n_bins=200, M=60,
+                                    n_cat=2, n_informative_cat=1, loss="binomial",
+                                    variant="acwb", gamma=0.05)
+    f = cwb.Fit(prob)
+    f.run(60)
+    f.sync()
+    rng = np.random.default_rng(72)
+    xn = rng.uniform(-0.2, 1.2, (5_000, 8))
+    for j in (6, 7):
+        xn[:, j] = rng.integers(0, prob["n_levels"][j], 5_000)
+    got = f.predict(xn)
+    model = f.model()
+    o = oracle.fit(prob)
+    same = oracle.predict(prob, {"f0": model["f0"], "coef_f": model["coef_f"], "d": o["d"]}, xn)
+    np.testing.assert_allclose(got, same, rtol=1e-11, atol=1e-11)
+    ref = oracle.predict(prob, o, xn)
+    assert rel_err(got, ref) <= 1e-4
+    bad = xn[:3].copy()
+    bad[0, 6] = prob["n_levels"][6]  # no such level
+    assert np.isnan(f.predict(bad)[0]) and np.isfinite(f.predict(bad)[1:]).all()
+    f.close()
+
+
+def test_predict_training_rows_of_unbinned_fit():
+    prob = datagen.additive_problem(20_000, 5, seed=73, n_informative=3, n_bins=0, M=40)
+    f = cwb.Fit(prob)
+    f.run(40)
+    f.sync()
+    got = f.predict(prob["x"])
+    assert rel_err(got, f.pred()) <= 1e-5  # the FP32 training state against FP64 evaluation
+    f.close()

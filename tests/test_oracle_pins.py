@@ -431,3 +431,27 @@ def test_rtr_is_signal_norm():
     out = oracle.fit(pr)
     np.testing.assert_allclose(out["rtr"], 2 * 500 * out["risk_train"][:-1], rtol=1e-12)
     assert (out["sse"] <= out["rtr"]).all()
+
+
+def test_prediction_reproduces_training_fit():
+    """The model evaluated at the training rows is the fit's own f when the
+    learners see exact values: unbinned splines, lossless binning (every
+    value on the equal grid) and categorical levels; values beyond the
+    training range are clamped to it."""
+    pr = datagen.tiny_problem(n=300, p=3, seed=41, n_bins=0, M=25)
+    o = oracle.fit(pr)
+    np.testing.assert_allclose(oracle.predict(pr, o, pr["x"]), o["f"], rtol=1e-12, atol=1e-12)
+    rng = np.random.default_rng(42)
+    nb = 40
+    xg = rng.integers(0, nb, size=(500, 2)) / (nb - 1.0)
+    xg[0, :], xg[1, :] = 0.0, 1.0
+    pb = dict(datagen.tiny_problem(n=500, p=2, seed=43, n_bins=nb, M=20), x=xg)
+    ob = oracle.fit(pb)
+    np.testing.assert_allclose(oracle.predict(pb, ob, xg), ob["f"], rtol=1e-12, atol=1e-12)
+    pc = datagen.additive_problem(400, 2, seed=44, n_informative=0, n_cat=2, n_informative_cat=2,
+                                  M=15)
+    oc = oracle.fit(pc)
+    np.testing.assert_allclose(oracle.predict(pc, oc, pc["x"]), oc["f"], rtol=1e-12, atol=1e-12)
+    lo = pr["x"].min(axis=0)
+    beyond = np.vstack([lo - 5.0, lo - 0.1])
+    np.testing.assert_array_equal(oracle.predict(pr, o, beyond), oracle.predict(pr, o, lo[None, :]).repeat(2))
