@@ -13,7 +13,8 @@ The numeric work is in ``cwb_oracle.c`` (C, FP64), called through ctypes.
 
 Problem dictionaries (also accepted by the GPU binding) hold:
   x (n, p) float64, y (n,) float64, loss "l2"|"binomial",
-  kind (p,) 0 = P-spline / 1 = ridge categorical, n_bins (p,), n_levels (p,),
+  kind (p,) 0 = P-spline / 1 = ridge categorical / 2 = binary categorical
+  (one least-squares learner per class), n_bins (p,), n_levels (p,),
   df (p,), lambda (p,), degree, n_knots, pen_order, nu, gamma, M,
   variant "cwb"|"acwb"|"hcwb", patience, val_mask (n,) uint8 or None.
 """
@@ -111,7 +112,7 @@ def _arr(a, dtype, n=None):
 
 def sizes(problem: dict) -> tuple[int, int]:
     kind = np.asarray(problem["kind"])
-    d = np.where(kind == 1, np.asarray(problem["n_levels"]),
+    d = np.where(kind != 0, np.asarray(problem["n_levels"]),
                  problem.get("n_knots", 20) + problem.get("degree", 3) + 1)
     return int(d.max()), int(d.sum())
 
@@ -276,7 +277,7 @@ def predict(problem: dict, result: dict, x_new) -> np.ndarray:
     for k in range(p):
         d = int(result["d"][k])
         c = result["coef_f"][off:off + d]
-        if kind[k] == 1:
+        if kind[k] != 0:
             f += c[xn[:, k].astype(np.int64)]
         else:
             lo, hi = float(x[:, k].min()), float(x[:, k].max())

@@ -31,6 +31,10 @@
  *    iteration); the step size called beta in the prose is nu.
  *  - HCWB keeps a separate patience counter compared against pat_0; the
  *    switch to CWB on all rows is permanent.
+ *  - A categorical feature in the binary representation (Appendix A.3.2)
+ *    stands for one unpenalised learner per class, ordered by class inside
+ *    the feature; a class with no fitted rows has no least-squares estimate
+ *    and is never selected.
  */
 #include <math.h>
 #include <stdint.h>
@@ -46,7 +50,7 @@
 
 enum { ORC_L2 = 0, ORC_BINOMIAL = 1 };
 enum { ORC_CWB = 0, ORC_ACWB = 1, ORC_HCWB = 2 };
-enum { ORC_PSPLINE = 0, ORC_RIDGE = 1 };
+enum { ORC_PSPLINE = 0, ORC_RIDGE = 1, ORC_BINARY = 2 };
 
 static char g_err[256];
 const char* orc_last_error(void) { return g_err; }
@@ -327,7 +331,7 @@ typedef struct {
   const double* y;          /* n */
   const uint8_t* val_mask;  /* NULL, or n bytes: 1 = validation row */
   int32_t loss;
-  const int32_t* kind;      /* p: 0 P-spline, 1 ridge categorical */
+  const int32_t* kind;      /* p: 0 P-spline, 1 ridge categorical, 2 binary categorical */
   const int32_t* n_bins;    /* p: P-spline bins (>= 2) or 0 = unbinned */
   const int32_t* n_levels;  /* p: ridge levels */
   const double* df;         /* p: target df (> 0) or <= 0 to use lambda */
@@ -420,6 +424,10 @@ static void gram(const feat_t* F, int64_t n, const uint8_t* mask, int all, doubl
 /* Smoothing parameter and Cholesky factor for one Gram set. */
 static int prepare_set(feat_t* F, int s, double df_target, double lambda_fixed) {
   int d = F->d;
+  if (F->kind == ORC_BINARY) {  /* unpenalised one-column learners: nothing to factor */
+    F->lambda[s] = 0.0;
+    return ORC_OK;
+  }
   double lam = lambda_fixed;
   if (df_target > 0.0) {
     if (F->kind == ORC_RIDGE && df_target >= (double)d) {
@@ -443,7 +451,7 @@ static int prepare_set(feat_t* F, int s, double df_target, double lambda_fixed) 
 int orc_sizes(const orc_problem* pr, int32_t* d_max, int32_t* sum_d) {
   int dm = 0, sd = 0;
   for (int j = 0; j < pr->p; ++j) {
-    int d = (pr->kind[j] == ORC_RIDGE) ? pr->n_levels[j] : pr->n_knots + pr->degree + 1;
+    int d = (pr->kind[j] != ORC_PSPLINE) ? pr->n_levels[j] : pr->n_knots + pr->degree + 1;
     if (d > dm) dm = d;
     sd += d;
   }
@@ -477,6 +485,35 @@ static void find_best(const feat_t* F, int p, int64_t n, const double* r,
     int d = Fk->d;
     double v[64], th[64];
     memset(v, 0, sizeof(v));
+    if (Fk->kind == ORC_BINARY) {
+      /* Binary representation (Appendix A.3.2): class l alone is a learner
+       * with the indicator column of that class; its least-squares estimate
+       * is the mean of r over the class's fitted rows, and its SSE is taken
+       * over all fitted rows.  The best class stands for the feature. */
+      double best_sse = INFINITY, best_th = 0.0;
+      int best_l = -1;
+      for (int l = 0; l < d; ++l) {
+        double sum = 0.0;
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i) {
+          if (!all && mask && mask[i]) continue;
+          if (Fk->ind[i] == l) { sum += r[i]; ++cnt; }
+        }
+        if (cnt == 0) continue;
+        double t = sum / (double)cnt;
+        double e2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+          if (!all && mask && mask[i]) continue;
+          double e = r[i] - ((Fk->ind[i] == l) ? t : 0.0);
+          e2 += e * e;
+        }
+        if (e2 < best_sse) { best_sse = e2; best_th = t; best_l = l; }
+      }
+      sse_all[k] = best_sse;
+      for (int a = 0; a < d_max; ++a)
+        theta_all[(size_t)k * d_max + a] = (a == best_l) ? best_th : 0.0;
+      continue;
+    }
     if (Fk->nb > 0) {
       /* binMatVec: u(l) = sum of r over bin l, then v = Z^b^T u. */
       double* u = (double*)calloc((size_t)Fk->nb, sizeof(double));
@@ -586,7 +623,7 @@ static int setup(const orc_problem* pr, feat_t** out, int need_all_set, orc_resu
     feat_t* Fj = &F[j];
     const double* xj = pr->x + (size_t)j * n;
     Fj->kind = pr->kind[j];
-    if (Fj->kind == ORC_RIDGE) {
+    if (Fj->kind == ORC_RIDGE || Fj->kind == ORC_BINARY) {
       int c = pr->n_levels[j];
       Fj->d = c;
       Fj->nb = c;
@@ -660,7 +697,7 @@ static int validate(const orc_problem* pr) {
   }
   for (int j = 0; j < pr->p; ++j) {
     const double* xj = pr->x + (size_t)j * pr->n;
-    if (pr->kind[j] == ORC_RIDGE) {
+    if (pr->kind[j] == ORC_RIDGE || pr->kind[j] == ORC_BINARY) {
       if (pr->n_levels[j] < 1 || pr->n_levels[j] > 64) return fail(ORC_E_ARG, "bad level count");
       for (int64_t i = 0; i < pr->n; ++i) {
         double v = xj[i];

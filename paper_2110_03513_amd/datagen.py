@@ -24,7 +24,7 @@ import math
 
 import numpy as np
 
-PSPLINE, RIDGE = 0, 1
+PSPLINE, RIDGE, BINARY = 0, 1, 2
 
 # Defaults the paper fixes for the simulation and benchmarks (Section 4):
 # cubic P-splines with 20 knots, df = 5, patience 5; gamma recommendations
@@ -60,8 +60,10 @@ def _norm_cdf(x: np.ndarray) -> np.ndarray:
 def learner_specs(p: int, n_bins, df: float = 5.0, kinds=None, n_levels=None) -> dict:
     kinds = np.zeros(p, np.int32) if kinds is None else np.asarray(kinds, np.int32)
     n_levels = np.zeros(p, np.int32) if n_levels is None else np.asarray(n_levels, np.int32)
-    nb = np.where(kinds == RIDGE, n_levels, np.broadcast_to(np.asarray(n_bins), (p,)))
-    dfs = np.where(kinds == RIDGE, np.minimum(df, n_levels.astype(np.float64)), df)
+    cat = kinds != PSPLINE
+    nb = np.where(cat, n_levels, np.broadcast_to(np.asarray(n_bins), (p,)))
+    dfs = np.where(kinds == RIDGE, np.minimum(df, n_levels.astype(np.float64)),
+                   np.where(kinds == BINARY, 0.0, df))
     return {
         "kind": kinds, "n_bins": nb.astype(np.int32), "n_levels": n_levels,
         "df": dfs.astype(np.float64), "lambda": np.zeros(p),
@@ -74,14 +76,16 @@ def additive_problem(n: int, p: int, *, seed: int, n_informative: int, loss: str
                      gamma: float | None = None, patience: int = 5, val_frac: float = 0.0,
                      snr: float = 1.0, amp_one: bool = False, n_normal: int = 0,
                      n_informative_normal: int = 0, n_cat: int = 0,
-                     n_informative_cat: int = 0, df: float = 5.0) -> dict:
+                     n_informative_cat: int = 0, df: float = 5.0,
+                     cat_kind: int | None = None) -> dict:
     """Numeric columns (uniform, then normal) followed by categorical codes.
 
     Columns [0, p_num - n_normal) are Uniform[0, 1], the next n_normal are
     N(0, 1), the last n_cat are level codes 0..c_j-1 with c_j ~ U{5..20}.
     The first n_informative uniform columns, the first n_informative_normal
     normal columns and the first n_informative_cat categorical columns carry
-    signal.
+    signal.  Categorical columns get ridge learners, or the learners of
+    ``cat_kind`` (BINARY: one least-squares learner per class).
     """
     rng = _rng(seed)
     p_num = p - n_cat
@@ -106,7 +110,7 @@ def additive_problem(n: int, p: int, *, seed: int, n_informative: int, loss: str
         c = int(rng.integers(5, 21))
         codes = rng.integers(0, c, size=n)
         x[:, j] = codes
-        kinds[j] = RIDGE
+        kinds[j] = RIDGE if cat_kind is None else cat_kind
         n_levels[j] = c
         if jj < n_informative_cat:
             lev = rng.normal(0.0, 0.5, size=c)

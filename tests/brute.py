@@ -6,6 +6,11 @@ built with scipy's B-spline design matrix), every fit solves the penalised
 normal equations with numpy, and every SSE is formed from an explicit
 residual vector.  No binMatVec, no cached factorisation, nothing shared with
 the oracle's C code.  Only for n * p small.
+
+A categorical feature in the binary representation becomes one learner per
+class with that class's indicator column and no penalty (least squares); the
+learner sequence is reported by feature, with the coefficient vector over the
+feature's classes (one nonzero entry).
 """
 from __future__ import annotations
 
@@ -40,9 +45,12 @@ def second_diff_penalty(d, order=2):
 
 
 class Learner:
-    def __init__(self, Z, D, rows_fit, df, lam=0.0, all_rows=None):
+    def __init__(self, Z, D, rows_fit, df, lam=0.0, all_rows=None, feat=0, cls=-1, width=None):
         self.Z = Z
         self.D = D
+        self.feat = feat    # feature index
+        self.cls = cls      # class of a binary learner, else -1
+        self.width = Z.shape[1] if width is None else width  # coefficient length of the feature
         self.lam = {}
         self.lam["train"] = self._lambda(Z[rows_fit], df, lam)
         if all_rows is not None:
@@ -66,6 +74,8 @@ class Learner:
     def fit(self, r, rows, which):
         Z = self.Z[rows]
         A = Z.T @ Z + self.lam[which] * self.D
+        if self.cls >= 0 and A[0, 0] == 0.0:  # empty class: no estimate
+            return np.zeros(1), np.inf
         theta = np.linalg.solve(A, Z.T @ r[rows])
         resid = r[rows] - Z @ theta
         return theta, float(resid @ resid)
@@ -78,6 +88,13 @@ def build(problem, binned=True):
     train = np.ones(n, bool) if vm is None else (np.asarray(vm) == 0)
     learners = []
     for j in range(p):
+        if int(problem["kind"][j]) == 2:
+            c = int(problem["n_levels"][j])
+            for l in range(c):
+                Z = (x[:, j].astype(int) == l).astype(float)[:, None]
+                learners.append(Learner(Z, np.zeros((1, 1)), train, 0.0, 0.0, all_rows=True,
+                                        feat=j, cls=l, width=c))
+            continue
         if int(problem["kind"][j]) == 1:
             c = int(problem["n_levels"][j])
             Z = np.eye(c)[x[:, j].astype(int)]
@@ -94,7 +111,7 @@ def build(problem, binned=True):
             D = second_diff_penalty(Z.shape[1], problem.get("pen_order", 2))
         learners.append(Learner(Z, D, train, float(problem["df"][j]),
                                 float(problem.get("lambda", np.zeros(p))[j]),
-                                all_rows=True))
+                                all_rows=True, feat=j))
     return learners, train
 
 
@@ -118,6 +135,16 @@ def best(learners, r, rows, which):
         sses.append(s)
     k = int(np.argmin(sses))
     return k, thetas[k], np.array(sses)
+
+
+def by_feature(learners, k, th):
+    """Feature index and the coefficient vector over the feature's basis."""
+    L = learners[k]
+    if L.cls < 0:
+        return L.feat, th
+    full = np.zeros(L.width)
+    full[L.cls] = th[0]
+    return L.feat, full
 
 
 def run(problem, binned=True, f0=None):
@@ -155,9 +182,10 @@ def run(problem, binned=True, f0=None):
             r = grad(loss, y, f)
             k, th, _ = best(learners, r, rows, which)
             f = f + nu * learners[k].Z @ th
-            ks.append(k)
+            kf, thf = by_feature(learners, k, th)
+            ks.append(kf)
             kcs.append(-1)
-            thetas.append(th)
+            thetas.append(thf)
         else:
             vt = 2.0 / (m + 1)
             g = (1 - vt) * f + vt * h
@@ -173,9 +201,10 @@ def run(problem, binned=True, f0=None):
             eta = gamma * nu / vt
             h = h + eta * learners[kc].Z @ thc
             prev_cor = (kc, thc)
-            ks.append(k)
-            kcs.append(kc)
-            thetas.append(th)
+            kf, thf = by_feature(learners, k, th)
+            ks.append(kf)
+            kcs.append(by_feature(learners, kc, thc)[0])
+            thetas.append(thf)
         if val.any():
             rv.append(risk(loss, y[val], f[val]))
             if variant == "hcwb" and acwb:

@@ -455,3 +455,73 @@ def test_prediction_reproduces_training_fit():
     lo = pr["x"].min(axis=0)
     beyond = np.vstack([lo - 5.0, lo - 0.1])
     np.testing.assert_array_equal(oracle.predict(pr, o, beyond), oracle.predict(pr, o, lo[None, :]).repeat(2))
+
+
+# --- Binary representation of categorical features (Appendix A.3.2) ---------
+
+@pytest.mark.parametrize("loss,variant,seed", [("l2", "cwb", 81), ("binomial", "acwb", 82),
+                                               ("l2", "hcwb", 83), ("binomial", "hcwb", 84)])
+def test_binary_categorical_matches_brute_force(loss, variant, seed):
+    """One least-squares learner per class, selected among all learners."""
+    pr = datagen.additive_problem(400, 5, seed=seed, n_informative=1, loss=loss, n_bins=16,
+                                  M=40, variant=variant, gamma=0.5, n_cat=3,
+                                  n_informative_cat=3, cat_kind=datagen.BINARY, patience=1)
+    out = oracle.fit(pr)
+    ref = brute.run(pr, binned=True)
+    assert (pr["kind"][-3:] == datagen.BINARY).all()
+    assert np.isin(out["k"], [2, 3, 4]).any(), "no binary learner selected"
+    np.testing.assert_array_equal(out["k"], ref["k"])
+    np.testing.assert_array_equal(out["kcor"], ref["kcor"])
+    assert out["switch_iter"] == ref["switch_iter"]
+    np.testing.assert_allclose(out["f"], ref["f"], atol=1e-9)
+    for m in range(pr["M"]):
+        d = ref["theta"][m].shape[0]
+        np.testing.assert_allclose(out["theta"][m, :d], ref["theta"][m], atol=1e-9)
+        if out["k"][m] >= 2:  # a binary learner moves one class only
+            assert np.count_nonzero(out["theta"][m, :d]) <= 1
+
+
+def test_binary_categorical_selection_order_closed_form():
+    """With one categorical feature, L2 and nu = 1, the class learners are
+    orthogonal: each step sets the mean residual of the chosen class to zero
+    without touching the others, so the classes come in decreasing order of
+    s_l^2 / n_l of the initial residual (ties to the lower class), each with
+    the class mean as its coefficient, and after one step per class f is the
+    vector of class means."""
+    rng = np.random.default_rng(85)
+    c, n = 7, 700
+    codes = rng.integers(0, c, n)
+    means = rng.normal(0, 1, c)
+    y = means[codes] + rng.normal(0, 0.3, n)
+    pr = {"x": codes[:, None].astype(float), "y": y, "loss": "l2", "kind": [2],
+          "n_bins": [c], "n_levels": [c], "df": [0.0], "lambda": [0.0], "nu": 1.0, "M": c,
+          "variant": "cwb"}
+    out = oracle.fit(pr)
+    r0 = y - y.mean()
+    cnt = np.bincount(codes, minlength=c).astype(float)
+    s = np.bincount(codes, weights=r0, minlength=c)
+    order = np.argsort(-(s * s / cnt), kind="stable")
+    chosen = [int(np.flatnonzero(out["theta"][m, :c])[0]) for m in range(c)]
+    assert chosen == list(order)
+    for m, l in enumerate(order):
+        assert abs(out["theta"][m, l] - s[l] / cnt[l]) < 1e-12
+    group_mean = np.bincount(codes, weights=y, minlength=c) / cnt
+    np.testing.assert_allclose(out["f"], group_mean[codes], atol=1e-12)
+
+
+def test_binary_categorical_empty_class_never_selected():
+    """A level without rows has no least-squares estimate; it is skipped."""
+    rng = np.random.default_rng(86)
+    n, c = 300, 6
+    codes = rng.integers(0, c - 1, n)  # level c-1 never occurs
+    x = np.column_stack([rng.random(n), codes.astype(float)])
+    y = np.sin(3 * x[:, 0]) + 0.5 * (codes == 2) + rng.normal(0, 0.2, n)
+    pr = {"x": x, "y": y, "loss": "l2", "kind": [0, 2], "n_bins": [20, c],
+          "n_levels": [0, c], "df": [5.0, 0.0], "lambda": [0.0, 0.0], "nu": 0.3, "M": 30,
+          "variant": "cwb"}
+    out = oracle.fit(pr)
+    ref = brute.run(pr, binned=True)
+    np.testing.assert_array_equal(out["k"], ref["k"])
+    np.testing.assert_allclose(out["f"], ref["f"], atol=1e-10)
+    assert (out["k"] == 1).any()
+    assert (out["theta"][out["k"] == 1, c - 1] == 0).all()
