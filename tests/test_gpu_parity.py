@@ -343,3 +343,45 @@ def test_predict_training_rows_of_unbinned_fit():
     got = f.predict(prob["x"])
     assert rel_err(got, f.pred()) <= 1e-5  # the FP32 training state against FP64 evaluation
     f.close()
+
+
+def test_partial_effects_sum_to_prediction():
+    prob = datagen.additive_problem(20_000, 6, seed=74, n_informative=3, n_bins=150, M=50,
+                                    n_cat=1, n_informative_cat=1)
+    f = cwb.Fit(prob)
+    f.run(50)
+    f.sync()
+    rng = np.random.default_rng(75)
+    xn = rng.uniform(0, 1, (2_000, 6))
+    xn[:, 5] = rng.integers(0, prob["n_levels"][5], 2_000)
+    total = f.model()["f0"] + sum(f.partial_effect(k, xn[:, k]) for k in range(6))
+    np.testing.assert_allclose(total, f.predict(xn), rtol=1e-12, atol=1e-12)
+    f.close()
+
+
+@pytest.mark.parametrize("variant,loss", [("cwb", "l2"), ("acwb", "binomial"), ("hcwb", "l2")])
+def test_binary_categorical_against_oracle(variant, loss):
+    """Categorical features in the binary representation: one least-squares
+    learner per class, the best class standing for the feature."""
+    prob = datagen.additive_problem(60_000, 10, seed=91, n_informative=3, loss=loss, n_bins=200,
+                                    M=150, variant=variant, gamma=0.2, n_cat=4,
+                                    n_informative_cat=3, cat_kind=datagen.BINARY, patience=2)
+    gpu = _run(prob)
+    compare(gpu, prob)
+    cat = np.isin(gpu["k"], np.arange(6, 10))
+    assert cat.any(), "no binary learner selected"
+    c = prob["n_levels"]
+    for m in np.nonzero(cat)[0]:
+        assert np.count_nonzero(gpu["theta"][m, :c[gpu["k"][m]]]) == 1
+
+
+def test_fourth_root_bins_against_oracle():
+    n = 200_000
+    prob = datagen.additive_problem(n, 8, seed=92, n_informative=4, n_bins=-2, M=120)
+    b = 21  # floor(200000^(1/4))
+    assert b ** 4 <= n < (b + 1) ** 4
+    f = cwb.Fit(prob)
+    assert f.info.nb_max == b
+    f.close()
+    gpu = _run(prob)
+    compare(gpu, dict(prob, n_bins=np.full(8, b, np.int32)))
