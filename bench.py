@@ -117,6 +117,34 @@ def headline(args, torch, cwb, datagen):
     }
 
 
+def setup_leg(prob, cwb):
+    """Fit creation of the headline problem with binning and bin counts on
+    host threads and on the GPU (the tile autotuner off for both, so that
+    only the setup differs); best of two creations each."""
+    old = os.environ.get("CWB_AUTOTUNE")
+    os.environ["CWB_AUTOTUNE"] = "0"
+    out = {}
+    try:
+        for setup in ("host", "device"):
+            best = None
+            for _ in range(2):
+                t0 = time.perf_counter()
+                f = cwb.Fit(dict(prob, setup=setup))
+                dt = time.perf_counter() - t0
+                f.close()
+                best = dt if best is None else min(best, dt)
+            out[f"{setup}_s"] = round(best, 4)
+            log(f"[bench] setup on {setup}: {best:.3f}s")
+    finally:
+        if old is None:
+            os.environ.pop("CWB_AUTOTUNE", None)
+        else:
+            os.environ["CWB_AUTOTUNE"] = old
+    out["speedup"] = round(out["host_s"] / max(out["device_s"], 1e-9), 2)
+    out["host_threads"] = os.cpu_count()
+    return out
+
+
 def unbinned_leg(args, torch, cwb, datagen):
     """The headline workload with unbinned learners (each row's own cubic
     basis, no binning), timed beside the binned path."""
@@ -335,6 +363,7 @@ def served(args, torch, cwb, datagen):
                 "p50_from_submit_s": round(x["p50_latency_s"], 4),
                 "p99_from_submit_s": round(x["p99_latency_s"], 4),
                 "mean_setup_s": round(x["mean_setup_s"], 4), "mean_queue_s": round(x["mean_queue_s"], 4),
+                "rounds": x["rounds"], "round_time_share": round(x["round_s"] / max(x["busy_s"], 1e-9), 3),
                 "completed": x["completed"],
                 "rejected": x["rejected"], "failed": x["failed"],
                 "arena_peak_gb": round(x["arena_peak"] / 2**30, 3), "wall_s": round(x["wall_s"], 2),
@@ -375,6 +404,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-setup", action="store_true",
+                    help="skip timing fit creation with host vs device binning")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-fits", type=int, default=64)
     ap.add_argument("--batch-iters", type=int, default=1000)
@@ -435,6 +466,8 @@ def main():
                         "method": "HIP events on the fit's stream around every k-th histogram "
                                   "launch of the timed region"},
     }
+    if not args.no_setup:
+        out["setup"] = setup_leg(prob, cwb)
     if not args.no_cpu:
         cb, par = cpu_baseline(args, prob, tr)
         out["cpu_baseline"] = cb

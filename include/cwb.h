@@ -12,10 +12,12 @@
  *   - ACWB: Algorithm 2 (Section 3.2), parameter bookkeeping Section 3.2.1;
  *   - HCWB: Algorithm 3 (Section 3.2.3);
  *   - P-spline and categorical ridge base learners with equal degrees of
- *     freedom: Section 2.2, Appendix A.2 and A.3.1.
- * Every iteration runs on the GPU in hand-written HIP kernels; the host only
- * does the one-off FP64 setup (binning, bases, Gram matrices, smoothing
- * parameters and their factorisations) in cwb_fit_create.
+ *     freedom: Section 2.2, Appendix A.2 and A.3.1; categorical features in
+ *     the binary representation (one learner per class): Appendix A.3.2.
+ * Every iteration runs on the GPU in hand-written HIP kernels.  The one-off
+ * FP64 setup in cwb_fit_create bins the features and counts the bins on the
+ * GPU (or on host threads, see cwb_problem.setup); the host builds the
+ * bases, Gram matrices, smoothing parameters and their factorisations.
  *
  * Conventions for every call:
  *   - Returns CWB_OK (0) or a negative CWB_E_* code; on error,
@@ -64,10 +66,19 @@ extern "C" {
 /* base-learner kinds */
 #define CWB_PSPLINE 0    /* univariate B-spline basis with difference penalty (Sec. 2.2) */
 #define CWB_RIDGE_CAT 1  /* categorical dummy basis with ridge penalty (App. A.3.1) */
+#define CWB_BINARY_CAT 2 /* categorical feature in the binary representation
+                            (App. A.3.2): one unpenalised learner per class,
+                            the indicator of that class, with the class mean of
+                            the signal as its estimate.  The feature's entry in
+                            the traces is the class learner chosen: k is the
+                            feature, and its coefficient row has one nonzero
+                            entry, at the class.  df and lambda are ignored; a
+                            class without fitted rows is never selected. */
 
-/* One base learner per feature (Section 2.2: univariate learners, K = p). */
+/* One base learner per feature (Section 2.2: univariate learners, K = p); a
+ * CWB_BINARY_CAT feature stands for its c_j class learners. */
 typedef struct {
-  int32_t kind;             /* CWB_PSPLINE or CWB_RIDGE_CAT */
+  int32_t kind;             /* CWB_PSPLINE, CWB_RIDGE_CAT or CWB_BINARY_CAT */
   int32_t degree;           /* P-spline degree, 1..3 (the paper uses 3) */
   int32_t n_interior_knots; /* equally spaced interior knots (the paper uses 20) */
   int32_t penalty_order;    /* difference order of the penalty (2) */
@@ -75,11 +86,12 @@ typedef struct {
                                equals df (App. A.2); <= 0: use `lambda` */
   double lambda;            /* smoothing parameter when df <= 0 (>= 0) */
   int32_t n_bins;           /* P-spline design points n* (Sec. 3.1.1), 2..65535;
-                               -1 selects floor(sqrt(n)); 0 selects an unbinned
+                               -1 selects floor(sqrt(n)), -2 floor(n^(1/4))
+                               (the smaller grid of App. B.3); 0 selects an unbinned
                                learner (each row's own basis, Sec. 2.2; cubic
                                only, and then every learner of the fit must be
                                unbinned: no categorical learners; not served) */
-  int32_t n_levels;         /* CWB_RIDGE_CAT: number of levels c_j (1..64) */
+  int32_t n_levels;         /* categorical kinds: number of levels c_j (1..64) */
 } cwb_learner_spec;
 
 /* The fitting problem (all pointers are host memory, read during create). */
@@ -101,7 +113,22 @@ typedef struct {
                                     the other rows and report validation risk. */
   int64_t ldx;                   /* column stride of x in elements: column j
                                     starts at x + j*ldx; 0 means n; else >= n */
+  int32_t setup;                 /* where binning and bin counts run during
+                                    create: CWB_SETUP_AUTO, CWB_SETUP_HOST or
+                                    CWB_SETUP_DEVICE (binned fits with
+                                    n < 2^31 only, else UNSUPPORTED).  Both
+                                    give bitwise the same fit. */
 } cwb_problem;
+
+/* cwb_problem.setup */
+#define CWB_SETUP_AUTO 0   /* device for binned fits with n < 2^31, else host;
+                              the server always bins on its host setup
+                              threads, which overlap the running batch */
+#define CWB_SETUP_HOST 1   /* host threads bin every column (Sec. 3.1.1) */
+#define CWB_SETUP_DEVICE 2 /* columns are copied to the workspace one at a
+                              time and binned and counted on the GPU; the host
+                              then builds the learner tables from the ranges
+                              and counts */
 
 /* Sizes of a created fit (for sizing getter buffers). */
 typedef struct {
@@ -300,6 +327,9 @@ typedef struct {
   size_t arena_in_use, arena_peak;
   double mean_setup_s;  /* host setup time per completed request */
   double mean_queue_s;  /* submit -> admitted, per completed request */
+  double round_s;       /* device-thread time inside rounds (launch to end of round) */
+  double busy_s;        /* device-thread time from the first round to the last */
+  int64_t rounds;       /* rounds run */
 } cwb_stats;
 
 int cwb_server_create(const cwb_server_cfg* cfg, cwb_server** out);

@@ -1,0 +1,168 @@
+// binning.hip -- the device binning pass of fit setup (Sec. 3.1.1 and the
+// counts of binMatMat, Algorithm 1), one feature column at a time:
+//   k_range  largest and smallest value of a numeric column (and whether any
+//            value is not finite);
+//   k_bin    every row's design-point index, nearest of the nb equally
+//            spaced points on [min, max] with ties to the lower point, by the
+//            same FP64 operations in the same order as the host rule (this
+//            file is built without floating-point contraction), or the
+//            level code of a categorical column; the rows are taken in the
+//            fit's order (training rows first), and the bin counts over the
+//            training rows and over all rows are accumulated in LDS and added
+//            to the column's counters.
+#include <hip/hip_runtime.h>
+
+#include "cwb_internal.h"
+#include "kernels.h"
+
+namespace cwb {
+namespace {
+
+constexpr int kSetupThreads = 256;
+
+// Doubles as unsigned integers whose order is the order of the values, so
+// that 64-bit integer atomics give the exact minimum and maximum.
+__device__ __forceinline__ unsigned long long ordered(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double from_ordered(unsigned long long o) {
+  const unsigned long long b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+  const double v = __longlong_as_double((long long)b);
+  return v == 0.0 ? 0.0 : v;  // one zero for both signs
+}
+
+__device__ __forceinline__ double grid_point(double xmin, double xmax, double h, int l, int nb) {
+  return (l == nb - 1) ? xmax : xmin + (double)l * h;
+}
+
+// Closest design point, ties to the lower one: an arithmetic estimate of the
+// enclosing interval, corrected by exact comparisons with the design points,
+// then the two distances decide.
+__device__ __forceinline__ int bin_of(double x, double xmin, double xmax, double h, int nb) {
+  if (x <= xmin) return 0;
+  if (x >= xmax) return nb - 1;
+  int l = (int)((x - xmin) / h);
+  if (l < 0) l = 0;
+  if (l > nb - 2) l = nb - 2;
+  while (l > 0 && grid_point(xmin, xmax, h, l, nb) > x) --l;
+  while (l < nb - 2 && grid_point(xmin, xmax, h, l + 1, nb) <= x) ++l;
+  const double dlo = x - grid_point(xmin, xmax, h, l, nb);
+  const double dhi = grid_point(xmin, xmax, h, l + 1, nb) - x;
+  return (dhi < dlo) ? l + 1 : l;
+}
+
+__global__ void __launch_bounds__(kSetupThreads)
+k_range(const double* __restrict__ x, int64_t n, unsigned long long* __restrict__ mm,
+        int* __restrict__ flag) {
+  __shared__ unsigned long long s_lo[kSetupThreads / 64], s_hi[kSetupThreads / 64];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  unsigned long long lo = ~0ull, hi = 0ull;
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * kSetupThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kSetupThreads + threadIdx.x; i < n; i += stride) {
+    const double v = x[i];
+    if (!isfinite(v)) {
+      bad = true;
+      continue;
+    }
+    const unsigned long long o = ordered(v);
+    lo = o < lo ? o : lo;
+    hi = o > hi ? o : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a = __shfl_down(lo, off, 64), b = __shfl_down(hi, off, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if (bad) s_bad = 1;
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[w] = lo;
+    s_hi[w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kSetupThreads / 64; ++k) {
+      lo = s_lo[k] < lo ? s_lo[k] : lo;
+      hi = s_hi[k] > hi ? s_hi[k] : hi;
+    }
+    if (lo != ~0ull) atomicMin(mm, lo);
+    if (hi != 0ull) atomicMax(mm + 1, hi);
+    if (s_bad) atomicOr(flag, 1);
+  }
+}
+
+// rows_per_block consecutive rows of the fit's order per block.  counts:
+// training-row counts at [0, nb), all-row counts at [half, half + nb).
+__global__ void __launch_bounds__(kSetupThreads)
+k_bin(const double* __restrict__ x, const int32_t* __restrict__ perm, int64_t n, int64_t n_pad,
+      int64_t n_train, int categorical, int nb, const unsigned long long* __restrict__ mm,
+      int64_t rows_per_block, uint16_t* __restrict__ out, uint32_t* __restrict__ counts,
+      int64_t half, int* __restrict__ flag) {
+  extern __shared__ uint32_t s_cnt[];  // [2][nb]
+  for (int l = threadIdx.x; l < 2 * nb; l += kSetupThreads) s_cnt[l] = 0u;
+  __syncthreads();
+  double xmin = 0.0, xmax = 0.0, h = 0.0;
+  bool ok = true;
+  if (!categorical) {
+    xmin = from_ordered(mm[0]);
+    xmax = from_ordered(mm[1]);
+    ok = xmax > xmin;  // a constant column is reported by the host
+    h = (xmax - xmin) / (double)(nb - 1);
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = (r0 + rows_per_block < n_pad) ? r0 + rows_per_block : n_pad;
+  bool bad = false;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += kSetupThreads) {
+    int l = 0;
+    if (i < n && ok) {
+      const double v = x[perm ? (int64_t)perm[i] : i];
+      if (categorical) {
+        if (!(v >= 0.0) || v >= (double)nb || v != floor(v)) bad = true;
+        else l = (int)v;
+      } else {
+        l = bin_of(v, xmin, xmax, h, nb);
+      }
+      atomicAdd(&s_cnt[nb + l], 1u);
+      if (i < n_train) atomicAdd(&s_cnt[l], 1u);
+    }
+    out[i] = (uint16_t)l;
+  }
+  if (bad) atomicOr(flag, 2);
+  __syncthreads();
+  for (int l = threadIdx.x; l < nb; l += kSetupThreads) {
+    if (s_cnt[l]) atomicAdd(counts + l, s_cnt[l]);
+    if (s_cnt[nb + l]) atomicAdd(counts + half + l, s_cnt[nb + l]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_range(hipStream_t st, const double* x, int64_t n, unsigned long long* mm, int* flag) {
+  int64_t blocks = (n + kSetupThreads * 16 - 1) / (kSetupThreads * 16);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_range, dim3((unsigned)blocks), dim3(kSetupThreads), 0, st, x, n, mm, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(hipStream_t st, const double* x, const int32_t* perm, int64_t n, int64_t n_pad,
+                      int64_t n_train, int categorical, int nb, const unsigned long long* mm,
+                      uint16_t* out, uint32_t* counts, int64_t half, int* flag) {
+  if (nb < 1 || nb > kMaxBins || (!categorical && nb < 2) || n_pad < n || n_pad % 64 != 0)
+    return hipErrorInvalidValue;
+  int64_t rows = 4 * (int64_t)nb;
+  if (rows < 4096) rows = 4096;
+  rows = (rows + kSetupThreads - 1) / kSetupThreads * kSetupThreads;
+  const int64_t blocks = (n_pad + rows - 1) / rows;
+  const size_t lds = (size_t)2 * nb * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(kSetupThreads), lds, st, x, perm, n, n_pad,
+                     n_train, categorical, nb, mm, rows, out, counts, half, flag);
+  return hipGetLastError();
+}
+
+}  // namespace cwb

@@ -179,6 +179,7 @@ struct SelItem {
   int32_t k, nb, band, d;
   int32_t n_off, d_max, nb_max, p;
   int32_t M, variant, n_row_blocks, fit;
+  int32_t kind, pad_;         // learner kind (CWB_BINARY_CAT: best class only)
 };
 
 // Fixed-point exponent for the int64 histogram of a signal whose largest

@@ -23,5 +23,16 @@ hipError_t launch_predict(hipStream_t st, const FitDev* fit, const double* x, in
                           double f0, int k0, int k1, double* out);
 // Aggregated coefficients of one fit (sum_d of them) from its traces.
 hipError_t launch_coef(hipStream_t st, const FitDev* fit, int sum_d);
+// Device binning pass of fit setup (binning.hip).  mm: the column's range as
+// order-preserving integers (minimum, maximum), to be initialised to
+// (all ones, 0); flag |= 1 when a value is not finite.
+hipError_t launch_range(hipStream_t st, const double* x, int64_t n, unsigned long long* mm, int* flag);
+// Bin indices of rows [0, n_pad) in the fit's order (perm: fit row -> x row,
+// or NULL for the identity; rows from n on get 0), and the bin counts of
+// the training rows (counts[0, nb)) and of all rows (counts[half, half+nb)),
+// added to the counters.  flag |= 2 when a categorical code is invalid.
+hipError_t launch_bin(hipStream_t st, const double* x, const int32_t* perm, int64_t n, int64_t n_pad,
+                      int64_t n_train, int categorical, int nb, const unsigned long long* mm,
+                      uint16_t* out, uint32_t* counts, int64_t half, int* flag);
 
 }  // namespace cwb

@@ -406,15 +406,40 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       s_v[threadIdx.x] = acc;
     }
     __syncthreads();
-    // theta = (G + lambda D)^-1 v
-    mat_vec(s_ai, s_v, s_th, d, s_part);
-    // G theta
-    mat_vec(s_g, s_th, s_gt, d, s_part);
-    // q = theta^T G theta - 2 theta^T v
-    if (threadIdx.x == 0) {
-      double w = 0.0;
-      for (int j = 0; j < d; ++j) w += s_th[j] * (s_gt[j] - 2.0 * s_v[j]);
-      it.q[(size_t)sig * it.p] = w;
+    if (it.kind == CWB_BINARY_CAT) {
+      // one learner per class (indicator column, no penalty): theta_l =
+      // s_l / n_l and q_l = theta_l (n_l theta_l - 2 s_l); the best class
+      // (ties to the lower one) stands for the feature.  Empty classes
+      // (n_l = 0) have no estimate and are skipped.
+      if (threadIdx.x == 0) {
+        int bl = -1;
+        double bq = INFINITY, bt = 0.0;
+        for (int j = 0; j < d; ++j) {
+          const double nl = s_g[(size_t)j * d + j];
+          if (!(nl > 0.0)) continue;
+          const double t = s_v[j] / nl;
+          const double qj = t * (nl * t - 2.0 * s_v[j]);
+          if (qj < bq) {
+            bq = qj;
+            bt = t;
+            bl = j;
+          }
+        }
+        for (int j = 0; j < d; ++j) s_th[j] = (j == bl) ? bt : 0.0;
+        it.q[(size_t)sig * it.p] = bq;
+      }
+      __syncthreads();
+    } else {
+      // theta = (G + lambda D)^-1 v
+      mat_vec(s_ai, s_v, s_th, d, s_part);
+      // G theta
+      mat_vec(s_g, s_th, s_gt, d, s_part);
+      // q = theta^T G theta - 2 theta^T v
+      if (threadIdx.x == 0) {
+        double w = 0.0;
+        for (int j = 0; j < d; ++j) w += s_th[j] * (s_gt[j] - 2.0 * s_v[j]);
+        it.q[(size_t)sig * it.p] = w;
+      }
     }
     GLOBAL double* th = gp(it.theta + (size_t)sig * it.p * it.d_max);
     for (int j = threadIdx.x; j < it.d_max; j += kSelectThreads) th[j] = (j < d) ? s_th[j] : 0.0;
@@ -614,7 +639,7 @@ k_predict(const FitDev* __restrict__ fits, const double* __restrict__ x, int64_t
   for (int k = k0; k < k1; ++k) {
     const FeatDev fd = F.feat[k];
     const double v = xg[(size_t)(k - k0) * ldx + i];
-    if (fd.kind == CWB_RIDGE_CAT) {
+    if (fd.kind != CWB_PSPLINE) {  // categorical: the level's coefficient
       const int lev = (int)v;
       acc += (v >= 0.0 && lev < fd.d && (double)lev == v) ? cf[fd.coef_off + lev] : NAN;
       continue;

@@ -69,7 +69,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
   for (int j = 0; j < pr->p; ++j) {
     const cwb_learner_spec& s = pr->specs[j];
     int nb, d;
-    if (s.kind == CWB_RIDGE_CAT) {
+    if (s.kind == CWB_RIDGE_CAT || s.kind == CWB_BINARY_CAT) {
       nb = s.n_levels;
       d = s.n_levels;
     } else if (s.n_bins == 0) {  // unbinned: the basis functions take the place of bins
@@ -77,8 +77,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
       nb = d;
       sh->unbinned = true;
     } else {
-      nb = s.n_bins == -1 ? (int)std::floor(std::sqrt((double)pr->n)) : s.n_bins;
-      if (nb < 2) nb = 2;
+      nb = bins_for(s.n_bins, pr->n);
       d = s.n_interior_knots + s.degree + 1;
     }
     if (nb < 1 || nb > kMaxBins || d < 1 || d > kMaxD) {
@@ -556,6 +555,7 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
   it.variant = D.variant;
   it.n_row_blocks = D.n_row_blocks;
   it.fit = fit;
+  it.kind = fd.kind;
   return it;
 }
 
@@ -667,8 +667,87 @@ static int fit_install(cwb_fit* f, const Tune& t, Schedule&& S) {
   return CWB_OK;
 }
 
+namespace {
+
+// Host view of the order-preserving integers of the device range pass.
+double from_ordered(unsigned long long o) {
+  const unsigned long long b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+  double v;
+  std::memcpy(&v, &b, 8);
+  return v == 0.0 ? 0.0 : v;
+}
+
+}  // namespace
+
+// Binning pass on the device (binning.hip) for a fit whose host setup ran
+// its first phase only: each column of x is copied into the workspace (the
+// label and residual vectors, not yet written, hold one FP64 column), its
+// range found, and its rows binned straight into X with the bin counts.
+// The ranges, counts and error flags come back to the host, which builds
+// the learner tables (finish_host_fit).  Other scratch used here, all
+// written later by the upload: the state vector f (row order), theta (the
+// ranges), q (the flags), the partials (the counts).
+int device_binning(const cwb_problem* pr, const FitShape& sh, HostFit& hf, const Layout& L,
+                   char* ws, hipStream_t st) {
+  const int64_t n = sh.n, np = sh.n_pad;
+  const int p = sh.p;
+  if (sh.unbinned || n >= (int64_t)INT32_MAX)
+    return set_error(CWB_E_UNSUPPORTED, "device setup covers binned fits with n < 2^31");
+  const int64_t cstride = 2 * (int64_t)sh.nb_stride;  // per feature: training | all rows
+  if (L.r != L.y + (size_t)np * 4 || L.st_items - L.partials < (size_t)p * cstride * 4 ||
+      L.theta - L.q < (size_t)p * 4 || L.table - L.theta < (size_t)p * 16)
+    return set_error(CWB_E_INVALID_ARG, "internal: scratch regions of the device setup");
+  double* stage = dptr<double>(ws, L.y);
+  const bool permuted = hf.n_train < n;
+  int32_t* d_perm = permuted ? dptr<int32_t>(ws, L.fg) : nullptr;
+  unsigned long long* d_mm = dptr<unsigned long long>(ws, L.theta);
+  int* d_flag = dptr<int>(ws, L.q);
+  uint32_t* d_cnt = dptr<uint32_t>(ws, L.partials);
+  uint16_t* d_X = dptr<uint16_t>(ws, L.X);
+  std::vector<unsigned long long> mm((size_t)2 * p);
+  for (int j = 0; j < p; ++j) {
+    mm[2 * j] = ~0ull;
+    mm[2 * j + 1] = 0ull;
+  }
+  std::vector<int32_t> perm32;
+  HIP_TRY(hipMemcpyAsync(d_mm, mm.data(), mm.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(d_flag, 0, (size_t)p * 4, st));
+  HIP_TRY(hipMemsetAsync(d_cnt, 0, (size_t)p * cstride * 4, st));
+  if (permuted) {
+    perm32.assign(hf.perm.begin(), hf.perm.end());
+    HIP_TRY(hipMemcpyAsync(d_perm, perm32.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+  }
+  const int64_t ldx = pr->ldx ? pr->ldx : n;
+  for (int j = 0; j < p; ++j) {
+    const bool cat = pr->specs[j].kind != CWB_PSPLINE;
+    HIP_TRY(hipMemcpyAsync(stage, pr->x + (size_t)j * ldx, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    if (!cat) HIP_TRY(launch_range(st, stage, n, d_mm + 2 * j, d_flag + j));
+    HIP_TRY(launch_bin(st, stage, d_perm, n, np, hf.n_train, cat ? 1 : 0, hf.L[j].nb, d_mm + 2 * j,
+                       d_X + (size_t)j * np, d_cnt + (size_t)j * cstride, cstride / 2, d_flag + j));
+  }
+  std::vector<int> flag(p);
+  std::vector<uint32_t> cnt((size_t)p * cstride);
+  HIP_TRY(hipMemcpyAsync(mm.data(), d_mm, mm.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(flag.data(), d_flag, flag.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<double> xr((size_t)2 * p, 0.0);
+  for (int j = 0; j < p; ++j) {
+    if (flag[j] & 1) return set_error(CWB_E_INVALID_ARG, "non-finite x");
+    if (flag[j] & 2) return set_error(CWB_E_INVALID_ARG, "level code out of range in feature " + std::to_string(j));
+    if (pr->specs[j].kind != CWB_PSPLINE) continue;
+    xr[2 * j] = from_ordered(mm[2 * j]);
+    xr[2 * j + 1] = from_ordered(mm[2 * j + 1]);
+    if (!(xr[2 * j + 1] > xr[2 * j])) return set_error(CWB_E_INVALID_ARG, "constant feature " + std::to_string(j));
+  }
+  std::string err;
+  const int rc = finish_host_fit(pr, &hf, xr.data(), cnt.data(), cstride, &err);
+  if (rc) return set_error(rc, err);
+  return CWB_OK;
+}
+
 int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
-               bool autotune, cwb_fit** out) {
+               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device) {
   *out = nullptr;
   std::unique_ptr<cwb_fit> f(new cwb_fit());
   f->stream = stream;
@@ -688,6 +767,10 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   HIP_TRY(hipGetDevice(&f->device));
   f->ws = reinterpret_cast<char*>(dev_ws);
   f->ws_bytes = ws_bytes;
+  if (bin_on_device) {
+    const int rc = device_binning(bin_on_device, sh, hf, f->lay, f->ws, f->stream);
+    if (rc) return rc;
+  }
   f->f0 = hf.f0;
   f->perm = std::move(hf.perm);
   const Layout& L = f->lay;
@@ -808,7 +891,7 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
     HIP_TRY(hipMemcpyAsync(ws + L.h, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
   if (sh.unbinned)
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.XU.data(), hf.XU.size() * 4, hipMemcpyHostToDevice, st));
-  else
+  else if (!bin_on_device)  // else the device pass wrote X already
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
@@ -911,10 +994,17 @@ static int fit_create_impl(const cwb_problem* pr, void* dev_ws, size_t ws_bytes,
   FitShape sh;
   int rc = shape_from_problem(pr, &sh, &err);
   if (rc) return set_error(rc, err);
+  if (pr->setup < CWB_SETUP_AUTO || pr->setup > CWB_SETUP_DEVICE)
+    return set_error(CWB_E_INVALID_ARG, "unknown setup mode");
+  const bool device_ok = !sh.unbinned && sh.n < (int64_t)INT32_MAX;
+  if (pr->setup == CWB_SETUP_DEVICE && !device_ok)
+    return set_error(CWB_E_UNSUPPORTED, "device setup covers binned fits with n < 2^31");
+  const bool on_device = pr->setup == CWB_SETUP_DEVICE || (pr->setup == CWB_SETUP_AUTO && device_ok);
   HostFit hf;
-  rc = build_host_fit(pr, &hf, &err);
+  rc = on_device ? prepare_host_fit(pr, &hf, &err) : build_host_fit(pr, &hf, &err);
   if (rc) return set_error(rc, err);
-  return fit_upload(sh, hf, dev_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), true, out);
+  return fit_upload(sh, hf, dev_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), true, out,
+                    on_device ? pr : nullptr);
 }
 
 int cwb_fit_create(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream, cwb_fit** out) {

@@ -166,9 +166,11 @@ int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const 
 int fit_footprint(const FitShape& sh, size_t* bytes, bool all);
 // Upload a fit whose host setup is done into `dev_ws` on `stream`, autotune
 // its histogram tiles if asked, and wait; the new fit enqueues its
-// iterations on the same stream.
+// iterations on the same stream.  With `bin_on_device` (the problem), the
+// host setup ran its first phase only and the binning pass runs on the
+// device first.
 int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
-               bool autotune, cwb_fit** out);
+               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device = nullptr);
 // Device bytes of the batch workspace (combined schedule, partials, work
 // lists) for fits of these shapes; 0 for none.
 int batch_footprint(const std::vector<const FitShape*>& shapes, size_t* bytes, bool all);

@@ -139,6 +139,8 @@ struct cwb_server {
   int32_t in_flight = 0;
   double t_first = -1.0, t_last_done = 0.0;
   double sum_setup_s = 0.0, sum_queue_s = 0.0;
+  double round_s = 0.0, t_first_round = -1.0, t_last_round = 0.0;
+  int64_t rounds = 0;
   std::vector<double> latencies;
 
   // device thread only
@@ -360,6 +362,7 @@ void device_loop(cwb_server* s) {
     // 2. one round of the current batch, enqueued before the uploads so
     //    that the copies overlap it
     int32_t q = 0;
+    const double t_round = now_s();
     if (s->batch && !s->active.empty()) {
       q = s->cfg.quantum;
       for (Request* r : s->active) q = std::min(q, r->fit->shape.M - r->fit->iters);
@@ -391,7 +394,15 @@ void device_loop(cwb_server* s) {
       joined.push_back(r);
     }
     // 4. end of the round: retire finished or failed fits
-    if (q > 0) (void)hipStreamSynchronize(s->stream);
+    if (q > 0) {
+      (void)hipStreamSynchronize(s->stream);
+      const double t_end = now_s();
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->round_s += t_end - t_round;
+      if (s->t_first_round < 0) s->t_first_round = t_round;
+      s->t_last_round = t_end;
+      s->rounds += 1;
+    }
     bool changed = !joined.empty();
     std::vector<Request*> keep;
     for (Request* r : s->active) {
@@ -551,6 +562,9 @@ int cwb_server_stats(cwb_server* s, cwb_stats* st) {
     st->mean_setup_s = s->sum_setup_s / (double)s->completed;
     st->mean_queue_s = s->sum_queue_s / (double)s->completed;
   }
+  st->round_s = s->round_s;
+  st->busy_s = s->t_first_round >= 0 ? s->t_last_round - s->t_first_round : 0.0;
+  st->rounds = s->rounds;
   return CWB_OK;
 }
 

@@ -274,6 +274,21 @@ void set_error(std::string* err, const std::string& msg) {
 
 }  // namespace
 
+int bins_for(int32_t n_bins, int64_t n) {
+  if (n_bins > 0) return n_bins;
+  // largest b with b^e <= n (e = 2 or 4), in exact integer arithmetic
+  const int e = (n_bins == -2) ? 4 : 2;
+  auto pow_le = [&](int64_t b) {
+    __int128 v = 1;
+    for (int i = 0; i < e; ++i) v *= b;
+    return v <= (__int128)n;
+  };
+  int64_t b = (int64_t)std::floor(std::pow((double)n, 1.0 / (double)e));
+  while (b > 1 && !pow_le(b)) --b;
+  while (pow_le(b + 1)) ++b;
+  return (int)std::max<int64_t>(2, std::min<int64_t>(b, 65535));
+}
+
 int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z, std::string* err) {
   if (!x || !ind || n < 1) { *err = "null pointer or n < 1"; return CWB_E_INVALID_ARG; }
   if (nb < 2 || nb > 65535) { *err = "n_bins must be 2..65535"; return CWB_E_INVALID_ARG; }
@@ -317,8 +332,9 @@ int validate_problem(const cwb_problem* pr, std::string* err) {
   }
   for (int j = 0; j < pr->p; ++j) {
     const cwb_learner_spec& s = pr->specs[j];
-    if (s.kind == CWB_RIDGE_CAT) {
+    if (s.kind == CWB_RIDGE_CAT || s.kind == CWB_BINARY_CAT) {
       if (s.n_levels < 1 || s.n_levels > kMaxD) { *err = "level count must be 1..64"; return CWB_E_INVALID_ARG; }
+      if (s.kind == CWB_BINARY_CAT) continue;  // unpenalised: df and lambda unused
     } else if (s.kind == CWB_PSPLINE) {
       if (s.degree < 1 || s.degree > 3) { *err = "P-spline degree must be 1..3"; return CWB_E_UNSUPPORTED; }
       if (s.n_interior_knots < 0) { *err = "negative knot count"; return CWB_E_INVALID_ARG; }
@@ -326,8 +342,8 @@ int validate_problem(const cwb_problem* pr, std::string* err) {
       if (d > kMaxD) { *err = "basis larger than 64"; return CWB_E_UNSUPPORTED; }
       if (s.penalty_order < 0 || s.penalty_order >= d) { *err = "bad penalty order"; return CWB_E_INVALID_ARG; }
       if (s.n_bins == 0 && s.degree != 3) { *err = "unbinned learners must be cubic"; return CWB_E_UNSUPPORTED; }
-      if (s.n_bins != -1 && s.n_bins != 0 && (s.n_bins < 2 || s.n_bins > 65535)) {
-        *err = "n_bins must be 2..65535 (or 0: unbinned, -1: floor(sqrt(n)))";
+      if (s.n_bins != -1 && s.n_bins != -2 && s.n_bins != 0 && (s.n_bins < 2 || s.n_bins > 65535)) {
+        *err = "n_bins must be 2..65535 (or 0: unbinned, -1: floor(sqrt(n)), -2: floor(n^(1/4)))";
         return CWB_E_INVALID_ARG;
       }
       if (s.df > 0.0 && (s.df <= (double)s.penalty_order || s.df >= (double)d)) {
@@ -364,7 +380,171 @@ void uniform_cubic(double t, double* b) {
 
 }  // namespace
 
-int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
+namespace {
+
+// Knots and the banded basis at the design points of a binned P-spline
+// learner (Sec. 2.2, Sec. 3.1.1), from its range and design-point count.
+void pspline_design(const cwb_learner_spec& s, HostLearner& L) {
+  const int deg = s.degree;
+  const int nint = s.n_interior_knots;
+  const int nk = nint + 2 + 2 * deg;
+  const int d = nk - deg - 1;
+  L.d = d;
+  L.band = deg + 1;
+  std::vector<double> t(nk);
+  const double hk = (L.xmax - L.xmin) / (double)(nint + 1);
+  for (int q = 0; q < nk; ++q) t[q] = L.xmin + (double)(q - deg) * hk;
+  const double h = (L.xmax - L.xmin) / (double)(L.nb - 1);
+  L.bstart.resize(L.nb);
+  L.bval.assign((size_t)L.nb * kMaxBand, 0.0);
+  for (int l = 0; l < L.nb; ++l) {
+    const double z = grid_point(L.xmin, L.xmax, h, l, L.nb);
+    L.bstart[l] = bspline_band(z, t, deg, d, &L.bval[(size_t)l * kMaxBand]);
+  }
+}
+
+// Identity reduced design of a categorical learner (the levels are the bins).
+void categorical_design(HostLearner& L, int c) {
+  L.nb = c;
+  L.band = 1;
+  L.d = c;
+  L.bstart.resize(c);
+  L.bval.assign((size_t)c * kMaxBand, 0.0);
+  for (int l = 0; l < c; ++l) {
+    L.bstart[l] = l;
+    L.bval[(size_t)l * kMaxBand] = 1.0;
+  }
+}
+
+// Support ranges, Gram matrices over the training rows and over all rows,
+// smoothing parameters and the inverses of G + lambda D.  Binned learners
+// take their Grams from the bin counts (binMatMat, Algorithm 1); unbinned
+// ones bring them in G_unb.
+int learner_algebra(const cwb_learner_spec& s, int64_t n, HostLearner& L,
+                    const std::vector<double>& cnt_t, const std::vector<double>& cnt_a,
+                    const std::vector<double>* G_unb, int j, std::string* err) {
+  const int d = L.d;
+  // support ranges: design points whose band covers basis index q
+  L.jr.assign((size_t)2 * d, 0);
+  for (int q = 0; q < d; ++q) {
+    int lo = L.nb, hi = -1;
+    for (int l = 0; l < L.nb; ++l)
+      if (L.bstart[l] <= q && q < L.bstart[l] + L.band) {
+        lo = std::min(lo, l);
+        hi = std::max(hi, l);
+      }
+    L.jr[2 * q] = lo;
+    L.jr[2 * q + 1] = hi;
+  }
+  const std::vector<double> D = (s.kind != CWB_PSPLINE) ? difference_penalty(d, 0)
+                                                         : difference_penalty(d, s.penalty_order);
+  for (int set = 0; set < 2; ++set) {
+    const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
+    if (s.kind == CWB_BINARY_CAT) {
+      // one unpenalised learner per class: G = diag(n_l); the class
+      // estimate is s_l / n_l, and an empty class has none (its inverse
+      // entry stays 0)
+      L.gram[set].assign((size_t)d * d, 0.0);
+      L.ainv[set].assign((size_t)d * d, 0.0);
+      for (int l = 0; l < d; ++l) {
+        L.gram[set][(size_t)l * d + l] = cnt[l];
+        if (cnt[l] > 0.0) L.ainv[set][(size_t)l * d + l] = 1.0 / cnt[l];
+      }
+      L.lambda[set] = 0.0;
+      continue;
+    }
+    std::vector<double> G((size_t)d * d, 0.0);
+    if (G_unb) {
+      G = G_unb[set];
+    } else {
+      for (int l = 0; l < L.nb; ++l) {
+        if (cnt[l] == 0.0) continue;
+        const int b0 = L.bstart[l];
+        const double* bv = &L.bval[(size_t)l * kMaxBand];
+        for (int a = 0; a < L.band; ++a)
+          for (int b = 0; b < L.band; ++b) G[(size_t)(b0 + a) * d + (b0 + b)] += cnt[l] * bv[a] * bv[b];
+      }
+    }
+    double lam = s.lambda;
+    if (s.df > 0.0) {
+      if (s.kind == CWB_RIDGE_CAT) {
+        if (s.df >= (double)d) {
+          lam = 0.0;
+        } else {  // sum_l n_l / (n_l + lambda) = df, bisection in log(lambda)
+          double lo = 1e-12, hi = 1e12 * (double)n;
+          for (int it = 0; it < 400 && hi / lo > 1.0 + 1e-15; ++it) {
+            const double mid = std::sqrt(lo * hi);
+            double v = 0.0;
+            for (int l = 0; l < d; ++l) v += cnt[l] / (cnt[l] + mid);
+            if (v > s.df) lo = mid; else hi = mid;
+          }
+          lam = std::sqrt(lo * hi);
+        }
+      } else {
+        std::string e;
+        const int r2 = lambda_for_df(d, G, D, s.df, &lam, &e);
+        if (r2) {
+          *err = e + " (feature " + std::to_string(j) + ")";
+          return r2;
+        }
+      }
+    }
+    L.lambda[set] = lam;
+    std::vector<double> A((size_t)d * d);
+    for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
+    if (!spd_inverse(d, A, L.ainv[set])) {
+      *err = "penalised Gram matrix is singular (feature " + std::to_string(j) + ")";
+      return CWB_E_NUMERIC;
+    }
+    L.gram[set] = G;
+  }
+  return CWB_OK;
+}
+
+// Runs fn(j) for j in [0, p) on up to 32 threads; the first failing feature
+// (lowest j) decides the status.
+template <class Fn>
+int for_features(int p, std::string* err, Fn fn) {
+  std::vector<std::string> ferr(p);
+  std::vector<int> frc(p, 0);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    for (;;) {
+      const int j = next.fetch_add(1);
+      if (j >= p) break;
+      frc[j] = fn(j, &ferr[j]);
+    }
+  };
+  unsigned nth = std::thread::hardware_concurrency();
+  if (nth == 0) nth = 4;
+  nth = std::min<unsigned>(nth, 32);
+  nth = std::min<unsigned>(nth, (unsigned)p);
+  std::vector<std::thread> pool;
+  for (unsigned i = 1; i < nth; ++i) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  for (int j = 0; j < p; ++j)
+    if (frc[j]) {
+      set_error(err, ferr[j]);
+      return frc[j];
+    }
+  return CWB_OK;
+}
+
+void learner_sizes(HostFit* hf) {
+  hf->nb_max = 0;
+  hf->d_max = 0;
+  hf->sum_d = 0;
+  for (int j = 0; j < hf->p; ++j) {
+    hf->nb_max = std::max(hf->nb_max, hf->L[j].nb);
+    hf->d_max = std::max(hf->d_max, hf->L[j].d);
+    hf->sum_d += hf->L[j].d;
+  }
+}
+
+}  // namespace
+
+int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
   int rc = validate_problem(pr, err);
   if (rc) return rc;
   const int64_t n = pr->n;
@@ -402,234 +582,157 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
     *err = "training labels are all equal (binomial intercept not finite)";
     return CWB_E_NUMERIC;
   }
-
   hf->unbinned = pr->specs[0].kind == CWB_PSPLINE && pr->specs[0].n_bins == 0;
+  hf->L.assign(p, HostLearner());
+  for (int j = 0; j < p; ++j) {
+    const cwb_learner_spec& s = pr->specs[j];
+    HostLearner& L = hf->L[j];
+    L.kind = s.kind;
+    L.degree = s.degree;
+    L.n_int = s.n_interior_knots;
+    if (s.kind != CWB_PSPLINE) {
+      L.nb = L.d = s.n_levels;
+      L.band = 1;
+    } else if (hf->unbinned) {
+      L.nb = L.d = s.n_interior_knots + 4;
+      L.band = 1;
+    } else {
+      L.nb = bins_for(s.n_bins, n);
+      L.d = s.n_interior_knots + s.degree + 1;
+      L.band = s.degree + 1;
+    }
+  }
+  return CWB_OK;
+}
+
+int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
+  int rc = prepare_host_fit(pr, hf, err);
+  if (rc) return rc;
+  const int64_t n = pr->n;
+  const int p = pr->p;
+  const int64_t nt = hf->n_train;
   if (hf->unbinned)
     hf->XU.assign((size_t)p * hf->n_pad, 0u);
   else
     hf->X.assign((size_t)p * hf->n_pad, 0);
-  hf->L.resize(p);
-  std::vector<std::string> ferr(p);
-  std::vector<int> frc(p, 0);
-  std::atomic<int> next(0);
-  auto worker = [&]() {
-    std::vector<double> t;
-    for (;;) {
-      const int j = next.fetch_add(1);
-      if (j >= p) break;
-      const cwb_learner_spec& s = pr->specs[j];
-      const double* xj = pr->x + (size_t)j * (size_t)(pr->ldx ? pr->ldx : n);
-      HostLearner& L = hf->L[j];
-      L.degree = s.degree;
-      L.n_int = s.n_interior_knots;
-      uint16_t* Xj = hf->unbinned ? nullptr : hf->X.data() + (size_t)j * hf->n_pad;
-      uint32_t* XUj = hf->unbinned ? hf->XU.data() + (size_t)j * hf->n_pad : nullptr;
-      L.kind = s.kind;
-      if (s.kind == CWB_RIDGE_CAT) {
-        const int c = s.n_levels;
-        L.nb = c;
-        L.band = 1;
-        L.d = c;
-        for (int64_t i = 0; i < n; ++i) {
-          const double v = xj[hf->perm[i]];
-          if (!(v >= 0.0) || v >= (double)c || v != std::floor(v)) {
-            frc[j] = CWB_E_INVALID_ARG;
-            ferr[j] = "level code out of range in feature " + std::to_string(j);
-            break;
-          }
-          Xj[i] = (uint16_t)v;
+  rc = for_features(p, err, [&](int j, std::string* ferr) -> int {
+    const cwb_learner_spec& s = pr->specs[j];
+    const double* xj = pr->x + (size_t)j * (size_t)(pr->ldx ? pr->ldx : n);
+    HostLearner& L = hf->L[j];
+    uint16_t* Xj = hf->unbinned ? nullptr : hf->X.data() + (size_t)j * hf->n_pad;
+    uint32_t* XUj = hf->unbinned ? hf->XU.data() + (size_t)j * hf->n_pad : nullptr;
+    if (s.kind != CWB_PSPLINE) {
+      const int c = s.n_levels;
+      for (int64_t i = 0; i < n; ++i) {
+        const double v = xj[hf->perm[i]];
+        if (!(v >= 0.0) || v >= (double)c || v != std::floor(v)) {
+          *ferr = "level code out of range in feature " + std::to_string(j);
+          return CWB_E_INVALID_ARG;
         }
-        if (frc[j]) continue;
-        L.bstart.resize(c);
-        L.bval.assign((size_t)c * kMaxBand, 0.0);
-        for (int l = 0; l < c; ++l) {
-          L.bstart[l] = l;
-          L.bval[(size_t)l * kMaxBand] = 1.0;
-        }
-      } else {
-        double xmin = xj[0], xmax = xj[0];
-        for (int64_t i = 0; i < n; ++i) {
-          const double v = xj[i];
-          if (!std::isfinite(v)) { frc[j] = CWB_E_INVALID_ARG; ferr[j] = "non-finite x"; break; }
-          xmin = std::min(xmin, v);
-          xmax = std::max(xmax, v);
-        }
-        if (frc[j]) continue;
-        if (!(xmax > xmin)) {
-          frc[j] = CWB_E_INVALID_ARG;
-          ferr[j] = "constant feature " + std::to_string(j);
-          continue;
-        }
-        if (hf->unbinned) {
-          // unbinned cubic P-spline: knot-interval codes and an identity
-          // reduced design (its "bins" are the basis functions)
-          const int nint = s.n_interior_knots;
-          const int d = nint + 4;
-          const double hk = (xmax - xmin) / (double)(nint + 1);
-          L.xmin = xmin;
-          L.xmax = xmax;
-          L.nb = d;
-          L.d = d;
-          L.band = 1;
-          for (int64_t i = 0; i < n; ++i) {
-            const double u = (xj[hf->perm[i]] - xmin) / hk;
-            int iv = (int)std::floor(u);
-            iv = std::max(0, std::min(nint, iv));
-            const double tt = std::max(0.0, std::min(1.0, u - (double)iv));
-            XUj[i] = ((uint32_t)iv << 24) | (uint32_t)std::llround(tt * (double)kUnbFracMax);
-          }
-          L.bstart.resize(d);
-          L.bval.assign((size_t)d * kMaxBand, 0.0);
-          for (int l = 0; l < d; ++l) {
-            L.bstart[l] = l;
-            L.bval[(size_t)l * kMaxBand] = 1.0;
-          }
-        } else {
-        int nb = s.n_bins;
-        if (nb == -1) nb = (int)std::floor(std::sqrt((double)n));
-        if (nb < 2) nb = 2;
-        if (nb > kMaxBins) {
-          frc[j] = CWB_E_UNSUPPORTED;
-          ferr[j] = "more than 8192 bins per learner is not supported";
-          continue;
-        }
-        L.nb = nb;
-        L.xmin = xmin;
-        L.xmax = xmax;
-        const double h = (xmax - xmin) / (double)(nb - 1);
-        for (int64_t i = 0; i < n; ++i) Xj[i] = (uint16_t)bin_of(xj[hf->perm[i]], xmin, xmax, h, nb);
-        // knots and banded basis at the design points
-        const int deg = s.degree;
-        const int nint = s.n_interior_knots;
-        const int nk = nint + 2 + 2 * deg;
-        const int d = nk - deg - 1;
-        L.d = d;
-        L.band = deg + 1;
-        t.resize(nk);
-        const double hk = (xmax - xmin) / (double)(nint + 1);
-        for (int q = 0; q < nk; ++q) t[q] = xmin + (double)(q - deg) * hk;
-        L.bstart.resize(nb);
-        L.bval.assign((size_t)nb * kMaxBand, 0.0);
-        for (int l = 0; l < nb; ++l) {
-          const double z = grid_point(xmin, xmax, h, l, nb);
-          L.bstart[l] = bspline_band(z, t, deg, d, &L.bval[(size_t)l * kMaxBand]);
-        }
-        }
+        Xj[i] = (uint16_t)v;
       }
-      // support ranges: design points whose band covers basis index q
-      const int d = L.d;
-      L.jr.assign((size_t)2 * d, 0);
-      for (int q = 0; q < d; ++q) {
-        int lo = L.nb, hi = -1;
-        for (int l = 0; l < L.nb; ++l)
-          if (L.bstart[l] <= q && q < L.bstart[l] + L.band) {
-            lo = std::min(lo, l);
-            hi = std::max(hi, l);
-          }
-        L.jr[2 * q] = lo;
-        L.jr[2 * q + 1] = hi;
+      categorical_design(L, c);
+    } else {
+      double xmin = xj[0], xmax = xj[0];
+      for (int64_t i = 0; i < n; ++i) {
+        const double v = xj[i];
+        if (!std::isfinite(v)) { *ferr = "non-finite x"; return CWB_E_INVALID_ARG; }
+        xmin = std::min(xmin, v);
+        xmax = std::max(xmax, v);
       }
-      // Gram matrices over the training rows and over all rows: from the bin
-      // counts (binMatMat, Algorithm 1), or row by row for unbinned learners
-      // (with the basis at the stored interval positions)
-      std::vector<double> cnt_t, cnt_a, G_unb[2];
+      if (!(xmax > xmin)) {
+        *ferr = "constant feature " + std::to_string(j);
+        return CWB_E_INVALID_ARG;
+      }
+      L.xmin = xmin == 0.0 ? 0.0 : xmin;  // one zero for both signs
+      L.xmax = xmax == 0.0 ? 0.0 : xmax;
+      xmin = L.xmin;
+      xmax = L.xmax;
       if (hf->unbinned) {
-        for (int set = 0; set < 2; ++set) G_unb[set].assign((size_t)d * d, 0.0);
+        // unbinned cubic P-spline: knot-interval codes and an identity
+        // reduced design (its "bins" are the basis functions)
+        const int nint = s.n_interior_knots;
+        const double hk = (xmax - xmin) / (double)(nint + 1);
         for (int64_t i = 0; i < n; ++i) {
-          const uint32_t code = XUj[i];
-          const int b0 = (int)(code >> 24);
-          double bv[4];
-          uniform_cubic((double)(code & kUnbFracMax) / (double)kUnbFracMax, bv);
-          for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) {
-              const double v = bv[a] * bv[b];
-              G_unb[1][(size_t)(b0 + a) * d + (b0 + b)] += v;
-              if (i < nt) G_unb[0][(size_t)(b0 + a) * d + (b0 + b)] += v;
-            }
+          const double u = (xj[hf->perm[i]] - xmin) / hk;
+          int iv = (int)std::floor(u);
+          iv = std::max(0, std::min(nint, iv));
+          const double tt = std::max(0.0, std::min(1.0, u - (double)iv));
+          XUj[i] = ((uint32_t)iv << 24) | (uint32_t)std::llround(tt * (double)kUnbFracMax);
         }
+        categorical_design(L, nint + 4);
       } else {
-        cnt_t.assign(L.nb, 0.0);
-        cnt_a.assign(L.nb, 0.0);
-        for (int64_t i = 0; i < n; ++i) {
-          cnt_a[Xj[i]] += 1.0;
-          if (i < nt) cnt_t[Xj[i]] += 1.0;
+        if (L.nb > kMaxBins) {
+          *ferr = "more than 8192 bins per learner is not supported";
+          return CWB_E_UNSUPPORTED;
         }
-      }
-      const std::vector<double> D = (s.kind == CWB_RIDGE_CAT) ? difference_penalty(d, 0)
-                                                               : difference_penalty(d, s.penalty_order);
-      for (int set = 0; set < 2; ++set) {
-        std::vector<double> G((size_t)d * d, 0.0);
-        if (hf->unbinned) {
-          G = G_unb[set];
-        } else {
-          const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
-          for (int l = 0; l < L.nb; ++l) {
-            if (cnt[l] == 0.0) continue;
-            const int b0 = L.bstart[l];
-            const double* bv = &L.bval[(size_t)l * kMaxBand];
-            for (int a = 0; a < L.band; ++a)
-              for (int b = 0; b < L.band; ++b) G[(size_t)(b0 + a) * d + (b0 + b)] += cnt[l] * bv[a] * bv[b];
-          }
-        }
-        double lam = s.lambda;
-        if (s.df > 0.0) {
-          if (s.kind == CWB_RIDGE_CAT) {
-            if (s.df >= (double)d) {
-              lam = 0.0;
-            } else {  // sum_l n_l / (n_l + lambda) = df, bisection in log(lambda)
-              double lo = 1e-12, hi = 1e12 * (double)n;
-              for (int it = 0; it < 400 && hi / lo > 1.0 + 1e-15; ++it) {
-                const double mid = std::sqrt(lo * hi);
-                double v = 0.0;
-                const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
-                for (int l = 0; l < d; ++l) v += cnt[l] / (cnt[l] + mid);
-                if (v > s.df) lo = mid; else hi = mid;
-              }
-              lam = std::sqrt(lo * hi);
-            }
-          } else {
-            std::string e;
-            const int r2 = lambda_for_df(d, G, D, s.df, &lam, &e);
-            if (r2) {
-              frc[j] = r2;
-              ferr[j] = e + " (feature " + std::to_string(j) + ")";
-              break;
-            }
-          }
-        }
-        L.lambda[set] = lam;
-        std::vector<double> A((size_t)d * d);
-        for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
-        if (!spd_inverse(d, A, L.ainv[set])) {
-          frc[j] = CWB_E_NUMERIC;
-          ferr[j] = "penalised Gram matrix is singular (feature " + std::to_string(j) + ")";
-          break;
-        }
-        L.gram[set] = G;
+        const double h = (xmax - xmin) / (double)(L.nb - 1);
+        for (int64_t i = 0; i < n; ++i) Xj[i] = (uint16_t)bin_of(xj[hf->perm[i]], xmin, xmax, h, L.nb);
+        pspline_design(s, L);
       }
     }
-  };
-  unsigned nth = std::thread::hardware_concurrency();
-  if (nth == 0) nth = 4;
-  nth = std::min<unsigned>(nth, 32);
-  nth = std::min<unsigned>(nth, (unsigned)p);
-  std::vector<std::thread> pool;
-  for (unsigned i = 1; i < nth; ++i) pool.emplace_back(worker);
-  worker();
-  for (auto& th : pool) th.join();
-  for (int j = 0; j < p; ++j)
-    if (frc[j]) {
-      set_error(err, ferr[j]);
-      return frc[j];
+    // Gram matrices over the training rows and over all rows: from the bin
+    // counts (binMatMat, Algorithm 1), or row by row for unbinned learners
+    // (with the basis at the stored interval positions)
+    const int d = L.d;
+    std::vector<double> cnt_t, cnt_a, G_unb[2];
+    if (hf->unbinned) {
+      for (int set = 0; set < 2; ++set) G_unb[set].assign((size_t)d * d, 0.0);
+      for (int64_t i = 0; i < n; ++i) {
+        const uint32_t code = XUj[i];
+        const int b0 = (int)(code >> 24);
+        double bv[4];
+        uniform_cubic((double)(code & kUnbFracMax) / (double)kUnbFracMax, bv);
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) {
+            const double v = bv[a] * bv[b];
+            G_unb[1][(size_t)(b0 + a) * d + (b0 + b)] += v;
+            if (i < nt) G_unb[0][(size_t)(b0 + a) * d + (b0 + b)] += v;
+          }
+      }
+    } else {
+      cnt_t.assign(L.nb, 0.0);
+      cnt_a.assign(L.nb, 0.0);
+      for (int64_t i = 0; i < n; ++i) {
+        cnt_a[Xj[i]] += 1.0;
+        if (i < nt) cnt_t[Xj[i]] += 1.0;
+      }
     }
-  hf->nb_max = 0;
-  hf->d_max = 0;
-  hf->sum_d = 0;
-  for (int j = 0; j < p; ++j) {
-    hf->nb_max = std::max(hf->nb_max, hf->L[j].nb);
-    hf->d_max = std::max(hf->d_max, hf->L[j].d);
-    hf->sum_d += hf->L[j].d;
-  }
+    return learner_algebra(s, n, L, cnt_t, cnt_a, hf->unbinned ? G_unb : nullptr, j, ferr);
+  });
+  if (rc) return rc;
+  learner_sizes(hf);
+  return CWB_OK;
+}
+
+int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
+                    const uint32_t* counts, int64_t counts_stride, std::string* err) {
+  const int p = pr->p;
+  const int64_t n = pr->n;
+  int rc = for_features(p, err, [&](int j, std::string* ferr) -> int {
+    const cwb_learner_spec& s = pr->specs[j];
+    HostLearner& L = hf->L[j];
+    if (s.kind != CWB_PSPLINE) {
+      categorical_design(L, s.n_levels);
+    } else {
+      L.xmin = xrange[2 * j];
+      L.xmax = xrange[2 * j + 1];
+      if (L.nb > kMaxBins) {
+        *ferr = "more than 8192 bins per learner is not supported";
+        return CWB_E_UNSUPPORTED;
+      }
+      pspline_design(s, L);
+    }
+    const uint32_t* c = counts + (size_t)j * counts_stride;
+    std::vector<double> cnt_t(L.nb), cnt_a(L.nb);
+    for (int l = 0; l < L.nb; ++l) {
+      cnt_t[l] = (double)c[l];
+      cnt_a[l] = (double)c[counts_stride / 2 + l];
+    }
+    return learner_algebra(s, n, L, cnt_t, cnt_a, nullptr, j, ferr);
+  });
+  if (rc) return rc;
+  learner_sizes(hf);
   return CWB_OK;
 }
 

@@ -38,8 +38,23 @@ struct HostFit {
   std::vector<HostLearner> L;
 };
 
+// Design points of a P-spline learner for the n_bins setting of its spec:
+// the value itself when positive, floor(sqrt(n)) for -1, floor(n^(1/4)) for
+// -2 (at least 2).
+int bins_for(int32_t n_bins, int64_t n);
 int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z, std::string* err);
 int validate_problem(const cwb_problem* pr, std::string* err);
+// Host setup of a fit in full: validation, row order, labels, binning, bin
+// counts and every learner's tables.
 int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err);
+// Its first phase only (nothing that reads x): validation, row order,
+// labels, intercept and each learner's kind and sizes.
+int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err);
+// Its last phase after a device binning pass: every learner's tables from
+// the feature ranges (xrange[2j], xrange[2j+1]) and bin counts (feature j's
+// training-row counts at counts[j * counts_stride], all-row counts
+// counts_stride / 2 further).
+int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
+                    const uint32_t* counts, int64_t counts_stride, std::string* err);
 
 }  // namespace cwb

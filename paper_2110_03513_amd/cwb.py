@@ -17,8 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libcwb.so")
 
 CWB_OK, CWB_E_INVALID_ARG, CWB_E_UNSUPPORTED, CWB_E_NO_MEMORY = 0, -1, -2, -3
 CWB_E_DEVICE, CWB_E_NUMERIC, CWB_E_AGAIN, CWB_E_STATE = -4, -5, -6, -7
+CWB_PSPLINE, CWB_RIDGE_CAT, CWB_BINARY_CAT = 0, 1, 2
 LOSSES = {"l2": 0, "binomial": 1}
 VARIANTS = {"cwb": 0, "acwb": 1, "hcwb": 2}
+SETUPS = {"auto": 0, "host": 1, "device": 2}
 
 
 class CwbError(RuntimeError):
@@ -38,7 +40,8 @@ class cwb_problem(C.Structure):
                 ("y", C.POINTER(C.c_double)), ("loss", C.c_int32),
                 ("specs", C.POINTER(cwb_learner_spec)), ("nu", C.c_double), ("M", C.c_int32),
                 ("variant", C.c_int32), ("gamma", C.c_double), ("patience", C.c_int32),
-                ("val_mask", C.POINTER(C.c_uint8)), ("ldx", C.c_int64)]
+                ("val_mask", C.POINTER(C.c_uint8)), ("ldx", C.c_int64),
+                ("setup", C.c_int32)]
 
 
 class cwb_info(C.Structure):
@@ -67,7 +70,8 @@ class cwb_stats(C.Structure):
                 ("in_flight", C.c_int32), ("queued", C.c_int32), ("fits_per_s", C.c_double),
                 ("p50_latency_s", C.c_double), ("p99_latency_s", C.c_double),
                 ("arena_in_use", C.c_size_t), ("arena_peak", C.c_size_t),
-                ("mean_setup_s", C.c_double), ("mean_queue_s", C.c_double)]
+                ("mean_setup_s", C.c_double), ("mean_queue_s", C.c_double),
+                ("round_s", C.c_double), ("busy_s", C.c_double), ("rounds", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -176,7 +180,7 @@ class Problem:
             M=int(prob["M"]), variant=VARIANTS[prob.get("variant", "cwb")],
             gamma=float(prob.get("gamma", 0.0)), patience=int(prob.get("patience", 5)),
             val_mask=None if self.vm is None else self.vm.ctypes.data_as(C.POINTER(C.c_uint8)),
-            ldx=ldx)
+            ldx=ldx, setup=SETUPS[prob.get("setup", "auto")])
         self.n, self.p, self.M = n, p, int(prob["M"])
 
 

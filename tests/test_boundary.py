@@ -69,7 +69,9 @@ def _shape_only_problem(n, p, nb, variant):
 
 
 def _create_error(prob, ws_bytes=1 << 40):
-    pr = cwb.Problem(prob)
+    # host setup: the checks of x's values run before any device call (the
+    # device setup makes the same checks on the GPU; GPU tests cover those)
+    pr = cwb.Problem(dict(prob, setup=prob.get("setup", "host")))
     h = C.c_void_p()
     rc = cwb.lib().cwb_fit_create(C.byref(pr.c), C.c_void_p(1 << 20), ws_bytes, None, C.byref(h))
     return rc, cwb.lib().cwb_last_error().decode()
@@ -201,3 +203,51 @@ def test_unbinned_learners_shape_and_rules():
     quad = dict(base, degree=2)
     rc, msg = _create_error(quad)
     assert rc == cwb.CWB_E_UNSUPPORTED and "cubic" in msg
+
+
+@pytest.mark.parametrize("n", [16, 80, 81, 9999, 10000, 10001, 65535, 65536, 1_000_000])
+def test_fourth_root_bin_rule(n):
+    """n_bins = -2 selects floor(n^(1/4)) design points (at least 2), exactly
+    as if that count had been given (same workspace, same schedule)."""
+    import math
+    b = math.isqrt(math.isqrt(n))
+    assert b ** 4 <= n < (b + 1) ** 4
+    quarter = _shape_only_problem(n, 3, -2, "cwb")
+    explicit = _shape_only_problem(n, 3, max(2, b), "cwb")
+    assert cwb.workspace_bytes(quarter) == cwb.workspace_bytes(explicit)
+    sq = _shape_only_problem(n, 3, max(2, math.isqrt(n)), "cwb")
+    assert cwb.workspace_bytes(_shape_only_problem(n, 3, -1, "cwb")) == cwb.workspace_bytes(sq)
+
+
+def test_binary_categorical_rules():
+    pc = datagen.additive_problem(300, 3, seed=9, n_informative=1, n_cat=1, n_bins=10, M=3,
+                                  cat_kind=datagen.BINARY)
+    assert pc["kind"][2] == cwb.CWB_BINARY_CAT and pc["df"][2] == 0.0
+    assert pc["n_bins"][2] == pc["n_levels"][2]
+    xc = pc["x"].copy()
+    xc[0, 2] = pc["n_levels"][2]
+    rc, msg = _create_error(dict(pc, x=xc))
+    assert rc == cwb.CWB_E_INVALID_ARG and "level" in msg
+    nl = pc["n_levels"].copy()
+    nl[2] = 65
+    rc, msg = _create_error(dict(pc, n_levels=nl))
+    assert rc == cwb.CWB_E_INVALID_ARG and "64" in msg
+    # the workspace of a binary feature equals that of a ridge feature with
+    # the same levels (same histogram, Gram and coefficient sizes)
+    ridge = dict(pc, kind=np.where(pc["kind"] == cwb.CWB_BINARY_CAT, cwb.CWB_RIDGE_CAT, pc["kind"]),
+                 df=np.where(pc["kind"] == cwb.CWB_BINARY_CAT, 3.0, pc["df"]))
+    assert cwb.workspace_bytes(pc) == cwb.workspace_bytes(ridge)
+
+
+def test_setup_mode_rules():
+    base = datagen.tiny_problem(n=300, p=3, seed=5, n_bins=10, M=5)
+    pr = cwb.Problem(base)
+    pr.c.setup = 7
+    h = C.c_void_p()
+    rc = cwb.lib().cwb_fit_create(C.byref(pr.c), C.c_void_p(1 << 20), 1 << 40, None, C.byref(h))
+    assert rc == cwb.CWB_E_INVALID_ARG and "setup mode" in cwb.lib().cwb_last_error().decode()
+    unb = datagen.tiny_problem(n=300, p=3, seed=5, n_bins=0, M=5)
+    rc, msg = _create_error(dict(unb, setup="device"))
+    assert rc == cwb.CWB_E_UNSUPPORTED and "device setup" in msg
+    # the two explicit modes size the same workspace
+    assert cwb.workspace_bytes(dict(base, setup="device")) == cwb.workspace_bytes(base)
