@@ -343,8 +343,10 @@ def served(args, torch, cwb, datagen):
 
     log("[bench] served: continuous batching")
     st, res = one_stream(args.serve_slots)
-    log("[bench] served: one fit at a time")
-    st1, _ = one_stream(1)
+    st1 = None
+    if not args.serve_batched_only:
+        log("[bench] served: one fit at a time")
+        st1, _ = one_stream(1)
     # alone vs in the mix
     bitwise = 0
     worst = 0.0
@@ -372,8 +374,10 @@ def served(args, torch, cwb, datagen):
     return {"requests": len(specs), "rate_per_s": 20.0, "arrival_span_s": round(span, 2),
             "max_slots": args.serve_slots, "quantum": args.serve_quantum,
             "arena_gb": args.serve_arena_gb,
-            "continuous_batching": summary(st), "one_at_a_time": summary(st1),
-            "speedup_fits_per_s": round(st["fits_per_s"] / max(st1["fits_per_s"], 1e-12), 3),
+            "continuous_batching": summary(st),
+            "one_at_a_time": summary(st1) if st1 else None,
+            "speedup_fits_per_s": (round(st["fits_per_s"] / max(st1["fits_per_s"], 1e-12), 3)
+                                   if st1 else None),
             "index_gbs": round(index_bytes / max(st["wall_s"], 1e-9) / 1e9, 1),
             "alone_vs_mix": {"requests": len(sample), "bitwise_equal": bitwise,
                              "max_rel_err_f": worst}}
@@ -418,6 +422,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-quantum", type=int, default=50)
+    ap.add_argument("--serve-batched-only", action="store_true",
+                    help="skip serving the stream one fit at a time")
     ap.add_argument("--serve-arena-gb", type=float, default=64.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain streaming copy of this many MiB (counter calibration)")

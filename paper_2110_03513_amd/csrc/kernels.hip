@@ -255,7 +255,8 @@ template <bool STAGED>
 __global__ void __launch_bounds__(kSelectThreads)
 k_select(const SelItem* __restrict__ items, const long long* __restrict__ partials, int nb_cap,
          int d_cap) {
-  // dynamic LDS: s[nb_cap] | Ainv[d_cap^2] | G[d_cap^2] | (STAGED) bval[nb_cap*4] | bstart[nb_cap]
+  // dynamic LDS: s[nb_cap] | Ainv[d_cap^2] | G[d_cap^2] | bstart[nb_cap, padded to even]
+  // | (STAGED) bval[nb_cap*4]
   extern __shared__ double s_dyn[];
   __shared__ double s_v[kMaxD], s_th[kMaxD], s_gt[kMaxD];
   __shared__ double s_part[kMaxD * kChunks];
@@ -265,8 +266,8 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   double* s_bins = s_dyn;
   double* s_ai = s_dyn + nb_cap;
   double* s_g = s_ai + (size_t)d_cap * d_cap;
-  double* s_bv = s_g + (size_t)d_cap * d_cap;
-  int* s_bs = reinterpret_cast<int*>(s_bv + (size_t)nb_cap * kMaxBand);
+  int* s_bs = reinterpret_cast<int*>(s_g + (size_t)d_cap * d_cap);
+  double* s_bv = reinterpret_cast<double*>(s_bs + ((nb_cap + 1) & ~1));
   const SelItem it = items[blockIdx.x];
   const int d = it.d, nb = it.nb, band = it.band, n_off = it.n_off;
   // the first chunk of signal 0's partials, loaded in the first round when
@@ -312,10 +313,10 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
     stage<kSelectThreads, 4>(s_ai, it.ainv[0], d * d);
     stage<kSelectThreads, 4>(s_g, it.gram[0], d * d);
     stage<kSelectThreads, 1>(s_jr, it.jr, 2 * d);
-    if (STAGED) {
-      stage<kSelectThreads, 16>(s_bv, it.bval, nb * kMaxBand);
-      stage<kSelectThreads, 4>(s_bs, it.bstart, nb);
-    }
+    // the band starts always (the loops below index the design through
+    // them); the design values only when they fit
+    stage<kSelectThreads, 4>(s_bs, it.bstart, nb);
+    if (STAGED) stage<kSelectThreads, 16>(s_bv, it.bval, nb * kMaxBand);
   }
   if (P >= it.M) return;
   const bool hcwb_all = it.variant == CWB_HCWB && switched;
@@ -339,7 +340,7 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
     stage<kSelectThreads, 4>(s_ai, it.ainv[1], d * d);
     stage<kSelectThreads, 4>(s_g, it.gram[1], d * d);
   }
-  const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{it.bval, it.bstart};
+  const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{it.bval, s_bs};
   block_max2<kSelectThreads>(am0, am1, s_red);
   const float amax[2] = {am0, am1};
   for (int sig = 0; sig < nsig; ++sig) {
@@ -674,9 +675,41 @@ hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int n
                          const long long* partials) {
   if (nitems <= 0) return hipSuccess;
   // static LDS of the kernel (incl. the selection step) stays below 16 KiB
-  size_t lds = ((size_t)nb_max + 2 * (size_t)d_max * d_max) * sizeof(double);
-  const size_t extra = (size_t)nb_max * kMaxBand * sizeof(double) + (size_t)nb_max * sizeof(int);
-  const bool staged = nb_max <= kStageBins && lds + extra <= 144 * 1024;
+  size_t lds = ((size_t)nb_max + 2 * (size_t)d_max * d_max) * sizeof(double) +
+               (size_t)((nb_max + 1) & ~1) * sizeof(int);
+  const size_t extra = (size_t)nb_max * kMaxBand * sizeof(double);
+  bool staged = nb_max <= kStageBins && lds + extra <= 144 * 1024;
+  if (staged) {
+    // Staging the reduced design in LDS shortens each block, but a large
+    // footprint can leave fewer blocks per CU: with many learners (a batch)
+    // keep the variant that needs fewer rounds of blocks over the chip.
+    struct Occ {
+      int cus = 0;
+      size_t stat = 16 * 1024;
+    };
+    static Occ occ[64];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    Occ& o = occ[dev & 63];
+    if (o.cus == 0) {
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 1;
+      hipFuncAttributes fa;
+      if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_select<true>)) == hipSuccess)
+        o.stat = fa.sharedSizeBytes;
+      (void)hipGetLastError();
+      o.cus = cus;
+    }
+    const size_t cu_lds = 160 * 1024;
+    auto rounds = [&](size_t per_block) {
+      int bpc = (int)(cu_lds / (per_block + o.stat));
+      bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);  // 8 blocks of 4 waves fill a CU
+      const int64_t slots = (int64_t)o.cus * bpc;
+      return (nitems + slots - 1) / slots;
+    };
+    staged = rounds(lds + extra) <= rounds(lds);
+  }
   if (staged) lds += extra;
   // 160 KiB per workgroup minus the kernel's own static LDS (< 16 KiB)
   static const bool attr = [] {

@@ -227,11 +227,12 @@ inline double grid_point(double xmin, double xmax, double h, int l, int nb) {
 
 // Closest design point, ties to the lower one.  An arithmetic estimate of the
 // enclosing interval is corrected with exact comparisons against the design
-// points, then the two distances decide.
-inline int bin_of(double x, double xmin, double xmax, double h, int nb) {
+// points, then the two distances decide; the result does not depend on the
+// estimate, which may use the reciprocal of h.
+inline int bin_of(double x, double xmin, double xmax, double h, int nb, double inv_h) {
   if (x <= xmin) return 0;
   if (x >= xmax) return nb - 1;
-  int l = (int)((x - xmin) / h);
+  int l = (int)((x - xmin) * inv_h);
   if (l < 0) l = 0;
   if (l > nb - 2) l = nb - 2;
   while (l > 0 && grid_point(xmin, xmax, h, l, nb) > x) --l;
@@ -300,7 +301,7 @@ int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z
   }
   if (!(xmax > xmin)) { *err = "constant feature"; return CWB_E_INVALID_ARG; }
   const double h = (xmax - xmin) / (double)(nb - 1);
-  for (int64_t i = 0; i < n; ++i) ind[i] = (uint16_t)bin_of(x[i], xmin, xmax, h, nb);
+  for (int64_t i = 0; i < n; ++i) ind[i] = (uint16_t)bin_of(x[i], xmin, xmax, h, nb, 1.0 / h);
   if (z)
     for (int l = 0; l < nb; ++l) z[l] = grid_point(xmin, xmax, h, l, nb);
   return CWB_OK;
@@ -612,15 +613,19 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
   const int p = pr->p;
   const int64_t nt = hf->n_train;
   if (hf->unbinned)
-    hf->XU.assign((size_t)p * hf->n_pad, 0u);
+    hf->XU.resize((size_t)p * hf->n_pad);
   else
-    hf->X.assign((size_t)p * hf->n_pad, 0);
+    hf->X.resize((size_t)p * hf->n_pad);
   rc = for_features(p, err, [&](int j, std::string* ferr) -> int {
     const cwb_learner_spec& s = pr->specs[j];
     const double* xj = pr->x + (size_t)j * (size_t)(pr->ldx ? pr->ldx : n);
     HostLearner& L = hf->L[j];
     uint16_t* Xj = hf->unbinned ? nullptr : hf->X.data() + (size_t)j * hf->n_pad;
     uint32_t* XUj = hf->unbinned ? hf->XU.data() + (size_t)j * hf->n_pad : nullptr;
+    for (int64_t i = n; i < hf->n_pad; ++i) {  // padding rows: index 0
+      if (Xj) Xj[i] = 0;
+      if (XUj) XUj[i] = 0;
+    }
     if (s.kind != CWB_PSPLINE) {
       const int c = s.n_levels;
       for (int64_t i = 0; i < n; ++i) {
@@ -667,7 +672,13 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
           return CWB_E_UNSUPPORTED;
         }
         const double h = (xmax - xmin) / (double)(L.nb - 1);
-        for (int64_t i = 0; i < n; ++i) Xj[i] = (uint16_t)bin_of(xj[hf->perm[i]], xmin, xmax, h, L.nb);
+        const double inv_h = 1.0 / h;
+        if (pr->val_mask) {
+          for (int64_t i = 0; i < n; ++i)
+            Xj[i] = (uint16_t)bin_of(xj[hf->perm[i]], xmin, xmax, h, L.nb, inv_h);
+        } else {  // identity row order
+          for (int64_t i = 0; i < n; ++i) Xj[i] = (uint16_t)bin_of(xj[i], xmin, xmax, h, L.nb, inv_h);
+        }
         pspline_design(s, L);
       }
     }
@@ -691,11 +702,14 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
           }
       }
     } else {
-      cnt_t.assign(L.nb, 0.0);
-      cnt_a.assign(L.nb, 0.0);
-      for (int64_t i = 0; i < n; ++i) {
-        cnt_a[Xj[i]] += 1.0;
-        if (i < nt) cnt_t[Xj[i]] += 1.0;
+      std::vector<int64_t> ct(L.nb, 0), ca(L.nb, 0);
+      for (int64_t i = 0; i < nt; ++i) ct[Xj[i]] += 1;
+      for (int64_t i = nt; i < n; ++i) ca[Xj[i]] += 1;
+      cnt_t.resize(L.nb);
+      cnt_a.resize(L.nb);
+      for (int l = 0; l < L.nb; ++l) {
+        cnt_t[l] = (double)ct[l];
+        cnt_a[l] = (double)(ct[l] + ca[l]);
       }
     }
     return learner_algebra(s, n, L, cnt_t, cnt_a, hf->unbinned ? G_unb : nullptr, j, ferr);

@@ -2,12 +2,35 @@
 #pragma once
 #include <cstdint>
 #include <string>
+#include <memory>
+#include <utility>
 #include <vector>
 
 #include "../../include/cwb.h"
 #include "cwb_internal.h"
 
 namespace cwb {
+
+// Allocator that leaves new elements uninitialised (for the large index
+// matrices, every element of which setup writes).
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = UninitAlloc<U>;
+  };
+  UninitAlloc() = default;
+  template <class U>
+  UninitAlloc(const UninitAlloc<U>&) {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
 
 struct HostLearner {
   int kind = 0;
@@ -31,9 +54,9 @@ struct HostFit {
   double nu = 0, gamma = 0, f0 = 0;
   int nb_max = 0, d_max = 0, sum_d = 0;
   std::vector<int64_t> perm;     // internal row -> original row
-  std::vector<uint16_t> X;       // p x n_pad, feature-major (binned learners)
+  std::vector<uint16_t, UninitAlloc<uint16_t>> X;  // p x n_pad, feature-major (binned learners)
   bool unbinned = false;         // every learner is an unbinned cubic P-spline
-  std::vector<uint32_t> XU;      // p x n_pad knot-interval codes (unbinned)
+  std::vector<uint32_t, UninitAlloc<uint32_t>> XU;  // p x n_pad knot-interval codes (unbinned)
   std::vector<float> y;          // n_pad
   std::vector<HostLearner> L;
 };

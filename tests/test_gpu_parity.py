@@ -385,3 +385,42 @@ def test_fourth_root_bins_against_oracle():
     f.close()
     gpu = _run(prob)
     compare(gpu, dict(prob, n_bins=np.full(8, b, np.int32)))
+
+
+def test_binary_categorical_prediction_batch_and_checkpoint():
+    """Binary categorical learners through prediction, a batch with other
+    fits (bitwise equal to alone) and a checkpoint resume."""
+    import oracle
+    prob = datagen.additive_problem(25_000, 6, seed=93, n_informative=2, n_bins=100, M=60,
+                                    n_cat=3, n_informative_cat=3, cat_kind=datagen.BINARY,
+                                    loss="binomial", variant="acwb", gamma=0.1)
+    alone = _run(prob)
+    o = oracle.fit(prob)
+    rng = np.random.default_rng(94)
+    xn = rng.uniform(0, 1, (3_000, 6))
+    for j in (3, 4, 5):
+        xn[:, j] = rng.integers(0, prob["n_levels"][j], 3_000)
+    f = cwb.Fit(prob)
+    f.run(25)
+    f.sync()
+    blob = f.save_state()
+    g = cwb.Fit(prob)
+    g.load_state(blob)
+    g.run(35)
+    g.sync()
+    np.testing.assert_array_equal(g.trace()["k"], alone["k"])
+    np.testing.assert_array_equal(g.pred(), alone["f"])
+    got = g.predict(xn)
+    assert rel_err(got, oracle.predict(prob, o, xn)) <= 1e-4
+    f.close()
+    g.close()
+    other = datagen.additive_problem(18_000, 9, seed=95, n_informative=3, n_bins=64, M=60)
+    fits = [cwb.Fit(prob), cwb.Fit(other)]
+    b = cwb.Batch(fits)
+    b.run(60)
+    b.sync()
+    np.testing.assert_array_equal(fits[0].trace()["k"], alone["k"])
+    np.testing.assert_array_equal(fits[0].pred(), alone["f"])
+    b.close()
+    for x in fits:
+        x.close()
