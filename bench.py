@@ -145,6 +145,29 @@ def setup_leg(prob, cwb):
     return out
 
 
+def mise_leg(cwb, datagen):
+    """Partial-effect quality (the MISE of the simulation study) on the
+    small additive workload (n = 10,000, p = 10, five informative effects,
+    L2, SNR 1), 500 iterations, from the GPU's partial effects."""
+    from paper_2110_03513_amd import evaluate
+    out = {}
+    cases = [("cwb_sqrt_n_bins", dict(variant="cwb", n_bins=100)),
+             ("cwb_fourth_root_bins", dict(variant="cwb", n_bins=-2)),
+             ("cwb_unbinned", dict(variant="cwb", n_bins=0)),
+             ("acwb", dict(variant="acwb", n_bins=100, gamma=datagen.GAMMA_ACWB)),
+             ("hcwb", dict(variant="hcwb", n_bins=100, gamma=datagen.GAMMA_HCWB))]
+    for name, kw in cases:
+        prob = datagen.additive_problem(10_000, 10, seed=1, n_informative=5, M=500, amp_one=True,
+                                        **kw)
+        f = cwb.Fit(prob)
+        f.run(500)
+        f.sync()
+        out[name] = round(evaluate.mise(prob, lambda j, v: f.partial_effect(j, v)), 6)
+        f.close()
+    log(f"[bench] mise {out}")
+    return out
+
+
 def unbinned_leg(args, torch, cwb, datagen):
     """The headline workload with unbinned learners (each row's own cubic
     basis, no binning), timed beside the binned path."""
@@ -408,6 +431,7 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-mise", action="store_true", help="skip the partial-effect MISE leg")
     ap.add_argument("--no-setup", action="store_true",
                     help="skip timing fit creation with host vs device binning")
     ap.add_argument("--no-serve", action="store_true")
@@ -474,6 +498,8 @@ def main():
     }
     if not args.no_setup:
         out["setup"] = setup_leg(prob, cwb)
+    if not args.no_mise:
+        out["mise"] = mise_leg(cwb, datagen)
     if not args.no_cpu:
         cb, par = cpu_baseline(args, prob, tr)
         out["cpu_baseline"] = cb

@@ -285,3 +285,21 @@ def predict(problem: dict, result: dict, x_new) -> np.ndarray:
             f += bspline(np.clip(xn[:, k], lo, hi), t, degree) @ c
         off += d
     return f
+
+
+
+def partial_effect(problem: dict, result: dict, k: int, values) -> np.ndarray:
+    """Learner k's fitted function alone at the given values: ``predict``
+    with the intercept and every other learner's coefficients set to zero."""
+    x = np.asarray(problem["x"], dtype=np.float64)
+    kind = np.asarray(problem["kind"])
+    v = np.asarray(values, dtype=np.float64)
+    xn = np.empty((v.shape[0], x.shape[1]))
+    for j in range(x.shape[1]):  # any valid value: these learners contribute 0
+        xn[:, j] = 0.0 if kind[j] != 0 else x[0, j]
+    xn[:, k] = v
+    d = np.asarray(result["d"])
+    off = int(d[:k].sum())
+    coef = np.zeros_like(np.asarray(result["coef_f"], dtype=np.float64))
+    coef[off:off + int(d[k])] = result["coef_f"][off:off + int(d[k])]
+    return predict(problem, dict(result, f0=0.0, coef_f=coef), xn)

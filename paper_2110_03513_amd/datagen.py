@@ -37,7 +37,7 @@ def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def _effect(idx: int, u: np.ndarray) -> np.ndarray:
+def _raw_effect(idx: int, u: np.ndarray) -> np.ndarray:
     e = idx % 5
     if e == 0:
         v = np.sin(2.0 * math.pi * u)
@@ -49,7 +49,25 @@ def _effect(idx: int, u: np.ndarray) -> np.ndarray:
         v = np.tanh(4.0 * (u - 0.5))
     else:
         v = np.cos(3.0 * math.pi * u)
+    return v
+
+
+def _effect(idx: int, u: np.ndarray) -> np.ndarray:
+    v = _raw_effect(idx, u)
     return v - v.mean()
+
+
+def true_effect(prob: dict, j: int, x: np.ndarray) -> np.ndarray:
+    """The generating effect of numeric column j at values x, on the scale of
+    the model (the logit for binomial targets), centred like the generator
+    (by its mean over the sample rows); zero for a noise column."""
+    x = np.asarray(x, dtype=np.float64)
+    t = prob.get("truth", {}).get("numeric", {}).get(j)
+    if t is None:
+        return np.zeros_like(x)
+    idx, amp, transform, center = t
+    u = _norm_cdf(x) if transform == "norm_cdf" else x
+    return prob["truth"]["scale"] * amp * (_raw_effect(idx, u) - center)
 
 
 def _norm_cdf(x: np.ndarray) -> np.ndarray:
@@ -92,17 +110,21 @@ def additive_problem(n: int, p: int, *, seed: int, n_informative: int, loss: str
     n_unif = p_num - n_normal
     x = np.empty((n, p), dtype=np.float64, order="F")
     eta = np.zeros(n)
+    truth = {}
     for j in range(n_unif):
         x[:, j] = rng.random(n)
         if j < n_informative:
             a = 1.0 if amp_one else 1.0 + j / 19.0
             eta += a * _effect(j, x[:, j])
+            truth[j] = (j, a, "id", float(_raw_effect(j, x[:, j]).mean()))
     for jj in range(n_normal):
         j = n_unif + jj
         x[:, j] = rng.standard_normal(n)
         if jj < n_informative_normal:
             a = 1.0 + (n_informative + jj) / 19.0
-            eta += a * _effect(n_informative + jj, _norm_cdf(x[:, j]))
+            u = _norm_cdf(x[:, j])
+            eta += a * _effect(n_informative + jj, u)
+            truth[j] = (n_informative + jj, a, "norm_cdf", float(_raw_effect(n_informative + jj, u).mean()))
     kinds = np.zeros(p, np.int32)
     n_levels = np.zeros(p, np.int32)
     for jj in range(n_cat):
@@ -115,12 +137,14 @@ def additive_problem(n: int, p: int, *, seed: int, n_informative: int, loss: str
         if jj < n_informative_cat:
             lev = rng.normal(0.0, 0.5, size=c)
             eta += lev[codes] - lev[codes].mean()
+    scale = 1.0
     if loss == "l2":
         sd = math.sqrt(max(eta.var(), 1e-300)) / snr
         y = eta + rng.normal(0.0, sd, size=n)
     elif loss == "binomial":
         s = eta.std()
         z = eta / s if s > 0 else eta
+        scale = 1.0 / s if s > 0 else 1.0
         prob = 1.0 / (1.0 + np.exp(-z))
         y = (rng.random(n) < prob).astype(np.float64)
     else:
@@ -134,7 +158,8 @@ def additive_problem(n: int, p: int, *, seed: int, n_informative: int, loss: str
     if gamma is None:
         gamma = GAMMA_HCWB if variant == "hcwb" else GAMMA_ACWB
     prob = {"x": x, "y": y, "loss": loss, "nu": nu, "M": M, "variant": variant,
-            "gamma": gamma, "patience": patience, "val_mask": val_mask}
+            "gamma": gamma, "patience": patience, "val_mask": val_mask,
+            "truth": {"scale": scale, "numeric": truth}}
     prob.update(learner_specs(p, n_bins, df=df, kinds=kinds, n_levels=n_levels))
     return prob
 

@@ -424,3 +424,23 @@ def test_binary_categorical_prediction_batch_and_checkpoint():
     b.close()
     for x in fits:
         x.close()
+
+
+@pytest.mark.parametrize("variant,loss,nb", [("cwb", "l2", 100), ("hcwb", "binomial", 100),
+                                             ("cwb", "l2", 0)])
+def test_mise_against_oracle(variant, loss, nb):
+    """The MISE of Sec. 4.1 from the GPU's partial effects against the same
+    measure from the oracle's fit of the same input."""
+    import oracle
+    from paper_2110_03513_amd import evaluate
+    prob = datagen.additive_problem(10_000, 10, seed=96, n_informative=5, loss=loss, n_bins=nb,
+                                    M=300, variant=variant, gamma=0.037, patience=5)
+    f = cwb.Fit(prob)
+    f.run(300)
+    f.sync()
+    o = oracle.fit(prob)
+    m_gpu = evaluate.mise(prob, lambda j, v: f.partial_effect(j, v))
+    m_orc = evaluate.mise(prob, lambda j, v: oracle.partial_effect(prob, o, j, v))
+    _say(f"MISE gpu {m_gpu:.6e} oracle {m_orc:.6e}")
+    assert abs(m_gpu - m_orc) <= 1e-2 * m_orc + 1e-7
+    f.close()
