@@ -145,6 +145,46 @@ def setup_leg(prob, cwb):
     return out
 
 
+def cv_leg(args, torch, cwb, datagen):
+    """Five-fold cross-validation (n = 1e6, p = 50, 1,000 bins, CWB, L2):
+    the folds sharing one index matrix and one histogram pass, against the
+    same five folds as separate fits (each with its fold as validation
+    mask) in one batch.  Iterations per second of all folds together."""
+    n, p, K, iters = args.n, 50, 5, args.cv_iters
+    prob = datagen.config2(n=n, p=p, M=iters + 10, n_bins=1000)
+    rng = np.random.default_rng(7)
+    fold = (np.arange(n) % K).astype(np.int32)
+    rng.shuffle(fold)
+    log(f"[bench] cv: {K} folds, n={n} p={p}, {iters} iterations")
+    out = {"folds": K, "n": n, "p": p, "iterations": iters}
+    cv = cwb.CV(prob, fold)
+    cv.run(5)
+    cv.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cv.run(iters)
+    cv.sync()
+    out["shared_pass_iters_s"] = round(iters / (time.perf_counter() - t0), 2)
+    out["cv_risk_last"] = float(cv.risk()[-1])
+    cv.close()
+    del cv
+    fits = [cwb.Fit(dict(prob, val_mask=(fold == k).astype(np.uint8))) for k in range(K)]
+    b = cwb.Batch(fits)
+    b.run(5)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(iters)
+    b.sync()
+    out["separate_fits_iters_s"] = round(iters / (time.perf_counter() - t0), 2)
+    b.close()
+    for f in fits:
+        f.close()
+    out["speedup"] = round(out["shared_pass_iters_s"] / max(out["separate_fits_iters_s"], 1e-9), 3)
+    log(f"[bench] cv {out}")
+    return out
+
+
 def mise_leg(cwb, datagen):
     """Partial-effect quality (the MISE of the simulation study) on the
     small additive workload (n = 10,000, p = 10, five informative effects,
@@ -432,6 +472,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mise", action="store_true", help="skip the partial-effect MISE leg")
+    ap.add_argument("--no-cv", action="store_true", help="skip the cross-validation leg")
+    ap.add_argument("--cv-iters", type=int, default=200)
     ap.add_argument("--no-setup", action="store_true",
                     help="skip timing fit creation with host vs device binning")
     ap.add_argument("--no-serve", action="store_true")
@@ -500,6 +542,8 @@ def main():
         out["setup"] = setup_leg(prob, cwb)
     if not args.no_mise:
         out["mise"] = mise_leg(cwb, datagen)
+    if not args.no_cv:
+        out["cv"] = cv_leg(args, torch, cwb, datagen)
     if not args.no_cpu:
         cb, par = cpu_baseline(args, prob, tr)
         out["cpu_baseline"] = cb

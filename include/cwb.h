@@ -291,6 +291,37 @@ int cwb_batch_run(cwb_batch* b, int32_t iters);
 int cwb_batch_sync(cwb_batch* b);
 void cwb_batch_destroy(cwb_batch* b);
 
+/* ---- cross-validation: K folds sharing one index matrix ----------------
+ * The folds of a K-fold cross-validation (the benchmark protocol of Sec.
+ * 4.2) as K fits with 0/1 row weights: fold k trains on every row whose
+ * fold id is not k and reports its risk on the held-out rows as its
+ * validation risk.  The rows keep their order, the index matrix is binned
+ * once and stored once, and one histogram pass per iteration reads it once
+ * for all folds (held-out rows carry zero residuals), accumulating one
+ * histogram per fold.  Every fold's selections, coefficients and risks are
+ * those of a fit of the same problem with its fold as the validation mask,
+ * up to the rounding of the FP32 model state (the histogram scale can
+ * differ, since a fold's pass reads all n rows).
+ * Rules: 2 <= n_folds <= 8; fold: n host int32 ids in [0, n_folds), every
+ * fold with at least one row and two training rows; pr->val_mask NULL;
+ * variant CWB or ACWB; binned learners; the folds' histograms of one learner
+ * (n_folds x signals x bins x 8 bytes) within 152 KiB, else UNSUPPORTED.
+ * Setup bins on host threads (pr->setup is not used). */
+typedef struct cwb_cv cwb_cv;
+int cwb_cv_workspace_bytes(const cwb_problem* pr, int32_t n_folds, size_t* bytes);
+int cwb_cv_create(const cwb_problem* pr, int32_t n_folds, const int32_t* fold, void* dev_ws,
+                  size_t ws_bytes, void* stream, cwb_cv** out);
+/* Advance every fold by up to `iters` iterations (asynchronous). */
+int cwb_cv_run(cwb_cv* cv, int32_t iters);
+int cwb_cv_sync(cwb_cv* cv);
+/* Fold k's fit, owned by the cross-validation: every cwb_fit_get_* call and
+ * cwb_fit_predict / cwb_fit_partial_effect apply; do not destroy it. */
+int cwb_cv_fold(cwb_cv* cv, int32_t k, cwb_fit** out);
+/* Cross-validated risk: for m = 0..iterations done, the held-out loss summed
+ * over all folds' held-out rows, divided by n (m + 1 doubles). */
+int cwb_cv_risk(cwb_cv* cv, double* risk);
+void cwb_cv_destroy(cwb_cv* cv);
+
 /* ---- serving: continuous batching of fit requests ---------------------
  * A request loop on its own host thread.  Requests are admitted while their
  * workspace fits in the device arena the caller hands in; admitted fits

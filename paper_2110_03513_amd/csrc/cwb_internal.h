@@ -32,6 +32,7 @@ constexpr int kStageBins = 2048; // learners up to this many bins are solved fro
 constexpr int kMaxSlots = 512;   // segment slots staged per learner group and pass
 constexpr int kInlineOffs = 8;   // segment offsets carried in a select item (signal 0)
 constexpr int kHistMaxLds = 152 * 1024;  // dynamic LDS of one histogram block
+constexpr int kMaxFolds = 8;     // folds of a cross-validation sharing one histogram pass
 
 // Unbinned cubic P-spline learners.  Knots are equally spaced, so the four
 // nonzero basis functions at x are those of its knot interval j, and their
@@ -80,6 +81,11 @@ struct Ctl {
 
 struct FitDev {
   int64_t n, n_pad, n_train;
+  int64_t n_scan;        // rows the histogram pass reads before an HCWB switch:
+                         // n_train (training rows first), or n for a fold fit
+  const uint8_t* fold;   // fold fit: fold id of every row (rows of fold_k are
+                         // held out and carry zero residuals), else null
+  int32_t fold_k, pad2_;
   int32_t p, nb_max, d_max, sum_d;
   int32_t loss, variant, M, patience;
   double nu, gamma;
@@ -122,12 +128,14 @@ struct FitDev {
 // Histogram schedule.  A segment is one (fit, feature group, row range)
 // whose histogram is accumulated in LDS and flushed once, as int64, to its
 // own partial slot.  Row ranges are in 8-row units of the fit's n_pad and
-// are rescaled at run time to the rows the current phase fits.
+// are rescaled at run time to the rows the current phase fits.  The folds
+// of a cross-validation share one index matrix: their segment covers nfit
+// consecutive fits, one histogram per fit and signal, from one read of X.
 struct Seg {
   int32_t fit;
   int32_t k0;      // first learner of the group
   int32_t nf;      // learners in the group
-  int32_t pad;
+  int32_t nfit;    // fits sharing the segment (1, or the number of folds)
   int64_t u0, u1;  // unit range within [0, n_pad / 8)
   int64_t slot;    // offset (int64 words) of the partial slot
 };
@@ -154,7 +162,9 @@ struct RowItem {
   double nu, gamma;
   int32_t p, nb_max, loss, variant;
   int32_t M, two, blk, fit;          // two: the fit keeps h and c
-  int32_t unbinned, pad_;            // X holds 32-bit unbinned codes
+  int32_t unbinned;                  // X holds 32-bit unbinned codes
+  int32_t fold_k;                    // fold fit: its held-out fold
+  const uint8_t* fold;               // fold fit: fold id per row, else null
 };
 
 // One learner's solve, with every pointer and size it needs, so that a block
@@ -175,7 +185,7 @@ struct SelItem {
   double* tr_risk;            // the fit's risk traces (written by learner 0's block)
   double* tr_val;
   const double* risk_part;    // the fit's row-pass risk partials
-  int64_t n, n_train;
+  int64_t n, n_train, n_scan;
   int32_t k, nb, band, d;
   int32_t n_off, d_max, nb_max, p;
   int32_t M, variant, n_row_blocks, fit;

@@ -30,7 +30,7 @@ __device__ __forceinline__ bool is_acwb_step(const FitDev& F, int switched) {
   return F.variant == CWB_ACWB || (F.variant == CWB_HCWB && !switched);
 }
 __device__ __forceinline__ int64_t rows_fitted(const FitDev& F, int switched) {
-  return (F.variant == CWB_HCWB && switched) ? F.n : F.n_train;
+  return (F.variant == CWB_HCWB && switched) ? F.n : F.n_scan;
 }
 __device__ __forceinline__ int gram_set(const FitDev& F, int switched) {
   return (F.variant == CWB_HCWB && switched) ? 1 : 0;

@@ -86,6 +86,47 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
   }
 }
 
+// Rows [r0, r1) of a segment shared by the nfit folds of a cross-validation:
+// one read of the group's bin indices feeds every fold's signals (the fold's
+// held-out rows carry zero residuals).  LDS histogram of fold q, signal s,
+// learner f at ((q * NSIG + s) * nf + f) * nb; exponents in e[2q], e[2q+1].
+template <int NT, int FMAX, int NSIG>
+__device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits, const Seg& sg,
+                                                unsigned long long* __restrict__ hist, int nb,
+                                                int64_t r0, int64_t r1, const int* e) {
+  const FitDev& F0 = fits[sg.fit];
+  const uint16_t* __restrict__ Xg = F0.X + (size_t)sg.k0 * F0.n_pad;
+  const int nf = sg.nf;
+  const size_t ld = (size_t)F0.n_pad;
+  for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
+    u32x4 xw[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f)
+      if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
+    for (int q = 0; q < sg.nfit; ++q) {
+      const FitDev& Fq = fits[sg.fit + q];
+      float rv[8], cv[8];
+      load8f(Fq.r + base, rv);
+      if (NSIG == 2) load8f(Fq.c + base, cv);
+      long long q0[8], q1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e[2 * q]);
+      if (NSIG == 2) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e[2 * q + 1]);
+      }
+      unsigned long long* hq = hist + (size_t)q * NSIG * nf * nb;
+#pragma unroll
+      for (int f = 0; f < FMAX; ++f) {
+        if (f < nf) {
+          hist_add<NSIG>(hq + (size_t)f * nb, xw[f], q0);
+          if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb, xw[f], q1);
+        }
+      }
+    }
+  }
+}
+
 // Rows [r0, r1) of one segment of unbinned learners: per row and learner,
 // the four basis values at the row's code times r (and c), as int64 fixed
 // point, into the learner's basis sums (copy lane mod kUnbCopies, stride
@@ -142,6 +183,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
        const int64_t* __restrict__ blk, long long* __restrict__ partials) {
   extern __shared__ unsigned long long s_hist[];
   __shared__ float s_red[NT + 16];
+  __shared__ int s_e[2 * kMaxFolds];
   const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
   int cached_fit = -1;
   int e0 = 0, e1 = 0;
@@ -154,7 +196,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int nsig = is_acwb_step(F, switched) ? 2 : 1;
     const int64_t n_fit = rows_fitted(F, switched);
     const int nb = F.nb_stride;
-    const int words = nsig * sg.nf * nb;
+    const int words = sg.nfit * nsig * sg.nf * nb;
     for (int i = threadIdx.x; i < words; i += NT) s_hist[i] = 0ull;
     __syncthreads();
     const int64_t n8 = (n_fit + 7) >> 3;
@@ -163,7 +205,23 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int64_t r1 = 8 * (sg.u1 * n8 / U);
     const bool need_e = sg.fit != cached_fit;
     cached_fit = sg.fit;
-    if (UNB) {
+    if (!UNB && sg.nfit > 1) {  // the folds of a cross-validation
+      if (need_e) {
+        for (int q = 0; q < sg.nfit; ++q) {
+          int a = 0, b = 0;
+          fit_scale_exponents<NT>(fits[sg.fit + q], n_fit, &a, &b, s_red);
+          if (threadIdx.x == 0) {
+            s_e[2 * q] = a;
+            s_e[2 * q + 1] = b;
+          }
+        }
+        __syncthreads();
+      }
+      if (NSMAX == 1 || nsig == 1)
+        hist_rows_folds<NT, FMAX, 1>(fits, sg, s_hist, nb, r0, r1, s_e);
+      else
+        hist_rows_folds<NT, FMAX, NSMAX>(fits, sg, s_hist, nb, r0, r1, s_e);
+    } else if (UNB) {
       if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, s_red);
       if (NSMAX == 1 || nsig == 1)
         uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);

@@ -85,7 +85,9 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   const int m = S + 1;
   const bool acwb =
       !final_mode && (it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched));
-  const int64_t n_fit = (it.variant == CWB_HCWB && switched) ? it.n : it.n_train;
+  // fitted rows: all rows after an HCWB switch; else the training rows (a
+  // prefix, or for a fold fit every row outside its held-out fold)
+  const bool all_rows = it.variant == CWB_HCWB && switched;
   const int nb = it.nb_max;
   float* tf = s_tab;
   float* tc = s_tab + nb;
@@ -118,6 +120,12 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   const bool use_h = do_pick && sel_acwb && kc >= 0;
   const bool use_cc = acwb && have_sel && sel_acwb && kc >= 0;
   uint32_t ik[8], ic[8];
+  uint32_t fold_lo = 0u, fold_hi = 0u;  // fold fit: the 8 rows' fold ids, one byte each
+  if (rows && it.fold) {
+    const unsigned long long fv = *reinterpret_cast<const GLOBAL unsigned long long*>(gp(it.fold) + base);
+    fold_lo = (uint32_t)fv;
+    fold_hi = (uint32_t)(fv >> 32);
+  }
   const bool unb = it.unbinned != 0;
   if (unb) {
     const uint32_t* XU = reinterpret_cast<const uint32_t*>(it.X);
@@ -146,9 +154,12 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
       float hj = two ? hv[j] : 0.0f;
       if (live && use_t) fj = fj + nu * table_at(unb, ik[j], tf);
       if (live && use_h) hj = hj + eta * table_at(unb, ic[j], tc);
+      const bool train =
+          it.fold ? (int)(((j < 4 ? fold_lo : fold_hi) >> (8 * (j & 3))) & 0xffu) != it.fold_k
+                  : i < it.n_train;
       if (live) {
         const double L = loss_value(it.loss, yv[j], fj);
-        if (i < it.n_train) risk_t += L; else risk_v += L;
+        if (train) risk_t += L; else risk_v += L;
         if (!isfinite(fj) || !isfinite(hj)) bad = true;
       }
       f[j] = fj;
@@ -156,7 +167,7 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
       rr[j] = 0.0f;
       cc[j] = 0.0f;
       if (final_mode || !live) continue;
-      const bool fitrow = i < n_fit;
+      const bool fitrow = all_rows || train;
       if (acwb) {
         const float g = (1.0f - vt) * fj + vt * hj;
         const float r = neg_gradient(it.loss, yv[j], g);
@@ -322,7 +333,7 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   const bool hcwb_all = it.variant == CWB_HCWB && switched;
   const bool acwb = it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched);
   const int nsig = acwb ? 2 : 1;
-  const int64_t n_fit = hcwb_all ? it.n : it.n_train;
+  const int64_t n_fit = hcwb_all ? it.n : it.n_scan;
   if (it.k == 0) {
     // learner 0's block: the risk of f^[P] from this iteration's row pass,
     // and the count and kind of this selection for the next row pass

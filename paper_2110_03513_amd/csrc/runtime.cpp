@@ -59,6 +59,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
     for (int64_t i = 0; i < pr->n; ++i) nt += pr->val_mask[i] ? 0 : 1;
   }
   sh->n_train = nt;
+  sh->n_scan = nt;
   sh->p = pr->p;
   sh->M = pr->M;
   sh->variant = pr->variant;
@@ -181,13 +182,15 @@ void SchedCap::add(const Schedule& S) {
 Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t) {
   Schedule S;
   struct Item {
-    int fit, k0, nf;
+    int fit, k0, nf, nfit;
     int64_t u0, u1;
   };
   std::vector<Item> items;
   int64_t W = 0;
   for (int fi = 0; fi < (int)fits.size(); ++fi) {
     const FitShape& sh = *fits[fi];
+    if (sh.share == 0) continue;  // a later fold: its group head's segments cover it
+    const int nfit = sh.share;
     const int64_t U = sh.n_pad / 8;
     const int groups = (sh.p + t.F - 1) / t.F;
     const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(t.slices, U));
@@ -196,8 +199,8 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       for (int g = 0; g < groups; ++g) {
         const int k0 = g * t.F;
         const int nf = std::min(t.F, sh.p - k0);
-        items.push_back({fi, k0, nf, u0, u1});
-        W += (int64_t)nf * (u1 - u0);
+        items.push_back({fi, k0, nf, nfit, u0, u1});
+        W += (int64_t)nf * nfit * (u1 - u0);
       }
     }
   }
@@ -207,22 +210,23 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   int64_t vb = 0, wpos = 0;
   for (const Item& it : items) {
     int64_t u = it.u0;
+    const int64_t w = (int64_t)it.nf * it.nfit;  // work per 8-row unit
     while (u < it.u1) {
-      const int64_t wp = wpos + (u - it.u0) * it.nf;
+      const int64_t wp = wpos + (u - it.u0) * w;
       while (vb < B - 1 && ((vb + 1) * W) / B <= wp) ++vb;
       int64_t take;
       if (vb == B - 1) {
         take = it.u1 - u;
       } else {
         const int64_t bend = ((vb + 1) * W) / B;
-        take = (bend - wp + it.nf - 1) / it.nf;
+        take = (bend - wp + w - 1) / w;
       }
       const int64_t ue = std::min(it.u1, u + std::max<int64_t>(1, take));
       Seg sg;
       sg.fit = it.fit;
       sg.k0 = it.k0;
       sg.nf = it.nf;
-      sg.pad = 0;
+      sg.nfit = it.nfit;
       sg.u0 = u;
       sg.u1 = ue;
       sg.slot = 0;
@@ -230,14 +234,14 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       seg_vb.push_back(vb);
       u = ue;
     }
-    wpos += (int64_t)it.nf * (it.u1 - it.u0);
+    wpos += w * (it.u1 - it.u0);
   }
   // partial slots
   int64_t off = 0;
   for (Seg& sg : S.segs) {
     sg.slot = off;
     const FitShape& sh = *fits[sg.fit];
-    off += (int64_t)sh.nsig_max * sg.nf * sh.nb_stride;
+    off += (int64_t)sg.nfit * sh.nsig_max * sg.nf * sh.nb_stride;
   }
   S.partial_words = off;
   // virtual block ranges, then XCD-aware physical mapping: consecutive
@@ -268,9 +272,10 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   }
   S.grp_base[fits.size()] = ng;
   std::vector<std::vector<int64_t>> lists(ng);
-  for (size_t s = 0; s < S.segs.size(); ++s) {
+  for (size_t s = 0; s < S.segs.size(); ++s) {  // a fold segment serves every fold
     const Seg& sg = S.segs[s];
-    lists[S.grp_base[sg.fit] + sg.k0 / t.F].push_back((int64_t)s);
+    for (int q = 0; q < sg.nfit; ++q)
+      lists[S.grp_base[sg.fit + q] + sg.k0 / t.F].push_back((int64_t)s);
   }
   S.grp_ptr.assign(ng + 1, 0);
   for (int64_t g = 0; g < ng; ++g) {
@@ -289,14 +294,17 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       for (int sig = 0; sig < sh.nsig_max; ++sig)
         for (int64_t q = S.grp_ptr[g]; q < S.grp_ptr[g + 1]; ++q) {
           const Seg& sg = S.segs[S.grp_seg[q]];
-          S.sel_off.push_back(sg.slot + (int64_t)(sig * sg.nf + (k - sg.k0)) * sh.nb_stride);
+          const int member = (int)fi - sg.fit;  // 0 unless a later fold
+          S.sel_off.push_back(sg.slot + (int64_t)((member * sh.nsig_max + sig) * sg.nf + (k - sg.k0)) *
+                                            sh.nb_stride);
         }
     }
   }
-  int ns_max = 1, nbs_max = 4;
+  int ns_max = 1;
+  int64_t nbs_max = 4;  // widest histogram set of a learner: folds x bins
   for (const FitShape* f : fits) {
     ns_max = std::max(ns_max, f->nsig_max);
-    nbs_max = std::max(nbs_max, f->nb_stride);
+    nbs_max = std::max<int64_t>(nbs_max, (int64_t)f->nb_stride * std::max(1, f->share));
   }
   S.lds = (size_t)ns_max * t.F * nbs_max * sizeof(long long);
   S.nsig_max = ns_max;
@@ -320,16 +328,37 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
   }
   for (int64_t s = 0; s < nseg; ++s)
     if (seen[s] != 1) { *why = "segment not owned by exactly one block"; return false; }
+  // fold groups: a head with share = K followed by K - 1 folds of its shape
+  std::vector<int> head(fits.size(), -1);
+  for (size_t fi = 0; fi < fits.size(); ++fi) {
+    const FitShape& sh = *fits[fi];
+    if (sh.share < 0 || sh.share > kMaxFolds) { *why = "fold group size"; return false; }
+    if (sh.share >= 1) {
+      if (fi + sh.share > fits.size()) { *why = "fold group past the fit list"; return false; }
+      for (int q = 0; q < sh.share; ++q) {
+        const FitShape& m = *fits[fi + q];
+        if ((q > 0 && m.share != 0) || m.n_pad != sh.n_pad || m.p != sh.p ||
+            m.nb_stride != sh.nb_stride || m.nsig_max != sh.nsig_max || m.unbinned != sh.unbinned) {
+          *why = "fold group members differ";
+          return false;
+        }
+        head[fi + q] = (int)fi;
+      }
+    }
+    if (head[fi] < 0) { *why = "fold without a group head"; return false; }
+  }
   int64_t slot_end = 0;
   for (const Seg& sg : S.segs) {
     if (sg.fit < 0 || sg.fit >= (int)fits.size()) { *why = "segment fit"; return false; }
     const FitShape& sh = *fits[sg.fit];
+    if (sh.share < 1 || sg.nfit != sh.share) { *why = "segment fold count"; return false; }
     if (sg.nf < 1 || sg.nf > t.F || sg.nf > t.fmax || sg.k0 < 0 || sg.k0 + sg.nf > sh.p ||
         sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
     if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
     if (sg.slot != slot_end) { *why = "slot order"; return false; }
-    slot_end += (int64_t)sh.nsig_max * sg.nf * sh.nb_stride;
-    if ((size_t)sh.nsig_max * sg.nf * sh.nb_stride * sizeof(long long) > S.lds) { *why = "LDS size"; return false; }
+    const int64_t words = (int64_t)sg.nfit * sh.nsig_max * sg.nf * sh.nb_stride;
+    slot_end += words;
+    if ((size_t)words * sizeof(long long) > S.lds) { *why = "LDS size"; return false; }
   }
   if (slot_end != S.partial_words) { *why = "partial size"; return false; }
   for (int64_t o : S.sel_off)
@@ -344,7 +373,7 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
       std::vector<std::pair<int64_t, int64_t>> iv;
       for (int64_t q = S.grp_ptr[gi]; q < S.grp_ptr[gi + 1]; ++q) {
         const Seg& sg = S.segs[S.grp_seg[q]];
-        if (sg.fit != (int)fi || sg.k0 != g * t.F) { *why = "group membership"; return false; }
+        if (sg.fit != head[fi] || sg.k0 != g * t.F) { *why = "group membership"; return false; }
         iv.push_back({sg.u0, sg.u1});
       }
       std::sort(iv.begin(), iv.end());
@@ -390,7 +419,7 @@ Layout make_layout(const FitShape& sh, const SchedCap& s) {
   L.coef_h = take((size_t)sh.sum_d * 8);
   L.state_end = align_up(off, 256);
   // inputs and tables
-  L.X = take((size_t)sh.p * np * (sh.unbinned ? 4 : 2));
+  L.X = take(sh.external_x ? 0 : (size_t)sh.p * np * (sh.unbinned ? 4 : 2));
   L.y = take(np * 4);
   L.r = take(np * 4);
   L.feat = take((size_t)sh.p * sizeof(FeatDev));
@@ -505,6 +534,8 @@ RowItem make_row_item(int fit, int blk, const FitDev& D) {
   it.n = D.n;
   it.n_pad = D.n_pad;
   it.n_train = D.n_train;
+  it.fold = D.fold;
+  it.fold_k = D.fold_k;
   it.base = (int64_t)blk * kStateRows;
   it.nu = D.nu;
   it.gamma = D.gamma;
@@ -543,6 +574,7 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
   it.risk_part = D.risk_part;
   it.n = D.n;
   it.n_train = D.n_train;
+  it.n_scan = D.n_scan;
   it.k = k;
   it.nb = fd.nb;
   it.band = fd.band;
@@ -571,7 +603,7 @@ int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::v
                     SchedCap* cap, Schedule* first) {
   int nb = 1, ns = 1, pmax = 1;
   for (const FitShape* sh : shapes) {
-    nb = std::max(nb, sh->nb_stride);
+    nb = std::max(nb, sh->nb_stride * std::max(1, sh->share));  // a fold group's histograms
     ns = std::max(ns, sh->nsig_max);
     pmax = std::max(pmax, sh->p);
     if (sh->unbinned != shapes[0]->unbinned)
@@ -747,7 +779,9 @@ int device_binning(const cwb_problem* pr, const FitShape& sh, HostFit& hf, const
 }
 
 int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
-               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device) {
+               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device, const FoldSpec* fold) {
+  if (fold && (!sh.external_x || sh.n_scan != sh.n || bin_on_device))
+    return set_error(CWB_E_INVALID_ARG, "internal: fold fit shape");
   *out = nullptr;
   std::unique_ptr<cwb_fit> f(new cwb_fit());
   f->stream = stream;
@@ -823,6 +857,9 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   D.n = sh.n;
   D.n_pad = sh.n_pad;
   D.n_train = sh.n_train;
+  D.n_scan = sh.n_scan;
+  D.fold = nullptr;
+  D.fold_k = -1;
   D.p = sh.p;
   D.nb_max = sh.nb_max;
   D.d_max = sh.d_max;
@@ -840,7 +877,11 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   D.unbinned = sh.unbinned ? 1 : 0;
   if (sh.unbinned != hf.unbinned)
     return set_error(CWB_E_INVALID_ARG, "learner kinds disagree with the specification");
-  D.X = dptr<uint16_t>(ws, L.X);
+  D.X = fold ? fold->X : dptr<uint16_t>(ws, L.X);
+  if (fold) {
+    D.fold = fold->fold;
+    D.fold_k = fold->k;
+  }
   D.y = dptr<float>(ws, L.y);
   D.fg = dptr<float>(ws, L.fg);
   D.h = sh.nsig_max == 2 ? dptr<float>(ws, L.h) : nullptr;
@@ -891,7 +932,7 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
     HIP_TRY(hipMemcpyAsync(ws + L.h, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
   if (sh.unbinned)
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.XU.data(), hf.XU.size() * 4, hipMemcpyHostToDevice, st));
-  else if (!bin_on_device)  // else the device pass wrote X already
+  else if (!bin_on_device && !fold)  // else X is in place already (device pass, shared folds)
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
@@ -1287,7 +1328,9 @@ int batch_shapes(cwb_fit* const* fits, int32_t count, std::vector<const FitShape
     if (!fits[i]) return set_error(CWB_E_INVALID_ARG, "null fit in batch");
     for (int j = 0; j < i; ++j)
       if (fits[j] == fits[i]) return set_error(CWB_E_INVALID_ARG, "fit listed twice in batch");
-    shapes->push_back(&fits[i]->shape);
+    fits[i]->bshape = fits[i]->shape;
+    fits[i]->bshape.share = fits[i]->batch_share;
+    shapes->push_back(&fits[i]->bshape);
   }
   return CWB_OK;
 }
@@ -1501,6 +1544,203 @@ void cwb_batch_destroy(cwb_batch* b) {
   hipStreamSynchronize(b->stream);
   if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
   delete b;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Cross-validation: K folds sharing one index matrix and one histogram pass.
+// ---------------------------------------------------------------------------
+
+struct cwb_cv {
+  int K = 0;
+  int64_t n = 0;
+  std::vector<int64_t> rows;       // rows held out by each fold
+  std::vector<cwb_fit*> fits;      // fold k's fit (owned)
+  cwb_batch* batch = nullptr;      // all folds (owned)
+};
+
+namespace cwb {
+namespace {
+
+struct CvPlan {
+  FitShape sh;                     // a fold's shape (external index matrix, every row read)
+  size_t x_bytes = 0, fold_bytes = 0, fit_bytes = 0, batch_bytes = 0, total = 0;
+};
+
+int cv_plan(const cwb_problem* pr, int32_t K, CvPlan* pl) {
+  if (!pr) return set_error(CWB_E_INVALID_ARG, "null problem");
+  if (K < 2 || K > kMaxFolds)
+    return set_error(CWB_E_INVALID_ARG, "fold count must be 2.." + std::to_string(kMaxFolds));
+  if (pr->val_mask) return set_error(CWB_E_INVALID_ARG, "a cross-validation takes no validation mask");
+  if (pr->variant != CWB_CWB && pr->variant != CWB_ACWB)
+    return set_error(CWB_E_UNSUPPORTED, "cross-validation runs CWB or ACWB folds");
+  std::string err;
+  int rc = shape_from_problem(pr, &pl->sh, &err);
+  if (rc) return set_error(rc, err);
+  if (pl->sh.unbinned) return set_error(CWB_E_UNSUPPORTED, "cross-validation covers binned learners");
+  if ((size_t)K * pl->sh.nsig_max * pl->sh.nb_stride * sizeof(long long) > (size_t)kHistMaxLds)
+    return set_error(CWB_E_UNSUPPORTED, "the folds' histograms of one learner exceed the LDS");
+  pl->sh.n_scan = pl->sh.n;
+  pl->sh.external_x = true;
+  rc = fit_footprint(pl->sh, &pl->fit_bytes, false);
+  if (rc) return rc;
+  std::vector<FitShape> shapes(K, pl->sh);
+  std::vector<const FitShape*> sp;
+  for (int k = 0; k < K; ++k) {
+    shapes[k].share = (k == 0) ? K : 0;
+    sp.push_back(&shapes[k]);
+  }
+  rc = batch_footprint(sp, &pl->batch_bytes, true);
+  if (rc) return rc;
+  pl->x_bytes = align_up((size_t)pl->sh.p * pl->sh.n_pad * 2, 256);
+  pl->fold_bytes = align_up((size_t)pl->sh.n_pad, 256);
+  pl->fit_bytes = align_up(pl->fit_bytes, 256);
+  pl->total = pl->x_bytes + pl->fold_bytes + (size_t)K * pl->fit_bytes + pl->batch_bytes;
+  return CWB_OK;
+}
+
+int cv_create_impl(const cwb_problem* pr, int32_t K, const int32_t* fold, void* dev_ws,
+                   size_t ws_bytes, hipStream_t stream, cwb_cv** out) {
+  if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!fold) return set_error(CWB_E_INVALID_ARG, "null fold ids");
+  if (!dev_ws || reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+    return set_error(CWB_E_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+  CvPlan pl;
+  int rc = cv_plan(pr, K, &pl);
+  if (rc) return rc;
+  if (ws_bytes < pl.total)
+    return set_error(CWB_E_NO_MEMORY, "workspace too small: need " + std::to_string(pl.total) +
+                                          " bytes, got " + std::to_string(ws_bytes));
+  const int64_t n = pr->n;
+  std::unique_ptr<cwb_cv> cv(new cwb_cv());
+  cv->K = K;
+  cv->n = n;
+  cv->rows.assign(K, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (fold[i] < 0 || fold[i] >= K) return set_error(CWB_E_INVALID_ARG, "fold id out of range");
+    cv->rows[fold[i]] += 1;
+  }
+  for (int k = 0; k < K; ++k)
+    if (cv->rows[k] < 1 || n - cv->rows[k] < 2)
+      return set_error(CWB_E_INVALID_ARG, "every fold needs a row, and two training rows");
+  HostFit full;
+  std::vector<HostFit> folds;
+  std::string err;
+  rc = cv_host_fits(pr, K, fold, &full, &folds, &err);
+  if (rc) return set_error(rc, err);
+  char* ws = reinterpret_cast<char*>(dev_ws);
+  uint16_t* d_X = reinterpret_cast<uint16_t*>(ws);
+  uint8_t* d_fold = reinterpret_cast<uint8_t*>(ws + pl.x_bytes);
+  std::vector<uint8_t> f8((size_t)pl.sh.n_pad, (uint8_t)K);  // padding rows: no fold
+  for (int64_t i = 0; i < n; ++i) f8[i] = (uint8_t)fold[i];
+  HIP_TRY(hipMemcpyAsync(d_X, full.X.data(), full.X.size() * 2, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(d_fold, f8.data(), f8.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  full.X.clear();
+  char* fit_ws = ws + pl.x_bytes + pl.fold_bytes;
+  struct Cleanup {
+    cwb_cv* cv;
+    ~Cleanup() {
+      if (!cv) return;
+      cwb_batch_destroy(cv->batch);
+      for (cwb_fit* f : cv->fits) cwb_fit_destroy(f);
+    }
+  } guard{cv.get()};
+  for (int k = 0; k < K; ++k) {
+    FitShape sh = pl.sh;
+    sh.n_train = n - cv->rows[k];
+    FoldSpec fs;
+    fs.X = d_X;
+    fs.fold = d_fold;
+    fs.k = k;
+    cwb_fit* f = nullptr;
+    rc = fit_upload(sh, folds[k], fit_ws + (size_t)k * pl.fit_bytes, pl.fit_bytes, stream, false, &f,
+                    nullptr, &fs);
+    if (rc) return rc;
+    f->batch_share = (k == 0) ? K : 0;
+    cv->fits.push_back(f);
+  }
+  rc = batch_create(cv->fits.data(), K, fit_ws + (size_t)K * pl.fit_bytes, pl.batch_bytes, stream,
+                    true, &cv->batch);
+  if (rc) return rc;
+  guard.cv = nullptr;
+  *out = cv.release();
+  return CWB_OK;
+}
+
+}  // namespace
+}  // namespace cwb
+
+extern "C" {
+
+int cwb_cv_workspace_bytes(const cwb_problem* pr, int32_t n_folds, size_t* bytes) {
+  try {
+    if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
+    CvPlan pl;
+    const int rc = cv_plan(pr, n_folds, &pl);
+    if (rc) return rc;
+    *bytes = pl.total;
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  }
+}
+
+int cwb_cv_create(const cwb_problem* pr, int32_t n_folds, const int32_t* fold, void* dev_ws,
+                  size_t ws_bytes, void* stream, cwb_cv** out) {
+  try {
+    return cv_create_impl(pr, n_folds, fold, dev_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
+                          out);
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(CWB_E_INVALID_ARG, e.what());
+  }
+}
+
+int cwb_cv_run(cwb_cv* cv, int32_t iters) {
+  if (!cv) return set_error(CWB_E_INVALID_ARG, "null cross-validation");
+  return cwb_batch_run(cv->batch, iters);
+}
+
+int cwb_cv_sync(cwb_cv* cv) {
+  if (!cv) return set_error(CWB_E_INVALID_ARG, "null cross-validation");
+  return cwb_batch_sync(cv->batch);
+}
+
+int cwb_cv_fold(cwb_cv* cv, int32_t k, cwb_fit** out) {
+  if (!cv || !out) return set_error(CWB_E_INVALID_ARG, "null argument");
+  if (k < 0 || k >= cv->K) return set_error(CWB_E_INVALID_ARG, "fold index out of range");
+  *out = cv->fits[k];
+  return CWB_OK;
+}
+
+int cwb_cv_risk(cwb_cv* cv, double* risk) {
+  if (!cv || !risk) return set_error(CWB_E_INVALID_ARG, "null argument");
+  try {
+    const int M = cv->fits[0]->shape.M;
+    const int m = cv->fits[0]->iters;
+    std::vector<double> rv((size_t)M + 1);
+    for (int i = 0; i <= m; ++i) risk[i] = 0.0;
+    for (int k = 0; k < cv->K; ++k) {
+      const int rc = cwb_fit_get_trace(cv->fits[k], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                       rv.data(), nullptr, nullptr);
+      if (rc) return rc;
+      for (int i = 0; i <= m; ++i) risk[i] += rv[i] * (double)cv->rows[k] / (double)cv->n;
+    }
+    return CWB_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  }
+}
+
+void cwb_cv_destroy(cwb_cv* cv) {
+  if (!cv) return;
+  cwb_batch_destroy(cv->batch);
+  for (cwb_fit* f : cv->fits) cwb_fit_destroy(f);
+  delete cv;
 }
 
 }  // extern "C"

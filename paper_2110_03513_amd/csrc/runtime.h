@@ -23,6 +23,20 @@ struct FitShape {
   int64_t sum_nb = 0, sum_d2 = 0;
   int n_row_blocks = 0, n_val_blocks = 0;
   bool unbinned = false;  // learners are unbinned cubic P-splines
+  // Folds of a cross-validation share one index matrix and one histogram
+  // pass: the first fold's shape has share = the number of folds (the
+  // others follow it in the fit list, with share = 0); other fits have 1.
+  int share = 1;
+  int64_t n_scan = 0;     // rows the histogram pass reads (before an HCWB switch)
+  bool external_x = false;  // the index matrix lives outside the fit's workspace
+};
+
+// A fold of a cross-validation: the shared index matrix and fold ids (device)
+// and the fold it holds out.
+struct FoldSpec {
+  const uint16_t* X = nullptr;
+  const uint8_t* fold = nullptr;
+  int k = 0;
 };
 
 int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err);
@@ -114,6 +128,8 @@ struct cwb_fit {
   cwb::KernelTimer t_hist, t_state, t_select;
   int n_cands = 1;        // tile shapes considered
   double tuned_us = 0.0;  // histogram pass time of the chosen shape (0: not tuned)
+  int batch_share = 1;    // fold group size in a batch (first fold: K, others 0)
+  cwb::FitShape bshape;   // shape as seen by batch schedules (share = batch_share)
 };
 
 struct cwb_batch {
@@ -170,7 +186,8 @@ int fit_footprint(const FitShape& sh, size_t* bytes, bool all);
 // host setup ran its first phase only and the binning pass runs on the
 // device first.
 int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
-               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device = nullptr);
+               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device = nullptr,
+               const FoldSpec* fold = nullptr);
 // Device bytes of the batch workspace (combined schedule, partials, work
 // lists) for fits of these shapes; 0 for none.
 int batch_footprint(const std::vector<const FitShape*>& shapes, size_t* bytes, bool all);

@@ -751,3 +751,76 @@ int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
 }
 
 }  // namespace cwb
+
+namespace cwb {
+
+int cv_host_fits(const cwb_problem* pr, int K, const int32_t* fold, HostFit* full,
+                 std::vector<HostFit>* folds, std::string* err) {
+  cwb_problem all = *pr;
+  all.val_mask = nullptr;
+  int rc = build_host_fit(&all, full, err);
+  if (rc) return rc;
+  if (full->unbinned) {
+    *err = "cross-validation covers binned learners";
+    return CWB_E_UNSUPPORTED;
+  }
+  const int64_t n = pr->n;
+  const int p = pr->p;
+  std::vector<int64_t> rows(K, 0);
+  std::vector<double> ysum(K, 0.0);
+  double ytot = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    rows[fold[i]] += 1;
+    ysum[fold[i]] += pr->y[i];
+    ytot += pr->y[i];
+  }
+  folds->assign(K, HostFit());
+  for (int k = 0; k < K; ++k) {
+    HostFit& h = (*folds)[k];
+    h.n = n;
+    h.n_pad = full->n_pad;
+    h.n_train = n - rows[k];
+    h.p = p;
+    h.loss = full->loss;
+    h.variant = full->variant;
+    h.M = full->M;
+    h.patience = full->patience;
+    h.nu = full->nu;
+    h.gamma = full->gamma;
+    h.nb_max = full->nb_max;
+    h.d_max = full->d_max;
+    h.sum_d = full->sum_d;
+    h.unbinned = false;
+    h.perm = full->perm;  // identity: the folds keep the rows in place
+    h.y = full->y;
+    // loss-optimal constant over the fold's training rows (every other fold)
+    const double ybar = (ytot - ysum[k]) / (double)h.n_train;
+    h.f0 = (pr->loss == CWB_L2) ? ybar : std::log(ybar / (1.0 - ybar));
+    if (!std::isfinite(h.f0)) {
+      *err = "training labels of fold " + std::to_string(k) + " are all equal";
+      return CWB_E_NUMERIC;
+    }
+    h.L.assign(p, HostLearner());
+  }
+  // per feature: bin counts of each fold in one pass, then each fold's
+  // training counts (all rows but its own) and its learner tables
+  return for_features(p, err, [&](int j, std::string* ferr) -> int {
+    const HostLearner& Lf = full->L[j];
+    const uint16_t* Xj = full->X.data() + (size_t)j * full->n_pad;
+    std::vector<int64_t> c((size_t)K * Lf.nb, 0);
+    for (int64_t i = 0; i < n; ++i) c[(size_t)fold[i] * Lf.nb + Xj[i]] += 1;
+    std::vector<double> cnt_a(Lf.nb, 0.0), cnt_t(Lf.nb);
+    for (int k = 0; k < K; ++k)
+      for (int l = 0; l < Lf.nb; ++l) cnt_a[l] += (double)c[(size_t)k * Lf.nb + l];
+    for (int k = 0; k < K; ++k) {
+      for (int l = 0; l < Lf.nb; ++l) cnt_t[l] = cnt_a[l] - (double)c[(size_t)k * Lf.nb + l];
+      HostLearner& L = (*folds)[k].L[j];
+      L = Lf;  // the design at the shared design points
+      const int r = learner_algebra(pr->specs[j], n, L, cnt_t, cnt_a, nullptr, j, ferr);
+      if (r) return r;
+    }
+    return CWB_OK;
+  });
+}
+
+}  // namespace cwb

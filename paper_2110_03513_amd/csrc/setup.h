@@ -79,5 +79,11 @@ int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err);
 // counts_stride / 2 further).
 int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
                     const uint32_t* counts, int64_t counts_stride, std::string* err);
+// Host setup of the K folds of a cross-validation (fold[i] in [0, K) for
+// every row): `full` bins all rows once, in their own order, and keeps the
+// index matrix that the folds share; each fold's HostFit has its intercept
+// and learner tables from the training rows of every other fold.
+int cv_host_fits(const cwb_problem* pr, int K, const int32_t* fold, HostFit* full,
+                 std::vector<HostFit>* folds, std::string* err);
 
 }  // namespace cwb

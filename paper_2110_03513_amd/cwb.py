@@ -108,8 +108,15 @@ _SIGNATURES = {
     "cwb_server_poll": [_P, C.c_uint64, C.POINTER(cwb_result), _P, _P],
     "cwb_server_stats": [_P, C.POINTER(cwb_stats)],
     "cwb_server_destroy": [_P],
+    "cwb_cv_workspace_bytes": [C.POINTER(cwb_problem), C.c_int32, C.POINTER(C.c_size_t)],
+    "cwb_cv_create": [C.POINTER(cwb_problem), C.c_int32, _P, _P, C.c_size_t, _P, C.POINTER(_P)],
+    "cwb_cv_run": [_P, C.c_int32],
+    "cwb_cv_sync": [_P],
+    "cwb_cv_fold": [_P, C.c_int32, C.POINTER(_P)],
+    "cwb_cv_risk": [_P, _P],
+    "cwb_cv_destroy": [_P],
 }
-_VOID = {"cwb_fit_destroy", "cwb_batch_destroy", "cwb_server_destroy"}
+_VOID = {"cwb_fit_destroy", "cwb_batch_destroy", "cwb_server_destroy", "cwb_cv_destroy"}
 
 _lib = None
 
@@ -329,7 +336,25 @@ class Fit:
         check(lib().cwb_fit_kernel_time(self.h, name.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
 
+    @classmethod
+    def _view(cls, handle, owner):
+        """A fit owned by another object (a fold of a cross-validation)."""
+        f = cls.__new__(cls)
+        f.problem = owner.problem
+        f.device = owner.device
+        f.ws = None
+        f._sh, f.stream = owner._sh, owner.stream
+        f.h = handle
+        f._owner = owner
+        info = cwb_info()
+        check(lib().cwb_fit_info(f.h, C.byref(info)))
+        f.info = info
+        return f
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:  # owned elsewhere
+            self.h = None
+            return
         if getattr(self, "h", None):
             lib().cwb_fit_destroy(self.h)
             self.h = None
@@ -373,6 +398,58 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             lib().cwb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CV:
+    """K-fold cross-validation: the folds share one index matrix and one
+    histogram pass per iteration; ``folds[k]`` is fold k's fit."""
+
+    def __init__(self, prob: dict, fold, stream=None, device=None):
+        torch = _torch()
+        self.problem = Problem(prob)
+        self.fold = np.ascontiguousarray(np.asarray(fold, dtype=np.int32))
+        self.n_folds = int(self.fold.max()) + 1 if self.fold.size else 0
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            b = C.c_size_t()
+            check(lib().cwb_cv_workspace_bytes(C.byref(self.problem.c), self.n_folds, C.byref(b)))
+            self.ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+            self._sh, self.stream = _stream_handle(stream)
+            h = C.c_void_p()
+            check(lib().cwb_cv_create(C.byref(self.problem.c), self.n_folds, _ptr(self.fold),
+                                      C.c_void_p(self.ws.data_ptr()), b.value, self._sh, C.byref(h)))
+        self.h = h
+        self.folds = []
+        for k in range(self.n_folds):
+            fh = C.c_void_p()
+            check(lib().cwb_cv_fold(self.h, k, C.byref(fh)))
+            self.folds.append(Fit._view(fh, self))
+
+    def run(self, iters: int):
+        check(lib().cwb_cv_run(self.h, int(iters)))
+
+    def sync(self):
+        check(lib().cwb_cv_sync(self.h))
+
+    def risk(self) -> np.ndarray:
+        """Cross-validated risk of iterations 0..done (held-out loss / n)."""
+        m = self.folds[0].iters_done
+        out = np.zeros(self.folds[0].info.M + 1)
+        check(lib().cwb_cv_risk(self.h, _ptr(out)))
+        return out[:m + 1]
+
+    def close(self):
+        if getattr(self, "h", None):
+            for f in self.folds:
+                f.close()
+            lib().cwb_cv_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -251,3 +251,54 @@ def test_setup_mode_rules():
     assert rc == cwb.CWB_E_UNSUPPORTED and "device setup" in msg
     # the two explicit modes size the same workspace
     assert cwb.workspace_bytes(dict(base, setup="device")) == cwb.workspace_bytes(base)
+
+
+def _cv_bytes(prob, K):
+    pr = cwb.Problem(prob)
+    b = C.c_size_t()
+    rc = cwb.lib().cwb_cv_workspace_bytes(C.byref(pr.c), K, C.byref(b))
+    return rc, b.value, cwb.lib().cwb_last_error().decode()
+
+
+@pytest.mark.parametrize("env", [{}, {"CWB_HIST_F": "3"}, {"CWB_HIST_SLICES": "8"},
+                                 {"CWB_HIST_NT": "256", "CWB_HIST_BPC": "3"}])
+def test_cv_workspace_and_fold_schedules(env, monkeypatch):
+    """Fold groups: schedules for every fold count and tile shape validate
+    (one segment per group and row range serves every fold), and the
+    workspace grows with the folds."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    prob = datagen.additive_problem(5000, 6, seed=3, n_informative=2, n_bins=50, M=10, n_cat=1)
+    sizes = []
+    for K in range(2, 9):
+        rc, b, msg = _cv_bytes(prob, K)
+        assert rc == 0, msg
+        sizes.append(b)
+    assert all(b > a for a, b in zip(sizes, sizes[1:]))
+    assert sizes[0] >= 2 * 5000 * 6  # the shared index matrix at least
+    acwb = dict(prob, variant="acwb", gamma=0.01)
+    assert _cv_bytes(acwb, 8)[0] == 0
+
+
+def test_cv_rules():
+    prob = datagen.additive_problem(3000, 4, seed=4, n_informative=2, n_bins=40, M=5)
+    for K in (0, 1, 9):
+        rc, _, msg = _cv_bytes(prob, K)
+        assert rc == cwb.CWB_E_INVALID_ARG and "fold count" in msg
+    rc, _, msg = _cv_bytes(dict(prob, val_mask=np.zeros(3000, np.uint8)), 3)
+    assert rc == cwb.CWB_E_INVALID_ARG and "validation mask" in msg
+    rc, _, msg = _cv_bytes(dict(prob, variant="hcwb", val_mask=None), 3)
+    assert rc == cwb.CWB_E_UNSUPPORTED
+    unb = datagen.additive_problem(3000, 4, seed=4, n_informative=2, n_bins=0, M=5)
+    assert _cv_bytes(unb, 3)[0] == cwb.CWB_E_UNSUPPORTED
+    wide = dict(prob, variant="acwb", n_bins=np.full(4, 8192, np.int32))
+    rc, _, msg = _cv_bytes(wide, 8)
+    assert rc == cwb.CWB_E_UNSUPPORTED and "LDS" in msg
+    # fold ids are checked before any device call
+    pr = cwb.Problem(prob)
+    h = C.c_void_p()
+    for fold in (np.full(3000, 3, np.int32), np.zeros(3000, np.int32)):
+        rc = cwb.lib().cwb_cv_create(C.byref(pr.c), 3, fold.ctypes.data_as(C.c_void_p),
+                                     C.c_void_p(1 << 20), 1 << 40, None, C.byref(h))
+        assert rc == cwb.CWB_E_INVALID_ARG
+        assert "fold" in cwb.lib().cwb_last_error().decode()
