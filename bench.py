@@ -166,6 +166,7 @@ def cv_leg(args, torch, cwb, datagen):
     cv.sync()
     out["shared_pass_iters_s"] = round(iters / (time.perf_counter() - t0), 2)
     out["cv_risk_last"] = float(cv.risk()[-1])
+    out["shared_tile"] = cv.tile()
     cv.close()
     del cv
     fits = [cwb.Fit(dict(prob, val_mask=(fold == k).astype(np.uint8))) for k in range(K)]
@@ -177,6 +178,7 @@ def cv_leg(args, torch, cwb, datagen):
     b.run(iters)
     b.sync()
     out["separate_fits_iters_s"] = round(iters / (time.perf_counter() - t0), 2)
+    out["separate_tile"] = b.tile()
     b.close()
     for f in fits:
         f.close()

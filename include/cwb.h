@@ -295,10 +295,10 @@ void cwb_batch_destroy(cwb_batch* b);
  * The folds of a K-fold cross-validation (the benchmark protocol of Sec.
  * 4.2) as K fits with 0/1 row weights: fold k trains on every row whose
  * fold id is not k and reports its risk on the held-out rows as its
- * validation risk.  The rows keep their order, the index matrix is binned
- * once and stored once, and one histogram pass per iteration reads it once
- * for all folds (held-out rows carry zero residuals), accumulating one
- * histogram per fold.  Every fold's selections, coefficients and risks are
+ * validation risk.  The index matrix is binned once, with the rows grouped
+ * by fold, and stored once; one histogram pass per iteration reads it once
+ * for all folds, accumulating one histogram per fold (each fold leaves out
+ * its own block of rows).  Every fold's selections, coefficients and risks are
  * those of a fit of the same problem with its fold as the validation mask,
  * up to the rounding of the FP32 model state (the histogram scale can
  * differ, since a fold's pass reads all n rows).
@@ -308,7 +308,8 @@ void cwb_batch_destroy(cwb_batch* b);
  * (n_folds x signals x bins x 8 bytes) within 152 KiB, else UNSUPPORTED.
  * Setup bins on host threads (pr->setup is not used). */
 typedef struct cwb_cv cwb_cv;
-int cwb_cv_workspace_bytes(const cwb_problem* pr, int32_t n_folds, size_t* bytes);
+int cwb_cv_workspace_bytes(const cwb_problem* pr, int32_t n_folds, const int32_t* fold,
+                           size_t* bytes);
 int cwb_cv_create(const cwb_problem* pr, int32_t n_folds, const int32_t* fold, void* dev_ws,
                   size_t ws_bytes, void* stream, cwb_cv** out);
 /* Advance every fold by up to `iters` iterations (asynchronous). */
@@ -320,6 +321,8 @@ int cwb_cv_fold(cwb_cv* cv, int32_t k, cwb_fit** out);
 /* Cross-validated risk: for m = 0..iterations done, the held-out loss summed
  * over all folds' held-out rows, divided by n (m + 1 doubles). */
 int cwb_cv_risk(cwb_cv* cv, double* risk);
+/* The histogram tile the folds' shared pass runs with (autotuned at create). */
+int cwb_cv_tile(const cwb_cv* cv, cwb_tile* out);
 void cwb_cv_destroy(cwb_cv* cv);
 
 /* ---- serving: continuous batching of fit requests ---------------------

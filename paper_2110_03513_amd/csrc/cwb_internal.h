@@ -131,11 +131,14 @@ struct FitDev {
 // are rescaled at run time to the rows the current phase fits.  The folds
 // of a cross-validation share one index matrix: their segment covers nfit
 // consecutive fits, one histogram per fit and signal, from one read of X.
+// Their rows are grouped by fold, so most segments lie in one fold's rows:
+// that fold (skip) holds them out and is left out of the segment's work.
 struct Seg {
   int32_t fit;
   int32_t k0;      // first learner of the group
   int32_t nf;      // learners in the group
-  int32_t nfit;    // fits sharing the segment (1, or the number of folds)
+  int16_t nfit;    // fits sharing the segment (1, or the number of folds)
+  int16_t skip;    // the fold all of the segment's rows belong to, or -1
   int64_t u0, u1;  // unit range within [0, n_pad / 8)
   int64_t slot;    // offset (int64 words) of the partial slot
 };

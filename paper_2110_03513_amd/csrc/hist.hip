@@ -87,9 +87,10 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
 }
 
 // Rows [r0, r1) of a segment shared by the nfit folds of a cross-validation:
-// one read of the group's bin indices feeds every fold's signals (the fold's
-// held-out rows carry zero residuals).  LDS histogram of fold q, signal s,
-// learner f at ((q * NSIG + s) * nf + f) * nb; exponents in e[2q], e[2q+1].
+// one read of the group's bin indices feeds every fold's signals.  Held-out
+// rows carry zero residuals; the fold that holds out all of the segment's
+// rows (skip) is left out.  LDS histogram of fold q, signal s, learner f at
+// ((q * NSIG + s) * nf + f) * nb; exponents in e[2q], e[2q+1].
 template <int NT, int FMAX, int NSIG>
 __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits, const Seg& sg,
                                                 unsigned long long* __restrict__ hist, int nb,
@@ -98,16 +99,33 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
   const uint16_t* __restrict__ Xg = F0.X + (size_t)sg.k0 * F0.n_pad;
   const int nf = sg.nf;
   const size_t ld = (size_t)F0.n_pad;
-  for (int64_t base = r0 + (int64_t)threadIdx.x * 8; base < r1; base += (int64_t)NT * 8) {
-    u32x4 xw[FMAX];
+  const int nfit = sg.nfit, skip = sg.skip;
+  const int first = (skip == 0) ? 1 : 0;  // first fold with work (nfit >= 2)
+  auto next_fold = [&](int q) {
+    ++q;
+    if (q == skip) ++q;
+    return q < nfit ? q : -1;
+  };
+  int64_t base = r0 + (int64_t)threadIdx.x * 8;
+  if (base >= r1) return;
+  // software pipeline: the loads of the next fold (or of the next row step)
+  // are issued before the current fold's atomics
+  u32x4 xw[FMAX];
+  float rv[8], cv[8];
 #pragma unroll
-    for (int f = 0; f < FMAX; ++f)
-      if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
-    for (int q = 0; q < sg.nfit; ++q) {
-      const FitDev& Fq = fits[sg.fit + q];
-      float rv[8], cv[8];
-      load8f(Fq.r + base, rv);
-      if (NSIG == 2) load8f(Fq.c + base, cv);
+  for (int f = 0; f < FMAX; ++f)
+    if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
+  load8f(fits[sg.fit + first].r + base, rv);
+  if (NSIG == 2) load8f(fits[sg.fit + first].c + base, cv);
+  for (;;) {
+    const int64_t nxt = base + (int64_t)NT * 8;
+    const bool more = nxt < r1;
+    u32x4 xc[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
+    int q = first;
+    for (;;) {
+      const int qn = next_fold(q);
       long long q0[8], q1[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e[2 * q]);
@@ -115,15 +133,29 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
 #pragma unroll
         for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e[2 * q + 1]);
       }
+      if (qn >= 0) {
+        load8f(fits[sg.fit + qn].r + base, rv);
+        if (NSIG == 2) load8f(fits[sg.fit + qn].c + base, cv);
+      } else if (more) {
+#pragma unroll
+        for (int f = 0; f < FMAX; ++f)
+          if (f < nf) xw[f] = load_idx(Xg + f * ld + nxt);
+        load8f(fits[sg.fit + first].r + nxt, rv);
+        if (NSIG == 2) load8f(fits[sg.fit + first].c + nxt, cv);
+      }
       unsigned long long* hq = hist + (size_t)q * NSIG * nf * nb;
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
         if (f < nf) {
-          hist_add<NSIG>(hq + (size_t)f * nb, xw[f], q0);
-          if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb, xw[f], q1);
+          hist_add<NSIG>(hq + (size_t)f * nb, xc[f], q0);
+          if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb, xc[f], q1);
         }
       }
+      if (qn < 0) break;
+      q = qn;
     }
+    if (!more) break;
+    base = nxt;
   }
 }
 

@@ -179,6 +179,28 @@ void SchedCap::add(const Schedule& S) {
   partial_words = std::max(partial_words, S.partial_words);
 }
 
+int64_t unit_at_row(const FitShape& sh, int64_t row) {
+  const int64_t U = sh.n_pad / 8, n8 = (sh.n_scan + 7) / 8;
+  const int64_t r8 = (row + 7) / 8;  // first whole 8-row unit at or after row
+  if (n8 <= 0) return 0;
+  return std::min(U, (r8 * U + n8 - 1) / n8);
+}
+
+void unit_rows(const FitShape& sh, int64_t u0, int64_t u1, int64_t* r0, int64_t* r1) {
+  const int64_t U = sh.n_pad / 8, n8 = (sh.n_scan + 7) / 8;
+  *r0 = 8 * (u0 * n8 / U);
+  *r1 = 8 * (u1 * n8 / U);
+}
+
+int segment_fold(const FitShape& sh, int64_t r0, int64_t r1) {
+  const int K = (int)sh.fold_start.size() - 1;
+  r1 = std::min(r1, sh.n);
+  if (K < 1 || r1 <= r0) return -1;
+  for (int j = 0; j < K; ++j)
+    if (r0 >= sh.fold_start[j] && r1 <= sh.fold_start[j + 1]) return j;
+  return -1;
+}
+
 Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t) {
   Schedule S;
   struct Item {
@@ -194,13 +216,25 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
     const int64_t U = sh.n_pad / 8;
     const int groups = (sh.p + t.F - 1) / t.F;
     const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(t.slices, U));
+    // a fold group's rows split at the fold blocks
+    std::vector<int64_t> cuts;
+    if (nfit > 1)
+      for (size_t j = 1; j + 1 < sh.fold_start.size(); ++j) cuts.push_back(unit_at_row(sh, sh.fold_start[j]));
     for (int s = 0; s < slices; ++s) {
-      const int64_t u0 = U * s / slices, u1 = U * (s + 1) / slices;
-      for (int g = 0; g < groups; ++g) {
-        const int k0 = g * t.F;
-        const int nf = std::min(t.F, sh.p - k0);
-        items.push_back({fi, k0, nf, nfit, u0, u1});
-        W += (int64_t)nf * nfit * (u1 - u0);
+      const int64_t a = U * s / slices, b = U * (s + 1) / slices;
+      std::vector<int64_t> pts{a};
+      for (int64_t c : cuts)
+        if (c > a && c < b) pts.push_back(c);
+      pts.push_back(b);
+      for (size_t i = 0; i + 1 < pts.size(); ++i) {
+        const int64_t u0 = pts[i], u1 = pts[i + 1];
+        if (u1 <= u0) continue;
+        for (int g = 0; g < groups; ++g) {
+          const int k0 = g * t.F;
+          const int nf = std::min(t.F, sh.p - k0);
+          items.push_back({fi, k0, nf, nfit, u0, u1});
+          W += (int64_t)nf * nfit * (u1 - u0);
+        }
       }
     }
   }
@@ -226,7 +260,13 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       sg.fit = it.fit;
       sg.k0 = it.k0;
       sg.nf = it.nf;
-      sg.nfit = it.nfit;
+      sg.nfit = (int16_t)it.nfit;
+      sg.skip = -1;
+      if (it.nfit > 1) {
+        int64_t r0, r1;
+        unit_rows(*fits[it.fit], u, ue, &r0, &r1);
+        sg.skip = (int16_t)segment_fold(*fits[it.fit], r0, r1);
+      }
       sg.u0 = u;
       sg.u1 = ue;
       sg.slot = 0;
@@ -352,6 +392,12 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
     if (sg.fit < 0 || sg.fit >= (int)fits.size()) { *why = "segment fit"; return false; }
     const FitShape& sh = *fits[sg.fit];
     if (sh.share < 1 || sg.nfit != sh.share) { *why = "segment fold count"; return false; }
+    if (sg.skip < -1 || sg.skip >= sg.nfit) { *why = "segment fold"; return false; }
+    if (sg.skip >= 0) {  // every row it leaves out must belong to that fold
+      int64_t r0, r1;
+      unit_rows(sh, sg.u0, sg.u1, &r0, &r1);
+      if (segment_fold(sh, r0, r1) != sg.skip) { *why = "segment rows outside its fold"; return false; }
+    }
     if (sg.nf < 1 || sg.nf > t.F || sg.nf > t.fmax || sg.k0 < 0 || sg.k0 + sg.nf > sh.p ||
         sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
     if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
@@ -1565,13 +1611,24 @@ namespace {
 
 struct CvPlan {
   FitShape sh;                     // a fold's shape (external index matrix, every row read)
+  std::vector<int64_t> rows;       // rows of each fold
   size_t x_bytes = 0, fold_bytes = 0, fit_bytes = 0, batch_bytes = 0, total = 0;
 };
 
-int cv_plan(const cwb_problem* pr, int32_t K, CvPlan* pl) {
+int cv_plan(const cwb_problem* pr, int32_t K, const int32_t* fold, CvPlan* pl) {
   if (!pr) return set_error(CWB_E_INVALID_ARG, "null problem");
   if (K < 2 || K > kMaxFolds)
     return set_error(CWB_E_INVALID_ARG, "fold count must be 2.." + std::to_string(kMaxFolds));
+  if (!fold) return set_error(CWB_E_INVALID_ARG, "null fold ids");
+  if (pr->n < 2) return set_error(CWB_E_INVALID_ARG, "n must be >= 2");
+  pl->rows.assign(K, 0);
+  for (int64_t i = 0; i < pr->n; ++i) {
+    if (fold[i] < 0 || fold[i] >= K) return set_error(CWB_E_INVALID_ARG, "fold id out of range");
+    pl->rows[fold[i]] += 1;
+  }
+  for (int k = 0; k < K; ++k)
+    if (pl->rows[k] < 1 || pr->n - pl->rows[k] < 2)
+      return set_error(CWB_E_INVALID_ARG, "every fold needs a row, and two training rows");
   if (pr->val_mask) return set_error(CWB_E_INVALID_ARG, "a cross-validation takes no validation mask");
   if (pr->variant != CWB_CWB && pr->variant != CWB_ACWB)
     return set_error(CWB_E_UNSUPPORTED, "cross-validation runs CWB or ACWB folds");
@@ -1585,6 +1642,8 @@ int cv_plan(const cwb_problem* pr, int32_t K, CvPlan* pl) {
   pl->sh.external_x = true;
   rc = fit_footprint(pl->sh, &pl->fit_bytes, false);
   if (rc) return rc;
+  pl->sh.fold_start.assign(K + 1, 0);  // rows grouped by fold
+  for (int k = 0; k < K; ++k) pl->sh.fold_start[k + 1] = pl->sh.fold_start[k] + pl->rows[k];
   std::vector<FitShape> shapes(K, pl->sh);
   std::vector<const FitShape*> sp;
   for (int k = 0; k < K; ++k) {
@@ -1608,7 +1667,7 @@ int cv_create_impl(const cwb_problem* pr, int32_t K, const int32_t* fold, void* 
   if (!dev_ws || reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
     return set_error(CWB_E_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
   CvPlan pl;
-  int rc = cv_plan(pr, K, &pl);
+  int rc = cv_plan(pr, K, fold, &pl);
   if (rc) return rc;
   if (ws_bytes < pl.total)
     return set_error(CWB_E_NO_MEMORY, "workspace too small: need " + std::to_string(pl.total) +
@@ -1617,14 +1676,7 @@ int cv_create_impl(const cwb_problem* pr, int32_t K, const int32_t* fold, void* 
   std::unique_ptr<cwb_cv> cv(new cwb_cv());
   cv->K = K;
   cv->n = n;
-  cv->rows.assign(K, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    if (fold[i] < 0 || fold[i] >= K) return set_error(CWB_E_INVALID_ARG, "fold id out of range");
-    cv->rows[fold[i]] += 1;
-  }
-  for (int k = 0; k < K; ++k)
-    if (cv->rows[k] < 1 || n - cv->rows[k] < 2)
-      return set_error(CWB_E_INVALID_ARG, "every fold needs a row, and two training rows");
+  cv->rows = pl.rows;
   HostFit full;
   std::vector<HostFit> folds;
   std::string err;
@@ -1634,7 +1686,7 @@ int cv_create_impl(const cwb_problem* pr, int32_t K, const int32_t* fold, void* 
   uint16_t* d_X = reinterpret_cast<uint16_t*>(ws);
   uint8_t* d_fold = reinterpret_cast<uint8_t*>(ws + pl.x_bytes);
   std::vector<uint8_t> f8((size_t)pl.sh.n_pad, (uint8_t)K);  // padding rows: no fold
-  for (int64_t i = 0; i < n; ++i) f8[i] = (uint8_t)fold[i];
+  for (int64_t i = 0; i < n; ++i) f8[i] = (uint8_t)fold[full.perm[i]];  // fold-grouped order
   HIP_TRY(hipMemcpyAsync(d_X, full.X.data(), full.X.size() * 2, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(d_fold, f8.data(), f8.size(), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -1675,11 +1727,12 @@ int cv_create_impl(const cwb_problem* pr, int32_t K, const int32_t* fold, void* 
 
 extern "C" {
 
-int cwb_cv_workspace_bytes(const cwb_problem* pr, int32_t n_folds, size_t* bytes) {
+int cwb_cv_workspace_bytes(const cwb_problem* pr, int32_t n_folds, const int32_t* fold,
+                           size_t* bytes) {
   try {
     if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");
     CvPlan pl;
-    const int rc = cv_plan(pr, n_folds, &pl);
+    const int rc = cv_plan(pr, n_folds, fold, &pl);
     if (rc) return rc;
     *bytes = pl.total;
     return CWB_OK;
@@ -1734,6 +1787,11 @@ int cwb_cv_risk(cwb_cv* cv, double* risk) {
   } catch (const std::bad_alloc&) {
     return set_error(CWB_E_NO_MEMORY, "host allocation failed");
   }
+}
+
+int cwb_cv_tile(const cwb_cv* cv, cwb_tile* out) {
+  if (!cv) return set_error(CWB_E_INVALID_ARG, "null cross-validation");
+  return cwb_batch_tile(cv->batch, out);
 }
 
 void cwb_cv_destroy(cwb_cv* cv) {

@@ -29,7 +29,18 @@ struct FitShape {
   int share = 1;
   int64_t n_scan = 0;     // rows the histogram pass reads (before an HCWB switch)
   bool external_x = false;  // the index matrix lives outside the fit's workspace
+  // fold group head: first row of each fold's block (share + 1 entries, the
+  // last n); segments are split at these rows so that most hold one fold
+  std::vector<int64_t> fold_start;
 };
+
+// First schedule unit whose rows (as the histogram pass maps units onto the
+// n_scan rows it reads) start at or after `row`.
+int64_t unit_at_row(const FitShape& sh, int64_t row);
+// Rows [r0, r1) the histogram pass reads for units [u0, u1).
+void unit_rows(const FitShape& sh, int64_t u0, int64_t u1, int64_t* r0, int64_t* r1);
+// The fold that holds out every row of [r0, min(r1, n)), or -1.
+int segment_fold(const FitShape& sh, int64_t r0, int64_t r1);
 
 // A fold of a cross-validation: the shared index matrix and fold ids (device)
 // and the fold it holds out.

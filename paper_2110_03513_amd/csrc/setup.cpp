@@ -545,7 +545,8 @@ void learner_sizes(HostFit* hf) {
 
 }  // namespace
 
-int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
+int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,
+                     const std::vector<int64_t>* order) {
   int rc = validate_problem(pr, err);
   if (rc) return rc;
   const int64_t n = pr->n;
@@ -560,15 +561,21 @@ int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
   hf->gamma = pr->gamma;
   hf->patience = pr->patience;
 
-  // Training rows first, then validation rows (stable).
+  // Training rows first, then validation rows (stable), or the given order
+  // (every row a training row).
   hf->perm.resize(n);
   int64_t nt = 0;
-  for (int64_t i = 0; i < n; ++i)
-    if (!pr->val_mask || !pr->val_mask[i]) hf->perm[nt++] = i;
+  if (order) {
+    hf->perm = *order;
+    nt = n;
+  } else {
+    for (int64_t i = 0; i < n; ++i)
+      if (!pr->val_mask || !pr->val_mask[i]) hf->perm[nt++] = i;
+    int64_t pos = nt;
+    for (int64_t i = 0; i < n; ++i)
+      if (pr->val_mask && pr->val_mask[i]) hf->perm[pos++] = i;
+  }
   hf->n_train = nt;
-  int64_t pos = nt;
-  for (int64_t i = 0; i < n; ++i)
-    if (pr->val_mask && pr->val_mask[i]) hf->perm[pos++] = i;
 
   hf->y.assign(hf->n_pad, 0.0f);
   double ysum = 0.0;
@@ -606,8 +613,10 @@ int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
   return CWB_OK;
 }
 
-int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
-  int rc = prepare_host_fit(pr, hf, err);
+int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,
+                   const std::vector<int64_t>* order) {
+  int rc = prepare_host_fit(pr, hf, err, order);
+  const bool permuted = pr->val_mask != nullptr || order != nullptr;
   if (rc) return rc;
   const int64_t n = pr->n;
   const int p = pr->p;
@@ -673,7 +682,7 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err) {
         }
         const double h = (xmax - xmin) / (double)(L.nb - 1);
         const double inv_h = 1.0 / h;
-        if (pr->val_mask) {
+        if (permuted) {
           for (int64_t i = 0; i < n; ++i)
             Xj[i] = (uint16_t)bin_of(xj[hf->perm[i]], xmin, xmax, h, L.nb, inv_h);
         } else {  // identity row order
@@ -758,13 +767,23 @@ int cv_host_fits(const cwb_problem* pr, int K, const int32_t* fold, HostFit* ful
                  std::vector<HostFit>* folds, std::string* err) {
   cwb_problem all = *pr;
   all.val_mask = nullptr;
-  int rc = build_host_fit(&all, full, err);
+  // rows grouped by fold (stable): each fold's held-out rows form one block
+  const int64_t n = pr->n;
+  std::vector<int64_t> order;
+  order.reserve(n);
+  for (int k = 0; k < K; ++k)
+    for (int64_t i = 0; i < n; ++i)
+      if (fold[i] == k) order.push_back(i);
+  if ((int64_t)order.size() != n) {
+    *err = "fold id out of range";
+    return CWB_E_INVALID_ARG;
+  }
+  int rc = build_host_fit(&all, full, err, &order);
   if (rc) return rc;
   if (full->unbinned) {
     *err = "cross-validation covers binned learners";
     return CWB_E_UNSUPPORTED;
   }
-  const int64_t n = pr->n;
   const int p = pr->p;
   std::vector<int64_t> rows(K, 0);
   std::vector<double> ysum(K, 0.0);
@@ -791,7 +810,7 @@ int cv_host_fits(const cwb_problem* pr, int K, const int32_t* fold, HostFit* ful
     h.d_max = full->d_max;
     h.sum_d = full->sum_d;
     h.unbinned = false;
-    h.perm = full->perm;  // identity: the folds keep the rows in place
+    h.perm = full->perm;  // the fold-grouped row order
     h.y = full->y;
     // loss-optimal constant over the fold's training rows (every other fold)
     const double ybar = (ytot - ysum[k]) / (double)h.n_train;
@@ -808,7 +827,7 @@ int cv_host_fits(const cwb_problem* pr, int K, const int32_t* fold, HostFit* ful
     const HostLearner& Lf = full->L[j];
     const uint16_t* Xj = full->X.data() + (size_t)j * full->n_pad;
     std::vector<int64_t> c((size_t)K * Lf.nb, 0);
-    for (int64_t i = 0; i < n; ++i) c[(size_t)fold[i] * Lf.nb + Xj[i]] += 1;
+    for (int64_t i = 0; i < n; ++i) c[(size_t)fold[full->perm[i]] * Lf.nb + Xj[i]] += 1;
     std::vector<double> cnt_a(Lf.nb, 0.0), cnt_t(Lf.nb);
     for (int k = 0; k < K; ++k)
       for (int l = 0; l < Lf.nb; ++l) cnt_a[l] += (double)c[(size_t)k * Lf.nb + l];

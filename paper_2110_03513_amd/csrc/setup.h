@@ -69,10 +69,12 @@ int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z
 int validate_problem(const cwb_problem* pr, std::string* err);
 // Host setup of a fit in full: validation, row order, labels, binning, bin
 // counts and every learner's tables.
-int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err);
+int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,
+                   const std::vector<int64_t>* order = nullptr);
 // Its first phase only (nothing that reads x): validation, row order,
 // labels, intercept and each learner's kind and sizes.
-int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err);
+int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,
+                     const std::vector<int64_t>* order = nullptr);
 // Its last phase after a device binning pass: every learner's tables from
 // the feature ranges (xrange[2j], xrange[2j+1]) and bin counts (feature j's
 // training-row counts at counts[j * counts_stride], all-row counts
@@ -81,8 +83,10 @@ int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
                     const uint32_t* counts, int64_t counts_stride, std::string* err);
 // Host setup of the K folds of a cross-validation (fold[i] in [0, K) for
 // every row): `full` bins all rows once, in their own order, and keeps the
-// index matrix that the folds share; each fold's HostFit has its intercept
-// and learner tables from the training rows of every other fold.
+// index matrix that the folds share, with the rows grouped by fold (fold 0's
+// rows first, each group in the original order: full->perm); each fold's
+// HostFit has that row order, and its intercept and learner tables from the
+// training rows of every other fold.
 int cv_host_fits(const cwb_problem* pr, int K, const int32_t* fold, HostFit* full,
                  std::vector<HostFit>* folds, std::string* err);
 

@@ -108,13 +108,14 @@ _SIGNATURES = {
     "cwb_server_poll": [_P, C.c_uint64, C.POINTER(cwb_result), _P, _P],
     "cwb_server_stats": [_P, C.POINTER(cwb_stats)],
     "cwb_server_destroy": [_P],
-    "cwb_cv_workspace_bytes": [C.POINTER(cwb_problem), C.c_int32, C.POINTER(C.c_size_t)],
+    "cwb_cv_workspace_bytes": [C.POINTER(cwb_problem), C.c_int32, _P, C.POINTER(C.c_size_t)],
     "cwb_cv_create": [C.POINTER(cwb_problem), C.c_int32, _P, _P, C.c_size_t, _P, C.POINTER(_P)],
     "cwb_cv_run": [_P, C.c_int32],
     "cwb_cv_sync": [_P],
     "cwb_cv_fold": [_P, C.c_int32, C.POINTER(_P)],
     "cwb_cv_risk": [_P, _P],
     "cwb_cv_destroy": [_P],
+    "cwb_cv_tile": [_P, C.POINTER(cwb_tile)],
 }
 _VOID = {"cwb_fit_destroy", "cwb_batch_destroy", "cwb_server_destroy", "cwb_cv_destroy"}
 
@@ -419,7 +420,8 @@ class CV:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(self.device):
             b = C.c_size_t()
-            check(lib().cwb_cv_workspace_bytes(C.byref(self.problem.c), self.n_folds, C.byref(b)))
+            check(lib().cwb_cv_workspace_bytes(C.byref(self.problem.c), self.n_folds,
+                                               _ptr(self.fold), C.byref(b)))
             self.ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
             self._sh, self.stream = _stream_handle(stream)
             h = C.c_void_p()
@@ -437,6 +439,12 @@ class CV:
 
     def sync(self):
         check(lib().cwb_cv_sync(self.h))
+
+    def tile(self) -> dict:
+        t = cwb_tile()
+        check(lib().cwb_cv_tile(self.h, C.byref(t)))
+        return {"threads": t.threads, "learners": t.learners, "blocks": t.blocks,
+                "candidates": t.candidates, "tuned_us": t.tuned_us}
 
     def risk(self) -> np.ndarray:
         """Cross-validated risk of iterations 0..done (held-out loss / n)."""

@@ -253,10 +253,14 @@ def test_setup_mode_rules():
     assert cwb.workspace_bytes(dict(base, setup="device")) == cwb.workspace_bytes(base)
 
 
-def _cv_bytes(prob, K):
+def _cv_bytes(prob, K, fold=None):
     pr = cwb.Problem(prob)
+    n = prob["x"].shape[0]
+    if fold is None:
+        fold = (np.arange(n) * 7919 % max(K, 1)).astype(np.int32)
     b = C.c_size_t()
-    rc = cwb.lib().cwb_cv_workspace_bytes(C.byref(pr.c), K, C.byref(b))
+    rc = cwb.lib().cwb_cv_workspace_bytes(C.byref(pr.c), K, fold.ctypes.data_as(C.c_void_p),
+                                          C.byref(b))
     return rc, b.value, cwb.lib().cwb_last_error().decode()
 
 
