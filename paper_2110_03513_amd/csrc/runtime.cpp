@@ -690,7 +690,7 @@ int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const 
   EventPair ev;
   HIP_TRY(hipEventCreate(&ev.a));
   HIP_TRY(hipEventCreate(&ev.b));
-  double best_t = 0.0;
+  double best_t = 0.0, default_t = 0.0;
   for (size_t i = 0; i < cands.size(); ++i) {
     const Tune& t = cands[i];
     Schedule S = build_schedule(shapes, t);
@@ -708,11 +708,18 @@ int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const 
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
     const double us = (double)ms * 1e3 / kTimed;
+    if (i == 0) default_t = us;
     if (*best_us == 0.0 || us < best_t) {
       best_t = us;
       *best = (int)i;
       *best_us = us;
     }
+  }
+  // keep the default shape unless another is clearly faster: shapes within
+  // timing noise would otherwise change from run to run
+  if (*best != 0 && default_t > 0.0 && best_t > 0.98 * default_t) {
+    *best = 0;
+    *best_us = default_t;
   }
   return CWB_OK;
 }

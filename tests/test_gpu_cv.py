@@ -77,3 +77,30 @@ def test_cv_resumes_and_predicts():
     assert rel_err(a.folds[2].predict(xn), oracle.predict(prob, o, xn)) <= 1e-4
     a.close()
     b.close()
+
+
+def test_cv_uneven_folds_ragged_rows_and_categorical_learners():
+    """A one-row fold, very uneven folds, a ragged row count, and ridge and
+    binary categorical learners beside P-splines, in ACWB with eight folds."""
+    n = 10_001
+    prob = datagen.additive_problem(n, 7, seed=116, n_informative=2, loss="binomial",
+                                    n_bins=50, M=40, variant="acwb", gamma=0.1, n_cat=2,
+                                    n_informative_cat=2)
+    prob["kind"][-1] = datagen.BINARY
+    prob["df"][-1] = 0.0
+    rng = np.random.default_rng(117)
+    fold = rng.integers(1, 8, n).astype(np.int32)
+    fold[5_000] = 0  # fold 0 holds out a single row
+    fold[fold == 7] = rng.integers(5, 7, int((fold == 7).sum()))  # and fold 7 keeps few
+    fold[:3] = 7
+    K = 8
+    assert np.bincount(fold, minlength=K).min() >= 1
+    _say(f"cv: K={K} fold sizes {np.bincount(fold, minlength=K).tolist()}")
+    cv = cwb.CV(prob, fold)
+    cv.run(40)
+    cv.sync()
+    for k in range(K):
+        pk = dict(prob, val_mask=(fold == k).astype(np.uint8))
+        res = _fold_result(cv.folds[k])
+        compare(res, pk)
+    cv.close()
