@@ -444,3 +444,12 @@ def test_mise_against_oracle(variant, loss, nb):
     _say(f"MISE gpu {m_gpu:.6e} oracle {m_orc:.6e}")
     assert abs(m_gpu - m_orc) <= 1e-2 * m_orc + 1e-7
     f.close()
+
+
+@pytest.mark.parametrize("variant", ["cwb", "acwb"])
+def test_many_learners(variant):
+    """p = 600 learners: the argmin in the row pass takes several rounds of
+    its block, and the select pass runs 600 (or 1,200 signal) solves."""
+    prob = datagen.additive_problem(6_000, 600, seed=97, n_informative=5, n_bins=32, M=30,
+                                    variant=variant, gamma=0.05)
+    compare(_run(prob), prob)
