@@ -292,12 +292,30 @@ def cpu_baseline(args, prob, gpu_trace):
     first = int(np.argmin(eq)) if not eq.all() else -1
     gap = float(o["gap"][first]) if first >= 0 else None
     del o1
+    # the same oracle on one thread, over a shorter window
+    one = None
+    if args.cpu_iters_1thread > 0:
+        k1 = args.cpu_iters_1thread
+        oracle.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.fit(dict(prob, M=1))
+            s1 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.fit(dict(prob, M=1 + k1))
+            a1 = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(cores)
+        one = {"value": round(k1 / max(a1 - s1, 1e-9), 4), "unit": "iters/s", "cores": 1,
+               "kind": "oracle",
+               "sample": (f"FP64 C oracle on one thread, iterations 2..{1 + k1} of the same input "
+                          f"(setup excluded, {s1:.1f}s)")}
     return {
         "value": round(1.0 / per_iter, 4), "unit": "iters/s", "cores": cores, "kind": "oracle",
         "sample": (f"FP64 C oracle, iterations 2..{1 + iters} of the same n={prob['x'].shape[0]} "
                    f"p={prob['x'].shape[1]} input (setup excluded, {t_setup:.1f}s)"),
     }, {"iterations_compared": m, "k_match": match, "first_mismatch": first,
-        "oracle_gap_at_mismatch": gap}
+        "oracle_gap_at_mismatch": gap}, one
 
 
 def batched(args, torch, cwb, datagen):
@@ -470,6 +488,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=1200)
+    ap.add_argument("--cpu-iters-1thread", type=int, default=0,
+                    help="also time the oracle on one thread over this many iterations "
+                         "(its setup alone takes about 12 s at the headline shape)")
     ap.add_argument("--profile-iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -547,8 +568,10 @@ def main():
     if not args.no_cv:
         out["cv"] = cv_leg(args, torch, cwb, datagen)
     if not args.no_cpu:
-        cb, par = cpu_baseline(args, prob, tr)
+        cb, par, one = cpu_baseline(args, prob, tr)
         out["cpu_baseline"] = cb
+        if one:
+            out["cpu_baseline_1thread"] = one
         out["parity"] = par
     del prob
     if not args.no_unbinned:
