@@ -13,7 +13,10 @@
  *   - HCWB: Algorithm 3 (Section 3.2.3);
  *   - P-spline and categorical ridge base learners with equal degrees of
  *     freedom: Section 2.2, Appendix A.2 and A.3.1; categorical features in
- *     the binary representation (one learner per class): Appendix A.3.2.
+ *     the binary representation (one learner per class): Appendix A.3.2;
+ *   - the fitted model and its learners' functions at new rows (Section
+ *     2.3), single fits, batches of fits, a fit server, and K-fold
+ *     cross-validation whose folds share one index matrix (Section 4.2).
  * Every iteration runs on the GPU in hand-written HIP kernels.  The one-off
  * FP64 setup in cwb_fit_create bins the features and counts the bins on the
  * GPU (or on host threads, see cwb_problem.setup); the host builds the
