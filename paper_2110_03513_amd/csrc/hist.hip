@@ -207,12 +207,19 @@ __device__ __forceinline__ void uhist_rows(const FitDev& F, const Seg& sg,
 }
 
 // NSMAX: most signals any fit of the launch can have (1 when every fit is
-// plain CWB, so the two-signal path is not compiled in).  UNB: every fit of
-// the launch has unbinned learners.
-template <int NT, int FMAX, int NSMAX, bool UNB>
+// plain CWB, so the two-signal path is not compiled in).  KIND: kBinned
+// (one fit per segment), kUnbinned (every fit has unbinned learners) or
+// kFolds (binned, with fold groups of a cross-validation).  The fold path
+// is compiled into its own variant so that it does not raise the register
+// use of the others.
+constexpr int kBinned = 0, kUnbinned = 1, kFolds = 2;
+
+template <int NT, int FMAX, int NSMAX, int KIND>
 __global__ void __launch_bounds__(NT)
 k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
        const int64_t* __restrict__ blk, long long* __restrict__ partials) {
+  constexpr bool UNB = KIND == kUnbinned;
+  constexpr bool FOLDS = KIND == kFolds;
   extern __shared__ unsigned long long s_hist[];
   __shared__ float s_red[NT + 16];
   __shared__ int s_e[2 * kMaxFolds];
@@ -237,7 +244,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int64_t r1 = 8 * (sg.u1 * n8 / U);
     const bool need_e = sg.fit != cached_fit;
     cached_fit = sg.fit;
-    if (!UNB && sg.nfit > 1) {  // the folds of a cross-validation
+    if (FOLDS && sg.nfit > 1) {  // the folds of a cross-validation
       if (need_e) {
         for (int q = 0; q < sg.nfit; ++q) {
           int a = 0, b = 0;
@@ -286,62 +293,68 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
 
 namespace {
 
-template <int NT, int FMAX, int NSMAX, bool UNB>
+template <int NT, int FMAX, int NSMAX, int KIND>
 hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                          const int64_t* blk, long long* partials) {
   // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB);
   // set once (thread-safe static initialisation), before any graph capture
   static const bool attr = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, UNB>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, KIND>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
     (void)hipGetLastError();
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, UNB>), dim3(blocks), dim3(NT), lds, st, fits, segs, blk,
-                     partials);
+  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, KIND>), dim3(blocks), dim3(NT), lds, st, fits, segs,
+                     blk, partials);
   return hipGetLastError();
 }
 
-template <int NT, int NSMAX, bool UNB>
+template <int NT, int NSMAX, int KIND>
 hipError_t launch_hist_nt(hipStream_t st, int fmax, int blocks, size_t lds, const FitDev* fits,
                           const Seg* segs, const int64_t* blk, long long* partials) {
   switch (fmax) {
-    case 1: return launch_hist_t<NT, 1, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 2: return launch_hist_t<NT, 2, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 4: return launch_hist_t<NT, 4, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 8: return launch_hist_t<NT, 8, NSMAX, UNB>(st, blocks, lds, fits, segs, blk, partials);
-    case 16:
-      if (!UNB) return launch_hist_t<NT, 16, NSMAX, false>(st, blocks, lds, fits, segs, blk, partials);
+    case 1: return launch_hist_t<NT, 1, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
+    case 2: return launch_hist_t<NT, 2, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
+    case 4: return launch_hist_t<NT, 4, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
+    case 8: return launch_hist_t<NT, 8, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
+    case 16:  // binned kinds only (the unbinned variant holds 32-bit codes)
+      if (KIND == kBinned) return launch_hist_t<NT, 16, NSMAX, kBinned>(st, blocks, lds, fits, segs, blk, partials);
+      if (KIND == kFolds) return launch_hist_t<NT, 16, NSMAX, kFolds>(st, blocks, lds, fits, segs, blk, partials);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int NSMAX, bool UNB>
+template <int NSMAX, int KIND>
 hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
                           const FitDev* fits, const Seg* segs, const int64_t* blk,
                           long long* partials) {
   switch (nt) {
-    case 256: return launch_hist_nt<256, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 512: return launch_hist_nt<512, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 1024: return launch_hist_nt<1024, NSMAX, UNB>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 256: return launch_hist_nt<256, NSMAX, KIND>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 512: return launch_hist_nt<512, NSMAX, KIND>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 1024: return launch_hist_nt<1024, NSMAX, KIND>(st, fmax, blocks, lds, fits, segs, blk, partials);
     default: return hipErrorInvalidValue;
   }
 }
 
+template <int KIND>
+hipError_t launch_hist_k(hipStream_t st, int nt, int fmax, int nsmax, int blocks, size_t lds,
+                         const FitDev* fits, const Seg* segs, const int64_t* blk, long long* partials) {
+  if (nsmax == 1) return launch_hist_ns<1, KIND>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_ns<2, KIND>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+}
+
 }  // namespace
 
-hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, int blocks,
-                       size_t lds, const FitDev* fits, const Seg* segs, const int64_t* blk,
-                       long long* partials) {
+hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, bool folds,
+                       int blocks, size_t lds, const FitDev* fits, const Seg* segs,
+                       const int64_t* blk, long long* partials) {
   if (blocks <= 0) return hipSuccess;
-  if (unbinned) {
-    if (nsmax == 1) return launch_hist_ns<1, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-    return launch_hist_ns<2, true>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-  }
-  if (nsmax == 1) return launch_hist_ns<1, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-  return launch_hist_ns<2, false>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  if (unbinned && folds) return hipErrorInvalidValue;
+  if (unbinned) return launch_hist_k<kUnbinned>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+  if (folds) return launch_hist_k<kFolds>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_k<kBinned>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
 }
 
 }  // namespace cwb

@@ -126,8 +126,8 @@ Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, in
   F = std::min(F, std::max(1, p_max));
   while (F > 1 && (size_t)F * per_learner > (size_t)kHistMaxLds) --F;
   // register budget at 1024 threads: groups of at most 8 learners (one
-  // signal) or 2 learners (two signals); wider groups would spill
-  if (t.nt == 1024) F = std::min(F, nsig_max == 1 ? 8 : 2);
+  // signal) or 4 learners (two signals); wider groups would spill
+  if (t.nt == 1024) F = std::min(F, nsig_max == 1 ? 8 : 4);
   // unbinned groups hold 32 bytes of codes per learner and thread
   if (unbinned) F = std::min(F, t.nt == 1024 ? (nsig_max == 1 ? 4 : 2) : 8);
   t.F = F;
@@ -140,8 +140,7 @@ Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, in
 
 // Default tile shape (measured on the headline and momentum workloads): one
 // signal, 1,024 threads with 32 KiB of histograms; two signals, 512 threads
-// with 128 KiB, since 1,024-thread blocks can hold only two learners of two
-// signals in registers.
+// with 128 KiB (eight learners per group).
 Tune make_tune(int nb_stride, int nsig_max, int p_max, bool unbinned) {
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -349,6 +348,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   S.lds = (size_t)ns_max * t.F * nbs_max * sizeof(long long);
   S.nsig_max = ns_max;
   S.unbinned = !fits.empty() && fits[0]->unbinned;
+  for (const Seg& sg : S.segs) S.folds = S.folds || sg.nfit > 1;
   return S;
 }
 
@@ -544,7 +544,7 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Sch
   HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
-  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   HIP_TRY(launch_select(st, d_sel, n_sel, nb_max, d_max, d_part));
@@ -699,10 +699,10 @@ int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const 
     HIP_TRY(hipMemcpyAsync(d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
     for (int w = 0; w < kWarm; ++w)
-      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
     HIP_TRY(hipEventRecord(ev.a, st));
     for (int r = 0; r < kTimed; ++r)
-      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
     HIP_TRY(hipEventRecord(ev.b, st));
     HIP_TRY(hipEventSynchronize(ev.b));
     float ms = 0.0f;

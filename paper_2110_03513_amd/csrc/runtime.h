@@ -80,6 +80,7 @@ struct Schedule {
   int blocks = 0;
   int nsig_max = 1;  // most signals of any fit in the schedule
   bool unbinned = false;  // the fits' learners are unbinned (one kind per schedule)
+  bool folds = false;     // some segment serves a fold group (nfit > 1)
   size_t lds = 0;
 };
 
