@@ -212,4 +212,22 @@ inline int scale_exponent(float amax, int64_t n_fit) {
   return 62 - N - E;
 }
 
+// Learners with few bins (categorical levels, coarse binnings) get several
+// interleaved copies of their histogram inside their LDS region of `region`
+// words: lane l of a wave adds into copy l mod C, so the lanes seldom add
+// into the same word, which the LDS would serialise.  Copies start
+// s = nb | 1 words apart (an odd stride puts the copies of one bin on
+// different banks) and C * s <= region.  Returns C - 1 (a lane mask) and s.
+constexpr int kMaxCopies = 32;
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline int copy_mask(int nbk, int region, int* stride) {
+  const int s = nbk | 1;
+  int c = 1;
+  while (c < kMaxCopies && 2 * c * s <= region) c *= 2;
+  *stride = s;
+  return c - 1;
+}
+
 }  // namespace cwb

@@ -10,6 +10,17 @@
 
 namespace cwb {
 
+// The lane index, opaque to the optimiser: the copy bases derived from it
+// are recomputed at each use (a few VALU operations next to many LDS
+// atomics) rather than held in a register per learner across the row loop.
+__device__ __forceinline__ int opaque_lane() {
+  int l = (int)threadIdx.x & 63;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
+// The 8 rows of one index load of one learner into its histogram h (this
+// lane's copy).
 template <int NSIG>
 __device__ __forceinline__ void hist_add(unsigned long long* __restrict__ h, const u32x4& x,
                                          const long long* q) {
@@ -45,14 +56,20 @@ __device__ __forceinline__ void hist_step_load(const FitDev& F, const uint16_t* 
 // signal.  The next step's loads are issued before this step's atomics.
 // With `need_e`, the fit's scale exponents are computed (by all threads)
 // while the first step's loads are in flight.
-template <int NT, int FMAX, int NSIG>
+template <int NT, int FMAX, int NSIG, bool COPIES>
 __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
                                           unsigned long long* __restrict__ hist, int nb,
                                           int64_t r0, int64_t r1, int& e0, int& e1, bool need_e,
-                                          int64_t n_fit, float* red) {
+                                          int64_t n_fit, float* red, const int (*cp)[16]) {
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
   const int nf = sg.nf;
   const size_t ld = (size_t)F.n_pad;
+  int cm[FMAX], cs[FMAX];  // copy masks and strides, wave-uniform
+#pragma unroll
+  for (int f = 0; f < FMAX; ++f) {
+    cm[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[0][f]) : 0;
+    cs[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[1][f]) : 0;
+  }
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
   const bool any = base < r1;
   float rv[8], cv[8];
@@ -74,11 +91,13 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
     if (more) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, nxt, rv, cv, xw);
+    const int lane = COPIES ? opaque_lane() : 0;
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) {
       if (f < nf) {
-        hist_add<NSIG>(hist + (size_t)f * nb, xc[f], q0);
-        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb, xc[f], q1);
+        const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;  // this lane's copy
+        hist_add<NSIG>(hist + (size_t)f * nb + cb, xc[f], q0);
+        if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb + cb, xc[f], q1);
       }
     }
     if (!more) break;
@@ -91,10 +110,17 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
 // rows carry zero residuals; the fold that holds out all of the segment's
 // rows (skip) is left out.  LDS histogram of fold q, signal s, learner f at
 // ((q * NSIG + s) * nf + f) * nb; exponents in e[2q], e[2q+1].
-template <int NT, int FMAX, int NSIG>
+template <int NT, int FMAX, int NSIG, bool COPIES>
 __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits, const Seg& sg,
                                                 unsigned long long* __restrict__ hist, int nb,
-                                                int64_t r0, int64_t r1, const int* e) {
+                                                int64_t r0, int64_t r1, const int* e,
+                                                const int (*cp)[16]) {
+  int cm[FMAX], cs[FMAX];
+#pragma unroll
+  for (int f = 0; f < FMAX; ++f) {
+    cm[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[0][f]) : 0;
+    cs[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[1][f]) : 0;
+  }
   const FitDev& F0 = fits[sg.fit];
   const uint16_t* __restrict__ Xg = F0.X + (size_t)sg.k0 * F0.n_pad;
   const int nf = sg.nf;
@@ -144,11 +170,13 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
         if (NSIG == 2) load8f(fits[sg.fit + first].c + nxt, cv);
       }
       unsigned long long* hq = hist + (size_t)q * NSIG * nf * nb;
+      const int lane = COPIES ? opaque_lane() : 0;
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
         if (f < nf) {
-          hist_add<NSIG>(hq + (size_t)f * nb, xc[f], q0);
-          if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb, xc[f], q1);
+          const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;
+          hist_add<NSIG>(hq + (size_t)f * nb + cb, xc[f], q0);
+          if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb + cb, xc[f], q1);
         }
       }
       if (qn < 0) break;
@@ -211,18 +239,22 @@ __device__ __forceinline__ void uhist_rows(const FitDev& F, const Seg& sg,
 // (one fit per segment), kUnbinned (every fit has unbinned learners) or
 // kFolds (binned, with fold groups of a cross-validation).  The fold path
 // is compiled into its own variant so that it does not raise the register
-// use of the others.
+// use of the others.  COPIES (binned kinds): some learner of the launch has
+// few enough bins for LDS copies (copy_mask); without it the row loops keep
+// no copy bases.
 constexpr int kBinned = 0, kUnbinned = 1, kFolds = 2;
 
-template <int NT, int FMAX, int NSMAX, int KIND>
+template <int NT, int FMAX, int NSMAX, int KIND, bool COPIES>
 __global__ void __launch_bounds__(NT)
 k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
        const int64_t* __restrict__ blk, long long* __restrict__ partials) {
   constexpr bool UNB = KIND == kUnbinned;
   constexpr bool FOLDS = KIND == kFolds;
+  static_assert(FMAX <= 16, "copy table holds 16 learners");
   extern __shared__ unsigned long long s_hist[];
   __shared__ float s_red[NT + 16];
   __shared__ int s_e[2 * kMaxFolds];
+  __shared__ int s_cp[2][16];  // binned learners of the segment: copy mask, copy stride
   const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
   int cached_fit = -1;
   int e0 = 0, e1 = 0;
@@ -237,6 +269,11 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int nb = F.nb_stride;
     const int words = sg.nfit * nsig * sg.nf * nb;
     for (int i = threadIdx.x; i < words; i += NT) s_hist[i] = 0ull;
+    if (COPIES && (int)threadIdx.x < sg.nf) {
+      int st = 0;
+      s_cp[0][threadIdx.x] = copy_mask(F.feat[sg.k0 + threadIdx.x].nb, nb, &st);
+      s_cp[1][threadIdx.x] = st;
+    }
     __syncthreads();
     const int64_t n8 = (n_fit + 7) >> 3;
     const int64_t U = F.n_pad >> 3;
@@ -257,9 +294,9 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
         __syncthreads();
       }
       if (NSMAX == 1 || nsig == 1)
-        hist_rows_folds<NT, FMAX, 1>(fits, sg, s_hist, nb, r0, r1, s_e);
+        hist_rows_folds<NT, FMAX, 1, COPIES>(fits, sg, s_hist, nb, r0, r1, s_e, s_cp);
       else
-        hist_rows_folds<NT, FMAX, NSMAX>(fits, sg, s_hist, nb, r0, r1, s_e);
+        hist_rows_folds<NT, FMAX, NSMAX, COPIES>(fits, sg, s_hist, nb, r0, r1, s_e, s_cp);
     } else if (UNB) {
       if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, s_red);
       if (NSMAX == 1 || nsig == 1)
@@ -268,9 +305,9 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
         uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
     } else {
       if (NSMAX == 1 || nsig == 1)
-        hist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
+        hist_rows<NT, FMAX, 1, COPIES>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red, s_cp);
       else
-        hist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red);
+        hist_rows<NT, FMAX, NSMAX, COPIES>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red, s_cp);
     }
     __syncthreads();
     GLOBAL long long* out = gp(partials + sg.slot);
@@ -283,8 +320,25 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
         for (int c = 0; c < kUnbCopies; ++c) acc += (long long)s_hist[(size_t)lf * nb + c * d + b];
         out[(size_t)lf * nb + b] = acc;
       }
-    } else {
+    } else if (!COPIES) {
       for (int i = threadIdx.x; i < words; i += NT) out[i] = (long long)s_hist[i];
+    } else {  // sum each learner's copies; words past its copies' stride are zero
+      const int nlf = sg.nfit * nsig * sg.nf;
+      for (int lf = 0, f = 0; lf < nlf; ++lf, f = (f + 1 == sg.nf) ? 0 : f + 1) {
+        const unsigned long long* h = s_hist + (size_t)lf * nb;
+        GLOBAL long long* o = out + (size_t)lf * nb;
+        const int cm = s_cp[0][f], cs = s_cp[1][f];
+        if (cm == 0) {
+          for (int b = threadIdx.x; b < nb; b += NT) o[b] = (long long)h[b];
+        } else {
+          for (int b = threadIdx.x; b < nb; b += NT) {
+            long long acc = 0;
+            if (b < cs)
+              for (int c = 0; c <= cm; ++c) acc += (long long)h[b + c * cs];
+            o[b] = acc;
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -293,68 +347,72 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
 
 namespace {
 
-template <int NT, int FMAX, int NSMAX, int KIND>
+template <int NT, int FMAX, int NSMAX, int KIND, bool COPIES>
 hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                          const int64_t* blk, long long* partials) {
   // 160 KiB per workgroup minus the kernel's static LDS (at most ~4 KiB);
   // set once (thread-safe static initialisation), before any graph capture
   static const bool attr = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, KIND>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<NT, FMAX, NSMAX, KIND, COPIES>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kHistMaxLds);
     (void)hipGetLastError();
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, KIND>), dim3(blocks), dim3(NT), lds, st, fits, segs,
+  hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, KIND, COPIES>), dim3(blocks), dim3(NT), lds, st, fits, segs,
                      blk, partials);
   return hipGetLastError();
 }
 
-template <int NT, int NSMAX, int KIND>
+template <int NT, int NSMAX, int KIND, bool COPIES>
 hipError_t launch_hist_nt(hipStream_t st, int fmax, int blocks, size_t lds, const FitDev* fits,
                           const Seg* segs, const int64_t* blk, long long* partials) {
   switch (fmax) {
-    case 1: return launch_hist_t<NT, 1, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
-    case 2: return launch_hist_t<NT, 2, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
-    case 4: return launch_hist_t<NT, 4, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
-    case 8: return launch_hist_t<NT, 8, NSMAX, KIND>(st, blocks, lds, fits, segs, blk, partials);
+    case 1: return launch_hist_t<NT, 1, NSMAX, KIND, COPIES>(st, blocks, lds, fits, segs, blk, partials);
+    case 2: return launch_hist_t<NT, 2, NSMAX, KIND, COPIES>(st, blocks, lds, fits, segs, blk, partials);
+    case 4: return launch_hist_t<NT, 4, NSMAX, KIND, COPIES>(st, blocks, lds, fits, segs, blk, partials);
+    case 8: return launch_hist_t<NT, 8, NSMAX, KIND, COPIES>(st, blocks, lds, fits, segs, blk, partials);
     case 16:  // binned kinds only (the unbinned variant holds 32-bit codes)
-      if (KIND == kBinned) return launch_hist_t<NT, 16, NSMAX, kBinned>(st, blocks, lds, fits, segs, blk, partials);
-      if (KIND == kFolds) return launch_hist_t<NT, 16, NSMAX, kFolds>(st, blocks, lds, fits, segs, blk, partials);
+      if (KIND == kBinned) return launch_hist_t<NT, 16, NSMAX, kBinned, COPIES>(st, blocks, lds, fits, segs, blk, partials);
+      if (KIND == kFolds) return launch_hist_t<NT, 16, NSMAX, kFolds, COPIES>(st, blocks, lds, fits, segs, blk, partials);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int NSMAX, int KIND>
+template <int NSMAX, int KIND, bool COPIES>
 hipError_t launch_hist_ns(hipStream_t st, int nt, int fmax, int blocks, size_t lds,
                           const FitDev* fits, const Seg* segs, const int64_t* blk,
                           long long* partials) {
   switch (nt) {
-    case 256: return launch_hist_nt<256, NSMAX, KIND>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 512: return launch_hist_nt<512, NSMAX, KIND>(st, fmax, blocks, lds, fits, segs, blk, partials);
-    case 1024: return launch_hist_nt<1024, NSMAX, KIND>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 256: return launch_hist_nt<256, NSMAX, KIND, COPIES>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 512: return launch_hist_nt<512, NSMAX, KIND, COPIES>(st, fmax, blocks, lds, fits, segs, blk, partials);
+    case 1024: return launch_hist_nt<1024, NSMAX, KIND, COPIES>(st, fmax, blocks, lds, fits, segs, blk, partials);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int KIND>
+template <int KIND, bool COPIES>
 hipError_t launch_hist_k(hipStream_t st, int nt, int fmax, int nsmax, int blocks, size_t lds,
                          const FitDev* fits, const Seg* segs, const int64_t* blk, long long* partials) {
-  if (nsmax == 1) return launch_hist_ns<1, KIND>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
-  return launch_hist_ns<2, KIND>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  if (nsmax == 1) return launch_hist_ns<1, KIND, COPIES>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_ns<2, KIND, COPIES>(st, nt, fmax, blocks, lds, fits, segs, blk, partials);
 }
 
 }  // namespace
 
 hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, bool folds,
-                       int blocks, size_t lds, const FitDev* fits, const Seg* segs,
+                       bool copies, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                        const int64_t* blk, long long* partials) {
   if (blocks <= 0) return hipSuccess;
   if (unbinned && folds) return hipErrorInvalidValue;
-  if (unbinned) return launch_hist_k<kUnbinned>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
-  if (folds) return launch_hist_k<kFolds>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
-  return launch_hist_k<kBinned>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+  if (unbinned) return launch_hist_k<kUnbinned, false>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+  if (folds) {
+    if (copies) return launch_hist_k<kFolds, true>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+    return launch_hist_k<kFolds, false>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+  }
+  if (copies) return launch_hist_k<kBinned, true>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
+  return launch_hist_k<kBinned, false>(st, nt, fmax, nsmax, blocks, lds, fits, segs, blk, partials);
 }
 
 }  // namespace cwb

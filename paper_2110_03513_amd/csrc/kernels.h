@@ -11,7 +11,7 @@ hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items
 // folds: the schedule has fold-group segments (nfit > 1); only the variant
 // compiled for them handles such segments.
 hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, bool folds,
-                       int blocks, size_t lds, const FitDev* fits, const Seg* segs,
+                       bool copies, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                        const int64_t* blk, long long* partials);
 hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nb_max, int d_max,
                          const long long* partials);

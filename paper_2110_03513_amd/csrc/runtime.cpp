@@ -67,6 +67,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
   sh->nb_max = sh->d_max = sh->sum_d = 0;
   sh->sum_nb = sh->sum_d2 = 0;
   sh->unbinned = false;
+  int nb_min = kMaxBins;
   for (int j = 0; j < pr->p; ++j) {
     const cwb_learner_spec& s = pr->specs[j];
     int nb, d;
@@ -86,6 +87,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
       return (nb > kMaxBins && nb <= 65535) ? CWB_E_UNSUPPORTED : CWB_E_INVALID_ARG;
     }
     sh->nb_max = std::max(sh->nb_max, nb);
+    nb_min = std::min(nb_min, nb);
     sh->d_max = std::max(sh->d_max, d);
     sh->sum_d += d;
     sh->sum_nb += nb;
@@ -93,6 +95,8 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
   }
   sh->nb_stride = (sh->nb_max + 3) / 4 * 4;
   if (sh->unbinned) sh->nb_stride = (kUnbCopies * sh->d_max + 3) / 4 * 4;
+  int st = 0;
+  sh->copies = !sh->unbinned && copy_mask(nb_min, sh->nb_stride, &st) != 0;
   sh->n_row_blocks = (int)((sh->n_pad + kStateRows - 1) / kStateRows);
   const int64_t nv = sh->n - sh->n_train;
   sh->n_val_blocks = (sh->variant == CWB_HCWB && nv > 0) ? (int)((nv + kStateRows - 1) / kStateRows) : 0;
@@ -349,6 +353,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   S.nsig_max = ns_max;
   S.unbinned = !fits.empty() && fits[0]->unbinned;
   for (const Seg& sg : S.segs) S.folds = S.folds || sg.nfit > 1;
+  for (const FitShape* f : fits) S.copies = S.copies || (f->copies && !S.unbinned);
   return S;
 }
 
@@ -544,7 +549,7 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Sch
   HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
-  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+  HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.copies, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   HIP_TRY(launch_select(st, d_sel, n_sel, nb_max, d_max, d_part));
@@ -699,10 +704,10 @@ int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const 
     HIP_TRY(hipMemcpyAsync(d_segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
     for (int w = 0; w < kWarm; ++w)
-      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.copies, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
     HIP_TRY(hipEventRecord(ev.a, st));
     for (int r = 0; r < kTimed; ++r)
-      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
+      HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.copies, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
     HIP_TRY(hipEventRecord(ev.b, st));
     HIP_TRY(hipEventSynchronize(ev.b));
     float ms = 0.0f;

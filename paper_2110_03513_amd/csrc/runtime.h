@@ -23,6 +23,7 @@ struct FitShape {
   int64_t sum_nb = 0, sum_d2 = 0;
   int n_row_blocks = 0, n_val_blocks = 0;
   bool unbinned = false;  // learners are unbinned cubic P-splines
+  bool copies = false;    // some binned learner gets LDS histogram copies (copy_mask)
   // Folds of a cross-validation share one index matrix and one histogram
   // pass: the first fold's shape has share = the number of folds (the
   // others follow it in the fit list, with share = 0); other fits have 1.
@@ -81,6 +82,7 @@ struct Schedule {
   int nsig_max = 1;  // most signals of any fit in the schedule
   bool unbinned = false;  // the fits' learners are unbinned (one kind per schedule)
   bool folds = false;     // some segment serves a fold group (nfit > 1)
+  bool copies = false;    // some fit's learners get LDS histogram copies
   size_t lds = 0;
 };
 

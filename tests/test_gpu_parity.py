@@ -453,3 +453,57 @@ def test_many_learners(variant):
     prob = datagen.additive_problem(6_000, 600, seed=97, n_informative=5, n_bins=32, M=30,
                                     variant=variant, gamma=0.05)
     compare(_run(prob), prob)
+
+
+def _few_bin_problem(n, variant, loss, seed):
+    """Numeric learners with 1,000, 2, 7, 33, 100 and 257 bins, and ridge
+    learners with 5 and 17 levels: the LDS histogram pass gives learners with
+    few bins 2 to 32 interleaved copies, and 1,000 bins none."""
+    rng = np.random.default_rng(seed)
+    nbs = [1000, 2, 7, 33, 100, 257]
+    levels = [5, 17]
+    p = len(nbs) + len(levels)
+    x = np.empty((n, p))
+    x[:, :len(nbs)] = rng.uniform(-1.0, 2.0, (n, len(nbs)))
+    for j, c in enumerate(levels):
+        x[:, len(nbs) + j] = rng.integers(0, c, n)
+    lev5, lev17 = rng.normal(0, 0.6, 5), rng.normal(0, 0.6, 17)
+    eta = (np.sin(2 * x[:, 0]) + 0.8 * x[:, 1] + np.cos(3 * x[:, 2]) + 0.5 * x[:, 3] ** 2
+           + 0.6 * x[:, 4] - 0.7 * np.sin(2 * x[:, 5]) + lev5[x[:, 6].astype(int)]
+           + lev17[x[:, 7].astype(int)])
+    if loss == "l2":
+        y = eta + rng.normal(0, 0.5, n)
+    else:
+        y = (rng.uniform(size=n) < 1 / (1 + np.exp(-eta))).astype(np.float64)
+    kinds = np.array([datagen.PSPLINE] * len(nbs) + [datagen.RIDGE] * len(levels))
+    prob = {"x": x, "y": y, "loss": loss, "nu": 0.2, "M": 60, "variant": variant, "gamma": 0.05}
+    prob.update(datagen.learner_specs(p, np.array(nbs + [0, 0]), df=4.0, kinds=kinds,
+                                      n_levels=np.array([0] * len(nbs) + levels)))
+    prob["df"][1] = 0.0  # two design points: a fixed smoothing parameter
+    prob["lambda"][1] = 1.0
+    prob["df"][2] = 3.0
+    return prob
+
+
+@pytest.mark.parametrize("variant,loss", [("cwb", "l2"), ("acwb", "binomial")])
+def test_few_bin_learners_against_oracle(variant, loss):
+    prob = _few_bin_problem(30_003, variant, loss, seed=131)
+    compare(_run(prob), prob)
+
+
+def test_few_bin_learners_in_folds():
+    """The fold-group variant of the histogram pass with learner copies."""
+    prob = _few_bin_problem(20_001, "cwb", "l2", seed=132)
+    fold = (np.arange(20_001) % 3).astype(np.int32)
+    np.random.default_rng(133).shuffle(fold)
+    _say("cv with few-bin learners: K=3 n=20001")
+    cv = cwb.CV(prob, fold)
+    cv.run(60)
+    cv.sync()
+    for k in range(3):
+        f = cv.folds[k]
+        res = f.trace()
+        res.update(f.model())
+        res["f"] = f.pred()
+        compare(res, dict(prob, val_mask=(fold == k).astype(np.uint8)))
+    cv.close()
