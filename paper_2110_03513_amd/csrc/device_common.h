@@ -42,6 +42,19 @@ __device__ __forceinline__ float neg_gradient(int loss, float y, float f) {
   return y - 1.0f / (1.0f + expf(-f));
 }
 
+// Row loss for the row pass's risk partials: the binomial softplus term
+// log(1 + e^-|f|) in FP32 (relative error about 1e-7, and the term is
+// below log 2), its linear part max(f, 0) - y f exact in FP64.
+__device__ __forceinline__ double row_loss(int loss, float y, float f) {
+  const double fd = (double)f, yd = (double)y;
+  if (loss == CWB_L2) {
+    const double e = yd - fd;
+    return 0.5 * e * e;
+  }
+  const float t = log1pf(expf(-fabsf(f)));
+  return (double)t + ((fd > 0.0 ? fd : 0.0) - yd * fd);
+}
+
 __device__ __forceinline__ double loss_value(int loss, float y, float f) {
   const double fd = (double)f, yd = (double)y;
   if (loss == CWB_L2) {
@@ -203,6 +216,7 @@ __device__ __forceinline__ void stage(T* dst, const T* src, int count) {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef long long i64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void load8f(const float* p, float* v) {
   const GLOBAL f32x4* q = (const GLOBAL f32x4*)p;

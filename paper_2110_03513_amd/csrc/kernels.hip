@@ -158,7 +158,7 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
           it.fold ? (int)(((j < 4 ? fold_lo : fold_hi) >> (8 * (j & 3))) & 0xffu) != it.fold_k
                   : i < it.n_train;
       if (live) {
-        const double L = loss_value(it.loss, yv[j], fj);
+        const double L = row_loss(it.loss, yv[j], fj);
         if (train) risk_t += L; else risk_v += L;
         if (!isfinite(fj) || !isfinite(hj)) bad = true;
       }
@@ -213,22 +213,27 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
 // ---------------------------------------------------------------------------
 namespace {
 
-// Deterministic sum of risk partials of the row-pass blocks.
-__device__ double sum_partials(const double* part, int count, int stride, int offset,
-                               double* red) {
-  const GLOBAL double* g = gp(part);
-  double s = 0.0;
+// This thread's share of the deterministic sums of the row-pass risk
+// partials (training rows, validation rows); block_sum completes them.
+__device__ void risk_shares(const double* part, int count, double* st, double* sv) {
+  const GLOBAL f64x2* g = (const GLOBAL f64x2*)gp(part);
+  double a = 0.0, b = 0.0;
   for (int b0 = 0; b0 < count; b0 += 4 * kSelectThreads) {
-    double v[4];
+    f64x2 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int b = b0 + u * kSelectThreads + (int)threadIdx.x;
-      v[u] = (b < count) ? g[(size_t)b * stride + offset] : 0.0;
+      const int i = b0 + u * kSelectThreads + (int)threadIdx.x;
+      if (i < count) v[u] = g[i];
+      else v[u].x = v[u].y = 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s += v[u];
+    for (int u = 0; u < 4; ++u) {
+      a += v[u].x;
+      b += v[u].y;
+    }
   }
-  return block_sum<kSelectThreads>(s, red);
+  *st = a;
+  *sv = b;
 }
 
 }  // namespace
@@ -317,6 +322,9 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       }
     }
   }
+  // learner 0's block: its shares of the risk sums, in the same round
+  double risk_t = 0.0, risk_v = 0.0;
+  if (it.k == 0) risk_shares(it.risk_part, it.n_row_blocks, &risk_t, &risk_v);
   const int n_stage = n_off < kMaxSlots ? n_off : kMaxSlots;
   {
     stage<kSelectThreads, 2>(s_off[0], (const long long*)it.offs, n_stage);
@@ -337,8 +345,8 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   if (it.k == 0) {
     // learner 0's block: the risk of f^[P] from this iteration's row pass,
     // and the count and kind of this selection for the next row pass
-    const double rt = sum_partials(it.risk_part, it.n_row_blocks, 2, 0, s_part);
-    const double rv = sum_partials(it.risk_part, it.n_row_blocks, 2, 1, s_part);
+    const double rt = block_sum<kSelectThreads>(risk_t, s_part);
+    const double rv = block_sum<kSelectThreads>(risk_v, s_part);
     if (threadIdx.x == 0) {
       it.tr_risk[P] = rt / (double)it.n_train;
       it.tr_val[P] = (it.n > it.n_train) ? rv / (double)(it.n - it.n_train) : 0.0;
@@ -407,6 +415,7 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       const int j = t / kChunks, c = t % kChunks;
       const int lo = s_jr[2 * j], hi = s_jr[2 * j + 1];
       double acc = 0.0;
+#pragma unroll 4
       for (int l = lo + c; l <= hi; l += kChunks)
         acc += B.bval[(size_t)l * kMaxBand + (j - B.bstart[l])] * s_bins[l];
       s_part[t] = acc;
@@ -460,7 +469,9 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
     for (int l = threadIdx.x; l < nb; l += kSelectThreads) {
       const int b0 = B.bstart[l];
       double t = 0.0;
-      for (int b = 0; b < band; ++b) t += B.bval[(size_t)l * kMaxBand + b] * s_th[b0 + b];
+#pragma unroll
+      for (int b = 0; b < kMaxBand; ++b)
+        if (b < band) t += B.bval[(size_t)l * kMaxBand + b] * s_th[b0 + b];
       tab[l] = (float)t;
     }
     __syncthreads();
@@ -554,8 +565,10 @@ __global__ void __launch_bounds__(kSelectThreads) k_finalize(const FitDev* __res
   const FitDev& F = fits[blockIdx.x];
   Ctl* ctl = F.ctl;
   const int S = ctl->sel_done;
-  const double rt = sum_partials(F.risk_part, F.n_row_blocks, 2, 0, s_red);
-  const double rv = sum_partials(F.risk_part, F.n_row_blocks, 2, 1, s_red);
+  double st = 0.0, sv = 0.0;
+  risk_shares(F.risk_part, F.n_row_blocks, &st, &sv);
+  const double rt = block_sum<kSelectThreads>(st, s_red);
+  const double rv = block_sum<kSelectThreads>(sv, s_red);
   if (threadIdx.x == 0) {
     F.tr_risk[S] = rt / (double)F.n_train;
     F.tr_val[S] = (F.n > F.n_train) ? rv / (double)(F.n - F.n_train) : 0.0;
