@@ -213,6 +213,46 @@ __device__ __forceinline__ void stage(T* dst, const T* src, int count) {
   }
 }
 
+// The first pass of a stage(), split in two so that a block can issue the
+// loads of several arrays before storing any of them: each array then costs
+// one memory round trip in total, not one after the other.  Elements past
+// the first pass (NT * U) are left to stage_rest().
+template <int NT, int U, typename T>
+struct StagePass {
+  T v[U];
+  __device__ __forceinline__ void load(const T* src, int count) {
+    const GLOBAL T* g = gp(src);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = u * NT + (int)threadIdx.x;
+      if (i < count) v[u] = g[i];
+    }
+  }
+  // the same, with zeros past `count` (for reductions over the values)
+  __device__ __forceinline__ void load_or_zero(const T* src, int count) {
+    const GLOBAL T* g = gp(src);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = u * NT + (int)threadIdx.x;
+      if (i < count) v[u] = g[i];
+      else v[u] = T();
+    }
+  }
+  __device__ __forceinline__ void store(T* dst, int count) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = u * NT + (int)threadIdx.x;
+      if (i < count) dst[i] = v[u];
+    }
+  }
+};
+
+// stage() of the elements from `first` on.
+template <int NT, int U, typename T>
+__device__ __forceinline__ void stage_rest(T* dst, const T* src, int count, int first) {
+  if (count > first) stage<NT, U>(dst + first, src + first, count - first);
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef long long i64x2 __attribute__((ext_vector_type(2)));

@@ -214,11 +214,13 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
 namespace {
 
 // This thread's share of the deterministic sums of the row-pass risk
-// partials (training rows, validation rows); block_sum completes them.
-__device__ void risk_shares(const double* part, int count, double* st, double* sv) {
+// partials (training rows, validation rows), continued from the partials
+// before `first` (a multiple of 4 * kSelectThreads) already in *st, *sv;
+// block_sum completes them.
+__device__ void risk_shares(const double* part, int count, double* st, double* sv, int first = 0) {
   const GLOBAL f64x2* g = (const GLOBAL f64x2*)gp(part);
-  double a = 0.0, b = 0.0;
-  for (int b0 = 0; b0 < count; b0 += 4 * kSelectThreads) {
+  double a = *st, b = *sv;
+  for (int b0 = first; b0 < count; b0 += 4 * kSelectThreads) {
     f64x2 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -300,18 +302,67 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       }
     }
   }
-  // one round of independent loads: control block, signal maxima, offsets,
-  // the learner's tables for the training-row Gram set
-  const int P = it.ctl->pick_done;  // = iterations before this selection
-  const int switched = it.ctl->switched;
+  // one round of independent loads: control block, signal maxima, (learner
+  // 0) risk partials, offsets and the learner's tables for the training-row
+  // Gram set.  Every load of the round is issued before the first use of
+  // any: the memory counter drains in order, so consuming a load waits for
+  // every load issued before it.
+  constexpr int NT = kSelectThreads;
+  const GLOBAL Ctl* ctl = gp(it.ctl);
+  const int P = ctl->pick_done;  // = iterations before this selection
+  const int switched = ctl->switched;
+  StagePass<NT, 4, f32x2> pm;  // per row-pass block: largest |r|, |c|
+  StagePass<NT, 4, f64x2> pr;  // per row-pass block: training, validation risk
+  pm.load_or_zero((const f32x2*)it.amax_part, it.n_row_blocks);
+  if (it.k == 0) pr.load_or_zero((const f64x2*)it.risk_part, it.n_row_blocks);
+  const int n_stage = n_off < kMaxSlots ? n_off : kMaxSlots;
+  const long long* offs = (const long long*)it.offs;
+  const bool two = it.variant != CWB_CWB;
+  {
+    // the band starts always (the loops below index the design through
+    // them); the design values only when they fit.  First passes here (one
+    // round trip for the usual sizes: d <= 32, n* <= 1,024, up to 1,024
+    // row-pass blocks); longer arrays finish below.
+    StagePass<NT, 2, long long> po0, po1;
+    StagePass<NT, 4, double> pa, pg;
+    StagePass<NT, 1, int> pj;
+    StagePass<NT, 4, int> pb;
+    StagePass<NT, 16, double> pv;
+    po0.load(offs, n_stage);
+    if (two) po1.load(offs + n_off, n_stage);
+    pa.load(it.ainv[0], d * d);
+    pg.load(it.gram[0], d * d);
+    pj.load(it.jr, 2 * d);
+    pb.load(it.bstart, nb);
+    if (STAGED) pv.load(it.bval, nb * kMaxBand);
+    po0.store(s_off[0], n_stage);
+    if (two) po1.store(s_off[1], n_stage);
+    pa.store(s_ai, d * d);
+    pg.store(s_g, d * d);
+    pj.store(s_jr, 2 * d);
+    pb.store(s_bs, nb);
+    if (STAGED) pv.store(s_bv, nb * kMaxBand);
+  }
+  stage_rest<NT, 2>(s_off[0], offs, n_stage, 2 * NT);
+  if (two) stage_rest<NT, 2>(s_off[1], offs + n_off, n_stage, 2 * NT);
+  stage_rest<NT, 4>(s_ai, it.ainv[0], d * d, 4 * NT);
+  stage_rest<NT, 4>(s_g, it.gram[0], d * d, 4 * NT);
+  stage_rest<NT, 1>(s_jr, it.jr, 2 * d, NT);
+  stage_rest<NT, 4>(s_bs, it.bstart, nb, 4 * NT);
+  if (STAGED) stage_rest<NT, 16>(s_bv, it.bval, nb * kMaxBand, 16 * NT);
   float am0 = 0.0f, am1 = 0.0f;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    am0 = fmaxf(am0, pm.v[u].x);
+    am1 = fmaxf(am1, pm.v[u].y);
+  }
   {
     const GLOBAL f32x2* am = (const GLOBAL f32x2*)it.amax_part;
-    for (int b0 = 0; b0 < it.n_row_blocks; b0 += 4 * kSelectThreads) {
+    for (int b0 = 4 * NT; b0 < it.n_row_blocks; b0 += 4 * NT) {
       f32x2 v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int b = b0 + u * kSelectThreads + (int)threadIdx.x;
+        const int b = b0 + u * NT + (int)threadIdx.x;
         if (b < it.n_row_blocks) v[u] = am[b];
         else v[u].x = v[u].y = 0.0f;
       }
@@ -322,20 +373,16 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       }
     }
   }
-  // learner 0's block: its shares of the risk sums, in the same round
+  // learner 0's block: its shares of the risk sums (first pass in order,
+  // then the rest)
   double risk_t = 0.0, risk_v = 0.0;
-  if (it.k == 0) risk_shares(it.risk_part, it.n_row_blocks, &risk_t, &risk_v);
-  const int n_stage = n_off < kMaxSlots ? n_off : kMaxSlots;
-  {
-    stage<kSelectThreads, 2>(s_off[0], (const long long*)it.offs, n_stage);
-    if (it.variant != CWB_CWB) stage<kSelectThreads, 2>(s_off[1], (const long long*)it.offs + n_off, n_stage);
-    stage<kSelectThreads, 4>(s_ai, it.ainv[0], d * d);
-    stage<kSelectThreads, 4>(s_g, it.gram[0], d * d);
-    stage<kSelectThreads, 1>(s_jr, it.jr, 2 * d);
-    // the band starts always (the loops below index the design through
-    // them); the design values only when they fit
-    stage<kSelectThreads, 4>(s_bs, it.bstart, nb);
-    if (STAGED) stage<kSelectThreads, 16>(s_bv, it.bval, nb * kMaxBand);
+  if (it.k == 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      risk_t += pr.v[u].x;
+      risk_v += pr.v[u].y;
+    }
+    risk_shares(it.risk_part, it.n_row_blocks, &risk_t, &risk_v, 4 * NT);
   }
   if (P >= it.M) return;
   const bool hcwb_all = it.variant == CWB_HCWB && switched;
@@ -350,8 +397,8 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
     if (threadIdx.x == 0) {
       it.tr_risk[P] = rt / (double)it.n_train;
       it.tr_val[P] = (it.n > it.n_train) ? rv / (double)(it.n - it.n_train) : 0.0;
-      it.ctl->sel_done = P + 1;
-      it.ctl->sel_acwb = acwb ? 1 : 0;
+      gp(it.ctl)->sel_done = P + 1;
+      gp(it.ctl)->sel_acwb = acwb ? 1 : 0;
     }
   }
   if (hcwb_all) {  // HCWB after the switch: Grams over all rows
