@@ -507,3 +507,23 @@ def test_few_bin_learners_in_folds():
         res["f"] = f.pred()
         compare(res, dict(prob, val_mask=(fold == k).astype(np.uint8)))
     cv.close()
+
+
+@pytest.mark.parametrize("variant,loss", [("cwb", "l2"), ("acwb", "binomial")])
+def test_select_staging_past_one_pass(variant, loss):
+    """Sizes whose select-pass arrays take more than the first staging pass:
+    basis size 44 (44^2 Gram entries), 1,100 and 1,500 design points (band
+    starts and staged design values), and 1,075 row-pass blocks (signal
+    maxima and risk partials)."""
+    n = 2_200_003
+    rng = np.random.default_rng(141)
+    x = rng.uniform(-1, 3, (n, 3))
+    eta = np.sin(2 * x[:, 0]) + 0.3 * x[:, 1] ** 2
+    if loss == "l2":
+        y = eta + rng.normal(0, 0.5, n)
+    else:
+        y = (rng.uniform(size=n) < 1 / (1 + np.exp(-eta))).astype(np.float64)
+    prob = {"x": x, "y": y, "loss": loss, "nu": 0.2, "M": 12, "variant": variant, "gamma": 0.05}
+    prob.update(datagen.learner_specs(3, np.array([1500, 1100, 700]), df=5.0))
+    prob["n_knots"] = 40
+    compare(_run(prob), prob)
