@@ -50,30 +50,32 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   __shared__ Arg2 s_w[2][kStateThreads / 64];
   __shared__ int s_bad;
   const RowItem it = items[blockIdx.x];
-  // one round: the control block, the criteria of the last selection and
-  // this thread's rows of the model state
+  const int64_t base = it.base + (int64_t)threadIdx.x * kRowsPerThread;
+  const bool rows = base < it.n_pad;
+  const bool two = it.two != 0;
+  // One round of loads, none of the model state's behind a branch (a branch
+  // join makes the compiler wait for loads issued inside it): threads past
+  // the end read the last 8 rows and store nothing, and a one-signal fit,
+  // which keeps no h and c, reads f again there (cache hits).  The control
+  // block comes in through scalar loads, so testing it does not wait for
+  // the model state.
+  float f[8], yv[8], hv[8], cv[8], rr[8], cc[8];
+  const int64_t lb = rows ? base : it.n_pad - kRowsPerThread;
+  load8f((two ? it.h : it.fg) + lb, hv);
+  load8f((two ? it.c : it.fg) + lb, cv);
   double qv0 = INFINITY, qv1 = INFINITY;
   if ((int)threadIdx.x < it.p) {
     qv0 = gp(it.q)[threadIdx.x];
     qv1 = gp(it.q)[it.p + threadIdx.x];  // used only after an ACWB selection
   }
   Ctl* ctl = it.ctl;
-  const int S = ctl->sel_done;
-  const int fin = ctl->fin_done;
-  const int sel_acwb = ctl->sel_acwb;
-  const int switched = ctl->switched;
-  const int64_t base = it.base + (int64_t)threadIdx.x * kRowsPerThread;
-  const bool rows = base < it.n_pad;
-  const bool two = it.two != 0;
-  float f[8], yv[8], hv[8], cv[8], rr[8], cc[8];
-  if (rows) {
-    load8f(it.fg + base, f);
-    load8f(it.y + base, yv);
-    if (two) {
-      load8f(it.h + base, hv);
-      load8f(it.c + base, cv);
-    }
-  }
+  const GLOBAL Ctl* gctl = gp(it.ctl);
+  const int S = gctl->sel_done;
+  const int fin = gctl->fin_done;
+  const int sel_acwb = gctl->sel_acwb;
+  const int switched = gctl->switched;
+  load8f(it.fg + lb, f);
+  load8f(it.y + lb, yv);
   if (!final_mode && S >= it.M) {
     // all M selections made (a batch runs on for other fits): mark the fit
     // done for the histogram and select passes; finalize records the last
