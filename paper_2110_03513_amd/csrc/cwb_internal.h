@@ -182,6 +182,7 @@ struct SelItem {
   const int32_t* jr;
   const int64_t* offs;        // its histogram offsets: offs[sig * n_off + i]
   int64_t off0[kInlineOffs];  // the first offsets of signal 0, inline
+  int64_t off1[kInlineOffs];  // and of signal 1 (two-signal fits)
   double* q;                  // &q[k] (signal 1 at + p)
   double* theta;              // &theta[k * d_max] (signal 1 at + p * d_max)
   float* table;               // &table[k * nb_max] (signal 1 at + p * nb_max)

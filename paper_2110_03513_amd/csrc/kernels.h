@@ -13,7 +13,7 @@ hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items
 hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, bool folds,
                        bool copies, int blocks, size_t lds, const FitDev* fits, const Seg* segs,
                        const int64_t* blk, long long* partials);
-hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nb_max, int d_max,
+hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nsig, int nb_max, int d_max,
                          const long long* partials);
 hipError_t launch_valrisk(hipStream_t st, const FitDev* fits, const StateItem* items, int nitems,
                           int nb_max);

@@ -14,7 +14,7 @@
 //             for every learner k and design point l, s_kl = sum of r_i over
 //             the rows with ind_ki = l (binMatVec, Algorithm 1, first stage),
 //             and the same for c, as exact int64 fixed-point sums.
-//   k_select  one block per learner: merge the segment partials, v = Z^bT s
+//   k_select  one block per learner and signal: merge the segment partials, v = Z^bT s
 //             (second stage of binMatVec), theta = (G + lambda D)^-1 v with
 //             the cached inverse (Section 2.4), criterion
 //             q = theta^T G theta - 2 theta^T v, so SSE_k = r^T r + q_k
@@ -280,7 +280,7 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   extern __shared__ double s_dyn[];
   __shared__ double s_v[kMaxD], s_th[kMaxD], s_gt[kMaxD];
   __shared__ double s_part[kMaxD * kChunks];
-  __shared__ long long s_off[kNumSig][kMaxSlots];
+  __shared__ long long s_off[kMaxSlots];  // this signal's segment offsets
   __shared__ int s_jr[2 * kMaxD];
   __shared__ float s_red[kSelectThreads + 16];
   double* s_bins = s_dyn;
@@ -289,8 +289,11 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   int* s_bs = reinterpret_cast<int*>(s_g + (size_t)d_cap * d_cap);
   double* s_bv = reinterpret_cast<double*>(s_bs + ((nb_cap + 1) & ~1));
   const SelItem it = items[blockIdx.x];
+  // blockIdx.y is the signal this block solves (ACWB: 0 for r, 1 for c)
+  const int sig = (int)blockIdx.y;
+  if (sig > 0 && it.variant == CWB_CWB) return;
   const int d = it.d, nb = it.nb, band = it.band, n_off = it.n_off;
-  // the first chunk of signal 0's partials, loaded in the first round when
+  // the first chunk of the signal's partials, loaded in the first round when
   // its offsets are inline (bins 4t .. 4t+3 of every segment)
   const bool pre = n_off <= kInlineOffs && nb <= 4 * kSelectThreads;
   i64x2 pv[kInlineOffs][2];
@@ -298,7 +301,8 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
 #pragma unroll
     for (int i = 0; i < kInlineOffs; ++i) {
       if (i < n_off) {
-        const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + it.off0[i] + 4 * threadIdx.x);
+        const int64_t o = sig ? it.off1[i] : it.off0[i];
+        const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + o + 4 * threadIdx.x);
         pv[i][0] = src[0];
         pv[i][1] = src[1];
       }
@@ -316,37 +320,34 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   StagePass<NT, 4, f32x2> pm;  // per row-pass block: largest |r|, |c|
   StagePass<NT, 4, f64x2> pr;  // per row-pass block: training, validation risk
   pm.load_or_zero((const f32x2*)it.amax_part, it.n_row_blocks);
-  if (it.k == 0) pr.load_or_zero((const f64x2*)it.risk_part, it.n_row_blocks);
+  const bool book = it.k == 0 && sig == 0;  // the fit's risk bookkeeping
+  if (book) pr.load_or_zero((const f64x2*)it.risk_part, it.n_row_blocks);
   const int n_stage = n_off < kMaxSlots ? n_off : kMaxSlots;
-  const long long* offs = (const long long*)it.offs;
-  const bool two = it.variant != CWB_CWB;
+  const long long* offs = (const long long*)it.offs + (int64_t)sig * n_off;  // this signal's
   {
     // the band starts always (the loops below index the design through
     // them); the design values only when they fit.  First passes here (one
     // round trip for the usual sizes: d <= 32, n* <= 1,024, up to 1,024
     // row-pass blocks); longer arrays finish below.
-    StagePass<NT, 2, long long> po0, po1;
+    StagePass<NT, 2, long long> po0;
     StagePass<NT, 4, double> pa, pg;
     StagePass<NT, 1, int> pj;
     StagePass<NT, 4, int> pb;
     StagePass<NT, 16, double> pv;
     po0.load(offs, n_stage);
-    if (two) po1.load(offs + n_off, n_stage);
     pa.load(it.ainv[0], d * d);
     pg.load(it.gram[0], d * d);
     pj.load(it.jr, 2 * d);
     pb.load(it.bstart, nb);
     if (STAGED) pv.load(it.bval, nb * kMaxBand);
-    po0.store(s_off[0], n_stage);
-    if (two) po1.store(s_off[1], n_stage);
+    po0.store(s_off, n_stage);
     pa.store(s_ai, d * d);
     pg.store(s_g, d * d);
     pj.store(s_jr, 2 * d);
     pb.store(s_bs, nb);
     if (STAGED) pv.store(s_bv, nb * kMaxBand);
   }
-  stage_rest<NT, 2>(s_off[0], offs, n_stage, 2 * NT);
-  if (two) stage_rest<NT, 2>(s_off[1], offs + n_off, n_stage, 2 * NT);
+  stage_rest<NT, 2>(s_off, offs, n_stage, 2 * NT);
   stage_rest<NT, 4>(s_ai, it.ainv[0], d * d, 4 * NT);
   stage_rest<NT, 4>(s_g, it.gram[0], d * d, 4 * NT);
   stage_rest<NT, 1>(s_jr, it.jr, 2 * d, NT);
@@ -375,10 +376,10 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       }
     }
   }
-  // learner 0's block: its shares of the risk sums (first pass in order,
-  // then the rest)
+  // learner 0's signal-0 block: its shares of the risk sums (first pass in
+  // order, then the rest)
   double risk_t = 0.0, risk_v = 0.0;
-  if (it.k == 0) {
+  if (book) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       risk_t += pr.v[u].x;
@@ -390,8 +391,9 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   const bool hcwb_all = it.variant == CWB_HCWB && switched;
   const bool acwb = it.variant == CWB_ACWB || (it.variant == CWB_HCWB && !switched);
   const int nsig = acwb ? 2 : 1;
+  if (sig >= nsig) return;  // the fit fits one signal this iteration
   const int64_t n_fit = hcwb_all ? it.n : it.n_scan;
-  if (it.k == 0) {
+  if (book) {
     // learner 0's block: the risk of f^[P] from this iteration's row pass,
     // and the count and kind of this selection for the next row pass
     const double rt = block_sum<kSelectThreads>(risk_t, s_part);
@@ -411,13 +413,13 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   const Basis B = STAGED ? Basis{s_bv, s_bs} : Basis{it.bval, s_bs};
   block_max2<kSelectThreads>(am0, am1, s_red);
   const float amax[2] = {am0, am1};
-  for (int sig = 0; sig < nsig; ++sig) {
+  {  // this block's signal
     const double isc = ldexp(1.0, -scale_exponent(amax[sig], n_fit));
     // bin sums s_l: exact int64 merge of the group's segment partials
     for (int l0 = 0; l0 < nb; l0 += 4 * kSelectThreads) {
       long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
       const int l = l0 + 4 * threadIdx.x;
-      if (pre && sig == 0) {  // l0 == 0: the preloaded chunk
+      if (pre) {  // l0 == 0: the preloaded chunk
         if (l < nb) {
 #pragma unroll
           for (int i = 0; i < kInlineOffs; ++i) {
@@ -432,10 +434,10 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       } else
       for (int c0 = 0; c0 < n_off; c0 += kMaxSlots) {
         const int cnt = (n_off - c0) < kMaxSlots ? (n_off - c0) : kMaxSlots;
-        const long long* so = s_off[sig];
+        const long long* so = s_off;
         if (n_off > kMaxSlots) {  // more segments than the staged list holds
           __syncthreads();
-          stage<kSelectThreads, 2>(s_off[sig], (const long long*)(it.offs + (int64_t)sig * n_off + c0), cnt);
+          stage<kSelectThreads, 2>(s_off, offs + c0, cnt);
           __syncthreads();
         }
         if (l < nb) {
@@ -744,9 +746,10 @@ hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items
 }
 
 
-hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nb_max, int d_max,
-                         const long long* partials) {
+hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int nsig, int nb_max,
+                         int d_max, const long long* partials) {
   if (nitems <= 0) return hipSuccess;
+  if (nsig < 1 || nsig > kNumSig) return hipErrorInvalidValue;
   // static LDS of the kernel (incl. the selection step) stays below 16 KiB
   size_t lds = ((size_t)nb_max + 2 * (size_t)d_max * d_max) * sizeof(double) +
                (size_t)((nb_max + 1) & ~1) * sizeof(int);
@@ -779,7 +782,7 @@ hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int n
       int bpc = (int)(cu_lds / (per_block + o.stat));
       bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);  // 8 blocks of 4 waves fill a CU
       const int64_t slots = (int64_t)o.cus * bpc;
-      return (nitems + slots - 1) / slots;
+      return ((int64_t)nitems * nsig + slots - 1) / slots;
     };
     staged = rounds(lds + extra) <= rounds(lds);
   }
@@ -795,10 +798,10 @@ hipError_t launch_select(hipStream_t st, const SelItem* items, int nitems, int n
   }();
   (void)attr;
   if (staged)
-    hipLaunchKernelGGL(k_select<true>, dim3(nitems), dim3(kSelectThreads), lds, st, items,
+    hipLaunchKernelGGL(k_select<true>, dim3(nitems, nsig), dim3(kSelectThreads), lds, st, items,
                        partials, nb_max, d_max);
   else
-    hipLaunchKernelGGL(k_select<false>, dim3(nitems), dim3(kSelectThreads), lds, st, items,
+    hipLaunchKernelGGL(k_select<false>, dim3(nitems, nsig), dim3(kSelectThreads), lds, st, items,
                        partials, nb_max, d_max);
   return hipGetLastError();
 }

@@ -552,7 +552,7 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Sch
   HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.copies, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
-  HIP_TRY(launch_select(st, d_sel, n_sel, nb_max, d_max, d_part));
+  HIP_TRY(launch_select(st, d_sel, n_sel, S.nsig_max, nb_max, d_max, d_part));
   if (tm & 4) HIP_TRY(timer_mark(timed->t_select, st));
   if (n_val > 0) {
     HIP_TRY(launch_valrisk(st, d_fits, d_val, n_val, nb_max));
@@ -616,7 +616,10 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
   it.bstart = D.bstart + fd.bin_off;
   it.jr = D.jr + 2 * (int64_t)fd.coef_off;
   it.offs = d_sel_off + S.sel_begin[idx];
-  for (int i = 0; i < kInlineOffs && i < S.sel_n[idx]; ++i) it.off0[i] = S.sel_off[S.sel_begin[idx] + i];
+  for (int i = 0; i < kInlineOffs && i < S.sel_n[idx]; ++i) {
+    it.off0[i] = S.sel_off[S.sel_begin[idx] + i];
+    if (D.nsig_max == 2) it.off1[i] = S.sel_off[S.sel_begin[idx] + S.sel_n[idx] + i];
+  }
   it.q = D.q + k;
   it.theta = D.theta + (int64_t)k * D.d_max;
   it.table = D.table + (int64_t)k * D.nb_max;
