@@ -12,8 +12,9 @@
 //             round (one launch per kernel per iteration covers every fit);
 //             finished fits retire at the end of a round: their results are
 //             copied to the host and their arena space is released.
-// Uploads of newly admitted fits go through a second stream, so they overlap
-// the round that is running; the fits join the batch in the next round.
+// Uploads of newly admitted fits run on their own host thread and a second
+// stream, so neither the rounds nor the GPU wait for them; an uploaded fit
+// joins the batch at the next round boundary.
 // A fit's result does not depend on which other fits share its rounds: the
 // histograms are exact integer sums and every selection is per fit.
 #include <hip/hip_runtime.h>
@@ -128,12 +129,15 @@ struct cwb_server {
   char* base = nullptr;
 
   std::mutex mu;
-  std::condition_variable cv_setup, cv_dev;
+  std::condition_variable cv_setup, cv_dev, cv_up;
   bool stop = false;
+  bool stop_up = false;  // the upload thread ends (after the device thread)
   uint64_t next_ticket = 1;
   std::map<uint64_t, std::unique_ptr<Request>> reqs;  // every request not yet polled
   std::deque<Request*> setup_q;
   std::deque<Request*> ready_q;
+  std::deque<Request*> upload_q;   // admitted, for the upload thread
+  std::vector<Request*> uploaded;  // uploaded (or failed), to join at a round boundary
   Arena arena;
   int64_t submitted = 0, completed = 0, rejected = 0;
   int32_t in_flight = 0;
@@ -145,11 +149,16 @@ struct cwb_server {
 
   // device thread only
   std::vector<Request*> active;
+  std::vector<Request*> pending;   // admitted and not yet joined
   cwb_batch* batch = nullptr;
   size_t batch_off = 0, batch_bytes = 0;
+  // batch workspace set aside at admission for the grown set (active and
+  // pending fits), so that the pending fits can always join
+  bool have_res = false;
+  size_t res_off = 0, res_bytes = 0;
 
   std::vector<std::thread> workers;
-  std::thread dev;
+  std::thread dev, up;
 };
 
 namespace {
@@ -263,12 +272,20 @@ void fail_fit(cwb_server* s, Request* r, int status, const std::string& err) {
 
 // Replace the batch by one over the active fits.  The old batch is never run
 // again once a fit it covers has retired, so it is destroyed first.  The new
-// batch workspace comes from `reserved` when the admission step set space
-// aside, else from a fresh allocation.
-void rebuild_batch(cwb_server* s, bool have_res, size_t res_off, size_t res_bytes) {
+// batch workspace is a fresh allocation, else the admission reservation; the
+// reservation is spent or released once no admitted fit is pending.  If
+// neither holds the new set, the fits that have just joined (`joined`) wait
+// for a later round and the batch covers the others; only when nothing else
+// runs are they failed.
+void rebuild_batch(cwb_server* s, std::vector<Request*> joined) {
   if (s->batch) {
     cwb_batch_destroy(s->batch);
     s->batch = nullptr;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->batch_bytes) s->arena.release(s->batch_off, s->batch_bytes);
+    s->batch_bytes = 0;
   }
   std::vector<const FitShape*> shapes;
   std::vector<cwb_fit*> fits;
@@ -282,27 +299,47 @@ void rebuild_batch(cwb_server* s, bool have_res, size_t res_off, size_t res_byte
   bool ok = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->batch_bytes) s->arena.release(s->batch_off, s->batch_bytes);
-    s->batch_bytes = 0;
-    if (have_res && (rc || fits.empty() || need > res_bytes)) {
-      s->arena.release(res_off, res_bytes);
-      have_res = false;
-    }
     if (!rc && !fits.empty()) {
-      if (have_res) {
-        off = res_off;
-        need = res_bytes;
+      if (s->have_res && s->pending.empty() && need <= s->res_bytes) {
+        off = s->res_off;
+        need = s->res_bytes;
+        s->have_res = false;
         ok = true;
       } else {
         ok = s->arena.alloc(need, &off);
+        if (!ok && s->have_res && need <= s->res_bytes) {
+          off = s->res_off;
+          need = s->res_bytes;
+          s->have_res = false;
+          ok = true;
+        }
       }
       if (ok) {
         s->batch_off = off;
         s->batch_bytes = need;
       }
     }
+    if (s->have_res && s->pending.empty()) {
+      s->arena.release(s->res_off, s->res_bytes);
+      s->have_res = false;
+    }
   }
   if (fits.empty()) return;
+  if (!rc && !ok && !joined.empty() && joined.size() < s->active.size()) {
+    // no room with the newcomers: they wait (still admitted) for a later round
+    std::vector<Request*> keep;
+    for (Request* r : s->active)
+      if (std::find(joined.begin(), joined.end(), r) == joined.end()) keep.push_back(r);
+    s->active.swap(keep);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (Request* r : joined) r->stage = Stage::kAdmitted;
+      s->uploaded.insert(s->uploaded.end(), joined.begin(), joined.end());
+    }
+    for (Request* r : joined) s->pending.push_back(r);
+    rebuild_batch(s, {});
+    return;
+  }
   std::string err;
   if (rc) {
     err = cwb_last_error();
@@ -319,22 +356,63 @@ void rebuild_batch(cwb_server* s, bool have_res, size_t res_off, size_t res_byte
   }
 }
 
+// Upload thread: copies admitted fits into their arena space on the upload
+// stream while the rounds go on.
+void upload_worker(cwb_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_up.wait(lk, [&] { return s->stop_up || !s->upload_q.empty(); });
+      if (s->upload_q.empty()) return;  // stopping
+      r = s->upload_q.front();
+      s->upload_q.pop_front();
+    }
+    cwb_fit* f = nullptr;
+    int rc = CWB_OK;
+    std::string err;
+    try {
+      rc = fit_upload(r->shape, r->hf, s->base + r->off, r->footprint, s->upload, false, &f);
+      if (rc) err = cwb_last_error();
+    } catch (const std::bad_alloc&) {
+      rc = set_error(CWB_E_NO_MEMORY, "host allocation failed during upload");
+      err = cwb_last_error();
+    }
+    r->hf = HostFit();
+    if (!rc) f->stream = s->stream;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      r->fit = rc ? nullptr : f;
+      if (rc) {
+        r->status = rc;
+        r->err = err;
+      }
+      s->uploaded.push_back(r);
+    }
+    s->cv_dev.notify_one();
+  }
+}
+
 void device_loop(cwb_server* s) {
   (void)hipSetDevice(s->device);
   for (;;) {
-    // 1. admission, in arrival order, while slots and arena space last; the
-    //    batch workspace of the grown set is reserved at the same time
-    std::vector<Request*> admit;
-    size_t res_off = 0, res_bytes = 0;
-    bool have_res = false;
+    // 1. admission, in arrival order, while slots and arena space last: each
+    //    admitted fit's workspace, and the batch workspace of the grown set
+    //    (active and pending fits) as the new reservation
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_dev.wait(lk, [&] { return s->stop || !s->ready_q.empty() || !s->active.empty(); });
-      if (s->stop && s->active.empty()) break;
+      s->cv_dev.wait(lk, [&] {
+        if (!s->active.empty() || !s->uploaded.empty()) return true;
+        return s->pending.empty() && (s->stop || !s->ready_q.empty());
+      });
+      if (s->stop && s->active.empty() && s->pending.empty() && s->uploaded.empty()) break;
       std::vector<const FitShape*> shapes;
       for (Request* r : s->active) shapes.push_back(&r->fit->shape);
+      for (Request* r : s->pending) shapes.push_back(&r->shape);
+      bool any = false;
       while (!s->stop && !s->ready_q.empty() &&
-             (int)(s->active.size() + admit.size()) < s->cfg.max_slots) {
+             (int)(s->active.size() + s->pending.size()) < s->cfg.max_slots) {
         Request* r = s->ready_q.front();
         shapes.push_back(&r->shape);
         size_t bb = 0, off = 0, boff = 0;
@@ -347,20 +425,22 @@ void device_loop(cwb_server* s) {
           shapes.pop_back();
           break;  // first come, first served: later requests wait too
         }
-        if (have_res) s->arena.release(res_off, res_bytes);
-        res_off = boff;
-        res_bytes = bb;
-        have_res = true;
+        if (s->have_res) s->arena.release(s->res_off, s->res_bytes);
+        s->res_off = boff;
+        s->res_bytes = bb;
+        s->have_res = true;
         r->off = off;
         r->stage = Stage::kAdmitted;
         r->t_admit = now_s();
         s->in_flight += 1;
         s->ready_q.pop_front();
-        admit.push_back(r);
+        s->pending.push_back(r);
+        s->upload_q.push_back(r);
+        any = true;
       }
+      if (any) s->cv_up.notify_one();
     }
-    // 2. one round of the current batch, enqueued before the uploads so
-    //    that the copies overlap it
+    // 2. one round of the current batch
     int32_t q = 0;
     const double t_round = now_s();
     if (s->batch && !s->active.empty()) {
@@ -372,28 +452,7 @@ void device_loop(cwb_server* s) {
         for (Request* r : s->active) r->status = CWB_E_DEVICE, r->err = e;
       }
     }
-    // 3. uploads of the admitted fits
-    std::vector<Request*> joined;
-    for (Request* r : admit) {
-      cwb_fit* f = nullptr;
-      int rc = CWB_OK;
-      try {
-        rc = fit_upload(r->shape, r->hf, s->base + r->off, r->footprint, s->upload, false, &f);
-      } catch (const std::bad_alloc&) {
-        rc = set_error(CWB_E_NO_MEMORY, "host allocation failed during upload");
-      }
-      r->hf = HostFit();
-      if (rc) {
-        fail_fit(s, r, rc, cwb_last_error());
-        continue;
-      }
-      f->stream = s->stream;
-      r->fit = f;
-      std::lock_guard<std::mutex> lk(s->mu);
-      r->stage = Stage::kRunning;
-      joined.push_back(r);
-    }
-    // 4. end of the round: retire finished or failed fits
+    // 3. end of the round: retire finished or failed fits
     if (q > 0) {
       (void)hipStreamSynchronize(s->stream);
       const double t_end = now_s();
@@ -403,7 +462,7 @@ void device_loop(cwb_server* s) {
       s->t_last_round = t_end;
       s->rounds += 1;
     }
-    bool changed = !joined.empty();
+    bool changed = false;
     std::vector<Request*> keep;
     for (Request* r : s->active) {
       if (r->status != CWB_OK) {
@@ -417,14 +476,28 @@ void device_loop(cwb_server* s) {
       }
     }
     s->active.swap(keep);
-    for (Request* r : joined) s->active.push_back(r);
-    // 5. a new batch whenever the membership changed
-    if (changed) {
-      rebuild_batch(s, have_res, res_off, res_bytes);
-    } else if (have_res) {
+    // 4. uploaded fits join (their uploads are complete: fit_upload waits)
+    std::vector<Request*> got, joined;
+    {
       std::lock_guard<std::mutex> lk(s->mu);
-      s->arena.release(res_off, res_bytes);
+      got.swap(s->uploaded);
     }
+    for (Request* r : got) {
+      s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+      changed = true;
+      if (r->status != CWB_OK) {
+        fail_fit(s, r, r->status, r->err);
+        continue;
+      }
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        r->stage = Stage::kRunning;
+      }
+      s->active.push_back(r);
+      joined.push_back(r);
+    }
+    // 5. a new batch whenever the membership changed
+    if (changed) rebuild_batch(s, joined);
   }
   if (s->batch) {
     cwb_batch_destroy(s->batch);
@@ -433,6 +506,8 @@ void device_loop(cwb_server* s) {
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->batch_bytes) s->arena.release(s->batch_off, s->batch_bytes);
   s->batch_bytes = 0;
+  if (s->have_res) s->arena.release(s->res_off, s->res_bytes);
+  s->have_res = false;
 }
 
 }  // namespace
@@ -463,6 +538,7 @@ int cwb_server_create(const cwb_server_cfg* cfg, cwb_server** out) {
     const int nw = cfg->setup_threads > 0 ? cfg->setup_threads : 4;
     cwb_server* sp = s.get();
     for (int i = 0; i < nw; ++i) s->workers.emplace_back(setup_worker, sp);
+    s->up = std::thread(upload_worker, sp);
     s->dev = std::thread(device_loop, sp);
     *out = s.release();
     return CWB_OK;
@@ -590,6 +666,12 @@ void cwb_server_destroy(cwb_server* s) {
   }
   s->cv_dev.notify_all();
   if (s->dev.joinable()) s->dev.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop_up = true;
+  }
+  s->cv_up.notify_all();
+  if (s->up.joinable()) s->up.join();
   if (s->upload) (void)hipStreamDestroy(s->upload);
   delete s;
 }
