@@ -378,6 +378,9 @@ void upload_worker(cwb_server* s) {
     } catch (const std::bad_alloc&) {
       rc = set_error(CWB_E_NO_MEMORY, "host allocation failed during upload");
       err = cwb_last_error();
+    } catch (...) {
+      rc = set_error(CWB_E_DEVICE, "unexpected error during upload");
+      err = cwb_last_error();
     }
     r->hf = HostFit();
     if (!rc) f->stream = s->stream;

@@ -116,3 +116,27 @@ def test_server_reports_setup_errors_per_request():
     assert done[tb]["status"] == cwb.CWB_E_INVALID_ARG and "error" in done[tb]
     assert done[tg]["status"] == 0
     np.testing.assert_array_equal(done[tg]["k"], cwb.fit(good)["k"])
+
+
+def test_server_close_with_requests_in_flight():
+    """Closing while requests are queued, in setup, uploading or running:
+    queued ones are cancelled, admitted ones finish, and close returns."""
+    probs = _requests()
+    srv = cwb.Server(arena_bytes=1 << 30, max_slots=3, quantum=5)
+    for p in probs:
+        srv.submit(p)
+    t0 = time.time()
+    while srv.stats()["in_flight"] < 1:  # at least one admitted (uploading or running)
+        assert time.time() - t0 < 30.0, "no request was admitted"
+        time.sleep(0.001)
+    _say(f"closing with stats {srv.stats()}")
+    t0 = time.time()
+    srv.close()
+    _say(f"close took {time.time() - t0:.2f} s")
+    # a new server on the same device still works
+    srv = cwb.Server(arena_bytes=256 << 20, max_slots=2, quantum=10)
+    t = srv.submit(probs[0])
+    done = _drain(srv, [t])
+    srv.close()
+    assert done[t]["status"] == 0
+    np.testing.assert_array_equal(done[t]["k"], cwb.fit(probs[0])["k"])
