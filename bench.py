@@ -480,6 +480,38 @@ def copy_probe(torch, mib):
                       "launches": 5}), flush=True)
 
 
+def lds_probe(torch, cwb, args):
+    """The LDS histogram ceiling: the histogram pass's inner loop (1,024
+    threads, 4 learners per group, 8 rows per index load, the headline's 2e8
+    int64 atomics over 256 blocks) with its bin indices read from a 512 KiB
+    table in L2 instead of HBM.  Random bins (uniform over 1,000) and
+    bank-conflict-free bins (lane l of a wave always on bank pair l mod 32)."""
+    nb, learners, blocks = 1000, 4, 256
+    atomics = float(args.n) * args.p  # one per (row, learner)
+    steps = int(round(atomics / (blocks * 1024 * learners * 8)))
+    chunks = 1 << 15
+    rng = np.random.default_rng(77)
+    rand = rng.integers(0, nb, size=chunks * 8, dtype=np.int64)
+    lane = (np.arange(chunks) % 32)[:, None]
+    free = (32 * rng.integers(0, nb // 32, size=(chunks, 8)) + lane).reshape(-1)
+    out = {"atomics": blocks * 1024 * learners * 8 * steps, "blocks": blocks, "nb": nb}
+    for name, tab in (("random", rand), ("conflict_free", free)):
+        idx = torch.from_numpy(tab.astype(np.int16)).cuda()
+        acc = torch.zeros(blocks, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            cwb.probe_lds_hist(idx, nb, learners, steps, blocks, acc)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            cwb.probe_lds_hist(idx, nb, learners, steps, blocks, acc)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_us"] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -495,6 +527,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mise", action="store_true", help="skip the partial-effect MISE leg")
+    ap.add_argument("--no-lds-probe", action="store_true",
+                    help="skip the LDS histogram ceiling probe")
     ap.add_argument("--no-cv", action="store_true", help="skip the cross-validation leg")
     ap.add_argument("--cv-iters", type=int, default=200)
     ap.add_argument("--no-setup", action="store_true",
@@ -561,6 +595,12 @@ def main():
                         "method": "HIP events on the fit's stream around every k-th histogram "
                                   "launch of the timed region"},
     }
+    if not args.no_lds_probe:
+        lp = lds_probe(torch, cwb, args)
+        # the histogram pass against the LDS ceiling of the same atomics
+        lp["hist_us"] = round(h["hist_avg_us"], 2)
+        lp["ceiling_frac"] = round(lp["random_us"] / h["hist_avg_us"], 4)
+        out["lds_ceiling"] = lp
     if not args.no_setup:
         out["setup"] = setup_leg(prob, cwb)
     if not args.no_mise:

@@ -26,6 +26,7 @@ HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 SOURCES = [
     ("kernels.hip", DEVICE),
     ("hist.hip", DEVICE),
+    ("probe.hip", DEVICE),
     # the device binning rule must not fuse its distances either
     ("binning.hip", DEVICE + ["-ffp-contract=off"]),
     ("runtime.cpp", HOST),
