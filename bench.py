@@ -559,8 +559,8 @@ def main():
         os.environ.update({"CWB_HIST_NT": str(nt), "CWB_HIST_LDS_KB": str(kb),
                            "CWB_HIST_BPC": str(bpc)})
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(multi-GPU sharding is a design note only)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not "
+                                   "supported (sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -49,7 +49,7 @@ extern "C" {
 /* status codes */
 #define CWB_OK 0
 #define CWB_E_INVALID_ARG -1  /* bad size, value, pointer or call argument */
-#define CWB_E_UNSUPPORTED -2  /* valid request this build does not implement */
+#define CWB_E_UNSUPPORTED -2  /* valid request the library does not implement */
 #define CWB_E_NO_MEMORY -3    /* workspace too small / memory budget exceeded */
 #define CWB_E_DEVICE -4       /* HIP runtime error (message has the HIP text) */
 #define CWB_E_NUMERIC -5      /* singular penalised Gram, non-finite model state */

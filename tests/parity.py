@@ -9,9 +9,8 @@ near-tie: running the oracle on the GPU's sequence (forced), the oracle's
 SSE of the GPU's learner may exceed its own best by at most
     TIE_REL * |q_best| + TIE_ABS * r^T r,   q_best = SSE_best - r^T r,
 the error band of a criterion evaluated from FP32 model state (the FP32
-state drifts from the FP64 one by a few float ulps per iteration; see the
-near-tie discussion in the design notes).  f and the coefficients are then
-compared with the forced oracle run.
+state drifts from the FP64 one by a few float ulps per iteration).  f and
+the coefficients are then compared with the forced oracle run.
 """
 from __future__ import annotations
 
