@@ -306,3 +306,27 @@ def test_cv_rules():
                                      C.c_void_p(1 << 20), 1 << 40, None, C.byref(h))
         assert rc == cwb.CWB_E_INVALID_ARG
         assert "fold" in cwb.lib().cwb_last_error().decode()
+
+
+def test_probe_argument_checks():
+    """The LDS ceiling probe rejects bad arguments before touching the GPU."""
+    L = cwb.lib()
+    buf = (C.c_int64 * 64)()
+    p = C.cast(buf, C.c_void_p)
+    aligned = C.c_void_p((p.value + 15) // 16 * 16)
+    cases = [
+        (None, 64, 100, 1, 1, 1, p),         # null table
+        (aligned, 64, 100, 1, 1, 1, None),   # null output
+        (aligned, 24, 100, 1, 1, 1, p),      # 3 chunks: not a power of two
+        (aligned, 12, 100, 1, 1, 1, p),      # not a multiple of 8
+        (C.c_void_p(aligned.value + 2), 64, 100, 1, 1, 1, p),  # misaligned
+        (aligned, 64, 0, 1, 1, 1, p),        # nb below 1
+        (aligned, 64, 100, 5, 1, 1, p),      # more than 4 learners
+        (aligned, 64, 8192, 4, 1, 1, p),     # 256 KiB of LDS
+        (aligned, 64, 100, 1, 0, 1, p),      # no steps
+        (aligned, 64, 100, 1, 1, 0, p),      # no blocks
+    ]
+    for idx, n, nb, learners, steps, blocks, out in cases:
+        rc = L.cwb_probe_lds_hist(idx, n, nb, learners, steps, blocks, out, None)
+        assert rc == cwb.CWB_E_INVALID_ARG, (n, nb, learners, steps, blocks)
+        assert L.cwb_last_error().decode()
