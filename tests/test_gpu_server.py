@@ -28,10 +28,12 @@ def _requests():
         p = int(rng.integers(3, 25))
         v = variants[i % 3]
         loss = "l2" if i % 2 == 0 else "binomial"
+        cat = 2 if i in (3, 5) else 0  # categorical learners: the LDS-copies kernel variant
         prob = datagen.additive_problem(n, p, seed=7000 + i, n_informative=min(3, p), loss=loss,
                                         n_bins=int(np.sqrt(n)), M=int(rng.integers(30, 160)),
                                         variant=v, gamma=0.05 if v == "acwb" else 0.2,
-                                        patience=3, val_frac=0.2 if v == "hcwb" else 0.0)
+                                        patience=3, val_frac=0.2 if v == "hcwb" else 0.0,
+                                        n_cat=cat, n_informative_cat=min(cat, 1))
         out.append(prob)
     return out
 
