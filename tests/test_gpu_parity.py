@@ -197,6 +197,22 @@ def test_full_size_config2_first_iterations():
     compare(gpu, dict(prob, M=M))
 
 
+def test_full_size_config3_acwb_first_iterations():
+    """The ACWB benchmark workload at full size (n = 2e6, 150 numeric and 10
+    categorical learners, binomial), in the tile the benchmark tunes."""
+    prob = datagen.config3("acwb", M=300)
+    M = 15
+    _say("full-size ACWB n=2e6 p=160: 15 iterations on the GPU")
+    f = cwb.Fit(prob)
+    f.run(M)
+    f.sync()
+    gpu = f.trace()
+    gpu.update(f.model())
+    gpu["f"] = f.pred()
+    f.close()
+    compare(gpu, dict(prob, M=M))
+
+
 @pytest.mark.parametrize("nt,F,blocks,variant", [
     (512, 16, 8, "cwb"), (512, 7, 13, "acwb"), (256, 3, 5, "cwb"), (1024, 4, 9, "acwb"),
     (512, 5, 3, "hcwb"), (256, 1, 16, "cwb"), (512, 2, 7, "acwb")])
