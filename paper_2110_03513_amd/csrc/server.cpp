@@ -486,7 +486,8 @@ void device_loop(cwb_server* s) {
       got.swap(s->uploaded);
     }
     for (Request* r : got) {
-      s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+      const auto pos = std::find(s->pending.begin(), s->pending.end(), r);
+      if (pos != s->pending.end()) s->pending.erase(pos);
       changed = true;
       if (r->status != CWB_OK) {
         fail_fit(s, r, r->status, r->err);
