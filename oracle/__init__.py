@@ -100,7 +100,7 @@ class _Result(C.Structure):
         ("risk_train", C.c_double), ("risk_val", C.c_double),
         ("switch_iter", C.c_int32), ("own_switch", C.c_int32), ("f", C.c_double),
         ("coef_f", C.c_double), ("coef_h", C.c_double), ("rtr", C.c_double),
-        ("rtr_cor", C.c_double)]]
+        ("rtr_cor", C.c_double), ("sse_cor", C.c_double), ("seconds", C.c_double)]]
 
 
 def _arr(a, dtype, n=None):
@@ -165,7 +165,8 @@ def fit(problem: dict, force_k=None, force_kcor=None, force_switch: int = -1,
         "risk_train": np.zeros(M + 1), "risk_val": np.zeros(M + 1),
         "switch_iter": np.zeros(1, np.int32), "own_switch": np.zeros(1, np.int32),
         "f": np.zeros(n), "coef_f": np.zeros(sum_d), "coef_h": np.zeros(sum_d),
-        "rtr": np.zeros(M), "rtr_cor": np.zeros(M),
+        "rtr": np.zeros(M), "rtr_cor": np.zeros(M), "sse_cor": np.zeros(M),
+        "seconds": np.zeros(2),
     }
     res = _Result(**{name: _p(out[name], t._type_) for name, t in _Result._fields_})
     rc = lib.orc_fit(C.byref(pr), C.byref(res))
@@ -174,6 +175,7 @@ def fit(problem: dict, force_k=None, force_kcor=None, force_switch: int = -1,
     out["f0"] = float(out["f0"][0])
     out["switch_iter"] = int(out["switch_iter"][0])
     out["own_switch"] = int(out["own_switch"][0])
+    out["setup_s"], out["iter_s"] = (float(v) for v in out.pop("seconds"))
     return out
 
 

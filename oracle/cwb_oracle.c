@@ -367,6 +367,8 @@ typedef struct {
   double* coef_h;         /* sum d: aggregated momentum-model coefficients */
   double* rtr;            /* M: r^T r of the signal fitted by the primary learner */
   double* rtr_cor;        /* M: c^T c of the corrected signal (ACWB steps) */
+  double* sse_cor;        /* M: SSE of the selected correction learner (ACWB steps) */
+  double* seconds;        /* 2 or NULL: wall time of setup and of the M iterations */
 } orc_result;
 
 typedef struct {
@@ -735,8 +737,10 @@ int orc_fit(const orc_problem* pr, orc_result* res) {
   int32_t d_max, sum_d;
   orc_sizes(pr, &d_max, &sum_d);
   feat_t* F = NULL;
+  const double t_start = omp_get_wtime();
   rc = setup(pr, &F, pr->variant == ORC_HCWB, res);
   if (rc) return rc;
+  const double t_setup = omp_get_wtime();
 
   double* f = (double*)malloc(sizeof(double) * n);
   double* h = (double*)malloc(sizeof(double) * n);
@@ -790,6 +794,7 @@ int orc_fit(const orc_problem* pr, orc_result* res) {
       res->own_kcor[mi] = -1;
       res->gapcor[mi] = 0.0;
       res->rtr_cor[mi] = 0.0;
+      res->sse_cor[mi] = 0.0;
       for (int a = 0; a < d_max; ++a) res->thetacor[(size_t)mi * d_max + a] = 0.0;
     } else {
       /* ACWB step on the training rows (Algorithm 2). */
@@ -822,6 +827,7 @@ int orc_fit(const orc_problem* pr, orc_result* res) {
       res->own_kcor[mi] = pc.own;
       res->gapcor[mi] = pc.gap;
       res->rtr_cor[mi] = pc.rtr;
+      res->sse_cor[mi] = pc.sse;
       for (int a = 0; a < d_max; ++a) res->thetacor[(size_t)mi * d_max + a] = pc.theta[a];
     }
     res->k[mi] = pk.k;
@@ -843,6 +849,10 @@ int orc_fit(const orc_problem* pr, orc_result* res) {
   }
   if (pr->variant == ORC_HCWB && !switched && counter >= pr->patience && *res->own_switch < 0)
     *res->own_switch = M + 1;
+  if (res->seconds) {
+    res->seconds[0] = t_setup - t_start;
+    res->seconds[1] = omp_get_wtime() - t_setup;
+  }
   memcpy(res->f, f, sizeof(double) * n);
   memcpy(res->coef_f, th_f, sizeof(double) * sum_d);
   memcpy(res->coef_h, th_h, sizeof(double) * sum_d);

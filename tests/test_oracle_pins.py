@@ -525,3 +525,50 @@ def test_binary_categorical_empty_class_never_selected():
     np.testing.assert_allclose(out["f"], ref["f"], atol=1e-10)
     assert (out["k"] == 1).any()
     assert (out["theta"][out["k"] == 1, c - 1] == 0).all()
+
+
+# --- Initial constant (Section 2.3: f^[0] minimises the empirical risk) ------
+
+@pytest.mark.parametrize("loss", ["l2", "binomial"])
+@pytest.mark.parametrize("masked", [False, True])
+def test_initial_constant_is_stationary(loss, masked):
+    """f^[0] is the loss-optimal constant over the training rows, so the
+    pseudo-residuals at f^[0] sum to zero there (first-order condition, the
+    residual being the negative gradient pinned by finite differences above),
+    and the risk rises on either side of it."""
+    rng = np.random.default_rng(91 if loss == "l2" else 92)
+    n = 700
+    pr = _one_learner(n=n, seed=93, nb=30, loss=loss, M=1, nu=0.1, df=4.0)
+    if loss == "binomial":  # an unbalanced label mix, away from 1/2
+        pr["y"] = (rng.random(n) < 0.23).astype(float)
+    if masked:
+        pr["val_mask"] = (rng.random(n) < 0.3).astype(np.uint8)
+        pr["variant"] = "hcwb"
+    train = np.ones(n, bool) if not masked else pr["val_mask"] == 0
+    out = oracle.fit(pr)
+    f0 = out["f0"]
+    r = np.array([oracle.pseudo_residual(loss, yi, f0) for yi in pr["y"][train]])
+    assert abs(r.sum()) <= 1e-12 * train.sum()
+
+    def risk(c):
+        return sum(oracle.loss(loss, yi, c) for yi in pr["y"][train]) / train.sum()
+
+    for step in (1e-3, 1e-1):
+        assert risk(f0 - step) > risk(f0) and risk(f0 + step) > risk(f0)
+    assert abs(out["risk_train"][0] - risk(f0)) <= 1e-12 * abs(risk(f0))
+
+
+def test_correction_criterion_recorded():
+    """The correction learner's SSE is its own fit's: c = r in the first ACWB
+    iteration, so it equals the primary SSE there; it never exceeds c^T c,
+    and forcing the oracle's own correction sequence leaves gaps of zero."""
+    pr = datagen.tiny_problem(n=600, p=5, seed=95, n_bins=25, M=25, variant="acwb")
+    out = oracle.fit(pr)
+    assert out["sse_cor"][0] == out["sse"][0] and out["rtr_cor"][0] == out["rtr"][0]
+    assert (out["sse_cor"] <= out["rtr_cor"] * (1 + 1e-12)).all()
+    assert (out["gapcor"] >= 0).all()
+    again = oracle.fit(pr, force_k=out["k"], force_kcor=out["kcor"])
+    assert (again["gapcor"] == 0).all()
+    np.testing.assert_array_equal(again["sse_cor"], out["sse_cor"])
+    cwb = oracle.fit(dict(pr, variant="cwb"))
+    assert (cwb["sse_cor"] == 0).all() and (cwb["kcor"] == -1).all()
