@@ -66,7 +66,9 @@ def measured_traffic(tile: dict):
 def headline(args, torch, cwb, datagen):
     n, p, nb = args.n, args.p, 1000
     log(f"[bench] generating C2 input n={n} p={p}")
-    M = args.warmup + args.steps + args.profile_iters
+    # the workload's fit has M = 2,000 iterations; the timed window is inside
+    # it, and the rest runs after it for the selection-parity check
+    M = max(args.fit_iters, args.warmup + args.steps + args.profile_iters)
     prob = datagen.config2(n=n, p=p, M=M, n_bins=nb)
     t0 = time.perf_counter()
     fit = cwb.Fit(prob)
@@ -96,7 +98,13 @@ def headline(args, torch, cwb, datagen):
         ms, cnt = fit.kernel_time("select")
         sel_us = ms / max(cnt, 1) * 1e3
     fit.set_timing(0)
+    left = M - fit.iters_done
+    if left > 0:  # the rest of the fit, untimed, for the parity check
+        fit.run(left)
+        fit.sync()
     tr = fit.trace()
+    tr.update(fit.model())
+    tr["f"] = fit.pred()
     fit.close()
     per_iter = wall / args.steps
     iters_s = 1.0 / per_iter
@@ -240,15 +248,17 @@ def unbinned_leg(args, torch, cwb, datagen):
 
 def momentum_legs(args, torch, cwb, datagen):
     """ACWB and HCWB, binomial, at the full n = 2e6 (150 numeric + 10
-    categorical learners): iterations per second of each phase."""
+    categorical learners): iterations per second and the histogram pass's
+    algorithmic bandwidth of each phase, and the oracle on a window of the
+    first ACWB iterations."""
     out = {}
     for variant in ("acwb", "hcwb"):
         M = args.momentum_iters
         log(f"[bench] {variant}: n=2e6 p=160, {M} iterations")
         prob = datagen.config3(variant, M=M)
         n, p = prob["x"].shape
+        n_train = int(n - (prob["val_mask"].sum() if prob.get("val_mask") is not None else 0))
         fit = cwb.Fit(prob)
-        del prob
         tile = fit.tile()
         fit.run(10)
         fit.sync()
@@ -262,60 +272,156 @@ def momentum_legs(args, torch, cwb, datagen):
         tr = fit.trace()
         sw = tr["switch_iter"]
         fit.close()
-        two = 2.0 * n * p + 8.0 * n
-        rec = {"iters_s": round((M - 10) / wall, 2), "hist_avg_us": round(hist_ms * 1e3 / max(hist_n, 1), 2),
-               "hist_alg_gbs": round(two / (hist_ms / 1e3 / max(hist_n, 1)) / 1e9, 1),
-               "iterations": M, "tile": tile}
-        if variant == "hcwb":
+        rec = {"iters_s": round((M - 10) / wall, 2), "iterations": M, "tile": tile}
+        if variant == "acwb":
+            two = 2.0 * n * p + 8.0 * n  # both signals from one read of the indices
+            avg = hist_ms / 1e3 / max(hist_n, 1)
+            rec.update({"hist_avg_us": round(avg * 1e6, 2), "hist_alg_gbs": round(two / avg / 1e9, 1),
+                        "hist_frac": round(two / avg / 1e9 / HBM_PEAK_GBS, 4)})
+            if not args.no_cpu:
+                import oracle
+                w = args.momentum_oracle_iters
+                log(f"[bench] acwb: oracle, first {w} iterations on {oracle.max_threads()} threads")
+                o = oracle.fit(dict(prob, M=w))
+                rec["oracle_window"] = {
+                    "iterations": w, "iters_s": round(w / o["iter_s"], 3),
+                    "cores": oracle.max_threads(), "setup_s": round(o["setup_s"], 2),
+                    "k_match": int(np.sum(tr["k"][:w] == o["k"])),
+                    "kcor_match": int(np.sum(tr["kcor"][:w] == o["kcor"]))}
+                del o
+        else:
             rec["switch_iter"] = sw
-            if sw != -1:  # the CWB phase streams one signal: no single byte count
-                rec.pop("hist_alg_gbs")
+            if sw > 11:  # each phase timed on a fresh fit of the same input
+                fit = cwb.Fit(prob)
+                phases = {}
+                for name, iters, rows, sig in (("acwb_phase", sw - 1, n_train, 2),
+                                               ("cwb_phase", M - sw + 1, n, 1)):
+                    fit.set_timing(1)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    fit.run(iters)
+                    fit.sync()
+                    dt = time.perf_counter() - t0
+                    ms, cnt = fit.kernel_time("hist")
+                    avg = ms / 1e3 / max(cnt, 1)
+                    byt = 2.0 * rows * p + 4.0 * sig * rows
+                    phases[name] = {"iterations": iters, "iters_s": round(iters / dt, 2),
+                                    "hist_avg_us": round(avg * 1e6, 2),
+                                    "hist_alg_gbs": round(byt / avg / 1e9, 1),
+                                    "hist_frac": round(byt / avg / 1e9 / HBM_PEAK_GBS, 4),
+                                    "rows": rows, "signals": sig}
+                assert fit.trace()["switch_iter"] == sw
+                fit.close()
+                rec["phases"] = phases
+        del prob
         out[variant] = rec
     return out
 
 
-def cpu_baseline(args, prob, gpu_trace):
-    import oracle
-    iters = args.cpu_iters
-    cores = oracle.max_threads()
-    log(f"[bench] CPU oracle: {iters} iterations on {cores} threads")
-    t0 = time.perf_counter()
-    o1 = oracle.fit(dict(prob, M=1))
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    o = oracle.fit(dict(prob, M=1 + iters))
-    t_all = time.perf_counter() - t0
-    per_iter = max((t_all - t_setup) / iters, 1e-9)
-    m = min(len(gpu_trace["k"]), 1 + iters)
-    eq = gpu_trace["k"][:m] == o["k"][:m]
-    match = int(np.sum(eq))
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def rel_err(a, b) -> float:
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300)) if a.size else 0.0
+
+
+def parity_summary(gpu, ref, keys=("k",)) -> dict:
+    """Selection sequences (exact) and f, coefficients, per-iteration theta
+    and risk trace (relative to the oracle's infinity norm) of a GPU fit
+    against the oracle's fit of the same input."""
+    m = min(len(gpu["k"]), len(ref["k"]))
+    eq = np.ones(m, bool)
+    for key in keys:
+        eq &= np.asarray(gpu[key][:m]) == np.asarray(ref[key][:m])
     first = int(np.argmin(eq)) if not eq.all() else -1
-    gap = float(o["gap"][first]) if first >= 0 else None
-    del o1
-    # the same oracle on one thread, over a shorter window
+    out = {"iterations_compared": m, "k_match": int(np.sum(eq)), "first_mismatch": first,
+           "oracle_gap_at_mismatch": float(ref["gap"][first]) if first >= 0 else None}
+    if "f" in gpu and m == len(ref["k"]):
+        dm = gpu["theta"].shape[1]
+        out.update({"err_f": rel_err(gpu["f"], ref["f"]),
+                    "err_coef_f": rel_err(gpu["coef_f"], ref["coef_f"]),
+                    "err_theta": rel_err(gpu["theta"][:m], ref["theta"][:m, :dm]),
+                    "err_risk": rel_err(gpu["risk_train"][:m + 1], ref["risk_train"][:m + 1])})
+        out["within_1e-4"] = bool(first < 0 and max(out["err_f"], out["err_coef_f"],
+                                                    out["err_theta"], out["err_risk"]) <= 1e-4)
+    return out
+
+
+def cpu_baseline(args, prob, gpu):
+    """The FP64 oracle on the same input: the whole fit (all M iterations) on
+    every host core, timed without its setup and compared with the GPU's fit,
+    then a short window on one thread."""
+    import oracle
+    cores = oracle.max_threads()
+    M = int(prob["M"])
+    log(f"[bench] CPU oracle: the whole {M}-iteration fit on {cores} threads")
+    o = oracle.fit(prob)
+    par = parity_summary(gpu, o)
+    log(f"[bench] parity {par}")
+    cb = {"value": round(M / o["iter_s"], 4), "unit": "iters/s", "cores": cores, "kind": "oracle",
+          "sample": (f"FP64 C oracle, all {M} iterations of the same n={prob['x'].shape[0]} "
+                     f"p={prob['x'].shape[1]} fit ({o['iter_s']:.1f}s; setup excluded, "
+                     f"{o['setup_s']:.1f}s)"),
+          "cpu_model": cpu_model()}
+    del o
     one = None
-    if args.cpu_iters_1thread > 0:
-        k1 = args.cpu_iters_1thread
+    k1 = args.cpu_iters_1thread
+    if k1 > 0:
+        log(f"[bench] CPU oracle: {k1} iterations on one thread")
         oracle.set_threads(1)
         try:
-            t0 = time.perf_counter()
-            oracle.fit(dict(prob, M=1))
-            s1 = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            oracle.fit(dict(prob, M=1 + k1))
-            a1 = time.perf_counter() - t0
+            o1 = oracle.fit(dict(prob, M=k1))
         finally:
             oracle.set_threads(cores)
-        one = {"value": round(k1 / max(a1 - s1, 1e-9), 4), "unit": "iters/s", "cores": 1,
+        one = {"value": round(k1 / o1["iter_s"], 4), "unit": "iters/s", "cores": 1,
                "kind": "oracle",
-               "sample": (f"FP64 C oracle on one thread, iterations 2..{1 + k1} of the same input "
-                          f"(setup excluded, {s1:.1f}s)")}
-    return {
-        "value": round(1.0 / per_iter, 4), "unit": "iters/s", "cores": cores, "kind": "oracle",
-        "sample": (f"FP64 C oracle, iterations 2..{1 + iters} of the same n={prob['x'].shape[0]} "
-                   f"p={prob['x'].shape[1]} input (setup excluded, {t_setup:.1f}s)"),
-    }, {"iterations_compared": m, "k_match": match, "first_mismatch": first,
-        "oracle_gap_at_mismatch": gap}, one
+               "sample": (f"FP64 C oracle on one thread, iterations 1..{k1} of the same input "
+                          f"({o1['iter_s']:.1f}s; setup excluded, {o1['setup_s']:.1f}s)"),
+               "cpu_model": cpu_model()}
+    return cb, par, one
+
+
+def config1_leg(torch, cwb, datagen):
+    """The small parity workload (n = 10,000, p = 10, 100 bins, M = 500): the
+    GPU's whole fit (launch-latency bound, not on the roofline) against the
+    oracle's whole fit on one thread."""
+    import oracle
+    prob = datagen.config1(M=500)
+    log("[bench] config1: n=10000 p=10, 500 iterations")
+    fit = cwb.Fit(prob)
+    fit.run(10)
+    fit.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit.run(490)
+    fit.sync()
+    wall = time.perf_counter() - t0
+    gpu = fit.trace()
+    gpu.update(fit.model())
+    gpu["f"] = fit.pred()
+    fit.close()
+    cores = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o = oracle.fit(prob)
+        whole = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    return {"iters_s": round(490 / wall, 1), "ms_per_iter": round(wall / 490 * 1e3, 4),
+            "oracle_1thread": {"iters_s": round(500 / o["iter_s"], 1),
+                               "whole_fit_s": round(whole, 3), "setup_s": round(o["setup_s"], 3)},
+            "parity": parity_summary(gpu, o)}
 
 
 def batched(args, torch, cwb, datagen):
@@ -324,6 +430,7 @@ def batched(args, torch, cwb, datagen):
     probs = [datagen.config4_problem(s) for s in specs]
     stream = torch.cuda.Stream()
     t_batch = {}
+    hist = None
     for graphs in ("1", "0"):
         os.environ["CWB_GRAPH"] = graphs
         t0 = time.perf_counter()
@@ -331,11 +438,16 @@ def batched(args, torch, cwb, datagen):
         setup = time.perf_counter() - t0
         b = cwb.Batch(fits, stream=stream)
         tile = b.tile()
+        if graphs == "0":  # eager launches: time the batched histogram pass
+            fits[0].set_timing(1, args.timing_period)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.run(args.batch_iters)
         b.sync()
         t_batch[graphs] = time.perf_counter() - t0
+        if graphs == "0":
+            hist = fits[0].kernel_time("hist")
+            fits[0].set_timing(0)
         ks = [f.trace()["k"] for f in fits]
         b.close()
         for f in fits:
@@ -354,6 +466,12 @@ def batched(args, torch, cwb, datagen):
     for f in fits:
         f.close()
     bytes_iter = sum(2.0 * p["x"].shape[0] * p["x"].shape[1] for p in probs)
+    # algorithmic bytes of one batched histogram launch (every fit runs all
+    # M iterations): each fit's indices once, and its signals (two for ACWB)
+    hist_bytes = sum(2.0 * p["x"].shape[0] * p["x"].shape[1] +
+                     4.0 * p["x"].shape[0] * (2 if p["variant"] == "acwb" else 1) for p in probs)
+    hist_avg = hist[0] / 1e3 / max(hist[1], 1)
+    achieved = hist_bytes / hist_avg / 1e9
     tb = t_batch["1"]
     return {"fits": len(probs), "iters": args.batch_iters,
             "fits_per_s": round(len(probs) / tb, 3),
@@ -361,6 +479,11 @@ def batched(args, torch, cwb, datagen):
             "loop_fits_per_s": round(len(probs) / t_loop, 3),
             "speedup_vs_loop": round(t_loop / tb, 3),
             "index_gbs": round(bytes_iter * args.batch_iters / tb / 1e9, 1),
+            "roofline": {"bound": "hbm", "kernel": "batched histogram pass",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "hist_avg_us": round(hist_avg * 1e6, 2), "launches_timed": hist[1],
+                         "bytes_per_launch": hist_bytes},
             "tile": tile,
             "same_selections_as_alone": bool(same), "setup_s": round(setup, 2)}
 
@@ -519,10 +642,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=1200)
-    ap.add_argument("--cpu-iters-1thread", type=int, default=0,
-                    help="also time the oracle on one thread over this many iterations "
-                         "(its setup alone takes about 12 s at the headline shape)")
+    ap.add_argument("--fit-iters", type=int, default=2000,
+                    help="iterations of the headline fit (the timed window lies inside it; "
+                         "the whole fit is compared with the oracle)")
+    ap.add_argument("--cpu-iters-1thread", type=int, default=20,
+                    help="time the oracle on one thread over this many iterations (0: skip)")
+    ap.add_argument("--momentum-oracle-iters", type=int, default=20)
+    ap.add_argument("--no-config1", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -580,7 +706,7 @@ def main():
         "config": {"workload": (f"binned CWB, L2, n={args.n}, p={args.p}, 1000 bins, cubic "
                                 "P-splines d=24 df=5, nu=0.1 (synthetic, seed 2)"),
                    "n": args.n, "p": args.p, "n_bins": 1000, "variant": "cwb", "loss": "l2",
-                   "iterations_in_fit": args.warmup + args.steps + args.profile_iters},
+                   "iterations_in_fit": int(prob["M"])},
         "precision": "uint16 bin indices; int64 fixed-point histograms; fp32 model state; "
                      "fp64 merge, solves and selection",
         "hbm_gbs": round(h["iter_gbs"], 1),
@@ -614,6 +740,8 @@ def main():
             out["cpu_baseline_1thread"] = one
         out["parity"] = par
     del prob
+    if not args.no_config1 and not args.no_cpu:
+        out["config1"] = config1_leg(torch, cwb, datagen)
     if not args.no_unbinned:
         out["unbinned"] = unbinned_leg(args, torch, cwb, datagen)
     if not args.no_momentum:

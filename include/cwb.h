@@ -252,7 +252,10 @@ int cwb_fit_load_state(cwb_fit* f, const void* host_buf, size_t bytes);
  * (histogram pass), 2 = "state" (row pass), 4 = "select" (solve and
  * selection); 0 turns timing off.  Setting a mask resets the accumulation;
  * the query synchronises and returns the summed milliseconds and the number
- * of timed launches of the named kernel. */
+ * of timed launches of the named kernel.  When the first fit of a batch has
+ * timing on, the batch's eagerly launched iterations (not those replayed
+ * from a captured graph) are timed into that fit's timer: the launches
+ * then cover every fit of the batch. */
 int cwb_fit_set_timing(cwb_fit* f, int32_t mask);
 /* The same, timing only every `period`-th iteration (period >= 1): each
  * event pair costs a few microseconds of queue time, so sampling keeps the

@@ -1,6 +1,7 @@
 """Build libcwb.so (gfx950 HIP kernels + host runtime) in-tree with hipcc.
 
-Usage: python -m paper_2110_03513_amd.build
+Usage: python -m paper_2110_03513_amd.build [-v] [-i]
+  -v  print the commands;  -i  recompile only sources older than their object
 """
 from __future__ import annotations
 
@@ -35,8 +36,21 @@ SOURCES = [
 ]
 
 
-def _compile(src, flags, verbose):
+def _stale(src, out) -> bool:
+    """The object is missing or older than its source or any header here."""
+    if not os.path.exists(out):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC)
+                                        if h.endswith(".h")]
+    deps.append(os.path.join(HERE, "..", "include", "cwb.h"))
+    t = os.path.getmtime(out)
+    return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
+
+
+def _compile(src, flags, verbose, incremental=False):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    if incremental and not _stale(src, out):
+        return out
     cmd = [HIPCC] + COMMON + flags + ["-c", os.path.join(CSRC, src), "-o", out]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -46,10 +60,12 @@ def _compile(src, flags, verbose):
     return out
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with `incremental`, those whose object is
+    older than the source or a header) and link libcwb.so."""
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s[0], s[1], verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s[0], s[1], verbose, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
@@ -62,4 +78,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -1529,11 +1529,14 @@ int cwb_batch_run(cwb_batch* b, int32_t iters) {
   HIP_TRY(hipSetDevice(b->device));
   int most = 0;
   for (cwb_fit* f : b->fits) most = std::max(most, std::min(iters, f->shape.M - f->iters));
-  auto eager = [&]() {
+  // Eager launches are timed with the first fit's timer when its timing is
+  // on (the batch's kernels, not that fit's share); captured ones never are.
+  auto eager = [&](bool capturing = false) {
+    cwb_fit* timed = (!capturing && b->fits[0]->timing) ? b->fits[0] : nullptr;
     return enqueue_iteration(b->stream, b->d_fits, (int)b->fits.size(), b->sched, b->tune, b->d_st,
                              b->n_st, b->d_sel, b->n_sel, b->d_val, b->any_hcwb ? b->n_val : 0,
                              b->nb_max, b->d_max, b->d_segs, b->d_blk, b->d_sel_off,
-                             b->d_partials, nullptr);
+                             b->d_partials, timed);
   };
   int i = 0;
   // The first iteration runs eagerly; after it, chunks of kGraphIters
@@ -1551,7 +1554,7 @@ int cwb_batch_run(cwb_batch* b, int32_t iters) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
       int rc = CWB_OK;
-      for (int c = 0; c < kGraphIters && !rc; ++c) rc = eager();
+      for (int c = 0; c < kGraphIters && !rc; ++c) rc = eager(true);
       const hipError_t e = hipStreamEndCapture(b->stream, &g);
       if (rc) {
         if (g) (void)hipGraphDestroy(g);

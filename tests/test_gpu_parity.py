@@ -51,12 +51,47 @@ def test_scaled_config3_acwb_binomial():
 
 
 def test_scaled_config3_hcwb_binomial():
-    prob = datagen.config3("hcwb", n=200_000, M=200, n_num=30, n_cat=4, n_bins=1000)
-    prob["gamma"] = 0.3
-    prob["patience"] = 3
+    """HCWB at the paper's recommended momentum (gamma = 0.037) and patience
+    (pat_0 = 5) on the ACWB/HCWB workload scaled to n = 2e5: the switch
+    happens inside the run (at iteration 156 in the oracle), and the
+    sequence, including the switch iteration, equals the oracle's."""
+    prob = datagen.config3("hcwb", n=200_000, M=300, n_num=30, n_cat=4, n_bins=1000)
+    assert prob["gamma"] == 0.037 and prob["patience"] == 5
     gpu = _run(prob)
     d = compare(gpu, prob)
     _say(f"hcwb switch iteration {gpu['switch_iter']}")
+    assert 1 < gpu["switch_iter"] < 300 and d["same_sequence"]
+
+
+def test_batched_config4_sampled_fits_against_oracle():
+    """The batched workload as benchmarked (64 heterogeneous fits, M = 1,000,
+    one batch with autotuned tiles): four fits taken from the batched run,
+    the smallest of each (variant, loss) kind, against the oracle."""
+    import torch
+    specs = datagen.config4_specs(count=64, M=1000)
+    pick = {}
+    for i, s in enumerate(specs):
+        key = (s["variant"], s["loss"])
+        if key not in pick or s["n"] * s["p"] < specs[pick[key]]["n"] * specs[pick[key]]["p"]:
+            pick[key] = i
+    assert len(pick) == 4
+    _say("batched: 64 fits of the batched workload, M=1000")
+    fits = [cwb.Fit(datagen.config4_problem(s)) for s in specs]
+    b = cwb.Batch(fits, stream=torch.cuda.Stream())
+    b.run(1000)
+    b.sync()
+    for key, i in sorted(pick.items()):
+        prob = datagen.config4_problem(specs[i])
+        f = fits[i]
+        res = f.trace()
+        res.update(f.model())
+        res["f"] = f.pred()
+        _say(f"fit {i} {key} n={specs[i]['n']} p={specs[i]['p']} against the oracle")
+        d = compare(res, prob)
+        assert d["same_sequence"] and d["M"] == 1000
+    b.close()
+    for f in fits:
+        f.close()
 
 
 def test_hcwb_forced_switch_by_mirrored_validation_labels():
