@@ -188,6 +188,23 @@ typedef struct cwb_fit cwb_fit;
 int cwb_fit_create(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
                    cwb_fit** out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): cwb_fit_create
+ * with the fit's histogram partials (the scratch its histogram and select
+ * passes exchange) in a 64 MiB array of the library's own device memory
+ * instead of in `dev_ws`, which still holds every input and output.  The
+ * call allocates no device memory: setup runs on the host threads, the
+ * default tile shape is kept (no autotuning), and a workspace of
+ * cwb_workspace_bytes() is always large enough.  Each GPU has its own copy
+ * of the array, held until the process ends, and every fit created by this
+ * call on a GPU shares it: runs of two such fits must not overlap on one
+ * GPU (the caller orders them, e.g. on one stream), and batches, which keep
+ * their own partials, are unaffected.  Errors as cwb_fit_create, plus
+ * NO_MEMORY when the partials of the default tile exceed 64 MiB and
+ * UNSUPPORTED for setup = CWB_SETUP_DEVICE. */
+int cwb_fit_create_noalloc(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
+                           cwb_fit** out);
+
 /* Enqueue `iters` boosting iterations on the fit's stream and return
  * without waiting.  May be called repeatedly (the fit resumes where it
  * stopped); STATE if this would run past M. */

@@ -28,6 +28,7 @@ SOURCES = [
     ("kernels.hip", DEVICE),
     ("hist.hip", DEVICE),
     ("probe.hip", DEVICE),
+    ("noalloc.hip", DEVICE),
     # the device binning rule must not fuse its distances either
     ("binning.hip", DEVICE + ["-ffp-contract=off"]),
     ("runtime.cpp", HOST),

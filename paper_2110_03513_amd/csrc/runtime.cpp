@@ -840,9 +840,12 @@ int device_binning(const cwb_problem* pr, const FitShape& sh, HostFit& hf, const
 }
 
 int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
-               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device, const FoldSpec* fold) {
+               bool autotune, cwb_fit** out, const cwb_problem* bin_on_device, const FoldSpec* fold,
+               long long* scratch, size_t scratch_bytes) {
   if (fold && (!sh.external_x || sh.n_scan != sh.n || bin_on_device))
     return set_error(CWB_E_INVALID_ARG, "internal: fold fit shape");
+  if (scratch && (autotune || bin_on_device || fold))
+    return set_error(CWB_E_INVALID_ARG, "internal: scratch partials with tuning, device setup or folds");
   *out = nullptr;
   std::unique_ptr<cwb_fit> f(new cwb_fit());
   f->stream = stream;
@@ -855,13 +858,25 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   }
   f->tune = cands[0];
   f->n_cands = (int)cands.size();
-  f->lay = make_layout(sh, cap);
+  if (scratch) {
+    const size_t need = (size_t)cap.partial_words * sizeof(long long);
+    if (need > scratch_bytes)
+      return set_error(CWB_E_NO_MEMORY, "histogram partials need " + std::to_string(need) +
+                                            " bytes, above the static scratch of " +
+                                            std::to_string(scratch_bytes) + " bytes");
+    SchedCap in_ws = cap;
+    in_ws.partial_words = 0;  // the partials live in the scratch array
+    f->lay = make_layout(sh, in_ws);
+  } else {
+    f->lay = make_layout(sh, cap);
+  }
   if (ws_bytes < f->lay.total)
     return set_error(CWB_E_NO_MEMORY, "workspace too small: need " + std::to_string(f->lay.total) +
                                           " bytes, got " + std::to_string(ws_bytes));
   HIP_TRY(hipGetDevice(&f->device));
   f->ws = reinterpret_cast<char*>(dev_ws);
   f->ws_bytes = ws_bytes;
+  f->partials = scratch ? scratch : dptr<long long>(f->ws, f->lay.partials);
   if (bin_on_device) {
     const int rc = device_binning(bin_on_device, sh, hf, f->lay, f->ws, f->stream);
     if (rc) return rc;
@@ -1035,8 +1050,7 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   if (cands.size() > 1) {
     int best = 0;
     int rc = autotune_hist(st, f->d_fit, {&f->shape}, cands, cap, dptr<Seg>(ws, L.segs),
-                           dptr<int64_t>(ws, L.blk), dptr<long long>(ws, L.partials), &best,
-                           &f->tuned_us);
+                           dptr<int64_t>(ws, L.blk), f->partials, &best, &f->tuned_us);
     if (rc) return rc;
     Schedule S = build_schedule({&f->shape}, cands[best]);
     rc = fit_install(f.get(), cands[best], std::move(S));
@@ -1044,6 +1058,37 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   }
   *out = f.release();
   return CWB_OK;
+}
+
+int fit_create_with_scratch(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
+                            cwb_fit** out, long long* scratch, size_t scratch_bytes) {
+  try {
+    if (!out) return set_error(CWB_E_INVALID_ARG, "null output handle");
+    *out = nullptr;
+    if (!dev_ws) return set_error(CWB_E_INVALID_ARG, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+      return set_error(CWB_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (!scratch) return set_error(CWB_E_INVALID_ARG, "internal: no scratch array");
+    std::string err;
+    FitShape sh;
+    int rc = shape_from_problem(pr, &sh, &err);
+    if (rc) return set_error(rc, err);
+    if (pr->setup < CWB_SETUP_AUTO || pr->setup > CWB_SETUP_DEVICE)
+      return set_error(CWB_E_INVALID_ARG, "unknown setup mode");
+    if (pr->setup == CWB_SETUP_DEVICE)
+      return set_error(CWB_E_UNSUPPORTED, "the no-allocation fit runs its setup on the host");
+    HostFit hf;
+    rc = build_host_fit(pr, &hf, &err);
+    if (rc) return set_error(rc, err);
+    return fit_upload(sh, hf, dev_ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), false, out,
+                      nullptr, nullptr, scratch, scratch_bytes);
+  } catch (const std::bad_alloc&) {
+    return set_error(CWB_E_NO_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(CWB_E_INVALID_ARG, e.what());
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
 }
 
 }  // namespace cwb
@@ -1135,7 +1180,7 @@ int cwb_fit_run(cwb_fit* f, int32_t iters) {
                                dptr<StateItem>(ws, L.val_items), f->n_val, f->shape.nb_max,
                                f->shape.d_max,
                                dptr<Seg>(ws, L.segs), dptr<int64_t>(ws, L.blk),
-                               dptr<int64_t>(ws, L.sel_off), dptr<long long>(ws, L.partials), f);
+                               dptr<int64_t>(ws, L.sel_off), f->partials, f);
     if (rc) return rc;
   }
   f->iters += iters;

@@ -144,6 +144,8 @@ struct cwb_fit {
   double tuned_us = 0.0;  // histogram pass time of the chosen shape (0: not tuned)
   int batch_share = 1;    // fold group size in a batch (first fold: K, others 0)
   cwb::FitShape bshape;   // shape as seen by batch schedules (share = batch_share)
+  long long* partials = nullptr;  // histogram partials of solo runs: in the workspace,
+                                  // or in the library's static scratch array
 };
 
 struct cwb_batch {
@@ -199,9 +201,17 @@ int fit_footprint(const FitShape& sh, size_t* bytes, bool all);
 // iterations on the same stream.  With `bin_on_device` (the problem), the
 // host setup ran its first phase only and the binning pass runs on the
 // device first.
+// With `scratch` (device memory of `scratch_bytes` that the fit does not
+// own), the histogram partials of solo runs live there instead of in the
+// workspace, whose layout then leaves them out.
 int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, hipStream_t stream,
                bool autotune, cwb_fit** out, const cwb_problem* bin_on_device = nullptr,
-               const FoldSpec* fold = nullptr);
+               const FoldSpec* fold = nullptr, long long* scratch = nullptr,
+               size_t scratch_bytes = 0);
+// cwb_fit_create with the histogram partials in `scratch`: host setup, the
+// default tile shape, and no device allocation of any kind.
+int fit_create_with_scratch(const cwb_problem* pr, void* dev_ws, size_t ws_bytes, void* stream,
+                            cwb_fit** out, long long* scratch, size_t scratch_bytes);
 // Device bytes of the batch workspace (combined schedule, partials, work
 // lists) for fits of these shapes; 0 for none.
 int batch_footprint(const std::vector<const FitShape*>& shapes, size_t* bytes, bool all);

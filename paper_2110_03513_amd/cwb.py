@@ -81,6 +81,7 @@ _SIGNATURES = {
     "cwb_bin_feature": [_P, C.c_int64, C.c_int32, _P, _P],
     "cwb_workspace_bytes": [C.POINTER(cwb_problem), C.POINTER(C.c_size_t)],
     "cwb_fit_create": [C.POINTER(cwb_problem), _P, C.c_size_t, _P, C.POINTER(_P)],
+    "cwb_fit_create_noalloc": [C.POINTER(cwb_problem), _P, C.c_size_t, _P, C.POINTER(_P)],
     "cwb_fit_run": [_P, C.c_int32],
     "cwb_fit_sync": [_P],
     "cwb_fit_info": [_P, C.POINTER(cwb_info)],
@@ -233,19 +234,28 @@ def _stream_handle(stream):
 
 
 class Fit:
-    """One fit: workspace owned by a torch uint8 tensor on the current device."""
+    """One fit: workspace owned by a torch uint8 tensor on the current device.
+    With ``workspace`` (a torch uint8 CUDA tensor of at least
+    ``workspace_bytes`` bytes) the fit uses it instead of allocating one; with
+    ``noalloc`` it is created by cwb_fit_create_noalloc (histogram partials
+    in the library's static array)."""
 
-    def __init__(self, prob: dict, stream=None, device=None):
+    def __init__(self, prob: dict, stream=None, device=None, workspace=None, noalloc=False):
         torch = _torch()
         self.problem = Problem(prob)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(self.device):
-            nbytes = workspace_bytes(self.problem)
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if workspace is None:
+                nbytes = workspace_bytes(self.problem)
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            else:
+                self.ws = workspace
+                nbytes = workspace.numel()
             self._sh, self.stream = _stream_handle(stream)
             h = C.c_void_p()
-            check(lib().cwb_fit_create(C.byref(self.problem.c), C.c_void_p(self.ws.data_ptr()),
-                                       nbytes, self._sh, C.byref(h)))
+            create = lib().cwb_fit_create_noalloc if noalloc else lib().cwb_fit_create
+            check(create(C.byref(self.problem.c), C.c_void_p(self.ws.data_ptr()), nbytes, self._sh,
+                         C.byref(h)))
         self.h = h
         info = cwb_info()
         check(lib().cwb_fit_info(self.h, C.byref(info)))
