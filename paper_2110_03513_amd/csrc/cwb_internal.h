@@ -94,7 +94,11 @@ struct FitDev {
   int32_t nsig_max;      // 2 for ACWB / HCWB, else 1
   int32_t nb_stride;     // histogram words per learner and signal (a multiple of 4)
   int32_t unbinned;      // learners are unbinned cubic P-splines (X holds 32-bit codes)
-  int32_t pad_;
+  int32_t acc32_bits;    // > 0: the histogram values are rounded at the 32-bit
+                         // scale (scale_exponent32 with these bits) for every
+                         // learner; groups whose learners' bins all hold fewer
+                         // than 2^acc32_bits rows then take 32-bit LDS words.
+                         // 0: truncated at the int64 scale (scale_exponent).
   const uint16_t* X;
   const float* y;
   float* fg;
@@ -139,6 +143,11 @@ struct Seg {
   int32_t nf;      // learners in the group
   int16_t nfit;    // fits sharing the segment (1, or the number of folds)
   int16_t skip;    // the fold all of the segment's rows belong to, or -1
+  int32_t acc32;   // 1: every learner of the group keeps its sums in int32 (its
+                   // fit's acc32_bits bound its bins' counts), so the LDS
+                   // histograms take 32-bit words (two signals: one packed
+                   // 64-bit word); else 64-bit words per signal
+  int32_t pad;
   int64_t u0, u1;  // unit range within [0, n_pad / 8)
   int64_t slot;    // offset (int64 words) of the partial slot
 };
@@ -193,7 +202,9 @@ struct SelItem {
   int32_t k, nb, band, d;
   int32_t n_off, d_max, nb_max, p;
   int32_t M, variant, n_row_blocks, fit;
-  int32_t kind, pad_;         // learner kind (CWB_BINARY_CAT: best class only)
+  int32_t kind;               // learner kind (CWB_BINARY_CAT: best class only)
+  int32_t acc32_bits;         // its fit's: > 0, sums at the 32-bit scale
+                              // (scale_exponent32 with these bits), else int64
 };
 
 // Fixed-point exponent for the int64 histogram of a signal whose largest
@@ -211,6 +222,25 @@ inline int scale_exponent(float amax, int64_t n_fit) {
   int N = 0;
   for (int64_t v = n_fit; v > 0; v >>= 1) ++N;  // n_fit < 2^N
   return 62 - N - E;
+}
+
+// 32-bit accumulation.  When every bin of a learner holds fewer than 2^B
+// rows (B = acc32_bits), its residuals are rounded to integers below
+// 2^(31 - B) in magnitude: |r| * 2^e < 2^(31 - B), so no bin's sum, over any
+// subset of the rows, leaves the int32 range.  The LDS then takes 4-byte
+// atomics (one signal), or one 8-byte atomic carrying both ACWB signals
+// (r in the high word, c in the low word; see pack_signals).
+constexpr int kAcc32MaxBits = 12;  // at least 19 bits of resolution below max |r|
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline int scale_exponent32(float amax, int bits) {
+  if (!(amax > 0.0f)) return 0;
+  uint32_t b;
+  __builtin_memcpy(&b, &amax, 4);
+  const uint32_t ex = (b >> 23) & 0xffu;
+  const int E = (ex == 0u) ? -125 : (int)ex - 126;  // max |r| < 2^E
+  return 31 - bits - E;
 }
 
 // Learners with few bins (categorical levels, coarse binnings) get several

@@ -167,8 +167,40 @@ __device__ __forceinline__ void block_max2(float& m0, float& m1, float* red) {
   __syncthreads();
 }
 
+// Fixed-point exponents of a fit's two signals: at the int64 scale
+// (scale_exponent) and at the 32-bit scale (scale_exponent32).
+struct Exps {
+  int e[2];
+  int e32[2];
+};
+
 // Scale exponents of both signals of a fit: maxima over the row-pass
 // blocks' maxima (order-free, so every block computes the same values).
+template <int NT>
+__device__ void fit_exponents(const FitDev& F, int64_t n_fit, Exps* x, float* red) {
+  float a = 0.0f, b = 0.0f;
+  const GLOBAL float* am = gp(F.amax_part);
+  for (int b0 = 0; b0 < F.n_row_blocks; b0 += 4 * NT) {
+    float v[4], w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = b0 + u * NT + (int)threadIdx.x;
+      v[u] = (k < F.n_row_blocks) ? am[2 * k] : 0.0f;
+      w[u] = (k < F.n_row_blocks) ? am[2 * k + 1] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a = fmaxf(a, v[u]);
+      b = fmaxf(b, w[u]);
+    }
+  }
+  block_max2<NT>(a, b, red);
+  x->e[0] = scale_exponent(a, n_fit);
+  x->e[1] = scale_exponent(b, n_fit);
+  x->e32[0] = scale_exponent32(a, F.acc32_bits);
+  x->e32[1] = scale_exponent32(b, F.acc32_bits);
+}
+
 template <int NT>
 __device__ void fit_scale_exponents(const FitDev& F, int64_t n_fit, int* e0, int* e1, float* red) {
   float a = 0.0f, b = 0.0f;
@@ -409,6 +441,27 @@ __device__ Picked block_pick(const double* q_, int p, int nsig, double v0, doubl
   return r;
 }
 
+
+// r * 2^e rounded to the nearest integer (ties to even), as int32: the
+// 32-bit scale keeps |r| * 2^e below 2^30, and the scaling by a power of two
+// is exact, so this is the exact rounding of the product.
+__device__ __forceinline__ int fixed32(float r, int e) {
+  return (int)rintf(ldexpf(r, e));
+}
+
+// Both ACWB signals of a row in one 64-bit word: r's value times 2^32 plus
+// c's (two's complement).  A sum of such words is R 2^32 + C for the sums R
+// of the r values and C of the c values, so while |C| < 2^31 the low word
+// read as int32 is C, and R = (W - C) / 2^32 (unpack_signals).
+__device__ __forceinline__ unsigned long long pack_signals(int qr, int qc) {
+  return ((unsigned long long)(uint32_t)qr << 32) + (unsigned long long)(long long)qc;
+}
+
+__device__ __forceinline__ void unpack_signals(unsigned long long w, long long* R, long long* Cs) {
+  const long long c = (long long)(int32_t)(uint32_t)w;
+  *Cs = c;
+  *R = (long long)(w - (unsigned long long)c) >> 32;
+}
 
 // trunc(r * 2^e) as int64, from the bits of the float: r = +-m 2^(x-150)
 // with a 24-bit integer m, so the product is m shifted by x - 150 + e.

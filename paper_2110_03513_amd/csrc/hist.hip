@@ -34,6 +34,31 @@ __device__ __forceinline__ void hist_add(unsigned long long* __restrict__ h, con
   }
 }
 
+// 32-bit words: one signal's values, 4-byte LDS atomics.
+__device__ __forceinline__ void hist_add32(uint32_t* __restrict__ h, const u32x4& x, const int* q) {
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    __hip_atomic_fetch_add(h + (w[j] & 0xffffu), (uint32_t)q[2 * j], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(h + (w[j] >> 16), (uint32_t)q[2 * j + 1], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Packed words: both ACWB signals of a row in one 8-byte LDS atomic.
+__device__ __forceinline__ void hist_add_packed(unsigned long long* __restrict__ h, const u32x4& x,
+                                                const unsigned long long* q) {
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    __hip_atomic_fetch_add(h + (w[j] & 0xffffu), q[2 * j], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(h + (w[j] >> 16), q[2 * j + 1], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 __device__ __forceinline__ u32x4 load_idx(const uint16_t* p) {
   return __builtin_nontemporal_load((const GLOBAL u32x4*)p);
 }
@@ -50,16 +75,19 @@ __device__ __forceinline__ void hist_step_load(const FitDev& F, const uint16_t* 
     if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
 }
 
-// Rows [r0, r1) of one segment.  Every thread takes 8 consecutive rows per
-// step: one 32-byte load of residuals per signal and one 16-byte load of bin
-// indices per learner of the group, then 8 LDS atomics per learner and
-// signal.  The next step's loads are issued before this step's atomics.
-// With `need_e`, the fit's scale exponents are computed (by all threads)
-// while the first step's loads are in flight.
+// Rows [r0, r1) of one segment with 64-bit LDS words.  Every thread takes
+// 8 consecutive rows per step: one 32-byte load of residuals per signal and
+// one 16-byte load of bin indices per learner of the group, then 8 LDS
+// atomics per learner and signal.  The next step's loads are issued before
+// this step's atomics.  The values are at the fit's scale: rounded at the
+// 32-bit one when the fit has acc32_bits, else truncated at the int64 one,
+// the same for every learner and group.  With `need_e`, the fit's scale
+// exponents are computed (by all threads) while the first step's loads are
+// in flight.
 template <int NT, int FMAX, int NSIG, bool COPIES>
 __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
                                           unsigned long long* __restrict__ hist, int nb,
-                                          int64_t r0, int64_t r1, int& e0, int& e1, bool need_e,
+                                          int64_t r0, int64_t r1, Exps& ex, bool need_e,
                                           int64_t n_fit, float* red, const int (*cp)[16]) {
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
   const int nf = sg.nf;
@@ -70,22 +98,33 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
     cm[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[0][f]) : 0;
     cs[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[1][f]) : 0;
   }
+  const bool r32 = F.acc32_bits > 0;
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
   const bool any = base < r1;
   float rv[8], cv[8];
   u32x4 xw[FMAX];
   if (any) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
-  if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, red);
+  if (need_e) fit_exponents<NT>(F, n_fit, &ex, red);
   if (!any) return;
+  const int e0 = r32 ? ex.e32[0] : ex.e[0], e1 = r32 ? ex.e32[1] : ex.e[1];
   for (;;) {
     const int64_t nxt = base + (int64_t)NT * 8;
     const bool more = nxt < r1;
     long long q0[8], q1[8];
+    if (r32) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e0);
-    if (NSIG == 2) {
+      for (int j = 0; j < 8; ++j) q0[j] = (long long)fixed32(rv[j], e0);
+      if (NSIG == 2) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e1);
+        for (int j = 0; j < 8; ++j) q1[j] = (long long)fixed32(cv[j], e1);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e0);
+      if (NSIG == 2) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e1);
+      }
     }
     u32x4 xc[FMAX];
 #pragma unroll
@@ -98,6 +137,56 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
         const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;  // this lane's copy
         hist_add<NSIG>(hist + (size_t)f * nb + cb, xc[f], q0);
         if (NSIG == 2) hist_add<NSIG>(hist + (size_t)(nf + f) * nb + cb, xc[f], q1);
+      }
+    }
+    if (!more) break;
+    base = nxt;
+  }
+}
+
+// Rows [r0, r1) of a segment whose learners all take 32-bit accumulation
+// (Seg.acc32).  One signal: 4-byte words, learner f at word f * nb.  Two
+// signals: both values of a row packed into one 8-byte word (pack_signals),
+// learner f at word f * nb, so an ACWB row costs one LDS atomic per
+// learner, as a CWB row does.
+template <int NT, int FMAX, int NSIG>
+__device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void* __restrict__ hist,
+                                            int nb, int64_t r0, int64_t r1, Exps& ex, bool need_e,
+                                            int64_t n_fit, float* red) {
+  const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
+  const int nf = sg.nf;
+  const size_t ld = (size_t)F.n_pad;
+  int64_t base = r0 + (int64_t)threadIdx.x * 8;
+  const bool any = base < r1;
+  float rv[8], cv[8];
+  u32x4 xw[FMAX];
+  if (any) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
+  if (need_e) fit_exponents<NT>(F, n_fit, &ex, red);
+  if (!any) return;
+  const int g0 = ex.e32[0], g1 = ex.e32[1];
+  uint32_t* __restrict__ h32 = static_cast<uint32_t*>(hist);
+  unsigned long long* __restrict__ h64 = static_cast<unsigned long long*>(hist);
+  for (;;) {
+    const int64_t nxt = base + (int64_t)NT * 8;
+    const bool more = nxt < r1;
+    int p0[8];
+    unsigned long long pk[8];
+    if (NSIG == 1) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) p0[j] = fixed32(rv[j], g0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pk[j] = pack_signals(fixed32(rv[j], g0), fixed32(cv[j], g1));
+    }
+    u32x4 xc[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
+    if (more) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, nxt, rv, cv, xw);
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f) {
+      if (f < nf) {
+        if (NSIG == 1) hist_add32(h32 + (size_t)f * nb, xc[f], p0);
+        else hist_add_packed(h64 + (size_t)f * nb, xc[f], pk);
       }
     }
     if (!more) break;
@@ -257,7 +346,7 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
   __shared__ int s_cp[2][16];  // binned learners of the segment: copy mask, copy stride
   const int64_t s0 = blk[2 * blockIdx.x], s1 = blk[2 * blockIdx.x + 1];
   int cached_fit = -1;
-  int e0 = 0, e1 = 0;
+  Exps ex{};
   for (int64_t s = s0; s < s1; ++s) {
     const Seg sg = segs[s];
     const FitDev& F = fits[sg.fit];
@@ -267,8 +356,10 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const int nsig = is_acwb_step(F, switched) ? 2 : 1;
     const int64_t n_fit = rows_fitted(F, switched);
     const int nb = F.nb_stride;
-    const int words = sg.nfit * nsig * sg.nf * nb;
-    for (int i = threadIdx.x; i < words; i += NT) s_hist[i] = 0ull;
+    const bool w32 = !UNB && !FOLDS && sg.acc32 != 0;  // 32-bit (or packed) LDS words
+    const int words = sg.nfit * nsig * sg.nf * nb;     // 64-bit LDS words, and partial words
+    const int lds_words = w32 ? (nsig == 1 ? (sg.nf * nb + 1) / 2 : sg.nf * nb) : words;
+    for (int i = threadIdx.x; i < lds_words; i += NT) s_hist[i] = 0ull;
     if (COPIES && (int)threadIdx.x < sg.nf) {
       int st = 0;
       s_cp[0][threadIdx.x] = copy_mask(F.feat[sg.k0 + threadIdx.x].nb, nb, &st);
@@ -298,20 +389,38 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
       else
         hist_rows_folds<NT, FMAX, NSMAX, COPIES>(fits, sg, s_hist, nb, r0, r1, s_e, s_cp);
     } else if (UNB) {
-      if (need_e) fit_scale_exponents<NT>(F, n_fit, &e0, &e1, s_red);
+      if (need_e) fit_exponents<NT>(F, n_fit, &ex, s_red);
       if (NSMAX == 1 || nsig == 1)
-        uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, e0, 0);
+        uhist_rows<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, ex.e[0], 0);
       else
-        uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, e0, e1);
+        uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, ex.e[0], ex.e[1]);
+    } else if (w32) {
+      if (NSMAX == 1 || nsig == 1)
+        hist_rows32<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+      else
+        hist_rows32<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
     } else {
       if (NSMAX == 1 || nsig == 1)
-        hist_rows<NT, FMAX, 1, COPIES>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red, s_cp);
+        hist_rows<NT, FMAX, 1, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       else
-        hist_rows<NT, FMAX, NSMAX, COPIES>(F, sg, s_hist, nb, r0, r1, e0, e1, need_e, n_fit, s_red, s_cp);
+        hist_rows<NT, FMAX, NSMAX, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
     }
     __syncthreads();
     GLOBAL long long* out = gp(partials + sg.slot);
-    if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
+    if (w32) {  // 32-bit sums to int64 partials, in the 64-bit layout
+      const int nw = sg.nf * nb;
+      if (nsig == 1) {
+        const uint32_t* h32 = reinterpret_cast<const uint32_t*>(s_hist);
+        for (int i = threadIdx.x; i < nw; i += NT) out[i] = (long long)(int32_t)h32[i];
+      } else {
+        for (int i = threadIdx.x; i < nw; i += NT) {
+          long long R, Cs;
+          unpack_signals(s_hist[i], &R, &Cs);
+          out[i] = R;        // signal 0 of learner i / nb, bin i % nb
+          out[nw + i] = Cs;  // signal 1 at (nf + f) * nb + b
+        }
+      }
+    } else if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
       const int d = F.d_max;
       for (int i = threadIdx.x; i < nsig * sg.nf * d; i += NT) {
         const int lf = i / d, b = i - lf * d;

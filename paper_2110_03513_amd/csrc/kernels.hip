@@ -414,7 +414,10 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   block_max2<kSelectThreads>(am0, am1, s_red);
   const float amax[2] = {am0, am1};
   {  // this block's signal
-    const double isc = ldexp(1.0, -scale_exponent(amax[sig], n_fit));
+    // the histogram pass's scale for this learner: 32-bit (rounded) or int64
+    const int e = it.acc32_bits > 0 ? scale_exponent32(amax[sig], it.acc32_bits)
+                                    : scale_exponent(amax[sig], n_fit);
+    const double isc = ldexp(1.0, -e);
     // bin sums s_l: exact int64 merge of the group's segment partials
     for (int l0 = 0; l0 < nb; l0 += 4 * kSelectThreads) {
       long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;

@@ -204,6 +204,14 @@ int segment_fold(const FitShape& sh, int64_t r0, int64_t r1) {
   return -1;
 }
 
+// 1 if every learner of [k0, k0 + nf) takes 32-bit accumulation.
+int group_acc32(const FitShape& sh, int k0, int nf) {
+  if ((int)sh.acc32.size() != sh.p || sh.acc32_bits < 1 || sh.acc32_bits > kAcc32MaxBits) return 0;
+  for (int k = k0; k < k0 + nf; ++k)
+    if (!sh.acc32[k]) return 0;
+  return 1;
+}
+
 Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t) {
   Schedule S;
   struct Item {
@@ -241,6 +249,9 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       }
     }
   }
+  // the fold variant of the histogram pass keeps int64 accumulators
+  bool any_folds = false;
+  for (const Item& it : items) any_folds = any_folds || it.nfit > 1;
   const int B = t.blocks > 0 ? t.blocks : std::max(1, t.cus * t.blocks_per_cu);
   S.blocks = B;
   std::vector<int64_t> seg_vb;
@@ -265,6 +276,8 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       sg.nf = it.nf;
       sg.nfit = (int16_t)it.nfit;
       sg.skip = -1;
+      sg.acc32 = any_folds ? 0 : group_acc32(*fits[it.fit], it.k0, it.nf);
+      sg.pad = 0;
       if (it.nfit > 1) {
         int64_t r0, r1;
         unit_rows(*fits[it.fit], u, ue, &r0, &r1);
@@ -406,6 +419,11 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
     if (sg.nf < 1 || sg.nf > t.F || sg.nf > t.fmax || sg.k0 < 0 || sg.k0 + sg.nf > sh.p ||
         sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
     if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
+    if (sg.acc32 != 0 && (sg.acc32 != 1 || sg.nfit != 1 || S.folds || sh.unbinned ||
+                          group_acc32(sh, sg.k0, sg.nf) != 1)) {
+      *why = "32-bit group";
+      return false;
+    }
     if (sg.slot != slot_end) { *why = "slot order"; return false; }
     const int64_t words = (int64_t)sg.nfit * sh.nsig_max * sg.nf * sh.nb_stride;
     slot_end += words;
@@ -642,6 +660,7 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
   it.n_row_blocks = D.n_row_blocks;
   it.fit = fit;
   it.kind = fd.kind;
+  it.acc32_bits = D.acc32_bits;
   return it;
 }
 
@@ -883,6 +902,31 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   }
   f->f0 = hf.f0;
   f->perm = std::move(hf.perm);
+  // 32-bit histogram accumulation, now that the bins are counted: a binned
+  // learner without LDS copies whose fullest bin holds fewer than
+  // 2^kAcc32MaxBits rows (CWB_ACC32=0 keeps int64 sums throughout)
+  if (!sh.unbinned && !fold && env_int("CWB_ACC32", 1) != 0) {
+    std::vector<uint8_t> acc(sh.p, 0);
+    int bits = 0;
+    for (int j = 0; j < sh.p; ++j) {
+      const HostLearner& hl = hf.L[j];
+      int N = 0;
+      for (int64_t v = hl.cnt_max; v > 0; v >>= 1) ++N;  // cnt_max < 2^N
+      int stride = 0;
+      if (hl.nb > 0 && hl.cnt_max > 0 && N <= kAcc32MaxBits && copy_mask(hl.nb, sh.nb_stride, &stride) == 0) {
+        acc[j] = 1;
+        bits = std::max(bits, N);
+      }
+    }
+    if (bits > 0) {
+      f->shape.acc32 = std::move(acc);
+      f->shape.acc32_bits = bits;
+      f->sched = build_schedule({&f->shape}, f->tune);
+      std::string why;
+      if (!schedule_is_valid(f->sched, {&f->shape}, f->tune, &why))
+        return set_error(CWB_E_INVALID_ARG, "internal schedule error: " + why);
+    }
+  }
   const Layout& L = f->lay;
   char* ws = f->ws;
   hipStream_t st = f->stream;
@@ -951,6 +995,7 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   D.nsig_max = sh.nsig_max;
   D.nb_stride = sh.nb_stride;
   D.unbinned = sh.unbinned ? 1 : 0;
+  D.acc32_bits = f->shape.acc32_bits;
   if (sh.unbinned != hf.unbinned)
     return set_error(CWB_E_INVALID_ARG, "learner kinds disagree with the specification");
   D.X = fold ? fold->X : dptr<uint16_t>(ws, L.X);

@@ -33,6 +33,11 @@ struct FitShape {
   // fold group head: first row of each fold's block (share + 1 entries, the
   // last n); segments are split at these rows so that most hold one fold
   std::vector<int64_t> fold_start;
+  // per learner, known after setup (empty before, and for unbinned fits and
+  // folds): 1 if its histogram sums fit 32-bit fixed point (every bin holds
+  // fewer than 2^acc32_bits rows and the learner takes no LDS copies)
+  std::vector<uint8_t> acc32;
+  int acc32_bits = 0;
 };
 
 // First schedule unit whose rows (as the histogram pass maps units onto the

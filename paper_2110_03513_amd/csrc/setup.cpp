@@ -425,6 +425,10 @@ int learner_algebra(const cwb_learner_spec& s, int64_t n, HostLearner& L,
                     const std::vector<double>& cnt_t, const std::vector<double>& cnt_a,
                     const std::vector<double>* G_unb, int j, std::string* err) {
   const int d = L.d;
+  // the largest bin count over all rows bounds every histogram sum of the
+  // learner (32-bit histogram accumulation)
+  L.cnt_max = 0;
+  for (double c : cnt_a) L.cnt_max = std::max(L.cnt_max, (int64_t)c);
   // support ranges: design points whose band covers basis index q
   L.jr.assign((size_t)2 * d, 0);
   for (int q = 0; q < d; ++q) {

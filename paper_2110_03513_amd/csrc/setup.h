@@ -45,6 +45,7 @@ struct HostLearner {
   std::vector<double> ainv[2];   // d x d, [0] training rows, [1] all rows
   std::vector<double> gram[2];
   double lambda[2] = {0, 0};
+  int64_t cnt_max = 0;           // binned: the largest bin count over all rows
 };
 
 struct HostFit {
