@@ -165,4 +165,30 @@ hipError_t launch_bin(hipStream_t st, const double* x, const int32_t* perm, int6
   return hipGetLastError();
 }
 
+// 12-bit copy of the bin-index matrix for the histogram pass: every 8
+// consecutive uint16 indices (16 bytes, all below 4,096) become 3 words,
+// index j in bits [12 j, 12 j + 12) of the 96.  `groups` = p n_pad / 8;
+// group t is X[8t, 8t + 8) -> X12[3t, 3t + 3), so every learner's row of
+// n_pad indices maps to n_pad / 8 * 3 contiguous words.
+__global__ void __launch_bounds__(kSetupThreads)
+k_pack12(const uint16_t* __restrict__ X, int64_t groups, uint32_t* __restrict__ X12) {
+  for (int64_t t = (int64_t)blockIdx.x * kSetupThreads + threadIdx.x; t < groups;
+       t += (int64_t)gridDim.x * kSetupThreads) {
+    const uint4 v = *reinterpret_cast<const uint4*>(X + 8 * t);
+    const uint32_t a[8] = {v.x & 0xfffu, (v.x >> 16) & 0xfffu, v.y & 0xfffu, (v.y >> 16) & 0xfffu,
+                           v.z & 0xfffu, (v.z >> 16) & 0xfffu, v.w & 0xfffu, (v.w >> 16) & 0xfffu};
+    X12[3 * t] = a[0] | (a[1] << 12) | (a[2] << 24);
+    X12[3 * t + 1] = (a[2] >> 8) | (a[3] << 4) | (a[4] << 16) | (a[5] << 28);
+    X12[3 * t + 2] = (a[5] >> 4) | (a[6] << 8) | (a[7] << 20);
+  }
+}
+
+hipError_t launch_pack12(hipStream_t st, const uint16_t* X, int64_t groups, uint32_t* X12) {
+  if (groups <= 0) return hipSuccess;
+  const int64_t want = (groups + kSetupThreads - 1) / kSetupThreads;
+  const int blocks = (int)(want < 65536 ? want : 65536);
+  hipLaunchKernelGGL(k_pack12, dim3(blocks), dim3(kSetupThreads), 0, st, X, groups, X12);
+  return hipGetLastError();
+}
+
 }  // namespace cwb

@@ -144,23 +144,54 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
   }
 }
 
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+
+// The 8 bin indices of one 12-byte word triple of the 12-bit copy of X, in
+// the 16-bit layout of a uint16 load (two indices per word), so the same
+// adders serve both.
+__device__ __forceinline__ u32x4 unpack12(const u32x3& w) {
+  u32x4 o;
+  o.x = (w.x & 0xfffu) | (((w.x >> 12) & 0xfffu) << 16);
+  o.y = __builtin_amdgcn_alignbit(w.y, w.x, 24) & 0xfffu;
+  o.y |= ((w.y >> 4) & 0xfffu) << 16;
+  o.z = ((w.y >> 16) & 0xfffu) | ((__builtin_amdgcn_alignbit(w.z, w.y, 28) & 0xfffu) << 16);
+  o.w = ((w.z >> 8) & 0xfffu) | ((w.z >> 20) << 16);
+  return o;
+}
+
 // Rows [r0, r1) of a segment whose learners all take 32-bit accumulation
 // (Seg.acc32).  One signal: 4-byte words, learner f at word f * nb.  Two
 // signals: both values of a row packed into one 8-byte word (pack_signals),
 // learner f at word f * nb, so an ACWB row costs one LDS atomic per
-// learner, as a CWB row does.
-template <int NT, int FMAX, int NSIG>
+// learner, as a CWB row does.  With X12 the indices come from the 12-bit
+// copy of X: 12 bytes instead of 16 per 8 rows and learner.
+template <int NT, int FMAX, int NSIG, bool X12>
 __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void* __restrict__ hist,
                                             int nb, int64_t r0, int64_t r1, Exps& ex, bool need_e,
                                             int64_t n_fit, float* red) {
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
+  const size_t ld12 = (size_t)F.n_pad / 8 * 3;  // words per learner in the 12-bit copy
+  const uint32_t* __restrict__ Xp = X12 ? F.X12 + (size_t)sg.k0 * ld12 : nullptr;
   const int nf = sg.nf;
   const size_t ld = (size_t)F.n_pad;
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
   const bool any = base < r1;
   float rv[8], cv[8];
   u32x4 xw[FMAX];
-  if (any) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, base, rv, cv, xw);
+  u32x3 xp[FMAX];
+  auto load = [&](int64_t b) {
+    if (!X12) {
+      hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, b, rv, cv, xw);
+      return;
+    }
+    load8f(F.r + b, rv);
+    if (NSIG == 2) load8f(F.c + b, cv);
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f)
+      if (f < nf)
+        xp[f] = __builtin_nontemporal_load((const GLOBAL u32x3*)(Xp + f * ld12 + (size_t)(b >> 3) * 3));
+  };
+  if (any) load(base);
   if (need_e) fit_exponents<NT>(F, n_fit, &ex, red);
   if (!any) return;
   const int g0 = ex.e32[0], g1 = ex.e32[1];
@@ -180,8 +211,8 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
     }
     u32x4 xc[FMAX];
 #pragma unroll
-    for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
-    if (more) hist_step_load<FMAX, NSIG>(F, Xg, ld, nf, nxt, rv, cv, xw);
+    for (int f = 0; f < FMAX; ++f) xc[f] = X12 ? unpack12(xp[f]) : xw[f];
+    if (more) load(nxt);
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) {
       if (f < nf) {
@@ -395,10 +426,17 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
       else
         uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, ex.e[0], ex.e[1]);
     } else if (w32) {
-      if (NSMAX == 1 || nsig == 1)
-        hist_rows32<NT, FMAX, 1>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
-      else
-        hist_rows32<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+      if (F.X12) {
+        if (NSMAX == 1 || nsig == 1)
+          hist_rows32<NT, FMAX, 1, true>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+        else
+          hist_rows32<NT, FMAX, NSMAX, true>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+      } else {
+        if (NSMAX == 1 || nsig == 1)
+          hist_rows32<NT, FMAX, 1, false>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+        else
+          hist_rows32<NT, FMAX, NSMAX, false>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+      }
     } else {
       if (NSMAX == 1 || nsig == 1)
         hist_rows<NT, FMAX, 1, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);

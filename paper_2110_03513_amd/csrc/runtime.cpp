@@ -97,6 +97,7 @@ int shape_from_problem(const cwb_problem* pr, FitShape* sh, std::string* err) {
   if (sh->unbinned) sh->nb_stride = (kUnbCopies * sh->d_max + 3) / 4 * 4;
   int st = 0;
   sh->copies = !sh->unbinned && copy_mask(nb_min, sh->nb_stride, &st) != 0;
+  sh->x12 = !sh->unbinned && sh->nb_max <= 4096;
   sh->n_row_blocks = (int)((sh->n_pad + kStateRows - 1) / kStateRows);
   const int64_t nv = sh->n - sh->n_train;
   sh->n_val_blocks = (sh->variant == CWB_HCWB && nv > 0) ? (int)((nv + kStateRows - 1) / kStateRows) : 0;
@@ -489,6 +490,7 @@ Layout make_layout(const FitShape& sh, const SchedCap& s) {
   L.state_end = align_up(off, 256);
   // inputs and tables
   L.X = take(sh.external_x ? 0 : (size_t)sh.p * np * (sh.unbinned ? 4 : 2));
+  L.X12 = take(sh.x12 && !sh.external_x ? (size_t)sh.p * np / 8 * 12 : 0);
   L.y = take(np * 4);
   L.r = take(np * 4);
   L.feat = take((size_t)sh.p * sizeof(FeatDev));
@@ -999,6 +1001,10 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   if (sh.unbinned != hf.unbinned)
     return set_error(CWB_E_INVALID_ARG, "learner kinds disagree with the specification");
   D.X = fold ? fold->X : dptr<uint16_t>(ws, L.X);
+  // the 12-bit copy serves the 32-bit histogram groups only
+  const bool pack12 = sh.x12 && !fold && !sh.external_x && f->shape.acc32_bits > 0 &&
+                      env_int("CWB_X12", 1) != 0;
+  D.X12 = pack12 ? dptr<uint32_t>(ws, L.X12) : nullptr;
   if (fold) {
     D.fold = fold->fold;
     D.fold_k = fold->k;
@@ -1055,6 +1061,9 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.XU.data(), hf.XU.size() * 4, hipMemcpyHostToDevice, st));
   else if (!bin_on_device && !fold)  // else X is in place already (device pass, shared folds)
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
+  if (pack12)
+    HIP_TRY(launch_pack12(st, dptr<uint16_t>(ws, L.X), (int64_t)sh.p * sh.n_pad / 8,
+                          dptr<uint32_t>(ws, L.X12)));
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
   HIP_TRY(hipMemcpyAsync(ws + L.feat, feat.data(), feat.size() * sizeof(FeatDev), hipMemcpyHostToDevice, st));
@@ -1748,6 +1757,7 @@ int cv_plan(const cwb_problem* pr, int32_t K, const int32_t* fold, CvPlan* pl) {
     return set_error(CWB_E_UNSUPPORTED, "the folds' histograms of one learner exceed the LDS");
   pl->sh.n_scan = pl->sh.n;
   pl->sh.external_x = true;
+  pl->sh.x12 = false;
   rc = fit_footprint(pl->sh, &pl->fit_bytes, false);
   if (rc) return rc;
   pl->sh.fold_start.assign(K + 1, 0);  // rows grouped by fold

@@ -24,6 +24,7 @@ struct FitShape {
   int n_row_blocks = 0, n_val_blocks = 0;
   bool unbinned = false;  // learners are unbinned cubic P-splines
   bool copies = false;    // some binned learner gets LDS histogram copies (copy_mask)
+  bool x12 = false;       // the workspace holds a 12-bit copy of X (every bin below 4,096)
   // Folds of a cross-validation share one index matrix and one histogram
   // pass: the first fold's shape has share = the number of folds (the
   // others follow it in the fit list, with share = 0); other fits have 1.
@@ -99,6 +100,7 @@ struct Layout {
       coef_h;
   size_t state_begin, state_end;  // mutable state region (checkpoint)
   size_t X, y, r, feat, bstart, bval, jr, ainv[2], gram[2], riskpart, amaxpart, valpart, fitdev;
+  size_t X12;
   size_t segs, blk, sel_off, partials, st_items, sel_items, val_items;
   size_t total;
 };
