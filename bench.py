@@ -120,7 +120,11 @@ def headline(args, torch, cwb, datagen):
         "hist_launches": hist_n, "hist_timed_every": args.timing_period,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # measured bytes (the 12-bit index copy moves fewer than the
+                     # uint16 formulation's algorithmic bytes) over the same time
+                     "traffic_gbs": (round(traffic / hist_avg_s / 1e9, 1)
+                                     if traffic else None)},
         "alg_iter_bytes": alg_iter_bytes, "hist_bytes_per_launch": hist_bytes, "tile": tile,
     }
 
