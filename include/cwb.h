@@ -166,6 +166,16 @@ int cwb_workspace_bytes(const cwb_problem* pr, size_t* bytes);
  * non-finite or constant x. */
 int cwb_bin_feature(const double* x, int64_t n, int32_t n_bins, uint16_t* ind_out, double* z_out);
 
+/* The smoothing parameter of a penalised learner for a target degrees of
+ * freedom (App. A.2), host only: lambda >= 0 with
+ * df(lambda) = trace((G + lambda D)^-1 G) = df, the computation
+ * cwb_fit_create runs for every P-spline learner with a df target.  G, D:
+ * d x d host doubles, row-major, symmetric (the learner's Gram matrix and
+ * penalty).  INVALID_ARG for NULL pointers, d outside 1..64, df outside
+ * (0, d) or a target the penalty's null space cannot reach; NUMERIC for a
+ * degenerate G or D. */
+int cwb_lambda_for_df(int32_t d, const double* G, const double* D, double df, double* lambda);
+
 typedef struct cwb_fit cwb_fit;
 
 /* Validate the problem, run the FP64 host setup (binning on an equal grid

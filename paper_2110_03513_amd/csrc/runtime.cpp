@@ -1169,6 +1169,20 @@ int cwb_bin_feature(const double* x, int64_t n, int32_t n_bins, uint16_t* ind_ou
   }
 }
 
+int cwb_lambda_for_df(int32_t d, const double* G, const double* D, double df, double* lambda) {
+  try {
+    if (!G || !D || !lambda) return set_error(CWB_E_INVALID_ARG, "null pointer");
+    if (d < 1 || d > kMaxD) return set_error(CWB_E_INVALID_ARG, "matrix size must be 1..64");
+    if (!(df > 0.0) || !(df < (double)d)) return set_error(CWB_E_INVALID_ARG, "df must lie in (0, d)");
+    std::vector<double> g(G, G + (size_t)d * d), p(D, D + (size_t)d * d);
+    std::string err;
+    const int rc = lambda_for_df(d, g, p, df, lambda, &err);
+    return rc ? set_error(rc == -5 ? CWB_E_NUMERIC : CWB_E_INVALID_ARG, err) : CWB_OK;
+  } catch (...) {
+    return set_error(CWB_E_INVALID_ARG, "unexpected error");
+  }
+}
+
 int cwb_workspace_bytes(const cwb_problem* pr, size_t* bytes) {
   try {
     if (!bytes) return set_error(CWB_E_INVALID_ARG, "null bytes pointer");

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <thread>
@@ -131,22 +132,16 @@ std::vector<double> difference_penalty(int d, int ord) {
   return P;
 }
 
-// df(lambda) = trace((G + lambda D)^-1 G), directly (fallback when G is singular).
-bool df_direct(int d, const std::vector<double>& G, const std::vector<double>& D, double lam,
-               double* out) {
-  std::vector<double> A((size_t)d * d), inv;
-  for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
-  if (!spd_inverse(d, A, inv)) return false;
-  double tr = 0.0;
-  for (int i = 0; i < d; ++i)
-    for (int k = 0; k < d; ++k) tr += inv[(size_t)i * d + k] * G[(size_t)k * d + i];
-  *out = tr;
-  return true;
-}
+}  // namespace
 
-// lambda with df(lambda) = target by bisection in log(lambda); df decreases
-// monotonically.  Uses the Demmler-Reinsch eigenvalues when G is positive
-// definite and the direct trace otherwise.
+// lambda with df(lambda) = target (App. A.2), by Newton's method on
+// g(u) = df(e^u) - target in u = log(lambda), safeguarded by a bracket on
+// which g changes sign (df decreases monotonically in lambda, so g does in
+// u).  With G positive definite, df and its derivative come from the
+// Demmler-Reinsch eigenvalues w of L^-1 D L^-T (G = L L^T):
+// df = sum 1/(1 + lambda w_i), d df/d lambda = -sum w_i/(1 + lambda w_i)^2.
+// Otherwise both come from A = G + lambda D directly:
+// df = tr(A^-1 G), d df/d lambda = -tr(A^-1 D A^-1 G).
 int lambda_for_df(int d, const std::vector<double>& G, const std::vector<double>& D, double target,
                   double* lam_out, std::string* err) {
   std::vector<double> L;
@@ -175,15 +170,42 @@ int lambda_for_df(int d, const std::vector<double>& G, const std::vector<double>
         S[(size_t)j * d + i] = a;
       }
     w = jacobi_eigenvalues(d, S);
+    for (double& wi : w) wi = std::max(wi, 0.0);
   }
-  auto df_at = [&](double lam, double* v) -> bool {
+  // g(u) and dg/du at u = log(lambda)
+  auto eval = [&](double u, double* g, double* dg) -> bool {
+    const double lam = std::exp(u);
     if (dro) {
-      double s = 0.0;
-      for (double wi : w) s += 1.0 / (1.0 + lam * std::max(wi, 0.0));
-      *v = s;
+      double f = 0.0, fp = 0.0;
+      for (double wi : w) {
+        const double q = 1.0 / (1.0 + lam * wi);
+        f += q;
+        fp -= wi * q * q;
+      }
+      *g = f - target;
+      *dg = lam * fp;
       return true;
     }
-    return df_direct(d, G, D, lam, v);
+    std::vector<double> A((size_t)d * d), inv;
+    for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
+    if (!spd_inverse(d, A, inv)) return false;
+    std::vector<double> P((size_t)d * d, 0.0), Q((size_t)d * d, 0.0);  // A^-1 G, A^-1 D
+    for (int i = 0; i < d; ++i)
+      for (int k = 0; k < d; ++k) {
+        const double a = inv[(size_t)i * d + k];
+        for (int j = 0; j < d; ++j) {
+          P[(size_t)i * d + j] += a * G[(size_t)k * d + j];
+          Q[(size_t)i * d + j] += a * D[(size_t)k * d + j];
+        }
+      }
+    double f = 0.0, fp = 0.0;
+    for (int i = 0; i < d; ++i) {
+      f += P[(size_t)i * d + i];
+      for (int k = 0; k < d; ++k) fp -= Q[(size_t)i * d + k] * P[(size_t)k * d + i];
+    }
+    *g = f - target;
+    *dg = lam * fp;
+    return true;
   };
   double trG = 0.0, trD = 0.0;
   for (int i = 0; i < d; ++i) {
@@ -194,29 +216,46 @@ int lambda_for_df(int d, const std::vector<double>& G, const std::vector<double>
     *err = "degenerate Gram or penalty matrix";
     return -5;
   }
-  const double s = trG / trD;
-  double lo = 1e-10 * s, hi = 1e10 * s, v = 0.0;
-  int k = 0;
-  for (; k < 40; ++k) {
-    if (!df_at(lo, &v)) { *err = "penalised Gram matrix not positive definite"; return -5; }
-    if (v > target) break;
-    lo *= 1e-3;
+  // bracket [ua, ub] with g(ua) > 0 > g(ub): widen in steps of 5 in u
+  // (a factor e^5 in lambda) from the scale trG / trD, within e^-35 .. e^35
+  // (about 1e-15 .. 1e15) times it.  A target that needs a lambda beyond
+  // that lies at the edge of what the basis or the penalty's null space
+  // allows (rounding decides there), and is reported as out of reach.
+  const double u0 = std::log(trG / trD);
+  constexpr double kStep = 5.0;
+  constexpr int kWiden = 7;
+  double ua = u0, ub = u0, ga = 0.0, gb = 0.0, dg = 0.0;
+  int i = 0;
+  for (; i <= kWiden; ++i, ua -= kStep) {
+    if (!eval(ua, &ga, &dg)) { *err = "penalised Gram matrix not positive definite"; return -5; }
+    if (ga > 0.0) break;
   }
-  if (k == 40) { *err = "df target not reachable (too large for the basis)"; return -1; }
-  for (k = 0; k < 40; ++k) {
-    if (!df_at(hi, &v)) { *err = "penalised Gram matrix not positive definite"; return -5; }
-    if (v < target) break;
-    hi *= 1e3;
+  if (i > kWiden) { *err = "df target not reachable (too large for the basis)"; return -1; }
+  for (i = 0; i <= kWiden; ++i, ub += kStep) {
+    if (!eval(ub, &gb, &dg)) { *err = "penalised Gram matrix not positive definite"; return -5; }
+    if (gb < 0.0) break;
   }
-  if (k == 40) { *err = "df target not reachable (too small for the penalty)"; return -1; }
-  for (k = 0; k < 400 && hi / lo > 1.0 + 1e-15; ++k) {
-    const double mid = std::sqrt(lo * hi);
-    df_at(mid, &v);
-    if (v > target) lo = mid; else hi = mid;
+  if (i > kWiden) { *err = "df target not reachable (too small for the penalty)"; return -1; }
+  // Newton steps inside the bracket; a step that leaves it, or a flat
+  // derivative, is replaced by the bracket's midpoint
+  double u = 0.5 * (ua + ub), g = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    if (!eval(u, &g, &dg)) { *err = "penalised Gram matrix not positive definite"; return -5; }
+    if (g == 0.0) break;
+    if (g > 0.0) ua = u; else ub = u;
+    double un = (dg < 0.0) ? u - g / dg : 0.5 * (ua + ub);
+    if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);
+    if (std::fabs(un - u) <= 4.0 * DBL_EPSILON * std::max(1.0, std::fabs(u))) {
+      u = un;
+      break;
+    }
+    u = un;
   }
-  *lam_out = std::sqrt(lo * hi);
+  *lam_out = std::exp(u);
   return 0;
 }
+
+namespace {
 
 // ---- binning and bases -----------------------------------------------------
 

@@ -68,6 +68,11 @@ struct HostFit {
 int bins_for(int32_t n_bins, int64_t n);
 int bin_one_feature(const double* x, int64_t n, int nb, uint16_t* ind, double* z, std::string* err);
 int validate_problem(const cwb_problem* pr, std::string* err);
+// The smoothing parameter lambda with df(lambda) = target for a learner's
+// Gram matrix G and penalty D (d x d, row-major): 0, -1 (target out of
+// reach) or -5 (degenerate or not positive definite), with a message.
+int lambda_for_df(int d, const std::vector<double>& G, const std::vector<double>& D, double target,
+                  double* lam_out, std::string* err);
 // Host setup of a fit in full: validation, row order, labels, binning, bin
 // counts and every learner's tables.
 int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,

@@ -79,6 +79,7 @@ _SIGNATURES = {
     "cwb_version": [C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "cwb_last_error": [],
     "cwb_bin_feature": [_P, C.c_int64, C.c_int32, _P, _P],
+    "cwb_lambda_for_df": [C.c_int32, _P, _P, C.c_double, _P],
     "cwb_workspace_bytes": [C.POINTER(cwb_problem), C.POINTER(C.c_size_t)],
     "cwb_fit_create": [C.POINTER(cwb_problem), _P, C.c_size_t, _P, C.POINTER(_P)],
     "cwb_fit_create_noalloc": [C.POINTER(cwb_problem), _P, C.c_size_t, _P, C.POINTER(_P)],
@@ -201,6 +202,15 @@ def bin_feature(x, n_bins: int):
     z = np.zeros(n_bins)
     check(lib().cwb_bin_feature(_ptr(x), x.shape[0], int(n_bins), _ptr(ind), _ptr(z)))
     return z, ind
+
+
+def lambda_for_df(G, D, df: float) -> float:
+    """Library smoothing parameter for a df target (host only)."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    out = np.zeros(1)
+    check(lib().cwb_lambda_for_df(int(G.shape[0]), _ptr(G), _ptr(D), float(df), _ptr(out)))
+    return float(out[0])
 
 
 def workspace_bytes(prob: dict | Problem) -> int:
