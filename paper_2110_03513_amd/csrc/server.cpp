@@ -30,6 +30,7 @@
 #include <new>
 #include <thread>
 
+#include "admission.h"
 #include "runtime.h"
 
 namespace cwb {
@@ -39,56 +40,6 @@ double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit allocator over [0, size) in 256-byte units; neighbouring free
-// ranges are merged on release.
-class Arena {
- public:
-  void reset(size_t bytes) {
-    free_.clear();
-    size_ = bytes / 256 * 256;
-    if (size_) free_[0] = size_;
-    in_use = peak = 0;
-  }
-  size_t size() const { return size_; }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = std::max<size_t>(256, (bytes + 255) / 256 * 256);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      *off = it->first;
-      const size_t rest = it->second - bytes;
-      const size_t at = it->first + bytes;
-      free_.erase(it);
-      if (rest) free_[at] = rest;
-      in_use += bytes;
-      peak = std::max(peak, in_use);
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = std::max<size_t>(256, (bytes + 255) / 256 * 256);
-    in_use -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t in_use = 0, peak = 0;
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t size_ = 0;
-};
 
 enum class Stage { kQueued, kSetup, kReady, kAdmitted, kRunning, kDone };
 
@@ -413,34 +364,30 @@ void device_loop(cwb_server* s) {
       std::vector<const FitShape*> shapes;
       for (Request* r : s->active) shapes.push_back(&r->fit->shape);
       for (Request* r : s->pending) shapes.push_back(&r->shape);
-      bool any = false;
-      while (!s->stop && !s->ready_q.empty() &&
-             (int)(s->active.size() + s->pending.size()) < s->cfg.max_slots) {
-        Request* r = s->ready_q.front();
+      const int free_slots =
+          s->stop ? 0 : s->cfg.max_slots - (int)(s->active.size() + s->pending.size());
+      // the batch workspace of the set grown by r, or kNoFit
+      auto batch_need = [&](Request* r) -> size_t {
         shapes.push_back(&r->shape);
-        size_t bb = 0, off = 0, boff = 0;
-        bool ok = !batch_footprint(shapes, &bb, false) && s->arena.alloc(r->footprint, &off);
-        if (ok && !s->arena.alloc(bb, &boff)) {
-          s->arena.release(off, r->footprint);
-          ok = false;
-        }
-        if (!ok) {
-          shapes.pop_back();
-          break;  // first come, first served: later requests wait too
-        }
-        if (s->have_res) s->arena.release(s->res_off, s->res_bytes);
-        s->res_off = boff;
-        s->res_bytes = bb;
-        s->have_res = true;
+        size_t bb = 0;
+        const int rc = batch_footprint(shapes, &bb, false);
+        shapes.pop_back();
+        return rc ? kNoFit : bb;
+      };
+      auto admit = [&](Request* r, size_t off) {
+        shapes.push_back(&r->shape);
         r->off = off;
         r->stage = Stage::kAdmitted;
         r->t_admit = now_s();
         s->in_flight += 1;
-        s->ready_q.pop_front();
         s->pending.push_back(r);
         s->upload_q.push_back(r);
-        any = true;
-      }
+      };
+      Reservation res{s->have_res, s->res_off, s->res_bytes};
+      const int any = admit_in_order(s->ready_q, free_slots, s->arena, res, batch_need, admit);
+      s->have_res = res.have;
+      s->res_off = res.off;
+      s->res_bytes = res.bytes;
       if (any) s->cv_up.notify_one();
     }
     // 2. one round of the current batch

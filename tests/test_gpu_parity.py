@@ -578,3 +578,23 @@ def test_select_staging_past_one_pass(variant, loss):
     prob.update(datagen.learner_specs(3, np.array([1500, 1100, 700]), df=5.0))
     prob["n_knots"] = 40
     compare(_run(prob), prob)
+
+
+@pytest.mark.parametrize("variant", ["cwb", "acwb"])
+def test_nonfinite_state_is_reported_at_sync(variant):
+    """An L2 fit with nu = 1e30 drives f to infinity: the row pass flags the
+    non-finite state and the sync reports CWB_E_NUMERIC.  Bin indices come
+    from X and a non-finite criterion maps to learner 0, so no address
+    depends on the model values.  A normal fit on the same device afterwards
+    still matches the oracle."""
+    prob = datagen.additive_problem(20_000, 5, seed=98, n_informative=2, n_bins=64, M=12,
+                                    variant=variant, gamma=0.05)
+    bad = dict(prob, nu=1e30)
+    _say(f"nu=1e30 {variant} fit, expecting CWB_E_NUMERIC at sync")
+    f = cwb.Fit(bad)
+    f.run(12)
+    with pytest.raises(cwb.CwbError) as err:
+        f.sync()
+    assert err.value.code == cwb.CWB_E_NUMERIC
+    f.close()
+    compare(_run(prob), prob)
