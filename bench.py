@@ -458,17 +458,19 @@ def batched(args, torch, cwb, datagen):
             f.close()
     os.environ.pop("CWB_GRAPH")
     # the same fits one after another, each alone
-    fits = [cwb.Fit(p) for p in probs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for f in fits:
-        f.run(args.batch_iters)
-    for f in fits:
-        f.sync()
-    t_loop = time.perf_counter() - t0
-    same = all(np.array_equal(f.trace()["k"], k) for f, k in zip(fits, ks))
-    for f in fits:
-        f.close()
+    t_loop, same = None, None
+    if not args.batch_no_loop:
+        fits = [cwb.Fit(p) for p in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in fits:
+            f.run(args.batch_iters)
+        for f in fits:
+            f.sync()
+        t_loop = time.perf_counter() - t0
+        same = all(np.array_equal(f.trace()["k"], k) for f, k in zip(fits, ks))
+        for f in fits:
+            f.close()
     bytes_iter = sum(2.0 * p["x"].shape[0] * p["x"].shape[1] for p in probs)
     # algorithmic bytes of one batched histogram launch (every fit runs all
     # M iterations): each fit's indices once, and its signals (two for ACWB)
@@ -480,8 +482,8 @@ def batched(args, torch, cwb, datagen):
     return {"fits": len(probs), "iters": args.batch_iters,
             "fits_per_s": round(len(probs) / tb, 3),
             "fits_per_s_without_graphs": round(len(probs) / t_batch["0"], 3),
-            "loop_fits_per_s": round(len(probs) / t_loop, 3),
-            "speedup_vs_loop": round(t_loop / tb, 3),
+            "loop_fits_per_s": round(len(probs) / t_loop, 3) if t_loop else None,
+            "speedup_vs_loop": round(t_loop / tb, 3) if t_loop else None,
             "index_gbs": round(bytes_iter * args.batch_iters / tb / 1e9, 1),
             "roofline": {"bound": "hbm", "kernel": "batched histogram pass",
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -489,7 +491,8 @@ def batched(args, torch, cwb, datagen):
                          "hist_avg_us": round(hist_avg * 1e6, 2), "launches_timed": hist[1],
                          "bytes_per_launch": hist_bytes},
             "tile": tile,
-            "same_selections_as_alone": bool(same), "setup_s": round(setup, 2)}
+            "same_selections_as_alone": None if same is None else bool(same),
+            "setup_s": round(setup, 2)}
 
 
 def served(args, torch, cwb, datagen):
@@ -610,32 +613,36 @@ def copy_probe(torch, mib):
 def lds_probe(torch, cwb, args):
     """The LDS histogram ceiling: the histogram pass's inner loop (1,024
     threads, 4 learners per group, 8 rows per index load, the headline's 2e8
-    int64 atomics over 256 blocks) with its bin indices read from a 512 KiB
-    table in L2 instead of HBM.  Random bins (uniform over 1,000) and
-    bank-conflict-free bins (lane l of a wave always on bank pair l mod 32)."""
+    atomics over 256 blocks) with its bin indices read from a 512 KiB table
+    in L2 instead of HBM, for 4-byte words (the pass's 32-bit groups) and
+    8-byte words (int64 groups).  Random bins (uniform over 1,000) and
+    bank-conflict-free bins (lane l of a wave always on its own bank, or
+    bank pair for 8-byte words)."""
     nb, learners, blocks = 1000, 4, 256
     atomics = float(args.n) * args.p  # one per (row, learner)
     steps = int(round(atomics / (blocks * 1024 * learners * 8)))
     chunks = 1 << 15
     rng = np.random.default_rng(77)
     rand = rng.integers(0, nb, size=chunks * 8, dtype=np.int64)
-    lane = (np.arange(chunks) % 32)[:, None]
-    free = (32 * rng.integers(0, nb // 32, size=(chunks, 8)) + lane).reshape(-1)
+    lane = np.arange(chunks) % 64
+    free8 = (32 * rng.integers(0, nb // 32, size=(chunks, 8)) + (lane % 32)[:, None]).reshape(-1)
+    free4 = (64 * rng.integers(0, nb // 64, size=(chunks, 8)) + lane[:, None]).reshape(-1)
     out = {"atomics": blocks * 1024 * learners * 8 * steps, "blocks": blocks, "nb": nb}
-    for name, tab in (("random", rand), ("conflict_free", free)):
-        idx = torch.from_numpy(tab.astype(np.int16)).cuda()
-        acc = torch.zeros(blocks, dtype=torch.int64, device="cuda")
-        for _ in range(3):
-            cwb.probe_lds_hist(idx, nb, learners, steps, blocks, acc)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record()
-        for _ in range(reps):
-            cwb.probe_lds_hist(idx, nb, learners, steps, blocks, acc)
-        e1.record()
-        torch.cuda.synchronize()
-        out[name + "_us"] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+    for wb, free in ((4, free4), (8, free8)):
+        for name, tab in (("random", rand), ("conflict_free", free)):
+            idx = torch.from_numpy(tab.astype(np.int16)).cuda()
+            acc = torch.zeros(blocks, dtype=torch.int64, device="cuda")
+            for _ in range(3):
+                cwb.probe_lds_hist(idx, nb, learners, steps, blocks, acc, word_bytes=wb)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                cwb.probe_lds_hist(idx, nb, learners, steps, blocks, acc, word_bytes=wb)
+            e1.record()
+            torch.cuda.synchronize()
+            out[f"{name}_{wb}b_us"] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
     return out
 
 
@@ -666,6 +673,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-fits", type=int, default=64)
     ap.add_argument("--batch-iters", type=int, default=1000)
+    ap.add_argument("--batch-no-loop", action="store_true",
+                    help="skip the plain loop of single fits (profiling runs)")
     ap.add_argument("--timing-period", type=int, default=8,
                     help="time every k-th histogram launch in the timed region")
     ap.add_argument("--unbinned-iters", type=int, default=200)
@@ -727,9 +736,10 @@ def main():
     }
     if not args.no_lds_probe:
         lp = lds_probe(torch, cwb, args)
-        # the histogram pass against the LDS ceiling of the same atomics
+        # the histogram pass against the LDS ceiling of its own atomics: the
+        # headline's groups take 4-byte words
         lp["hist_us"] = round(h["hist_avg_us"], 2)
-        lp["ceiling_frac"] = round(lp["random_us"] / h["hist_avg_us"], 4)
+        lp["ceiling_frac"] = round(lp["random_4b_us"] / h["hist_avg_us"], 4)
         out["lds_ceiling"] = lp
     if not args.no_setup:
         out["setup"] = setup_leg(prob, cwb)

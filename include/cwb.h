@@ -413,22 +413,6 @@ int cwb_server_stats(cwb_server* s, cwb_stats* st);
 /* Stop accepting, finish in-flight work, join the thread. */
 void cwb_server_destroy(cwb_server* s);
 
-/* ---- measurement utility (not part of the method) ---------------------
- * The LDS histogram ceiling: `blocks` blocks of 1,024 threads each add
- * `steps` x `learners` x 8 rows per thread into `learners` int64 LDS
- * histograms of `nb` bins, as the histogram pass does, but read their bin
- * indices from the device table `idx` (`idx_len` uint16 bins, 8 times a
- * power of two, 16-byte aligned, small enough to stay in L2; row r of the
- * probe reads entry r mod idx_len) instead of streaming them
- * from HBM.  Bins at or above nb are clamped to nb - 1.  Each block adds its
- * histogram total to out[block] (device, `blocks` int64, zeroed by the
- * caller).  Asynchronous on `stream`; the caller times it.  Returns
- * CWB_E_INVALID_ARG for sizes outside learners 1..4, nb 1..8192,
- * learners x nb x 8 bytes above 152 KiB, or a table of another length or
- * alignment. */
-int cwb_probe_lds_hist(const uint16_t* idx, int64_t idx_len, int32_t nb, int32_t learners,
-                       int32_t steps, int32_t blocks, long long* out, void* stream);
-
 #ifdef __cplusplus
 }
 #endif

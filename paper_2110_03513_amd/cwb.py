@@ -118,7 +118,7 @@ _SIGNATURES = {
     "cwb_cv_risk": [_P, _P],
     "cwb_cv_destroy": [_P],
     "cwb_cv_tile": [_P, C.POINTER(cwb_tile)],
-    "cwb_probe_lds_hist": [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P],
+    "cwb_probe_lds_hist": [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P],
 }
 _VOID = {"cwb_fit_destroy", "cwb_batch_destroy", "cwb_server_destroy", "cwb_cv_destroy"}
 
@@ -220,15 +220,17 @@ def workspace_bytes(prob: dict | Problem) -> int:
     return b.value
 
 
-def probe_lds_hist(idx, nb: int, learners: int, steps: int, blocks: int, out, stream=None):
+def probe_lds_hist(idx, nb: int, learners: int, steps: int, blocks: int, out, stream=None,
+                   word_bytes: int = 8):
     """Launch the LDS histogram ceiling probe (a measurement utility, not
-    part of the method) on `stream` (torch's current stream by default):
-    `idx` a CUDA uint16-compatible tensor of bins (int16 storage), `out` a
-    zeroed CUDA int64 tensor of `blocks` entries."""
+    part of the method, include/cwb_probe.h) on `stream` (torch's current
+    stream by default): `idx` a CUDA uint16-compatible tensor of bins (int16
+    storage), `out` a zeroed CUDA int64 tensor of `blocks` entries,
+    `word_bytes` the LDS word width (4 or 8)."""
     torch = _torch()
     st = stream if stream is not None else torch.cuda.current_stream()
     check(lib().cwb_probe_lds_hist(C.c_void_p(idx.data_ptr()), int(idx.numel()), int(nb),
-                                   int(learners), int(steps), int(blocks),
+                                   int(learners), int(word_bytes), int(steps), int(blocks),
                                    C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
 
 

@@ -15,7 +15,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    hdr = open(os.path.join(ROOT, "include", "cwb.h")).read()
+    inc = os.path.join(ROOT, "include")
+    hdr = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc))
+                  if f.endswith(".h"))
     hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
     return sorted(set(re.findall(r"\b(cwb_[a-z_]+)\s*\(", hdr)))
 
@@ -315,18 +317,19 @@ def test_probe_argument_checks():
     p = C.cast(buf, C.c_void_p)
     aligned = C.c_void_p((p.value + 15) // 16 * 16)
     cases = [
-        (None, 64, 100, 1, 1, 1, p),         # null table
-        (aligned, 64, 100, 1, 1, 1, None),   # null output
-        (aligned, 24, 100, 1, 1, 1, p),      # 3 chunks: not a power of two
-        (aligned, 12, 100, 1, 1, 1, p),      # not a multiple of 8
-        (C.c_void_p(aligned.value + 2), 64, 100, 1, 1, 1, p),  # misaligned
-        (aligned, 64, 0, 1, 1, 1, p),        # nb below 1
-        (aligned, 64, 100, 5, 1, 1, p),      # more than 4 learners
-        (aligned, 64, 8192, 4, 1, 1, p),     # 256 KiB of LDS
-        (aligned, 64, 100, 1, 0, 1, p),      # no steps
-        (aligned, 64, 100, 1, 1, 0, p),      # no blocks
+        (None, 64, 100, 1, 8, 1, 1, p),         # null table
+        (aligned, 64, 100, 1, 8, 1, 1, None),   # null output
+        (aligned, 24, 100, 1, 8, 1, 1, p),      # 3 chunks: not a power of two
+        (aligned, 12, 100, 1, 8, 1, 1, p),      # not a multiple of 8
+        (C.c_void_p(aligned.value + 2), 64, 100, 1, 8, 1, 1, p),  # misaligned
+        (aligned, 64, 0, 1, 8, 1, 1, p),        # nb below 1
+        (aligned, 64, 100, 5, 8, 1, 1, p),      # more than 4 learners
+        (aligned, 64, 8192, 4, 8, 1, 1, p),     # 256 KiB of LDS
+        (aligned, 64, 100, 1, 2, 1, 1, p),      # words of 2 bytes
+        (aligned, 64, 100, 1, 8, 0, 1, p),      # no steps
+        (aligned, 64, 100, 1, 8, 1, 0, p),      # no blocks
     ]
-    for idx, n, nb, learners, steps, blocks, out in cases:
-        rc = L.cwb_probe_lds_hist(idx, n, nb, learners, steps, blocks, out, None)
+    for idx, n, nb, learners, wb, steps, blocks, out in cases:
+        rc = L.cwb_probe_lds_hist(idx, n, nb, learners, wb, steps, blocks, out, None)
         assert rc == cwb.CWB_E_INVALID_ARG, (n, nb, learners, steps, blocks)
         assert L.cwb_last_error().decode()

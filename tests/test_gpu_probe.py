@@ -9,15 +9,17 @@ from paper_2110_03513_amd import cwb
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("word_bytes", [4, 8])
 @pytest.mark.parametrize("nb,learners,steps,blocks", [(1000, 4, 3, 7), (17, 1, 5, 3), (8192, 2, 1, 2)])
-def test_probe_checksums(nb, learners, steps, blocks):
+def test_probe_checksums(nb, learners, steps, blocks, word_bytes):
     import torch
     rng = np.random.default_rng(nb)
     tab = rng.integers(0, nb + 50, size=8 * 1024).astype(np.int16)  # some past nb: clamped
     idx = torch.from_numpy(tab).cuda()
     out = torch.zeros(blocks, dtype=torch.int64, device="cuda")
-    print(f"probe nb={nb} learners={learners} steps={steps} blocks={blocks}", flush=True)
-    cwb.probe_lds_hist(idx, nb, learners, steps, blocks, out)
+    print(f"probe nb={nb} learners={learners} steps={steps} blocks={blocks} words={word_bytes}",
+          flush=True)
+    cwb.probe_lds_hist(idx, nb, learners, steps, blocks, out, word_bytes=word_bytes)
     torch.cuda.synchronize()
     want = steps * learners * 8 * (1024 * 1025 // 2)
     assert out.cpu().tolist() == [want] * blocks
