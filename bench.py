@@ -47,9 +47,9 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(tile: dict):
-    """HBM bytes per hist launch from the committed rocprofv3 counter summary,
-    or None if it is missing, was taken on a different kernel source or on a
-    different tile shape than the one this run uses."""
+    """HBM bytes per hist launch from the committed rocprofv3 counter summary
+    (one entry per profiled tile shape), or None if it is missing, was taken
+    on a different kernel source or on no tile shape this run uses."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -57,10 +57,11 @@ def measured_traffic(tile: dict):
         return None
     if t.get("kernel_hash") != kernel_source_hash():
         return None
-    want = t.get("tile", {})
-    if any(want.get(k) != tile.get(k) for k in ("threads", "learners", "blocks")):
-        return None
-    return t.get("hbm_bytes_per_launch")
+    for entry in t.get("tiles", []):
+        want = entry.get("tile", {})
+        if all(want.get(k) == tile.get(k) for k in ("threads", "learners", "blocks")):
+            return entry.get("hbm_bytes_per_launch")
+    return None
 
 
 def headline(args, torch, cwb, datagen):
