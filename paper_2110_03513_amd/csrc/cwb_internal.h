@@ -181,6 +181,8 @@ struct RowItem {
   int32_t unbinned;                  // X holds 32-bit unbinned codes
   int32_t fold_k;                    // fold fit: its held-out fold
   const uint8_t* fold;               // fold fit: fold id per row, else null
+  int32_t chunks;                    // consecutive kStateRows chunks from base;
+  int32_t pad_;                      // risk_part and amax_part hold 2 per chunk
 };
 
 // One learner's solve, with every pointer and size it needs, so that a block
@@ -209,6 +211,20 @@ struct SelItem {
   int32_t kind;               // learner kind (CWB_BINARY_CAT: best class only)
   int32_t acc32_bits;         // its fit's: > 0, sums at the 32-bit scale
                               // (scale_exponent32 with these bits), else int64
+};
+
+// One learner solve of the device setup pass (alg::learner_solve): the Gram
+// matrix from the bin counts of one row set, lambda for the learner's df,
+// and the inverse of G + lambda D, written into the fit's tables.
+struct SolveJob {
+  const int32_t* bstart;   // the learner's band starts (nb)
+  const double* bval;      // its banded reduced design (nb x kMaxBand)
+  const uint32_t* cnt;     // its bin counts over the row set (nb)
+  double* gram;            // out: d x d
+  double* ainv;            // out: d x d
+  double df, lambda;       // df target (> 0), else the fixed lambda
+  int32_t kind, d, nb, band;
+  int32_t pen_order, pad;
 };
 
 // Fixed-point exponent for the int64 histogram of a signal whose largest

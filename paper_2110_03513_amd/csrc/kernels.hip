@@ -42,7 +42,11 @@ namespace cwb {
 // unless a finalize already did: every block computes the chosen learners
 // from q, block 0 records them in the traces, and every block applies the
 // update to its rows (f = g + nu b_k; ACWB: h += eta b_kcor with
-// eta = gamma nu (S + 1) / 2 for selection S).
+// eta = gamma nu (S + 1) / 2 for selection S).  A block covers it.chunks
+// consecutive chunks of kStateRows rows (several when a launch has many
+// more chunks than the chip has room for blocks, as a large batch does):
+// the selection and the winners' tables are taken once, and each chunk
+// writes its own risk and maximum partials.
 __global__ void __launch_bounds__(kStateThreads)
 k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int final_mode) {
   extern __shared__ float s_tab[];  // [2][nb_max]
@@ -50,8 +54,8 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   __shared__ Arg2 s_w[2][kStateThreads / 64];
   __shared__ int s_bad;
   const RowItem it = items[blockIdx.x];
-  const int64_t base = it.base + (int64_t)threadIdx.x * kRowsPerThread;
-  const bool rows = base < it.n_pad;
+  int64_t base = it.base + (int64_t)threadIdx.x * kRowsPerThread;
+  bool rows = base < it.n_pad;
   const bool two = it.two != 0;
   // One round of loads, none of the model state's behind a branch (a branch
   // join makes the compiler wait for loads issued inside it): threads past
@@ -60,7 +64,7 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   // block comes in through scalar loads, so testing it does not wait for
   // the model state.
   float f[8], yv[8], hv[8], cv[8], rr[8], cc[8];
-  const int64_t lb = rows ? base : it.n_pad - kRowsPerThread;
+  int64_t lb = rows ? base : it.n_pad - kRowsPerThread;
   load8f((two ? it.h : it.fg) + lb, hv);
   load8f((two ? it.c : it.fg) + lb, cv);
   double qv0 = INFINITY, qv1 = INFINITY;
@@ -121,93 +125,112 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   const bool use_t = do_pick;
   const bool use_h = do_pick && sel_acwb && kc >= 0;
   const bool use_cc = acwb && have_sel && sel_acwb && kc >= 0;
+  const bool unb = it.unbinned != 0;
   uint32_t ik[8], ic[8];
   uint32_t fold_lo = 0u, fold_hi = 0u;  // fold fit: the 8 rows' fold ids, one byte each
-  if (rows && it.fold) {
-    const unsigned long long fv = *reinterpret_cast<const GLOBAL unsigned long long*>(gp(it.fold) + base);
-    fold_lo = (uint32_t)fv;
-    fold_hi = (uint32_t)(fv >> 32);
-  }
-  const bool unb = it.unbinned != 0;
-  if (unb) {
-    const uint32_t* XU = reinterpret_cast<const uint32_t*>(it.X);
-    if (rows && use_t) load8c(XU + (size_t)kk * it.n_pad + base, ik);
-    if (rows && (use_h || use_cc)) load8c(XU + (size_t)kc * it.n_pad + base, ic);
-  } else {
-    if (rows && use_t) load8u(it.X + (size_t)kk * it.n_pad + base, ik);
-    if (rows && (use_h || use_cc)) load8u(it.X + (size_t)kc * it.n_pad + base, ic);
-  }
+  // this thread's winner-column and fold loads for the chunk at `base`
+  auto load_cols = [&]() {
+    if (rows && it.fold) {
+      const unsigned long long fv =
+          *reinterpret_cast<const GLOBAL unsigned long long*>(gp(it.fold) + base);
+      fold_lo = (uint32_t)fv;
+      fold_hi = (uint32_t)(fv >> 32);
+    }
+    if (unb) {
+      const uint32_t* XU = reinterpret_cast<const uint32_t*>(it.X);
+      if (rows && use_t) load8c(XU + (size_t)kk * it.n_pad + base, ik);
+      if (rows && (use_h || use_cc)) load8c(XU + (size_t)kc * it.n_pad + base, ic);
+    } else {
+      if (rows && use_t) load8u(it.X + (size_t)kk * it.n_pad + base, ik);
+      if (rows && (use_h || use_cc)) load8u(it.X + (size_t)kc * it.n_pad + base, ic);
+    }
+  };
+  load_cols();
   if (use_t) stage<kStateThreads, 4>(tf, it.table + (size_t)kk * nb, nb);
   if (use_h || use_cc) stage<kStateThreads, 4>(tc, it.table + ((size_t)it.p + kc) * nb, nb);
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
 
-  double risk_t = 0.0, risk_v = 0.0;
-  float amax_r = 0.0f, amax_c = 0.0f;
-  bool bad = false;
-  if (rows) {
-    const float vt = 2.0f / (float)(m + 1);
-    const float cw = (float)m / (float)(m + 1);
+  const float vt = 2.0f / (float)(m + 1);
+  const float cw = (float)m / (float)(m + 1);
+  for (int ch = 0;;) {
+    double risk_t = 0.0, risk_v = 0.0;
+    float amax_r = 0.0f, amax_c = 0.0f;
+    bool bad = false;
+    if (rows) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t i = base + j;
-      const bool live = i < it.n;
-      float fj = f[j];
-      float hj = two ? hv[j] : 0.0f;
-      if (live && use_t) fj = fj + nu * table_at(unb, ik[j], tf);
-      if (live && use_h) hj = hj + eta * table_at(unb, ic[j], tc);
-      const bool train =
-          it.fold ? (int)(((j < 4 ? fold_lo : fold_hi) >> (8 * (j & 3))) & 0xffu) != it.fold_k
-                  : i < it.n_train;
-      if (live) {
-        const double L = row_loss(it.loss, yv[j], fj);
-        if (train) risk_t += L; else risk_v += L;
-        if (!isfinite(fj) || !isfinite(hj)) bad = true;
-      }
-      f[j] = fj;
-      hv[j] = hj;
-      rr[j] = 0.0f;
-      cc[j] = 0.0f;
-      if (final_mode || !live) continue;
-      const bool fitrow = all_rows || train;
-      if (acwb) {
-        const float g = (1.0f - vt) * fj + vt * hj;
-        const float r = neg_gradient(it.loss, yv[j], g);
-        float c = r;
-        if (use_cc) c = r + cw * (cv[j] - table_at(unb, ic[j], tc));
-        f[j] = g;  // the primary model update f = g + nu b_k is pending
-        if (fitrow) {
-          rr[j] = r;
-          cc[j] = c;
+      for (int j = 0; j < 8; ++j) {
+        const int64_t i = base + j;
+        const bool live = i < it.n;
+        float fj = f[j];
+        float hj = two ? hv[j] : 0.0f;
+        if (live && use_t) fj = fj + nu * table_at(unb, ik[j], tf);
+        if (live && use_h) hj = hj + eta * table_at(unb, ic[j], tc);
+        const bool train =
+            it.fold ? (int)(((j < 4 ? fold_lo : fold_hi) >> (8 * (j & 3))) & 0xffu) != it.fold_k
+                    : i < it.n_train;
+        if (live) {
+          const double L = row_loss(it.loss, yv[j], fj);
+          if (train) risk_t += L; else risk_v += L;
+          if (!isfinite(fj) || !isfinite(hj)) bad = true;
         }
-      } else {
-        const float r = neg_gradient(it.loss, yv[j], fj);
-        if (fitrow) rr[j] = r;
+        f[j] = fj;
+        hv[j] = hj;
+        rr[j] = 0.0f;
+        cc[j] = 0.0f;
+        if (final_mode || !live) continue;
+        const bool fitrow = all_rows || train;
+        if (acwb) {
+          const float g = (1.0f - vt) * fj + vt * hj;
+          const float r = neg_gradient(it.loss, yv[j], g);
+          float c = r;
+          if (use_cc) c = r + cw * (cv[j] - table_at(unb, ic[j], tc));
+          f[j] = g;  // the primary model update f = g + nu b_k is pending
+          if (fitrow) {
+            rr[j] = r;
+            cc[j] = c;
+          }
+        } else {
+          const float r = neg_gradient(it.loss, yv[j], fj);
+          if (fitrow) rr[j] = r;
+        }
+        amax_r = fmaxf(amax_r, fabsf(rr[j]));
+        amax_c = fmaxf(amax_c, fabsf(cc[j]));
       }
-      amax_r = fmaxf(amax_r, fabsf(rr[j]));
-      amax_c = fmaxf(amax_c, fabsf(cc[j]));
+      store8f(it.fg + base, f);
+      if (two) store8f(it.h + base, hv);
+      if (!final_mode) {
+        store8f(it.r + base, rr);
+        if (acwb) store8f(it.c + base, cc);
+      }
     }
-    store8f(it.fg + base, f);
-    if (two) store8f(it.h + base, hv);
-    if (!final_mode) {
-      store8f(it.r + base, rr);
-      if (acwb) store8f(it.c + base, cc);
+    if (bad) s_bad = 1;
+    double st = risk_t, sv = risk_v;
+    float a = amax_r, b = amax_c;
+    block_sum2_max2<kStateThreads>(st, sv, a, b, s_red);
+    if (threadIdx.x == 0) {
+      it.risk_part[2 * ch] = st;
+      it.risk_part[2 * ch + 1] = sv;
+      if (!final_mode) {
+        if (!isfinite(a) || !isfinite(b)) s_bad = 1;
+        it.amax_part[2 * ch] = a;
+        it.amax_part[2 * ch + 1] = b;
+      }
     }
+    if (++ch >= it.chunks) break;
+    // the next chunk: its rows' state and winner columns (the reduction's
+    // barrier has passed, so s_red may be reused after this round)
+    base += kStateRows;
+    rows = base < it.n_pad;
+    lb = rows ? base : it.n_pad - kRowsPerThread;
+    load8f((two ? it.h : it.fg) + lb, hv);
+    load8f((two ? it.c : it.fg) + lb, cv);
+    load8f(it.fg + lb, f);
+    load8f(it.y + lb, yv);
+    load_cols();
+    __syncthreads();  // thread 0's partial writes and s_red reads precede the next reduction
   }
-  if (bad) s_bad = 1;
-  double st = risk_t, sv = risk_v;
-  float a = amax_r, b = amax_c;
-  block_sum2_max2<kStateThreads>(st, sv, a, b, s_red);
-  if (threadIdx.x == 0) {
-    it.risk_part[0] = st;
-    it.risk_part[1] = sv;
-    if (!final_mode) {
-      if (!isfinite(a) || !isfinite(b)) s_bad = 1;
-      it.amax_part[0] = a;
-      it.amax_part[1] = b;
-    }
-    if (s_bad) atomicOr(&it.ctl->error, 1);
-  }
+  if (threadIdx.x == 0 && s_bad) atomicOr(&it.ctl->error, 1);
 }
 
 // ---------------------------------------------------------------------------

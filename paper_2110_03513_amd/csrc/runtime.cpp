@@ -588,9 +588,23 @@ T* dptr(char* ws, size_t off) {
 
 }  // namespace
 
-RowItem make_row_item(int fit, int blk, const FitDev& D) {
+int row_chunks(int64_t total, int cus) {
+  const int forced = env_int("CWB_ROW_CHUNKS", 0);  // testing: force a chunk count
+  if (forced > 0) return std::min(forced, 16);
+  const int64_t room = 8 * (int64_t)std::max(cus, 1);  // about 8 row blocks per CU at a time
+  return (int)std::max<int64_t>(1, std::min<int64_t>(16, (total + room - 1) / room));
+}
+
+void append_row_items(std::vector<RowItem>* out, int fit, const FitDev& D, int n_row_blocks,
+                      int chunks) {
+  for (int b = 0; b < n_row_blocks; b += chunks)
+    out->push_back(make_row_item(fit, b, D, std::min(chunks, n_row_blocks - b)));
+}
+
+RowItem make_row_item(int fit, int blk, const FitDev& D, int chunks) {
   RowItem it;
   std::memset(&it, 0, sizeof(it));
+  it.chunks = chunks;
   it.ctl = D.ctl;
   it.q = D.q;
   it.X = D.X;
@@ -1082,14 +1096,18 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   HIP_TRY(hipMemcpyAsync(ws + L.segs, S.segs.data(), S.segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.blk, S.blk.data(), S.blk.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(ws + L.sel_off, S.sel_off.data(), S.sel_off.size() * 8, hipMemcpyHostToDevice, st));
-  std::vector<RowItem> st_items(sh.n_row_blocks);
-  for (int b = 0; b < sh.n_row_blocks; ++b) st_items[b] = make_row_item(0, b, D);
+  std::vector<RowItem> st_items;
+  {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    append_row_items(&st_items, 0, D, sh.n_row_blocks, row_chunks(sh.n_row_blocks, device_cus(dev)));
+  }
   std::vector<SelItem> sel_items(sh.p);
   for (int k = 0; k < sh.p; ++k)
     sel_items[k] = make_sel_item(0, k, feat[k], D, S, dptr<int64_t>(ws, L.sel_off), k);
   std::vector<StateItem> val_items(std::max(1, sh.n_val_blocks));
   for (int b = 0; b < sh.n_val_blocks; ++b) val_items[b] = {0, b};
-  f->n_st = sh.n_row_blocks;
+  f->n_st = (int)st_items.size();
   f->n_sel = sh.p;
   f->n_val = sh.n_val_blocks;
   HIP_TRY(hipMemcpyAsync(ws + L.st_items, st_items.data(), st_items.size() * sizeof(RowItem), hipMemcpyHostToDevice, st));
@@ -1576,14 +1594,18 @@ int batch_create(cwb_fit* const* fits, int32_t count, void* dev_ws, size_t ws_by
   std::vector<FitDev> fd(count);
   std::vector<RowItem> st;
   std::vector<StateItem> val;
+  int64_t chunks_total = 0;
+  for (int i = 0; i < count; ++i) chunks_total += fits[i]->shape.n_row_blocks;
+  const int chunks = row_chunks(chunks_total, cands[0].cus);
   for (int i = 0; i < count; ++i) {
     fd[i] = fits[i]->dev;
     b->nb_max = std::max(b->nb_max, fits[i]->shape.nb_max);
     b->d_max = std::max(b->d_max, fits[i]->shape.d_max);
     if (fits[i]->shape.variant == CWB_HCWB) b->any_hcwb = true;
-    for (int r = 0; r < fits[i]->shape.n_row_blocks; ++r) st.push_back(make_row_item(i, r, fits[i]->dev));
+    append_row_items(&st, i, fits[i]->dev, fits[i]->shape.n_row_blocks, chunks);
     for (int r = 0; r < fits[i]->shape.n_val_blocks; ++r) val.push_back({i, r});
   }
+  b->n_st = (int)st.size();
   char* ws = b->ws;
   hipStream_t s = b->stream;
   b->d_fits = dptr<FitDev>(ws, L.fits);

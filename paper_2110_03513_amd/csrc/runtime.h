@@ -185,7 +185,15 @@ namespace cwb {
 int set_error(int code, const std::string& msg);
 // Enqueue one finalize (apply pending updates, record the current risk).
 int finalize_fit(cwb_fit* f);
-RowItem make_row_item(int fit, int blk, const FitDev& D);
+RowItem make_row_item(int fit, int blk, const FitDev& D, int chunks = 1);
+// Row chunks per row-pass block for a launch over `total` chunks: one,
+// unless the launch holds far more chunks than the chip holds blocks (a
+// large batch), so that each block's selection and table staging serve
+// several chunks.
+int row_chunks(int64_t total, int cus);
+// The row-pass work list of one fit: blocks of `chunks` chunks each.
+void append_row_items(std::vector<RowItem>* out, int fit, const FitDev& D, int n_row_blocks,
+                      int chunks);
 SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const Schedule& S,
                       const int64_t* d_sel_off, size_t idx);
 // Every candidate tile shape for these fits (only the default unless `all`),

@@ -598,3 +598,31 @@ def test_nonfinite_state_is_reported_at_sync(variant):
     assert err.value.code == cwb.CWB_E_NUMERIC
     f.close()
     compare(_run(prob), prob)
+
+
+@pytest.mark.parametrize("variant,loss", [("cwb", "l2"), ("acwb", "binomial"), ("hcwb", "l2")])
+def test_row_pass_chunks_bitwise(variant, loss, monkeypatch):
+    """Row-pass blocks covering several 2,048-row chunks (as in large
+    batches) give bitwise the results of one chunk per block, alone and in a
+    batch, with ragged chunk counts at the end of each fit."""
+    probs = [datagen.additive_problem(41_111, 9, seed=151, n_informative=3, loss=loss, n_bins=130,
+                                      M=40, variant=variant, gamma=0.05, patience=2),
+             datagen.additive_problem(23_456, 6, seed=152, n_informative=2, n_bins=90, M=40)]
+    ref = [_run(p) for p in probs]
+    monkeypatch.setenv("CWB_ROW_CHUNKS", "3")
+    got = _run(probs[0])
+    for key in ("k", "kcor", "f", "coef_f", "coef_h", "risk_train", "risk_val"):
+        np.testing.assert_array_equal(got[key], ref[0][key], err_msg=key)
+    assert got["switch_iter"] == ref[0]["switch_iter"]
+    monkeypatch.setenv("CWB_ROW_CHUNKS", "7")
+    fits = [cwb.Fit(p) for p in probs]
+    b = cwb.Batch(fits)
+    b.run(40)
+    b.sync()
+    for f, r in zip(fits, ref):
+        np.testing.assert_array_equal(f.trace()["k"], r["k"])
+        np.testing.assert_array_equal(f.pred(), r["f"])
+        np.testing.assert_array_equal(f.trace()["risk_train"], r["risk_train"])
+        f.close()
+    b.close()
+    compare(got, probs[0])
