@@ -132,13 +132,17 @@ def headline(args, torch, cwb, datagen):
 
 def setup_leg(prob, cwb):
     """Fit creation of the headline problem with binning and bin counts on
-    host threads and on the GPU (the tile autotuner off for both, so that
-    only the setup differs); best of two creations each."""
-    old = os.environ.get("CWB_AUTOTUNE")
+    host threads and on the GPU, the latter with the learners' Gram, lambda
+    and inverse solves on the GPU too (device_s) or on host threads
+    (device_host_solves_s); the tile autotuner is off for all three, so that
+    only the setup differs; best of two creations each."""
+    saved = {k: os.environ.get(k) for k in ("CWB_AUTOTUNE", "CWB_DEVICE_SOLVES")}
     os.environ["CWB_AUTOTUNE"] = "0"
     out = {}
     try:
-        for setup in ("host", "device"):
+        for name, setup, solves in (("host", "host", "1"), ("device", "device", "1"),
+                                    ("device_host_solves", "device", "0")):
+            os.environ["CWB_DEVICE_SOLVES"] = solves
             best = None
             for _ in range(2):
                 t0 = time.perf_counter()
@@ -146,13 +150,14 @@ def setup_leg(prob, cwb):
                 dt = time.perf_counter() - t0
                 f.close()
                 best = dt if best is None else min(best, dt)
-            out[f"{setup}_s"] = round(best, 4)
-            log(f"[bench] setup on {setup}: {best:.3f}s")
+            out[f"{name}_s"] = round(best, 4)
+            log(f"[bench] setup {name}: {best:.3f}s")
     finally:
-        if old is None:
-            os.environ.pop("CWB_AUTOTUNE", None)
-        else:
-            os.environ["CWB_AUTOTUNE"] = old
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     out["speedup"] = round(out["host_s"] / max(out["device_s"], 1e-9), 2)
     out["host_threads"] = os.cpu_count()
     return out
@@ -497,8 +502,10 @@ def batched(args, torch, cwb, datagen):
 
 
 def served(args, torch, cwb, datagen):
-    """Poisson request stream through the fit server, then the same stream
-    served one fit at a time (max_slots = 1) on the same GPU."""
+    """Poisson request stream through the fit server (each request binned,
+    counted and solved on the GPU during its upload), the same stream with
+    the setup on host threads, then the stream served one fit at a time
+    (max_slots = 1) on the same GPU."""
     from concurrent.futures import ThreadPoolExecutor
     specs = datagen.config5_stream(count=args.serve_requests)
     n_max = max(s["n"] for s in specs)
@@ -509,7 +516,7 @@ def served(args, torch, cwb, datagen):
     sample = sorted(range(len(specs)), key=lambda i: specs[i]["n"] * specs[i]["p"] * specs[i]["M"])[:8]
     index_bytes = sum(2.0 * s["n"] * s["p"] * s["M"] for s in specs)
 
-    def one_stream(max_slots):
+    def one_stream(max_slots, setup="auto"):
         srv = cwb.Server(arena_bytes=int(args.serve_arena_gb * (1 << 30)), max_slots=max_slots,
                          quantum=args.serve_quantum)
         ex = ThreadPoolExecutor(max_workers=4)
@@ -522,6 +529,7 @@ def served(args, torch, cwb, datagen):
         t0 = time.perf_counter()
         for i, s in enumerate(specs):
             prob = futs.pop(i).result()
+            prob["setup"] = setup
             if i + ahead < len(specs):
                 futs[i + ahead] = ex.submit(datagen.config5_problem_pooled, specs[i + ahead], pool)
             wait = t0 + s["arrival"] - time.perf_counter()
@@ -555,10 +563,12 @@ def served(args, torch, cwb, datagen):
         st["failed"] = sum(1 for r in results.values() if r["status"] != 0)
         return st, results
 
-    log("[bench] served: continuous batching")
+    log("[bench] served: continuous batching (setup on the GPU during upload)")
     st, res = one_stream(args.serve_slots)
-    st1 = None
+    st1 = sth = None
     if not args.serve_batched_only:
+        log("[bench] served: continuous batching, setup on host threads")
+        sth, _ = one_stream(args.serve_slots, "host")
         log("[bench] served: one fit at a time")
         st1, _ = one_stream(1)
     # alone vs in the mix
@@ -589,6 +599,7 @@ def served(args, torch, cwb, datagen):
             "max_slots": args.serve_slots, "quantum": args.serve_quantum,
             "arena_gb": args.serve_arena_gb,
             "continuous_batching": summary(st),
+            "continuous_host_setup": summary(sth) if sth else None,
             "one_at_a_time": summary(st1) if st1 else None,
             "speedup_fits_per_s": (round(st["fits_per_s"] / max(st1["fits_per_s"], 1e-12), 3)
                                    if st1 else None),

@@ -124,14 +124,20 @@ typedef struct {
 } cwb_problem;
 
 /* cwb_problem.setup */
-#define CWB_SETUP_AUTO 0   /* device for binned fits with n < 2^31, else host;
-                              the server always bins on its host setup
-                              threads, which overlap the running batch */
+#define CWB_SETUP_AUTO 0   /* device for binned fits with n < 2^31, else host
+                              (the server alike: a request set up on the
+                              device is binned and solved during its upload,
+                              on the server's upload stream, overlapping the
+                              running batch) */
 #define CWB_SETUP_HOST 1   /* host threads bin every column (Sec. 3.1.1) */
 #define CWB_SETUP_DEVICE 2 /* columns are copied to the workspace one at a
                               time and binned and counted on the GPU; the host
-                              then builds the learner tables from the ranges
-                              and counts */
+                              builds the bases from the ranges, and the GPU
+                              the Gram matrices, smoothing parameters and
+                              inverses of learners with at most 32 basis
+                              functions from the counts (one block per
+                              learner and row set; the host those of larger
+                              ones) */
 
 /* Sizes of a created fit (for sizing getter buffers). */
 typedef struct {
@@ -392,7 +398,9 @@ typedef struct {
   double fits_per_s;    /* completed / seconds since the first submit */
   double p50_latency_s, p99_latency_s;
   size_t arena_in_use, arena_peak;
-  double mean_setup_s;  /* host setup time per completed request */
+  double mean_setup_s;  /* per completed request: host setup plus upload
+                           (the upload includes the device setup pass of a
+                           request set up on the GPU) */
   double mean_queue_s;  /* submit -> admitted, per completed request */
   double round_s;       /* device-thread time inside rounds (launch to end of round) */
   double busy_s;        /* device-thread time from the first round to the last */
@@ -402,7 +410,8 @@ typedef struct {
 int cwb_server_create(const cwb_server_cfg* cfg, cwb_server** out);
 /* Queue a request and return at once; `ticket` identifies it.  The learner
  * specifications are copied; the arrays x, y and val_mask are read later by
- * the server's setup threads, so the caller keeps them valid and unchanged
+ * the server's setup threads (x by its upload thread for a request set up on
+ * the GPU), so the caller keeps them valid and unchanged
  * until poll has returned the request's result. */
 int cwb_server_submit(cwb_server* s, const cwb_problem* pr, uint64_t* ticket);
 /* CWB_E_AGAIN while pending; else fills `res` and, if the pointers are not

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cwb_internal.h"
+#include "algebra.h"
 #include "kernels.h"
 
 namespace cwb {
@@ -188,6 +189,47 @@ hipError_t launch_pack12(hipStream_t st, const uint16_t* X, int64_t groups, uint
   const int64_t want = (groups + kSetupThreads - 1) / kSetupThreads;
   const int blocks = (int)(want < 65536 ? want : 65536);
   hipLaunchKernelGGL(k_pack12, dim3(blocks), dim3(kSetupThreads), 0, st, X, groups, X12);
+  return hipGetLastError();
+}
+
+// The learners' solves of the device setup pass, one block of one wavefront
+// per (learner, row set): alg::learner_solve in LDS -- the routine the host
+// setup runs, each value by the same operations, built without contraction
+// -- with its element loops spread over the 64 lanes; then the block copies
+// the Gram matrix and the inverse out.  status[job]: 0, -1 (df out of
+// reach) or -5 (singular); lam[job]: lambda.
+__global__ void __launch_bounds__(64)
+k_solve(const SolveJob* __restrict__ jobs, int* __restrict__ status, double* __restrict__ lam) {
+  extern __shared__ double s_m[];
+  const SolveJob jb = jobs[blockIdx.x];
+  const int d = jb.d;
+  double* G = s_m;
+  double* inv = s_m + d * d;
+  double* scr = s_m + 2 * d * d;
+  const alg::Lanes ex{(int)threadIdx.x, (int)blockDim.x};
+  double l = 0.0;
+  const int rc = alg::learner_solve(ex, jb.kind, d, jb.nb, jb.band, jb.bstart, jb.bval, kMaxBand,
+                                    jb.cnt, jb.pen_order, jb.df, jb.lambda, G, inv, &l, scr);
+  if (threadIdx.x == 0) {
+    status[blockIdx.x] = rc;
+    lam[blockIdx.x] = l;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d * d; i += blockDim.x) {
+    jb.gram[i] = G[i];
+    jb.ainv[i] = inv[i];
+  }
+}
+
+hipError_t launch_solve(hipStream_t st, const SolveJob* jobs, int njobs, int d_max, int* status,
+                        double* lam) {
+  if (njobs <= 0) return hipSuccess;
+  if (d_max < 1 || d_max > 64) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)2 * d_max * d_max + alg::solve_scratch(d_max)) * sizeof(double);
+  if (lds > 152 * 1024) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+  hipLaunchKernelGGL(k_solve, dim3(njobs), dim3(64), lds, st, jobs, status, lam);
   return hipGetLastError();
 }
 

@@ -37,6 +37,10 @@ hipError_t launch_bin(hipStream_t st, const double* x, const int32_t* perm, int6
                       int64_t n_train, int categorical, int nb, const unsigned long long* mm,
                       uint16_t* out, uint32_t* counts, int64_t half, int* flag);
 
+// The learners' solves of the device setup pass (binning.hip): njobs blocks,
+// LDS for basis sizes up to d_max (at most kDeviceSolveMaxD).
+hipError_t launch_solve(hipStream_t st, const SolveJob* jobs, int njobs, int d_max, int* status,
+                        double* lam);
 // The 12-bit copy of the index matrix (binning.hip): groups = p n_pad / 8,
 // every index below 4,096.
 hipError_t launch_pack12(hipStream_t st, const uint16_t* X, int64_t groups, uint32_t* X12);

@@ -869,8 +869,74 @@ int device_binning(const cwb_problem* pr, const FitShape& sh, HostFit& hf, const
     if (!(xr[2 * j + 1] > xr[2 * j])) return set_error(CWB_E_INVALID_ARG, "constant feature " + std::to_string(j));
   }
   std::string err;
-  const int rc = finish_host_fit(pr, &hf, xr.data(), cnt.data(), cstride, &err);
+  const int rc = finish_host_fit(pr, &hf, xr.data(), cnt.data(), cstride, &err,
+                                 env_int("CWB_DEVICE_SOLVES", 1) != 0);
   if (rc) return set_error(rc, err);
+  return CWB_OK;
+}
+
+// The device setup pass's learner solves (after device_binning): Gram
+// matrices from the bin counts still in the partials region, lambda and the
+// inverses, for every learner left to the device (solve_on_device), written
+// into the fit's tables.  The job list borrows the select work-list region
+// and the status and lambda outputs the criterion and theta regions, which
+// are cleared again.
+int device_solves(const cwb_problem* pr, const FitShape& sh, const HostFit& hf,
+                  const std::vector<FeatDev>& feat, const FitDev& D, const Layout& L, char* ws,
+                  hipStream_t st) {
+  const int64_t cstride = 2 * (int64_t)sh.nb_stride;
+  const uint32_t* d_cnt = dptr<uint32_t>(ws, L.partials);
+  std::vector<SolveJob> jobs;
+  std::vector<int> job_feat;
+  int dmax = 0;
+  for (int j = 0; j < sh.p; ++j) {
+    const HostLearner& hl = hf.L[j];
+    if (!hl.solve_on_device) continue;
+    const cwb_learner_spec& s = pr->specs[j];
+    const FeatDev& fd = feat[j];
+    for (int set = 0; set < 2; ++set) {
+      SolveJob jb;
+      std::memset(&jb, 0, sizeof(jb));
+      jb.bstart = D.bstart + fd.bin_off;
+      jb.bval = D.bval + fd.bin_off * kMaxBand;
+      jb.cnt = d_cnt + (size_t)j * cstride + (set ? cstride / 2 : 0);
+      jb.gram = const_cast<double*>(D.gram[set]) + fd.mat_off;
+      jb.ainv = const_cast<double*>(D.ainv[set]) + fd.mat_off;
+      jb.df = s.df;
+      jb.lambda = s.lambda;
+      jb.kind = s.kind;
+      jb.d = hl.d;
+      jb.nb = hl.nb;
+      jb.band = hl.band;
+      jb.pen_order = s.penalty_order;
+      jobs.push_back(jb);
+      job_feat.push_back(j);
+      dmax = std::max(dmax, hl.d);
+    }
+  }
+  if (jobs.empty()) return CWB_OK;
+  static_assert(2 * sizeof(SolveJob) <= sizeof(SelItem), "solve jobs fit the select work list");
+  if (jobs.size() * sizeof(SolveJob) > (size_t)sh.p * sizeof(SelItem) ||
+      jobs.size() * sizeof(int) > (size_t)kNumSig * sh.p * 8 ||
+      jobs.size() * sizeof(double) > (size_t)kNumSig * sh.p * sh.d_max * 8)
+    return set_error(CWB_E_INVALID_ARG, "internal: device solve scratch");
+  SolveJob* d_jobs = dptr<SolveJob>(ws, L.sel_items);
+  int* d_status = dptr<int>(ws, L.q);
+  double* d_lam = dptr<double>(ws, L.theta);
+  HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(SolveJob), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_solve(st, d_jobs, (int)jobs.size(), dmax, d_status, d_lam));
+  std::vector<int> status(jobs.size());
+  HIP_TRY(hipMemcpyAsync(status.data(), d_status, status.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemsetAsync(d_status, 0, jobs.size() * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(d_lam, 0, jobs.size() * sizeof(double), st));
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    if (status[i] == 0) continue;
+    const std::string what = status[i] == -1 ? "df target not reachable for this basis and penalty"
+                                             : "penalised Gram matrix is singular or degenerate";
+    return set_error(status[i] == -1 ? CWB_E_INVALID_ARG : CWB_E_NUMERIC,
+                     what + " (feature " + std::to_string(job_feat[i]) + ")");
+  }
   return CWB_OK;
 }
 
@@ -1090,6 +1156,10 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
     HIP_TRY(hipMemcpyAsync(ws + L.gram[set], gram[set].data(), gram[set].size() * 8, hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipMemcpyAsync(ws + L.fitdev, &D, sizeof(D), hipMemcpyHostToDevice, st));
+  if (bin_on_device) {  // the learners' solves left to the device
+    const int rc = device_solves(bin_on_device, sh, hf, feat, D, L, ws, st);
+    if (rc) return rc;
+  }
 
   // solo schedule and work lists
   const Schedule& S = f->sched;

@@ -3,8 +3,9 @@
 // Requests flow through four stages:
 //   submit    the request is queued for setup (the caller's arrays are read
 //             in place, so they stay valid until its result is polled);
-//   setup     host threads run the FP64 setup (binning, bases, Grams,
-//             smoothing parameters) and compute the device footprint;
+//   setup     host threads check the request and compute its device
+//             footprint; a request set up on the host also has its FP64
+//             setup run here (binning, bases, Grams, smoothing parameters);
 //   admission the device thread admits set-up requests in arrival order while
 //             the arena holds their workspace and the batch workspace of the
 //             grown set, and a slot is free;
@@ -14,7 +15,9 @@
 //             copied to the host and their arena space is released.
 // Uploads of newly admitted fits run on their own host thread and a second
 // stream, so neither the rounds nor the GPU wait for them; an uploaded fit
-// joins the batch at the next round boundary.
+// joins the batch at the next round boundary.  A request set up on the GPU
+// (cwb_problem.setup AUTO or DEVICE, binned, n < 2^31) is binned, counted
+// and solved during its upload, in its own arena space, on that stream.
 // A fit's result does not depend on which other fits share its rounds: the
 // histograms are exact integer sums and every selection is per fit.
 #include <hip/hip_runtime.h>
@@ -50,7 +53,8 @@ struct Request {
   // the problem (caller-owned arrays, copied specifications)
   cwb_problem pr;
   std::vector<cwb_learner_spec> specs;
-  double setup_s = 0;
+  double setup_s = 0;  // host setup, plus the upload (and device setup pass)
+  bool dev_setup = false;  // binning, counts and solves during the upload
   // setup result, dropped after upload
   FitShape shape;
   HostFit hf;
@@ -150,7 +154,21 @@ void setup_worker(cwb_server* s) {
     const double t0 = now_s();
     try {
       rc = shape_from_problem(&r->pr, &r->shape, &err);
-      if (!rc) rc = build_host_fit(&r->pr, &r->hf, &err);
+      if (!rc) {
+        const bool device_ok = !r->shape.unbinned && r->shape.n < (int64_t)INT32_MAX;
+        if (r->pr.setup < CWB_SETUP_AUTO || r->pr.setup > CWB_SETUP_DEVICE) {
+          rc = CWB_E_INVALID_ARG;
+          err = "unknown setup mode";
+        } else if (r->pr.setup == CWB_SETUP_DEVICE && !device_ok) {
+          rc = CWB_E_UNSUPPORTED;
+          err = "device setup covers binned fits with n < 2^31";
+        } else {
+          r->dev_setup = r->pr.setup == CWB_SETUP_DEVICE ||
+                         (r->pr.setup == CWB_SETUP_AUTO && device_ok);
+        }
+      }
+      if (!rc) rc = r->dev_setup ? prepare_host_fit(&r->pr, &r->hf, &err)
+                                 : build_host_fit(&r->pr, &r->hf, &err);
       if (!rc) {
         rc = fit_footprint(r->shape, &fp, false);
         if (rc) err = cwb_last_error();
@@ -323,8 +341,10 @@ void upload_worker(cwb_server* s) {
     cwb_fit* f = nullptr;
     int rc = CWB_OK;
     std::string err;
+    const double t0 = now_s();
     try {
-      rc = fit_upload(r->shape, r->hf, s->base + r->off, r->footprint, s->upload, false, &f);
+      rc = fit_upload(r->shape, r->hf, s->base + r->off, r->footprint, s->upload, false, &f,
+                      r->dev_setup ? &r->pr : nullptr);
       if (rc) err = cwb_last_error();
     } catch (const std::bad_alloc&) {
       rc = set_error(CWB_E_NO_MEMORY, "host allocation failed during upload");
@@ -337,6 +357,7 @@ void upload_worker(cwb_server* s) {
     if (!rc) f->stream = s->stream;
     {
       std::lock_guard<std::mutex> lk(s->mu);
+      r->setup_s += now_s() - t0;
       r->fit = rc ? nullptr : f;
       if (rc) {
         r->status = rc;

@@ -10,11 +10,17 @@
 //  * difference penalties (Appendix A.2) and, for a requested df, the
 //    smoothing parameter from the Demmler-Reinsch orthogonalisation:
 //    with G = L L^T and L^-1 D L^-T = U diag(w) U^T, df(lambda) =
-//    sum_i 1 / (1 + lambda w_i), solved by bisection in log(lambda);
+//    sum_i 1 / (1 + lambda w_i), solved by a safeguarded Newton iteration;
 //  * categorical ridge learners in closed form (Appendix A.3.1);
 //  * the inverse penalised Gram matrix (cached factorisation, Section 2.4).
-// Compiled with -ffp-contract=off so the binning distances are not fused.
+// The dense algebra is alg:: (algebra.h), which the device setup pass runs
+// as well; with device binning the Grams, lambdas and inverses of learners
+// up to kDeviceSolveMaxD basis functions are left to that pass.
+// Compiled with -ffp-contract=off so the binning distances and the algebra
+// are not fused.
 #include "setup.h"
+
+#include "algebra.h"
 
 #include <algorithm>
 #include <atomic>
@@ -25,234 +31,15 @@
 
 namespace cwb {
 
-namespace {
-
-// ---- dense FP64 helpers (row-major d x d) --------------------------------
-
-bool chol_lower(int d, const std::vector<double>& A, std::vector<double>& L) {
-  L.assign((size_t)d * d, 0.0);
-  for (int j = 0; j < d; ++j) {
-    double s = A[(size_t)j * d + j];
-    for (int k = 0; k < j; ++k) s -= L[(size_t)j * d + k] * L[(size_t)j * d + k];
-    if (!(s > 0.0) || !std::isfinite(s)) return false;
-    const double ljj = std::sqrt(s);
-    L[(size_t)j * d + j] = ljj;
-    for (int i = j + 1; i < d; ++i) {
-      double t = A[(size_t)i * d + j];
-      for (int k = 0; k < j; ++k) t -= L[(size_t)i * d + k] * L[(size_t)j * d + k];
-      L[(size_t)i * d + j] = t / ljj;
-    }
-  }
-  return true;
-}
-
-// Inverse of the lower-triangular L.
-std::vector<double> tri_inverse(int d, const std::vector<double>& L) {
-  std::vector<double> X((size_t)d * d, 0.0);
-  for (int c = 0; c < d; ++c) {
-    for (int i = c; i < d; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) t -= L[(size_t)i * d + k] * X[(size_t)k * d + c];
-      X[(size_t)i * d + c] = t / L[(size_t)i * d + i];
-    }
-  }
-  return X;
-}
-
-// A^-1 for symmetric positive definite A, as L^-T L^-1.
-bool spd_inverse(int d, const std::vector<double>& A, std::vector<double>& inv) {
-  std::vector<double> L;
-  if (!chol_lower(d, A, L)) return false;
-  std::vector<double> Li = tri_inverse(d, L);
-  inv.assign((size_t)d * d, 0.0);
-  for (int i = 0; i < d; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double s = 0.0;
-      for (int k = i; k < d; ++k) s += Li[(size_t)k * d + i] * Li[(size_t)k * d + j];
-      inv[(size_t)i * d + j] = s;
-      inv[(size_t)j * d + i] = s;
-    }
-  return true;
-}
-
-// Eigenvalues of a symmetric matrix by cyclic Jacobi rotations.
-std::vector<double> jacobi_eigenvalues(int d, std::vector<double> S) {
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) {
-        const double v = S[(size_t)i * d + j] * S[(size_t)i * d + j];
-        tot += v;
-        if (i != j) off += v;
-      }
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < d - 1; ++p)
-      for (int q = p + 1; q < d; ++q) {
-        const double apq = S[(size_t)p * d + q];
-        if (apq == 0.0) continue;
-        const double app = S[(size_t)p * d + p], aqq = S[(size_t)q * d + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < d; ++k) {  // columns p, q
-          const double akp = S[(size_t)k * d + p], akq = S[(size_t)k * d + q];
-          S[(size_t)k * d + p] = c * akp - s * akq;
-          S[(size_t)k * d + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < d; ++k) {  // rows p, q
-          const double apk = S[(size_t)p * d + k], aqk = S[(size_t)q * d + k];
-          S[(size_t)p * d + k] = c * apk - s * aqk;
-          S[(size_t)q * d + k] = s * apk + c * aqk;
-        }
-      }
-  }
-  std::vector<double> w(d);
-  for (int i = 0; i < d; ++i) w[i] = S[(size_t)i * d + i];
-  return w;
-}
-
-// Difference penalty Delta^T Delta of order `ord` (ord = 0: identity).
-std::vector<double> difference_penalty(int d, int ord) {
-  std::vector<double> Dm((size_t)d * d, 0.0);
-  for (int i = 0; i < d; ++i) Dm[(size_t)i * d + i] = 1.0;  // rows of Delta^(0) = I
-  int rows = d;
-  for (int o = 0; o < ord; ++o) {  // Delta^(o+1)[i] = Delta^(o)[i+1] - Delta^(o)[i]
-    for (int i = 0; i < rows - 1; ++i)
-      for (int j = 0; j < d; ++j)
-        Dm[(size_t)i * d + j] = Dm[(size_t)(i + 1) * d + j] - Dm[(size_t)i * d + j];
-    --rows;
-  }
-  std::vector<double> P((size_t)d * d, 0.0);
-  for (int r = 0; r < rows; ++r)
-    for (int i = 0; i < d; ++i) {
-      const double a = Dm[(size_t)r * d + i];
-      if (a == 0.0) continue;
-      for (int j = 0; j < d; ++j) P[(size_t)i * d + j] += a * Dm[(size_t)r * d + j];
-    }
-  return P;
-}
-
-}  // namespace
-
-// lambda with df(lambda) = target (App. A.2), by Newton's method on
-// g(u) = df(e^u) - target in u = log(lambda), safeguarded by a bracket on
-// which g changes sign (df decreases monotonically in lambda, so g does in
-// u).  With G positive definite, df and its derivative come from the
-// Demmler-Reinsch eigenvalues w of L^-1 D L^-T (G = L L^T):
-// df = sum 1/(1 + lambda w_i), d df/d lambda = -sum w_i/(1 + lambda w_i)^2.
-// Otherwise both come from A = G + lambda D directly:
-// df = tr(A^-1 G), d df/d lambda = -tr(A^-1 D A^-1 G).
+// lambda with df(lambda) = target (App. A.2): alg::lambda_for_df, the
+// routine the device setup pass runs too.
 int lambda_for_df(int d, const std::vector<double>& G, const std::vector<double>& D, double target,
                   double* lam_out, std::string* err) {
-  std::vector<double> L;
-  std::vector<double> w;
-  const bool dro = chol_lower(d, G, L);
-  if (dro) {
-    // S = L^-1 D L^-T
-    std::vector<double> Li = tri_inverse(d, L);
-    std::vector<double> T((size_t)d * d, 0.0), S((size_t)d * d, 0.0);
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) {
-        double s = 0.0;
-        for (int k = 0; k <= i; ++k) s += Li[(size_t)i * d + k] * D[(size_t)k * d + j];
-        T[(size_t)i * d + j] = s;
-      }
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) {
-        double s = 0.0;
-        for (int k = 0; k <= j; ++k) s += T[(size_t)i * d + k] * Li[(size_t)j * d + k];
-        S[(size_t)i * d + j] = s;
-      }
-    for (int i = 0; i < d; ++i)
-      for (int j = i + 1; j < d; ++j) {
-        const double a = 0.5 * (S[(size_t)i * d + j] + S[(size_t)j * d + i]);
-        S[(size_t)i * d + j] = a;
-        S[(size_t)j * d + i] = a;
-      }
-    w = jacobi_eigenvalues(d, S);
-    for (double& wi : w) wi = std::max(wi, 0.0);
-  }
-  // g(u) and dg/du at u = log(lambda)
-  auto eval = [&](double u, double* g, double* dg) -> bool {
-    const double lam = std::exp(u);
-    if (dro) {
-      double f = 0.0, fp = 0.0;
-      for (double wi : w) {
-        const double q = 1.0 / (1.0 + lam * wi);
-        f += q;
-        fp -= wi * q * q;
-      }
-      *g = f - target;
-      *dg = lam * fp;
-      return true;
-    }
-    std::vector<double> A((size_t)d * d), inv;
-    for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
-    if (!spd_inverse(d, A, inv)) return false;
-    std::vector<double> P((size_t)d * d, 0.0), Q((size_t)d * d, 0.0);  // A^-1 G, A^-1 D
-    for (int i = 0; i < d; ++i)
-      for (int k = 0; k < d; ++k) {
-        const double a = inv[(size_t)i * d + k];
-        for (int j = 0; j < d; ++j) {
-          P[(size_t)i * d + j] += a * G[(size_t)k * d + j];
-          Q[(size_t)i * d + j] += a * D[(size_t)k * d + j];
-        }
-      }
-    double f = 0.0, fp = 0.0;
-    for (int i = 0; i < d; ++i) {
-      f += P[(size_t)i * d + i];
-      for (int k = 0; k < d; ++k) fp -= Q[(size_t)i * d + k] * P[(size_t)k * d + i];
-    }
-    *g = f - target;
-    *dg = lam * fp;
-    return true;
-  };
-  double trG = 0.0, trD = 0.0;
-  for (int i = 0; i < d; ++i) {
-    trG += G[(size_t)i * d + i];
-    trD += D[(size_t)i * d + i];
-  }
-  if (!(trG > 0.0) || !(trD > 0.0)) {
-    *err = "degenerate Gram or penalty matrix";
-    return -5;
-  }
-  // bracket [ua, ub] with g(ua) > 0 > g(ub): widen in steps of 5 in u
-  // (a factor e^5 in lambda) from the scale trG / trD, within e^-35 .. e^35
-  // (about 1e-15 .. 1e15) times it.  A target that needs a lambda beyond
-  // that lies at the edge of what the basis or the penalty's null space
-  // allows (rounding decides there), and is reported as out of reach.
-  const double u0 = std::log(trG / trD);
-  constexpr double kStep = 5.0;
-  constexpr int kWiden = 7;
-  double ua = u0, ub = u0, ga = 0.0, gb = 0.0, dg = 0.0;
-  int i = 0;
-  for (; i <= kWiden; ++i, ua -= kStep) {
-    if (!eval(ua, &ga, &dg)) { *err = "penalised Gram matrix not positive definite"; return -5; }
-    if (ga > 0.0) break;
-  }
-  if (i > kWiden) { *err = "df target not reachable (too large for the basis)"; return -1; }
-  for (i = 0; i <= kWiden; ++i, ub += kStep) {
-    if (!eval(ub, &gb, &dg)) { *err = "penalised Gram matrix not positive definite"; return -5; }
-    if (gb < 0.0) break;
-  }
-  if (i > kWiden) { *err = "df target not reachable (too small for the penalty)"; return -1; }
-  // Newton steps inside the bracket; a step that leaves it, or a flat
-  // derivative, is replaced by the bracket's midpoint
-  double u = 0.5 * (ua + ub), g = 0.0;
-  for (int it = 0; it < 200; ++it) {
-    if (!eval(u, &g, &dg)) { *err = "penalised Gram matrix not positive definite"; return -5; }
-    if (g == 0.0) break;
-    if (g > 0.0) ua = u; else ub = u;
-    double un = (dg < 0.0) ? u - g / dg : 0.5 * (ua + ub);
-    if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);
-    if (std::fabs(un - u) <= 4.0 * DBL_EPSILON * std::max(1.0, std::fabs(u))) {
-      u = un;
-      break;
-    }
-    u = un;
-  }
-  *lam_out = std::exp(u);
-  return 0;
+  std::vector<double> scr((size_t)alg::lambda_scratch(d));
+  const int rc = alg::lambda_for_df(alg::Serial(), d, G.data(), D.data(), target, lam_out, scr.data());
+  if (rc == -5) *err = "degenerate or not positive definite penalised Gram matrix";
+  else if (rc) *err = "df target not reachable for this basis and penalty";
+  return rc;
 }
 
 namespace {
@@ -457,12 +244,14 @@ void categorical_design(HostLearner& L, int c) {
 }
 
 // Support ranges, Gram matrices over the training rows and over all rows,
-// smoothing parameters and the inverses of G + lambda D.  Binned learners
-// take their Grams from the bin counts (binMatMat, Algorithm 1); unbinned
-// ones bring them in G_unb.
+// smoothing parameters and the inverses of G + lambda D (alg::learner_solve,
+// the routine the device setup pass runs).  Binned learners take their Grams
+// from the bin counts (binMatMat, Algorithm 1); unbinned ones bring them in
+// G_unb.  Without `solves` only the support ranges and the count bound are
+// set, and the Gram and inverse are zero placeholders of the right size.
 int learner_algebra(const cwb_learner_spec& s, int64_t n, HostLearner& L,
                     const std::vector<double>& cnt_t, const std::vector<double>& cnt_a,
-                    const std::vector<double>* G_unb, int j, std::string* err) {
+                    const std::vector<double>* G_unb, int j, std::string* err, bool solves = true) {
   const int d = L.d;
   // the largest bin count over all rows bounds every histogram sum of the
   // learner (32-bit histogram accumulation)
@@ -480,67 +269,41 @@ int learner_algebra(const cwb_learner_spec& s, int64_t n, HostLearner& L,
     L.jr[2 * q] = lo;
     L.jr[2 * q + 1] = hi;
   }
-  const std::vector<double> D = (s.kind != CWB_PSPLINE) ? difference_penalty(d, 0)
-                                                         : difference_penalty(d, s.penalty_order);
   for (int set = 0; set < 2; ++set) {
     const std::vector<double>& cnt = set == 0 ? cnt_t : cnt_a;
-    if (s.kind == CWB_BINARY_CAT) {
-      // one unpenalised learner per class: G = diag(n_l); the class
-      // estimate is s_l / n_l, and an empty class has none (its inverse
-      // entry stays 0)
-      L.gram[set].assign((size_t)d * d, 0.0);
-      L.ainv[set].assign((size_t)d * d, 0.0);
-      for (int l = 0; l < d; ++l) {
-        L.gram[set][(size_t)l * d + l] = cnt[l];
-        if (cnt[l] > 0.0) L.ainv[set][(size_t)l * d + l] = 1.0 / cnt[l];
-      }
-      L.lambda[set] = 0.0;
-      continue;
-    }
-    std::vector<double> G((size_t)d * d, 0.0);
+    L.gram[set].assign((size_t)d * d, 0.0);
+    L.ainv[set].assign((size_t)d * d, 0.0);
+    L.lambda[set] = 0.0;
+    if (!solves) continue;  // placeholders: the device setup pass fills them in
+    std::vector<double> scr((size_t)alg::solve_scratch(d));
+    double lam = 0.0;
+    int rc;
     if (G_unb) {
-      G = G_unb[set];
+      // unbinned: the Gram matrix comes in; lambda and the inverse as for
+      // binned learners
+      L.gram[set] = G_unb[set];
+      double* D = scr.data();
+      double* A = D + (size_t)d * d;
+      double* rest = A + (size_t)d * d;
+      alg::penalty(alg::Serial(), d, s.penalty_order, D, rest);
+      lam = s.lambda;
+      rc = (s.df > 0.0) ? alg::lambda_for_df(alg::Serial(), d, L.gram[set].data(), D, s.df, &lam, rest) : 0;
+      if (!rc) {
+        for (size_t i = 0; i < (size_t)d * d; ++i) A[i] = L.gram[set][i] + lam * D[i];
+        rc = alg::spd_inverse(alg::Serial(), d, A, L.ainv[set].data(), rest) ? 0 : -5;
+      }
     } else {
-      for (int l = 0; l < L.nb; ++l) {
-        if (cnt[l] == 0.0) continue;
-        const int b0 = L.bstart[l];
-        const double* bv = &L.bval[(size_t)l * kMaxBand];
-        for (int a = 0; a < L.band; ++a)
-          for (int b = 0; b < L.band; ++b) G[(size_t)(b0 + a) * d + (b0 + b)] += cnt[l] * bv[a] * bv[b];
-      }
+      rc = alg::learner_solve(alg::Serial(), s.kind, d, L.nb, L.band, L.bstart.data(),
+                              L.bval.data(), kMaxBand, cnt.data(), s.penalty_order, s.df, s.lambda, L.gram[set].data(),
+                              L.ainv[set].data(), &lam, scr.data());
     }
-    double lam = s.lambda;
-    if (s.df > 0.0) {
-      if (s.kind == CWB_RIDGE_CAT) {
-        if (s.df >= (double)d) {
-          lam = 0.0;
-        } else {  // sum_l n_l / (n_l + lambda) = df, bisection in log(lambda)
-          double lo = 1e-12, hi = 1e12 * (double)n;
-          for (int it = 0; it < 400 && hi / lo > 1.0 + 1e-15; ++it) {
-            const double mid = std::sqrt(lo * hi);
-            double v = 0.0;
-            for (int l = 0; l < d; ++l) v += cnt[l] / (cnt[l] + mid);
-            if (v > s.df) lo = mid; else hi = mid;
-          }
-          lam = std::sqrt(lo * hi);
-        }
-      } else {
-        std::string e;
-        const int r2 = lambda_for_df(d, G, D, s.df, &lam, &e);
-        if (r2) {
-          *err = e + " (feature " + std::to_string(j) + ")";
-          return r2;
-        }
-      }
+    if (rc) {
+      *err = (rc == -1 ? std::string("df target not reachable for this basis and penalty")
+                       : std::string("penalised Gram matrix is singular or degenerate")) +
+             " (feature " + std::to_string(j) + ")";
+      return rc == -1 ? CWB_E_INVALID_ARG : CWB_E_NUMERIC;
     }
     L.lambda[set] = lam;
-    std::vector<double> A((size_t)d * d);
-    for (size_t i = 0; i < A.size(); ++i) A[i] = G[i] + lam * D[i];
-    if (!spd_inverse(d, A, L.ainv[set])) {
-      *err = "penalised Gram matrix is singular (feature " + std::to_string(j) + ")";
-      return CWB_E_NUMERIC;
-    }
-    L.gram[set] = G;
   }
   return CWB_OK;
 }
@@ -772,7 +535,8 @@ int build_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,
 }
 
 int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
-                    const uint32_t* counts, int64_t counts_stride, std::string* err) {
+                    const uint32_t* counts, int64_t counts_stride, std::string* err,
+                    bool device_solves) {
   const int p = pr->p;
   const int64_t n = pr->n;
   int rc = for_features(p, err, [&](int j, std::string* ferr) -> int {
@@ -795,7 +559,8 @@ int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
       cnt_t[l] = (double)c[l];
       cnt_a[l] = (double)c[counts_stride / 2 + l];
     }
-    return learner_algebra(s, n, L, cnt_t, cnt_a, nullptr, j, ferr);
+    L.solve_on_device = device_solves && L.d <= kDeviceSolveMaxD;
+    return learner_algebra(s, n, L, cnt_t, cnt_a, nullptr, j, ferr, !L.solve_on_device);
   });
   if (rc) return rc;
   learner_sizes(hf);

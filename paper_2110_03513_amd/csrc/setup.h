@@ -46,7 +46,12 @@ struct HostLearner {
   std::vector<double> gram[2];
   double lambda[2] = {0, 0};
   int64_t cnt_max = 0;           // binned: the largest bin count over all rows
+  bool solve_on_device = false;  // Grams, lambda and inverses left to the device pass
 };
+
+// Learners up to this basis size can take their solves (Gram, lambda,
+// inverse) in the device setup pass (12 d^2 + d doubles of LDS each).
+constexpr int kDeviceSolveMaxD = 32;
 
 struct HostFit {
   int64_t n = 0, n_pad = 0, n_train = 0;
@@ -84,9 +89,12 @@ int prepare_host_fit(const cwb_problem* pr, HostFit* hf, std::string* err,
 // Its last phase after a device binning pass: every learner's tables from
 // the feature ranges (xrange[2j], xrange[2j+1]) and bin counts (feature j's
 // training-row counts at counts[j * counts_stride], all-row counts
-// counts_stride / 2 further).
+// counts_stride / 2 further).  With `device_solves`, learners of basis size
+// up to kDeviceSolveMaxD get zero placeholders for their Grams and inverses
+// (solve_on_device), which the device solve pass computes.
 int finish_host_fit(const cwb_problem* pr, HostFit* hf, const double* xrange,
-                    const uint32_t* counts, int64_t counts_stride, std::string* err);
+                    const uint32_t* counts, int64_t counts_stride, std::string* err,
+                    bool device_solves = false);
 // Host setup of the K folds of a cross-validation (fold[i] in [0, K) for
 // every row): `full` bins all rows once, in their own order, and keeps the
 // index matrix that the folds share, with the rows grouped by fold (fold 0's

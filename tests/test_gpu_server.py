@@ -52,15 +52,18 @@ def _drain(srv, tickets, limit_s=120.0):
     return done
 
 
-def test_server_alone_vs_mix():
+@pytest.mark.parametrize("setup", ["host", "device"])
+def test_server_alone_vs_mix(setup):
+    """Alone with the host setup; in the server with the host setup, or
+    with binning, counts and solves on the GPU during each upload."""
     probs = _requests()
     _say("8 requests alone")
-    alone = [cwb.fit(p) for p in probs]
-    _say("8 requests through the server, staggered")
+    alone = [cwb.fit(dict(p, setup="host")) for p in probs]
+    _say(f"8 requests through the server, staggered, setup={setup}")
     srv = cwb.Server(arena_bytes=1 << 30, max_slots=4, quantum=16)
     tickets = []
     for p in probs:
-        tickets.append(srv.submit(p))
+        tickets.append(srv.submit(dict(p, setup=setup)))
         time.sleep(0.01)
     done = _drain(srv, tickets)
     st = srv.stats()
@@ -110,12 +113,18 @@ def test_server_reports_setup_errors_per_request():
     bad = dict(good)
     bad["loss"] = "binomial"
     bad["y"] = np.full_like(good["y"], 2.0)  # binomial labels must be 0 or 1
+    # a constant feature, found by the device setup pass during the upload
+    const = dict(good, setup="device", x=good["x"].copy())
+    const["x"][:, 1] = 0.5
     srv = cwb.Server(arena_bytes=256 << 20, max_slots=2, quantum=10)
     tb = srv.submit(bad)
+    tc = srv.submit(const)
     tg = srv.submit(good)
-    done = _drain(srv, [tb, tg])
+    done = _drain(srv, [tb, tc, tg])
     srv.close()
     assert done[tb]["status"] == cwb.CWB_E_INVALID_ARG and "error" in done[tb]
+    assert done[tc]["status"] == cwb.CWB_E_INVALID_ARG
+    assert "constant feature 1" in done[tc]["error"]
     assert done[tg]["status"] == 0
     np.testing.assert_array_equal(done[tg]["k"], cwb.fit(good)["k"])
 
