@@ -304,6 +304,11 @@ typedef struct {
   int32_t learners;    /* learners per LDS histogram group */
   int32_t blocks;      /* histogram blocks per launch */
   int32_t candidates;  /* tile shapes timed at create (1: not tuned) */
+  int32_t learners32;  /* learners (over all fits) whose LDS histograms take
+                          32-bit words: their group's every learner holds
+                          fewer than 2^acc32_bits rows in each bin */
+  int32_t acc32_bits;  /* the fit's count bound (the largest over the batch's
+                          fits); 0: int64 sums at the int64 scale */
   double tuned_us;     /* measured pass time of the chosen shape (0: not tuned) */
 } cwb_tile;
 int cwb_fit_tile(const cwb_fit* f, cwb_tile* out);

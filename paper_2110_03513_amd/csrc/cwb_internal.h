@@ -250,7 +250,7 @@ inline int scale_exponent(float amax, int64_t n_fit) {
 // subset of the rows, leaves the int32 range.  The LDS then takes 4-byte
 // atomics (one signal), or one 8-byte atomic carrying both ACWB signals
 // (r in the high word, c in the low word; see pack_signals).
-constexpr int kAcc32MaxBits = 12;  // at least 19 bits of resolution below max |r|
+constexpr int kAcc32MaxBits = 14;  // at least 17 bits of resolution below max |r|
 #if defined(__HIPCC__)
 __host__ __device__
 #endif

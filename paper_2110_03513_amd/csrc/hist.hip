@@ -164,11 +164,20 @@ __device__ __forceinline__ u32x4 unpack12(const u32x3& w) {
 // signals: both values of a row packed into one 8-byte word (pack_signals),
 // learner f at word f * nb, so an ACWB row costs one LDS atomic per
 // learner, as a CWB row does.  With X12 the indices come from the 12-bit
-// copy of X: 12 bytes instead of 16 per 8 rows and learner.
-template <int NT, int FMAX, int NSIG, bool X12>
+// copy of X: 12 bytes instead of 16 per 8 rows and learner.  With COPIES a
+// learner of few bins spreads over copies of its histogram by lane, as in
+// hist_rows (the schedule takes 32-bit words for it only while each copy
+// receives fewer than 2^acc32_bits rows of the segment).
+template <int NT, int FMAX, int NSIG, bool X12, bool COPIES>
 __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void* __restrict__ hist,
                                             int nb, int64_t r0, int64_t r1, Exps& ex, bool need_e,
-                                            int64_t n_fit, float* red) {
+                                            int64_t n_fit, float* red, const int (*cp)[16]) {
+  int cm[FMAX], cs[FMAX];  // copy masks and strides, wave-uniform
+#pragma unroll
+  for (int f = 0; f < FMAX; ++f) {
+    cm[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[0][f]) : 0;
+    cs[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[1][f]) : 0;
+  }
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
   const size_t ld12 = (size_t)F.n_pad / 8 * 3;  // words per learner in the 12-bit copy
   const uint32_t* __restrict__ Xp = X12 ? F.X12 + (size_t)sg.k0 * ld12 : nullptr;
@@ -213,11 +222,13 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) xc[f] = X12 ? unpack12(xp[f]) : xw[f];
     if (more) load(nxt);
+    const int lane = COPIES ? opaque_lane() : 0;
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) {
       if (f < nf) {
-        if (NSIG == 1) hist_add32(h32 + (size_t)f * nb, xc[f], p0);
-        else hist_add_packed(h64 + (size_t)f * nb, xc[f], pk);
+        const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;  // this lane's copy
+        if (NSIG == 1) hist_add32(h32 + (size_t)f * nb + cb, xc[f], p0);
+        else hist_add_packed(h64 + (size_t)f * nb + cb, xc[f], pk);
       }
     }
     if (!more) break;
@@ -428,14 +439,14 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     } else if (w32) {
       if (F.X12) {
         if (NSMAX == 1 || nsig == 1)
-          hist_rows32<NT, FMAX, 1, true>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+          hist_rows32<NT, FMAX, 1, true, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
         else
-          hist_rows32<NT, FMAX, NSMAX, true>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+          hist_rows32<NT, FMAX, NSMAX, true, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       } else {
         if (NSMAX == 1 || nsig == 1)
-          hist_rows32<NT, FMAX, 1, false>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+          hist_rows32<NT, FMAX, 1, false, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
         else
-          hist_rows32<NT, FMAX, NSMAX, false>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red);
+          hist_rows32<NT, FMAX, NSMAX, false, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       }
     } else {
       if (NSMAX == 1 || nsig == 1)
@@ -447,16 +458,31 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     GLOBAL long long* out = gp(partials + sg.slot);
     if (w32) {  // 32-bit sums to int64 partials, in the 64-bit layout
       const int nw = sg.nf * nb;
-      if (nsig == 1) {
-        const uint32_t* h32 = reinterpret_cast<const uint32_t*>(s_hist);
-        for (int i = threadIdx.x; i < nw; i += NT) out[i] = (long long)(int32_t)h32[i];
-      } else {
-        for (int i = threadIdx.x; i < nw; i += NT) {
-          long long R, Cs;
-          unpack_signals(s_hist[i], &R, &Cs);
-          out[i] = R;        // signal 0 of learner i / nb, bin i % nb
-          out[nw + i] = Cs;  // signal 1 at (nf + f) * nb + b
+      const uint32_t* h32 = reinterpret_cast<const uint32_t*>(s_hist);
+      for (int i = threadIdx.x; i < nw; i += NT) {
+        int cm = 0, cs = 0;
+        int b = i;
+        if (COPIES) {  // learner i / nb, bin i % nb: the sum of its copies
+          const int f = i / nb;
+          b = i - f * nb;
+          cm = s_cp[0][f];
+          cs = s_cp[1][f];
         }
+        long long R = 0, Cs = 0;
+        if (cm == 0 || b < cs) {
+          for (int c = 0, w = i; c <= cm; ++c, w += cs) {
+            if (nsig == 1) {
+              R += (long long)(int32_t)h32[w];
+            } else {
+              long long a, e;
+              unpack_signals(s_hist[w], &a, &e);
+              R += a;
+              Cs += e;
+            }
+          }
+        }
+        out[i] = R;                    // signal 0 of learner i / nb, bin i % nb
+        if (nsig == 2) out[nw + i] = Cs;  // signal 1 at (nf + f) * nb + b
       }
     } else if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
       const int d = F.d_max;

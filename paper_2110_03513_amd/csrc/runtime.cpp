@@ -206,11 +206,37 @@ int segment_fold(const FitShape& sh, int64_t r0, int64_t r1) {
 }
 
 // 1 if every learner of [k0, k0 + nf) takes 32-bit accumulation.
-int group_acc32(const FitShape& sh, int k0, int nf) {
+// 1 if every learner of the group keeps its sums over the segment's units
+// [u0, u1) in int32 at the fit's 32-bit scale, with nt threads per block: a
+// learner whose bins all hold fewer than 2^acc32_bits rows, or one with c
+// LDS copies, each of which takes the rows of nt / c threads -- at most
+// 8 rows per thread per step of 8 nt rows -- as long as those stay below
+// 2^acc32_bits.  The segment's rows are bounded by 8 (u1 - u0 + 1) for
+// either row count the pass maps its units onto (before and after an HCWB
+// switch).
+int group_acc32(const FitShape& sh, int k0, int nf, int64_t u0, int64_t u1, int nt) {
   if ((int)sh.acc32.size() != sh.p || sh.acc32_bits < 1 || sh.acc32_bits > kAcc32MaxBits) return 0;
-  for (int k = k0; k < k0 + nf; ++k)
-    if (!sh.acc32[k]) return 0;
+  const int64_t rows = 8 * (u1 - u0 + 1), step = 8 * (int64_t)nt;
+  const int64_t limit = ((int64_t)1 << sh.acc32_bits) - 1;
+  for (int k = k0; k < k0 + nf; ++k) {
+    if (sh.acc32[k]) continue;
+    const int c = (int)sh.acc32_copies.size() == sh.p ? sh.acc32_copies[k] : 0;
+    if (c < 2 || nt % c != 0) return 0;
+    const int64_t per_copy = (rows + step - 1) / step * 8 * (nt / c);
+    if (per_copy > limit) return 0;
+  }
   return 1;
+}
+
+// LDS bytes the histogram pass takes for a segment (at the fit's most
+// signals): 32-bit groups hold 4-byte words (one signal) or one packed
+// 8-byte word per bin (two signals), the others 8-byte words per signal
+// and fold.
+size_t seg_lds_bytes(const Seg& sg, const FitShape& sh) {
+  const int64_t nw = (int64_t)sg.nf * sh.nb_stride;
+  const int64_t words = sg.acc32 ? (sh.nsig_max == 1 ? (nw + 1) / 2 : nw)
+                                 : (int64_t)sg.nfit * sh.nsig_max * nw;
+  return (size_t)words * sizeof(long long);
 }
 
 Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t) {
@@ -277,7 +303,7 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       sg.nf = it.nf;
       sg.nfit = (int16_t)it.nfit;
       sg.skip = -1;
-      sg.acc32 = any_folds ? 0 : group_acc32(*fits[it.fit], it.k0, it.nf);
+      sg.acc32 = any_folds ? 0 : group_acc32(*fits[it.fit], it.k0, it.nf, u, ue, t.nt);
       sg.pad = 0;
       if (it.nfit > 1) {
         int64_t r0, r1;
@@ -358,12 +384,9 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
     }
   }
   int ns_max = 1;
-  int64_t nbs_max = 4;  // widest histogram set of a learner: folds x bins
-  for (const FitShape* f : fits) {
-    ns_max = std::max(ns_max, f->nsig_max);
-    nbs_max = std::max<int64_t>(nbs_max, (int64_t)f->nb_stride * std::max(1, f->share));
-  }
-  S.lds = (size_t)ns_max * t.F * nbs_max * sizeof(long long);
+  for (const FitShape* f : fits) ns_max = std::max(ns_max, f->nsig_max);
+  S.lds = 4 * sizeof(long long);  // the largest segment's histograms
+  for (const Seg& sg : S.segs) S.lds = std::max(S.lds, seg_lds_bytes(sg, *fits[sg.fit]));
   S.nsig_max = ns_max;
   S.unbinned = !fits.empty() && fits[0]->unbinned;
   for (const Seg& sg : S.segs) S.folds = S.folds || sg.nfit > 1;
@@ -421,14 +444,14 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
         sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
     if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
     if (sg.acc32 != 0 && (sg.acc32 != 1 || sg.nfit != 1 || S.folds || sh.unbinned ||
-                          group_acc32(sh, sg.k0, sg.nf) != 1)) {
+                          group_acc32(sh, sg.k0, sg.nf, sg.u0, sg.u1, t.nt) != 1)) {
       *why = "32-bit group";
       return false;
     }
     if (sg.slot != slot_end) { *why = "slot order"; return false; }
     const int64_t words = (int64_t)sg.nfit * sh.nsig_max * sg.nf * sh.nb_stride;
     slot_end += words;
-    if ((size_t)words * sizeof(long long) > S.lds) { *why = "LDS size"; return false; }
+    if (seg_lds_bytes(sg, sh) > S.lds) { *why = "LDS size"; return false; }
   }
   if (slot_end != S.partial_words) { *why = "partial size"; return false; }
   for (int64_t o : S.sel_off)
@@ -587,6 +610,16 @@ T* dptr(char* ws, size_t off) {
 }
 
 }  // namespace
+
+int learners32(const Schedule& S) {
+  int n = 0;
+  for (size_t g = 0; g + 1 < S.grp_ptr.size(); ++g) {
+    if (S.grp_ptr[g] == S.grp_ptr[g + 1]) continue;
+    const Seg& sg = S.segs[(size_t)S.grp_seg[(size_t)S.grp_ptr[g]]];
+    if (sg.acc32) n += sg.nf;
+  }
+  return n;
+}
 
 int row_chunks(int64_t total, int cus) {
   const int forced = env_int("CWB_ROW_CHUNKS", 0);  // testing: force a chunk count
@@ -988,20 +1021,24 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   // learner without LDS copies whose fullest bin holds fewer than
   // 2^kAcc32MaxBits rows (CWB_ACC32=0 keeps int64 sums throughout)
   if (!sh.unbinned && !fold && env_int("CWB_ACC32", 1) != 0) {
-    std::vector<uint8_t> acc(sh.p, 0);
+    std::vector<uint8_t> acc(sh.p, 0), copies(sh.p, 0);
     int bits = 0;
     for (int j = 0; j < sh.p; ++j) {
       const HostLearner& hl = hf.L[j];
       int N = 0;
       for (int64_t v = hl.cnt_max; v > 0; v >>= 1) ++N;  // cnt_max < 2^N
       int stride = 0;
-      if (hl.nb > 0 && hl.cnt_max > 0 && N <= kAcc32MaxBits && copy_mask(hl.nb, sh.nb_stride, &stride) == 0) {
+      const int cm = hl.nb > 0 ? copy_mask(hl.nb, sh.nb_stride, &stride) : 0;
+      if (hl.nb > 0 && cm > 0) {
+        copies[j] = (uint8_t)(cm + 1);  // 32-bit words where its segments allow
+      } else if (hl.nb > 0 && hl.cnt_max > 0 && N <= kAcc32MaxBits) {
         acc[j] = 1;
         bits = std::max(bits, N);
       }
     }
     if (bits > 0) {
       f->shape.acc32 = std::move(acc);
+      f->shape.acc32_copies = std::move(copies);
       f->shape.acc32_bits = bits;
       f->sched = build_schedule({&f->shape}, f->tune);
       std::string why;
@@ -1529,6 +1566,8 @@ int cwb_fit_tile(const cwb_fit* f, cwb_tile* out) {
   out->learners = f->tune.F;
   out->blocks = f->sched.blocks;
   out->candidates = f->n_cands;
+  out->learners32 = learners32(f->sched);
+  out->acc32_bits = f->shape.acc32_bits;
   out->tuned_us = f->tuned_us;
   return CWB_OK;
 }
@@ -1792,6 +1831,9 @@ int cwb_batch_tile(const cwb_batch* b, cwb_tile* out) {
   out->learners = b->tune.F;
   out->blocks = b->sched.blocks;
   out->candidates = b->n_cands;
+  out->learners32 = learners32(b->sched);
+  out->acc32_bits = 0;
+  for (const cwb_fit* f : b->fits) out->acc32_bits = std::max(out->acc32_bits, f->shape.acc32_bits);
   out->tuned_us = b->tuned_us;
   return CWB_OK;
 }

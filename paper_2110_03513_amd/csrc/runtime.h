@@ -38,6 +38,10 @@ struct FitShape {
   // folds): 1 if its histogram sums fit 32-bit fixed point (every bin holds
   // fewer than 2^acc32_bits rows and the learner takes no LDS copies)
   std::vector<uint8_t> acc32;
+  // per learner with LDS copies: its number of copies (else 0).  Its sums
+  // fit 32 bits in a segment whose rows give each copy fewer than
+  // 2^acc32_bits rows (group_acc32), whatever its bin counts.
+  std::vector<uint8_t> acc32_copies;
   int acc32_bits = 0;
 };
 
@@ -191,6 +195,8 @@ RowItem make_row_item(int fit, int blk, const FitDev& D, int chunks = 1);
 // large batch), so that each block's selection and table staging serve
 // several chunks.
 int row_chunks(int64_t total, int cus);
+// Learners of a schedule whose groups take 32-bit LDS words.
+int learners32(const Schedule& S);
 // The row-pass work list of one fit: blocks of `chunks` chunks each.
 void append_row_items(std::vector<RowItem>* out, int fit, const FitDev& D, int n_row_blocks,
                       int chunks);

@@ -626,3 +626,47 @@ def test_row_pass_chunks_bitwise(variant, loss, monkeypatch):
         f.close()
     b.close()
     compare(got, probs[0])
+
+
+@pytest.mark.parametrize("variant,loss", [("cwb", "l2"), ("acwb", "binomial")])
+def test_32bit_words_with_full_bins(variant, loss):
+    """Normal columns with 200 bins: their fullest bins hold 2^12 to 2^14
+    rows, so the whole fit takes the coarser 32-bit scale (at least 17 bits
+    below max |r|) and every group 32-bit LDS words (packed for ACWB).  The
+    selection sequence must still equal the oracle's."""
+    prob = datagen.additive_problem(400_000, 10, seed=161, n_informative=3, loss=loss, n_bins=200,
+                                    M=300, variant=variant, gamma=0.0034, n_normal=5,
+                                    n_informative_normal=2)
+    f = cwb.Fit(prob)
+    tile = f.tile()
+    f.close()
+    _say(f"tile {tile}")
+    assert tile["acc32_bits"] in (13, 14) and tile["learners32"] == 10
+    compare(_run(prob), prob)
+
+
+def test_copies_learners_take_32bit_words_by_segment(monkeypatch):
+    """Categorical learners (16 and 19 levels) spread over 16 and 8 LDS copies
+    and hold up to 63,000 rows per bin.  In a schedule of short segments
+    (256 blocks) each copy receives fewer than 2^12 rows, so their group
+    takes packed 32-bit words; with 2 blocks it keeps 8-byte words.  The
+    values are quantized at the fit's scale either way, so both runs agree
+    bit for bit, and with the oracle."""
+    prob = datagen.additive_problem(1_000_000, 8, seed=171, n_informative=3, loss="binomial",
+                                    n_bins=300, M=40, variant="acwb", gamma=0.05, n_cat=2,
+                                    n_informative_cat=1)
+    monkeypatch.setenv("CWB_HIST_NT", "512")
+    monkeypatch.setenv("CWB_HIST_F", "4")
+    out = {}
+    for blocks in (256, 2):
+        monkeypatch.setenv("CWB_HIST_BLOCKS", str(blocks))
+        f = cwb.Fit(prob)
+        tile = f.tile()
+        f.close()
+        _say(f"blocks={blocks}: tile {tile}")
+        assert tile["acc32_bits"] == 12
+        assert tile["learners32"] == (8 if blocks == 256 else 4)
+        out[blocks] = _run(prob)
+    for key in ("k", "kcor", "theta", "thetacor", "f", "coef_f", "coef_h", "risk_train"):
+        np.testing.assert_array_equal(out[256][key], out[2][key], err_msg=key)
+    compare(out[256], prob)
