@@ -75,7 +75,8 @@ struct Ctl {
   int32_t switched;     // HCWB: CWB phase reached
   int32_t switch_iter;  // HCWB: first CWB iteration (-1 until switched)
   int32_t counter;      // HCWB: consecutive validation-risk rises
-  int32_t error;        // non-finite model state seen
+  int32_t error;        // bit 0: non-finite model state seen; bit 1: a
+                        // histogram segment larger than its launch's LDS
   double rval_prev;     // HCWB: validation risk of the previous model
 };
 

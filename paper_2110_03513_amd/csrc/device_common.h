@@ -201,29 +201,6 @@ __device__ void fit_exponents(const FitDev& F, int64_t n_fit, Exps* x, float* re
   x->e32[1] = scale_exponent32(b, F.acc32_bits);
 }
 
-template <int NT>
-__device__ void fit_scale_exponents(const FitDev& F, int64_t n_fit, int* e0, int* e1, float* red) {
-  float a = 0.0f, b = 0.0f;
-  const GLOBAL float* am = gp(F.amax_part);
-  for (int b0 = 0; b0 < F.n_row_blocks; b0 += 4 * NT) {
-    float v[4], w[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = b0 + u * NT + (int)threadIdx.x;
-      v[u] = (k < F.n_row_blocks) ? am[2 * k] : 0.0f;
-      w[u] = (k < F.n_row_blocks) ? am[2 * k + 1] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a = fmaxf(a, v[u]);
-      b = fmaxf(b, w[u]);
-    }
-  }
-  block_max2<NT>(a, b, red);
-  *e0 = scale_exponent(a, n_fit);
-  *e1 = scale_exponent(b, n_fit);
-}
-
 // Copy `count` elements from global memory to LDS with all of a thread's
 // loads (up to U per pass) issued before its stores, so a block pays one
 // memory round trip per pass instead of one per element it copies.

@@ -239,12 +239,16 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
 // Rows [r0, r1) of a segment shared by the nfit folds of a cross-validation:
 // one read of the group's bin indices feeds every fold's signals.  Held-out
 // rows carry zero residuals; the fold that holds out all of the segment's
-// rows (skip) is left out.  LDS histogram of fold q, signal s, learner f at
-// ((q * NSIG + s) * nf + f) * nb; exponents in e[2q], e[2q+1].
-template <int NT, int FMAX, int NSIG, bool COPIES>
+// rows (skip) is left out.  Exponents in e[2q], e[2q+1]: the folds' 32-bit
+// scale (rounded values) when `r32`, else the int64 one (truncated).  W32
+// (a group of 32-bit learners, Seg.acc32): fold q, learner f at word
+// (q nf + f) nb of 4-byte words (one signal) or of packed 8-byte words
+// (two signals); else 8-byte words, fold q, signal s, learner f at
+// ((q NSIG + s) nf + f) nb.
+template <int NT, int FMAX, int NSIG, bool COPIES, bool W32>
 __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits, const Seg& sg,
                                                 unsigned long long* __restrict__ hist, int nb,
-                                                int64_t r0, int64_t r1, const int* e,
+                                                int64_t r0, int64_t r1, const int* e, bool r32,
                                                 const int (*cp)[16]) {
   int cm[FMAX], cs[FMAX];
 #pragma unroll
@@ -265,6 +269,7 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
   };
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
   if (base >= r1) return;
+  uint32_t* __restrict__ h32 = reinterpret_cast<uint32_t*>(hist);
   // software pipeline: the loads of the next fold (or of the next row step)
   // are issued before the current fold's atomics
   u32x4 xw[FMAX];
@@ -284,11 +289,29 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
     for (;;) {
       const int qn = next_fold(q);
       long long q0[8], q1[8];
+      int p0[8];
+      unsigned long long pk[8];
+      if (W32 && NSIG == 1) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e[2 * q]);
-      if (NSIG == 2) {
+        for (int j = 0; j < 8; ++j) p0[j] = fixed32(rv[j], e[2 * q]);
+      } else if (W32) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e[2 * q + 1]);
+        for (int j = 0; j < 8; ++j)
+          pk[j] = pack_signals(fixed32(rv[j], e[2 * q]), fixed32(cv[j], e[2 * q + 1]));
+      } else if (r32) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q0[j] = (long long)fixed32(rv[j], e[2 * q]);
+        if (NSIG == 2) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) q1[j] = (long long)fixed32(cv[j], e[2 * q + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e[2 * q]);
+        if (NSIG == 2) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e[2 * q + 1]);
+        }
       }
       if (qn >= 0) {
         load8f(fits[sg.fit + qn].r + base, rv);
@@ -300,14 +323,20 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
         load8f(fits[sg.fit + first].r + nxt, rv);
         if (NSIG == 2) load8f(fits[sg.fit + first].c + nxt, cv);
       }
-      unsigned long long* hq = hist + (size_t)q * NSIG * nf * nb;
       const int lane = COPIES ? opaque_lane() : 0;
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
         if (f < nf) {
           const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;
-          hist_add<NSIG>(hq + (size_t)f * nb + cb, xc[f], q0);
-          if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb + cb, xc[f], q1);
+          if (W32) {
+            const size_t w = (size_t)(q * nf + f) * nb + cb;
+            if (NSIG == 1) hist_add32(h32 + w, xc[f], p0);
+            else hist_add_packed(hist + w, xc[f], pk);
+          } else {
+            unsigned long long* hq = hist + (size_t)q * NSIG * nf * nb;
+            hist_add<NSIG>(hq + (size_t)f * nb + cb, xc[f], q0);
+            if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb + cb, xc[f], q1);
+          }
         }
       }
       if (qn < 0) break;
@@ -378,7 +407,7 @@ constexpr int kBinned = 0, kUnbinned = 1, kFolds = 2;
 template <int NT, int FMAX, int NSMAX, int KIND, bool COPIES>
 __global__ void __launch_bounds__(NT)
 k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
-       const int64_t* __restrict__ blk, long long* __restrict__ partials) {
+       const int64_t* __restrict__ blk, long long* __restrict__ partials, int lds_bytes) {
   constexpr bool UNB = KIND == kUnbinned;
   constexpr bool FOLDS = KIND == kFolds;
   static_assert(FMAX <= 16, "copy table holds 16 learners");
@@ -392,15 +421,20 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
   for (int64_t s = s0; s < s1; ++s) {
     const Seg sg = segs[s];
     const FitDev& F = fits[sg.fit];
-    const Ctl* ctl = F.ctl;
+    Ctl* ctl = F.ctl;
     if (ctl->pick_done >= F.M) continue;
     const int switched = ctl->switched;
     const int nsig = is_acwb_step(F, switched) ? 2 : 1;
     const int64_t n_fit = rows_fitted(F, switched);
     const int nb = F.nb_stride;
-    const bool w32 = !UNB && !FOLDS && sg.acc32 != 0;  // 32-bit (or packed) LDS words
-    const int words = sg.nfit * nsig * sg.nf * nb;     // 64-bit LDS words, and partial words
-    const int lds_words = w32 ? (nsig == 1 ? (sg.nf * nb + 1) / 2 : sg.nf * nb) : words;
+    const bool w32 = !UNB && sg.acc32 != 0;         // 32-bit (or packed) LDS words
+    const int words = sg.nfit * nsig * sg.nf * nb;  // 64-bit LDS words, and partial words
+    const int nw32 = sg.nfit * sg.nf * nb;          // 32-bit or packed words
+    const int lds_words = w32 ? (nsig == 1 ? (nw32 + 1) / 2 : nw32) : words;
+    if ((int64_t)lds_words * 8 > lds_bytes) {  // a schedule the launch's LDS cannot hold
+      if (threadIdx.x == 0) atomicOr(&ctl->error, 2);
+      continue;
+    }
     for (int i = threadIdx.x; i < lds_words; i += NT) s_hist[i] = 0ull;
     if (COPIES && (int)threadIdx.x < sg.nf) {
       int st = 0;
@@ -415,21 +449,29 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     const bool need_e = sg.fit != cached_fit;
     cached_fit = sg.fit;
     if (FOLDS && sg.nfit > 1) {  // the folds of a cross-validation
+      const bool r32 = F.acc32_bits > 0;  // the same for every fold of the group
       if (need_e) {
         for (int q = 0; q < sg.nfit; ++q) {
-          int a = 0, b = 0;
-          fit_scale_exponents<NT>(fits[sg.fit + q], n_fit, &a, &b, s_red);
+          Exps xq{};
+          fit_exponents<NT>(fits[sg.fit + q], n_fit, &xq, s_red);
           if (threadIdx.x == 0) {
-            s_e[2 * q] = a;
-            s_e[2 * q + 1] = b;
+            s_e[2 * q] = r32 ? xq.e32[0] : xq.e[0];
+            s_e[2 * q + 1] = r32 ? xq.e32[1] : xq.e[1];
           }
         }
         __syncthreads();
       }
-      if (NSMAX == 1 || nsig == 1)
-        hist_rows_folds<NT, FMAX, 1, COPIES>(fits, sg, s_hist, nb, r0, r1, s_e, s_cp);
-      else
-        hist_rows_folds<NT, FMAX, NSMAX, COPIES>(fits, sg, s_hist, nb, r0, r1, s_e, s_cp);
+      if (w32) {
+        if (NSMAX == 1 || nsig == 1)
+          hist_rows_folds<NT, FMAX, 1, COPIES, true>(fits, sg, s_hist, nb, r0, r1, s_e, r32, s_cp);
+        else
+          hist_rows_folds<NT, FMAX, NSMAX, COPIES, true>(fits, sg, s_hist, nb, r0, r1, s_e, r32, s_cp);
+      } else {
+        if (NSMAX == 1 || nsig == 1)
+          hist_rows_folds<NT, FMAX, 1, COPIES, false>(fits, sg, s_hist, nb, r0, r1, s_e, r32, s_cp);
+        else
+          hist_rows_folds<NT, FMAX, NSMAX, COPIES, false>(fits, sg, s_hist, nb, r0, r1, s_e, r32, s_cp);
+      }
     } else if (UNB) {
       if (need_e) fit_exponents<NT>(F, n_fit, &ex, s_red);
       if (NSMAX == 1 || nsig == 1)
@@ -459,12 +501,14 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
     if (w32) {  // 32-bit sums to int64 partials, in the 64-bit layout
       const int nw = sg.nf * nb;
       const uint32_t* h32 = reinterpret_cast<const uint32_t*>(s_hist);
-      for (int i = threadIdx.x; i < nw; i += NT) {
+      for (int i = threadIdx.x; i < nw32; i += NT) {
+        const int qf = (sg.nfit > 1) ? i / nw : 0;  // fold
+        const int j = i - qf * nw;                  // learner j / nb, bin j % nb
         int cm = 0, cs = 0;
-        int b = i;
-        if (COPIES) {  // learner i / nb, bin i % nb: the sum of its copies
-          const int f = i / nb;
-          b = i - f * nb;
+        int b = j;
+        if (COPIES) {  // the sum of the learner's copies
+          const int f = j / nb;
+          b = j - f * nb;
           cm = s_cp[0][f];
           cs = s_cp[1][f];
         }
@@ -481,8 +525,9 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
             }
           }
         }
-        out[i] = R;                    // signal 0 of learner i / nb, bin i % nb
-        if (nsig == 2) out[nw + i] = Cs;  // signal 1 at (nf + f) * nb + b
+        GLOBAL long long* o = out + (size_t)qf * nsig * nw;  // fold qf's slot
+        o[j] = R;                    // signal 0 of learner j / nb, bin j % nb
+        if (nsig == 2) o[nw + j] = Cs;  // signal 1 at (nf + f) * nb + b
       }
     } else if (UNB) {  // sum the copies: basis sums at the start of each learner's slot
       const int d = F.d_max;
@@ -533,7 +578,7 @@ hipError_t launch_hist_t(hipStream_t st, int blocks, size_t lds, const FitDev* f
   }();
   (void)attr;
   hipLaunchKernelGGL((k_hist<NT, FMAX, NSMAX, KIND, COPIES>), dim3(blocks), dim3(NT), lds, st, fits, segs,
-                     blk, partials);
+                     blk, partials, (int)lds);
   return hipGetLastError();
 }
 

@@ -233,9 +233,8 @@ int group_acc32(const FitShape& sh, int k0, int nf, int64_t u0, int64_t u1, int 
 // 8-byte word per bin (two signals), the others 8-byte words per signal
 // and fold.
 size_t seg_lds_bytes(const Seg& sg, const FitShape& sh) {
-  const int64_t nw = (int64_t)sg.nf * sh.nb_stride;
-  const int64_t words = sg.acc32 ? (sh.nsig_max == 1 ? (nw + 1) / 2 : nw)
-                                 : (int64_t)sg.nfit * sh.nsig_max * nw;
+  const int64_t nw = (int64_t)sg.nfit * sg.nf * sh.nb_stride;  // every fold's learners
+  const int64_t words = sg.acc32 ? (sh.nsig_max == 1 ? (nw + 1) / 2 : nw) : sh.nsig_max * nw;
   return (size_t)words * sizeof(long long);
 }
 
@@ -276,9 +275,6 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       }
     }
   }
-  // the fold variant of the histogram pass keeps int64 accumulators
-  bool any_folds = false;
-  for (const Item& it : items) any_folds = any_folds || it.nfit > 1;
   const int B = t.blocks > 0 ? t.blocks : std::max(1, t.cus * t.blocks_per_cu);
   S.blocks = B;
   std::vector<int64_t> seg_vb;
@@ -303,7 +299,9 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
       sg.nf = it.nf;
       sg.nfit = (int16_t)it.nfit;
       sg.skip = -1;
-      sg.acc32 = any_folds ? 0 : group_acc32(*fits[it.fit], it.k0, it.nf, u, ue, t.nt);
+      sg.acc32 = 1;  // every fold of the group must keep 32-bit sums
+      for (int q = 0; q < it.nfit; ++q)
+        sg.acc32 &= group_acc32(*fits[it.fit + q], it.k0, it.nf, u, ue, t.nt);
       sg.pad = 0;
       if (it.nfit > 1) {
         int64_t r0, r1;
@@ -443,10 +441,14 @@ bool schedule_is_valid(const Schedule& S, const std::vector<const FitShape*>& fi
     if (sg.nf < 1 || sg.nf > t.F || sg.nf > t.fmax || sg.k0 < 0 || sg.k0 + sg.nf > sh.p ||
         sg.k0 % t.F != 0) { *why = "segment learners"; return false; }
     if (sg.u0 < 0 || sg.u1 <= sg.u0 || sg.u1 > sh.n_pad / 8) { *why = "segment rows"; return false; }
-    if (sg.acc32 != 0 && (sg.acc32 != 1 || sg.nfit != 1 || S.folds || sh.unbinned ||
-                          group_acc32(sh, sg.k0, sg.nf, sg.u0, sg.u1, t.nt) != 1)) {
-      *why = "32-bit group";
-      return false;
+    if (sg.acc32 != 0) {
+      bool ok = sg.acc32 == 1 && !sh.unbinned;
+      for (int q = 0; ok && q < sg.nfit; ++q)
+        ok = group_acc32(*fits[sg.fit + q], sg.k0, sg.nf, sg.u0, sg.u1, t.nt) == 1;
+      if (!ok) {
+        *why = "32-bit group";
+        return false;
+      }
     }
     if (sg.slot != slot_end) { *why = "slot order"; return false; }
     const int64_t words = (int64_t)sg.nfit * sh.nsig_max * sg.nf * sh.nb_stride;
@@ -1020,7 +1022,7 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   // 32-bit histogram accumulation, now that the bins are counted: a binned
   // learner without LDS copies whose fullest bin holds fewer than
   // 2^kAcc32MaxBits rows (CWB_ACC32=0 keeps int64 sums throughout)
-  if (!sh.unbinned && !fold && env_int("CWB_ACC32", 1) != 0) {
+  if (!sh.unbinned && env_int("CWB_ACC32", 1) != 0) {
     std::vector<uint8_t> acc(sh.p, 0), copies(sh.p, 0);
     int bits = 0;
     for (int j = 0; j < sh.p; ++j) {
@@ -1383,6 +1385,7 @@ int cwb_fit_run(cwb_fit* f, int32_t iters) {
 static int check_device_error(cwb_fit* f) {
   int32_t e = 0;
   HIP_TRY(hipMemcpy(&e, f->ws + f->lay.ctl + offsetof(Ctl, error), sizeof(e), hipMemcpyDeviceToHost));
+  if (e & 2) return set_error(CWB_E_DEVICE, "internal: a histogram segment larger than its launch's LDS");
   if (e) return set_error(CWB_E_NUMERIC, "non-finite model state (diverged)");
   return CWB_OK;
 }

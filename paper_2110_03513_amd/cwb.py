@@ -479,8 +479,7 @@ class CV:
     def tile(self) -> dict:
         t = cwb_tile()
         check(lib().cwb_cv_tile(self.h, C.byref(t)))
-        return {"threads": t.threads, "learners": t.learners, "blocks": t.blocks,
-                "candidates": t.candidates, "tuned_us": t.tuned_us}
+        return {name: getattr(t, name) for name, _ in cwb_tile._fields_}
 
     def risk(self) -> np.ndarray:
         """Cross-validated risk of iterations 0..done (held-out loss / n)."""

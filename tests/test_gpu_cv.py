@@ -72,6 +72,8 @@ def test_cv_resumes_and_predicts():
         np.testing.assert_array_equal(a.folds[k].trace()["k"], b.folds[k].trace()["k"])
         np.testing.assert_array_equal(a.folds[k].pred(), b.folds[k].pred())
     np.testing.assert_array_equal(a.risk(), b.risk())
+    # the folds' shared groups take 32-bit words (every fold's learners)
+    assert a.tile()["learners32"] == 4 * 6
     xn = np.random.default_rng(115).uniform(0, 1, (1000, 6))
     o = oracle.fit(dict(prob, val_mask=(fold == 2).astype(np.uint8)))
     assert rel_err(a.folds[2].predict(xn), oracle.predict(prob, o, xn)) <= 1e-4
