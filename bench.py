@@ -726,14 +726,15 @@ def main():
     out = {
         "metric": METRIC, "value": round(h["iters_s"], 2), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32",
         "data": "synthetic",
         "config": {"workload": (f"binned CWB, L2, n={args.n}, p={args.p}, 1000 bins, cubic "
                                 "P-splines d=24 df=5, nu=0.1 (synthetic, seed 2)"),
                    "n": args.n, "p": args.p, "n_bins": 1000, "variant": "cwb", "loss": "l2",
                    "iterations_in_fit": int(prob["M"])},
-        "precision": "uint16 bin indices; int64 fixed-point histograms; fp32 model state; "
-                     "fp64 merge, solves and selection",
+        "precision": ("uint16 bin indices (read as a 12-bit packed copy); exact fixed-point "
+                      "histograms in 32-bit LDS words (int64 where a bin's count needs it); "
+                      "fp32 model state; int64 merge; fp64 solves and selection"),
         "hbm_gbs": round(h["iter_gbs"], 1),
         "hbm_frac": round(h["iter_gbs"] / HBM_PEAK_GBS, 4),
         "roofline": h["roofline"],

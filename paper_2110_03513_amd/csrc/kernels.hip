@@ -441,7 +441,48 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
     const int e = it.acc32_bits > 0 ? scale_exponent32(amax[sig], it.acc32_bits)
                                     : scale_exponent(amax[sig], n_fit);
     const double isc = ldexp(1.0, -e);
-    // bin sums s_l: exact int64 merge of the group's segment partials
+    // bin sums s_l: exact int64 merge of the group's segment partials.  Many
+    // segments and few bins (a small fit spread over many histogram blocks):
+    // the threads split the segments as well as the bins, and their int64
+    // sums meet in LDS through atomic adds (exact, so in any order).
+    const int nch = (nb + 3) / 4;  // 4-bin chunks
+    const int slices =
+        (!pre && 2 * nch <= kSelectThreads) ? min(kSelectThreads / nch, n_off) : 1;
+    if (slices > 1) {
+      unsigned long long* s_acc = reinterpret_cast<unsigned long long*>(s_part);  // 4 nch <= 512
+      for (int i = threadIdx.x; i < 4 * nch; i += kSelectThreads) s_acc[i] = 0ull;
+      __syncthreads();
+      const int ch = (int)threadIdx.x % nch, sl = (int)threadIdx.x / nch;
+      const int l = 4 * ch;
+      long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      for (int c0 = 0; c0 < n_off; c0 += kMaxSlots) {
+        const int cnt = (n_off - c0) < kMaxSlots ? (n_off - c0) : kMaxSlots;
+        if (n_off > kMaxSlots) {  // more segments than the staged list holds
+          __syncthreads();
+          stage<kSelectThreads, 2>(s_off, offs + c0, cnt);
+          __syncthreads();
+        }
+        if (sl < slices) {
+#pragma unroll 8
+          for (int i = sl; i < cnt; i += slices) {
+            const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + s_off[i] + l);
+            const i64x2 u = src[0], w = src[1];
+            a0 += u.x;
+            a1 += u.y;
+            a2 += w.x;
+            a3 += w.y;
+          }
+        }
+      }
+      if (sl < slices) {
+        __hip_atomic_fetch_add(s_acc + l, (unsigned long long)a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(s_acc + l + 1, (unsigned long long)a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(s_acc + l + 2, (unsigned long long)a2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(s_acc + l + 3, (unsigned long long)a3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += kSelectThreads) s_bins[i] = (double)(long long)s_acc[i] * isc;
+    } else
     for (int l0 = 0; l0 < nb; l0 += 4 * kSelectThreads) {
       long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
       const int l = l0 + 4 * threadIdx.x;

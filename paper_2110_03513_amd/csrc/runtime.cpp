@@ -160,22 +160,30 @@ Tune make_tune(int nb_stride, int nsig_max, int p_max, bool unbinned) {
 }
 
 // Tile shapes the autotuner tries: the default first, then threads x LDS
-// budget x blocks per CU.  Explicit CWB_HIST_* settings, or CWB_AUTOTUNE=0,
-// leave the default alone.
-std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all) {
+// budget x blocks per CU, and for small work (`small`: a few hundred
+// row-learner units per block at one block per CU) grids of 16 to 64
+// blocks, whose fewer segments per learner group also shorten the select
+// pass's merge.  Explicit CWB_HIST_* settings, or CWB_AUTOTUNE=0, leave the
+// default alone.
+std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all,
+                                  bool small) {
   std::vector<Tune> out{make_tune(nb_stride, nsig_max, p_max, unbinned)};
   if (!all || hist_env_set() || env_int("CWB_AUTOTUNE", 1) == 0) return out;
   const int cus = out[0].cus;
+  auto add = [&](const Tune& t) {
+    bool dup = false;
+    for (const Tune& u : out)
+      dup = dup || (u.nt == t.nt && u.F == t.F && u.blocks_per_cu == t.blocks_per_cu &&
+                    u.slices == t.slices && u.blocks == t.blocks);
+    if (!dup) out.push_back(t);
+  };
   for (int nt : {1024, 512, 256})
     for (int kb : {32, 64, 128})
-      for (int bpc : {1, 2}) {
-        const Tune t = tune_with(nt, kb, bpc, 1, 0, 0, nb_stride, nsig_max, p_max, unbinned, cus);
-        bool dup = false;
-        for (const Tune& u : out)
-          dup = dup || (u.nt == t.nt && u.F == t.F && u.blocks_per_cu == t.blocks_per_cu &&
-                        u.slices == t.slices && u.blocks == t.blocks);
-        if (!dup) out.push_back(t);
-      }
+      for (int bpc : {1, 2}) add(tune_with(nt, kb, bpc, 1, 0, 0, nb_stride, nsig_max, p_max, unbinned, cus));
+  if (small)
+    for (int nt : {512, 256})
+      for (int blocks : {16, 32, 64})
+        add(tune_with(nt, 32, 1, 1, blocks, 0, nb_stride, nsig_max, p_max, unbinned, cus));
   return out;
 }
 
@@ -729,14 +737,16 @@ int finalize_fit(cwb_fit* f) {
 int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::vector<Tune>* cands,
                     SchedCap* cap, Schedule* first) {
   int nb = 1, ns = 1, pmax = 1;
+  int64_t work = 0;  // 8-row units times learners over the fits
   for (const FitShape* sh : shapes) {
     nb = std::max(nb, sh->nb_stride * std::max(1, sh->share));  // a fold group's histograms
     ns = std::max(ns, sh->nsig_max);
     pmax = std::max(pmax, sh->p);
+    work += sh->n_pad / 8 * sh->p;
     if (sh->unbinned != shapes[0]->unbinned)
       return set_error(CWB_E_UNSUPPORTED, "binned and unbinned fits cannot share a batch");
   }
-  *cands = tune_candidates(nb, ns, pmax, shapes[0]->unbinned, all);
+  *cands = tune_candidates(nb, ns, pmax, shapes[0]->unbinned, all, work <= (int64_t)512 * 256);
   *cap = SchedCap();
   for (size_t i = 0; i < cands->size(); ++i) {
     Schedule S = build_schedule(shapes, (*cands)[i]);

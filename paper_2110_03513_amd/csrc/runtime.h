@@ -117,7 +117,8 @@ struct SchedCap {
   void add(const Schedule& S);
 };
 
-std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all);
+std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all,
+                                  bool small = false);
 
 Layout make_layout(const FitShape& sh, const SchedCap& s);
 

@@ -670,3 +670,21 @@ def test_copies_learners_take_32bit_words_by_segment(monkeypatch):
     for key in ("k", "kcor", "theta", "thetacor", "f", "coef_f", "coef_h", "risk_train"):
         np.testing.assert_array_equal(out[256][key], out[2][key], err_msg=key)
     compare(out[256], prob)
+
+
+@pytest.mark.parametrize("n,blocks,variant", [(10_001, 256, "cwb"), (70_001, 700, "acwb")])
+def test_select_merge_of_many_segments(n, blocks, variant, monkeypatch):
+    """A small fit spread over many histogram blocks: one learner group has
+    hundreds of segments (more than the select pass stages at once for 700),
+    which the select pass merges with the threads split over segments as
+    well as bins.  Integer sums make the result bitwise that of the
+    default tile, and it matches the oracle."""
+    prob = datagen.additive_problem(n, 4, seed=181, n_informative=2, n_bins=90, M=60,
+                                    variant=variant, gamma=0.05, loss="binomial")
+    ref = _run(prob)
+    monkeypatch.setenv("CWB_HIST_BLOCKS", str(blocks))
+    monkeypatch.setenv("CWB_HIST_F", "4")
+    got = _run(prob)
+    for key in ("k", "kcor", "theta", "f", "coef_f", "risk_train"):
+        np.testing.assert_array_equal(got[key], ref[key], err_msg=key)
+    compare(got, prob)
