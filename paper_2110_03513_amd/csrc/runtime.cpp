@@ -160,16 +160,21 @@ Tune make_tune(int nb_stride, int nsig_max, int p_max, bool unbinned) {
 }
 
 // Tile shapes the autotuner tries: the default first, then threads x LDS
-// budget x blocks per CU, and for small work (`small`: a few hundred
-// row-learner units per block at one block per CU) grids of 16 to 64
+// budget x blocks per CU, and for small work (`work`, 8-row units times
+// learners, at most 512 per block at one block per CU) grids of 16 to 64
 // blocks, whose fewer segments per learner group also shorten the select
 // pass's merge.  Explicit CWB_HIST_* settings, or CWB_AUTOTUNE=0, leave the
 // default alone.
 std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all,
-                                  bool small) {
+                                  int64_t work) {
   std::vector<Tune> out{make_tune(nb_stride, nsig_max, p_max, unbinned)};
-  if (!all || hist_env_set() || env_int("CWB_AUTOTUNE", 1) == 0) return out;
   const int cus = out[0].cus;
+  const bool small = work <= (int64_t)512 * 256;
+  // small work: by default about 512 units (4,096 rows) per learner group
+  // and block, so that each group's segments stay few for the select merge
+  if (small && !hist_env_set())
+    out[0].blocks = (int)std::max<int64_t>(16, std::min<int64_t>(cus, work / 512));
+  if (!all || hist_env_set() || env_int("CWB_AUTOTUNE", 1) == 0) return out;
   auto add = [&](const Tune& t) {
     bool dup = false;
     for (const Tune& u : out)
@@ -746,7 +751,7 @@ int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::v
     if (sh->unbinned != shapes[0]->unbinned)
       return set_error(CWB_E_UNSUPPORTED, "binned and unbinned fits cannot share a batch");
   }
-  *cands = tune_candidates(nb, ns, pmax, shapes[0]->unbinned, all, work <= (int64_t)512 * 256);
+  *cands = tune_candidates(nb, ns, pmax, shapes[0]->unbinned, all, work);
   *cap = SchedCap();
   for (size_t i = 0; i < cands->size(); ++i) {
     Schedule S = build_schedule(shapes, (*cands)[i]);

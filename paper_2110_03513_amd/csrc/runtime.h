@@ -118,7 +118,7 @@ struct SchedCap {
 };
 
 std::vector<Tune> tune_candidates(int nb_stride, int nsig_max, int p_max, bool unbinned, bool all,
-                                  bool small = false);
+                                  int64_t work);
 
 Layout make_layout(const FitShape& sh, const SchedCap& s);
 
