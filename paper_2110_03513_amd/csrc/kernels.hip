@@ -205,6 +205,20 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
       }
     }
     if (bad) s_bad = 1;
+    const bool last = ch + 1 >= it.chunks;
+    if (!last) {
+      // the next chunk's rows and winner columns, loaded into the registers
+      // this chunk has finished with, so that they arrive while this
+      // chunk's partials are reduced
+      base += kStateRows;
+      rows = base < it.n_pad;
+      lb = rows ? base : it.n_pad - kRowsPerThread;
+      load8f((two ? it.h : it.fg) + lb, hv);
+      load8f((two ? it.c : it.fg) + lb, cv);
+      load8f(it.fg + lb, f);
+      load8f(it.y + lb, yv);
+      load_cols();
+    }
     double st = risk_t, sv = risk_v;
     float a = amax_r, b = amax_c;
     block_sum2_max2<kStateThreads>(st, sv, a, b, s_red);
@@ -217,17 +231,8 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
         it.amax_part[2 * ch + 1] = b;
       }
     }
-    if (++ch >= it.chunks) break;
-    // the next chunk: its rows' state and winner columns (the reduction's
-    // barrier has passed, so s_red may be reused after this round)
-    base += kStateRows;
-    rows = base < it.n_pad;
-    lb = rows ? base : it.n_pad - kRowsPerThread;
-    load8f((two ? it.h : it.fg) + lb, hv);
-    load8f((two ? it.c : it.fg) + lb, cv);
-    load8f(it.fg + lb, f);
-    load8f(it.y + lb, yv);
-    load_cols();
+    if (last) break;
+    ++ch;
     __syncthreads();  // thread 0's partial writes and s_red reads precede the next reduction
   }
   if (threadIdx.x == 0 && s_bad) atomicOr(&it.ctl->error, 1);
