@@ -9,7 +9,7 @@
 //   lambda with tr((G + lambda D)^-1 G) = df   (App. A.2), by Newton's
 //       method on lambda inside a sign-change bracket, with df and its
 //       derivative from the Demmler-Reinsch eigenvalues (G = L L^T,
-//       eigenvalues of L^-1 D L^-T by cyclic Jacobi rotations), or from
+//       eigenvalues of L^-1 D L^-T by round-robin Jacobi rotations), or from
 //       the hat-matrix trace when G is singular;
 //   (G + lambda D)^-1 by Cholesky (Sec. 2.4).
 // Matrices are row-major d x d doubles, d <= 64; every routine takes its
@@ -115,9 +115,36 @@ CWB_HD inline bool spd_inverse(const E& ex, int d, const double* A, double* inv,
   return true;
 }
 
-// Eigenvalues w of the symmetric S (overwritten) by cyclic Jacobi rotations.
+// Scratch doubles jacobi needs beside S and w: a cosine, a sine and a flag
+// per rotation of one round.
+CWB_HD inline int jacobi_scratch(int d) { return 3 * ((d + 1) / 2); }
+
+// Eigenvalues w of the symmetric S (overwritten) by Jacobi rotations in
+// round-robin order: each sweep is d - 1 (d even; d for odd d, with one
+// index idle per round) rounds of disjoint pairs (p, q), which together
+// meet every pair once.  A round's rotations touch disjoint rows and
+// columns, so they are computed from the matrix at the round's start and
+// applied together: all pairs' columns, then all pairs' rows.
 template <class E>
-CWB_HD inline void jacobi(const E& ex, int d, double* S, double* w) {
+CWB_HD inline void jacobi(const E& ex, int d, double* S, double* w, double* rot) {
+  const int m = d + (d & 1);  // players of the round robin: a dummy for odd d
+  const int np = m / 2;
+  double* rc = rot;
+  double* rs = rot + np;
+  double* rf = rot + 2 * np;  // 1 if the pair rotates this round
+  // pair i of round r: m - 1 stays, the others turn around it
+  auto pair = [m](int r, int i, int* p, int* q) {
+    int a, b;
+    if (i == 0) {
+      a = m - 1;
+      b = r;
+    } else {
+      a = (r + i) % (m - 1);
+      b = (r - i + m - 1) % (m - 1);
+    }
+    *p = a < b ? a : b;
+    *q = a < b ? b : a;
+  };
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int i = 0; i < d; ++i)
@@ -127,25 +154,45 @@ CWB_HD inline void jacobi(const E& ex, int d, double* S, double* w) {
         if (i != j) off += v;
       }
     if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < d - 1; ++p)
-      for (int q = p + 1; q < d; ++q) {
-        const double apq = S[p * d + q];
-        if (apq == 0.0) continue;
-        const double app = S[p * d + p], aqq = S[q * d + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (dabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        ex.each(d, [&](int k) {  // columns p, q
-          const double akp = S[k * d + p], akq = S[k * d + q];
-          S[k * d + p] = c * akp - s * akq;
-          S[k * d + q] = s * akp + c * akq;
-        });
-        ex.each(d, [&](int k) {  // rows p, q
-          const double apk = S[p * d + k], aqk = S[q * d + k];
-          S[p * d + k] = c * apk - s * aqk;
-          S[q * d + k] = s * apk + c * aqk;
-        });
-      }
+    for (int r = 0; r < m - 1; ++r) {
+      ex.each(np, [&](int i) {  // the round's rotations
+        int p, q;
+        pair(r, i, &p, &q);
+        double c = 1.0, sn = 0.0, act = 0.0;
+        if (q < d && S[p * d + q] != 0.0) {
+          const double apq = S[p * d + q];
+          const double app = S[p * d + p], aqq = S[q * d + q];
+          const double theta = (aqq - app) / (2.0 * apq);
+          const double t = (theta >= 0 ? 1.0 : -1.0) / (dabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sn = t * c;
+          act = 1.0;
+        }
+        rc[i] = c;
+        rs[i] = sn;
+        rf[i] = act;
+      });
+      ex.each(np * d, [&](int e) {  // columns p, q of pair i, row k
+        const int i = e / d, k = e % d;
+        if (rf[i] == 0.0) return;
+        int p, q;
+        pair(r, i, &p, &q);
+        const double c = rc[i], sn = rs[i];
+        const double akp = S[k * d + p], akq = S[k * d + q];
+        S[k * d + p] = c * akp - sn * akq;
+        S[k * d + q] = sn * akp + c * akq;
+      });
+      ex.each(np * d, [&](int e) {  // rows p, q of pair i, column k
+        const int i = e / d, k = e % d;
+        if (rf[i] == 0.0) return;
+        int p, q;
+        pair(r, i, &p, &q);
+        const double c = rc[i], sn = rs[i];
+        const double apk = S[p * d + k], aqk = S[q * d + k];
+        S[p * d + k] = c * apk - sn * aqk;
+        S[q * d + k] = sn * apk + c * aqk;
+      });
+    }
   }
   ex.each(d, [&](int i) { w[i] = S[i * d + i]; });
 }
@@ -196,7 +243,7 @@ CWB_HD inline void gram_from_counts(const E& ex, int d, int nb, int band, const 
 }
 
 // Scratch doubles lambda_for_df needs.
-CWB_HD inline int lambda_scratch(int d) { return 8 * d * d + d; }
+CWB_HD inline int lambda_scratch(int d) { return 8 * d * d + d + jacobi_scratch(d); }
 
 // lambda >= 0 with df(lambda) = tr((G + lambda D)^-1 G) = target.  Newton's
 // method on g(lambda) = df(lambda) - target, which decreases monotonically,
@@ -223,6 +270,7 @@ CWB_HD inline int lambda_for_df(const E& ex, int d, const double* G, const doubl
   double* Q = scr + 6 * d * d;   // A^-1 D
   double* inv = scr + 7 * d * d;
   double* w = scr + 8 * d * d;
+  double* rot = w + d;
   const bool dro = chol(ex, d, G, L);
   if (dro) {
     tri_inverse(ex, d, L, Li);
@@ -245,7 +293,7 @@ CWB_HD inline int lambda_for_df(const E& ex, int d, const double* G, const doubl
       S[i * d + j] = a;
       S[j * d + i] = a;
     });
-    jacobi(ex, d, S, w);
+    jacobi(ex, d, S, w, rot);
     ex.each(d, [&](int i) { w[i] = dmax(w[i], 0.0); });
   }
   // g(lambda) and g'(lambda); false if A is not positive definite
