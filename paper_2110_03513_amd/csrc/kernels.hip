@@ -322,12 +322,16 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
   if (sig > 0 && it.variant == CWB_CWB) return;
   const int d = it.d, nb = it.nb, band = it.band, n_off = it.n_off;
   // the first chunk of the signal's partials, loaded in the first round when
-  // its offsets are inline (bins 4t .. 4t+3 of every segment)
-  const bool pre = n_off <= kInlineOffs && nb <= 4 * kSelectThreads;
-  i64x2 pv[kInlineOffs][2];
+  // its offsets are inline (bins 4t .. 4t+3 of every segment).  The variant
+  // for large launches (a batch, STAGED false) preloads at most half as many
+  // segments: 32 fewer registers per lane, more blocks resident per CU; its
+  // learner groups rarely span more segments.
+  constexpr int NPRE = STAGED ? kInlineOffs : kInlineOffs / 2;
+  const bool pre = n_off <= NPRE && nb <= 4 * kSelectThreads;
+  i64x2 pv[NPRE][2];
   if (pre && 4 * (int)threadIdx.x < nb) {
 #pragma unroll
-    for (int i = 0; i < kInlineOffs; ++i) {
+    for (int i = 0; i < NPRE; ++i) {
       if (i < n_off) {
         const int64_t o = sig ? it.off1[i] : it.off0[i];
         const GLOBAL i64x2* src = (const GLOBAL i64x2*)(partials + o + 4 * threadIdx.x);
@@ -494,7 +498,7 @@ k_select(const SelItem* __restrict__ items, const long long* __restrict__ partia
       if (pre) {  // l0 == 0: the preloaded chunk
         if (l < nb) {
 #pragma unroll
-          for (int i = 0; i < kInlineOffs; ++i) {
+          for (int i = 0; i < NPRE; ++i) {
             if (i < n_off) {
               a0 += pv[i][0].x;
               a1 += pv[i][0].y;
