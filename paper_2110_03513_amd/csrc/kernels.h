@@ -6,8 +6,9 @@
 
 namespace cwb {
 
+// unbinned: the fits' learners are unbinned (every fit of the launch alike).
 hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items, int nitems,
-                        int nb_max, int final_mode);
+                        int nb_max, int final_mode, bool unbinned);
 // folds: the schedule has fold-group segments (nfit > 1); only the variant
 // compiled for them handles such segments.
 hipError_t launch_hist(hipStream_t st, int nt, int fmax, int nsmax, bool unbinned, bool folds,

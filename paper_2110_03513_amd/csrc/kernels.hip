@@ -47,6 +47,9 @@ namespace cwb {
 // more chunks than the chip has room for blocks, as a large batch does):
 // the selection and the winners' tables are taken once, and each chunk
 // writes its own risk and maximum partials.
+// UNB: the launch's fits have unbinned learners (32-bit codes per row);
+// else the winners' columns stay as packed uint16 pairs until used.
+template <bool UNB>
 __global__ void __launch_bounds__(kStateThreads)
 k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int final_mode) {
   extern __shared__ float s_tab[];  // [2][nb_max]
@@ -63,7 +66,7 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   // which keeps no h and c, reads f again there (cache hits).  The control
   // block comes in through scalar loads, so testing it does not wait for
   // the model state.
-  float f[8], yv[8], hv[8], cv[8], rr[8], cc[8];
+  float f[8], yv[8], hv[8], cv[8];
   int64_t lb = rows ? base : it.n_pad - kRowsPerThread;
   load8f((two ? it.h : it.fg) + lb, hv);
   load8f((two ? it.c : it.fg) + lb, cv);
@@ -125,8 +128,13 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
   const bool use_t = do_pick;
   const bool use_h = do_pick && sel_acwb && kc >= 0;
   const bool use_cc = acwb && have_sel && sel_acwb && kc >= 0;
-  const bool unb = it.unbinned != 0;
-  uint32_t ik[8], ic[8];
+  constexpr bool unb = UNB;
+  constexpr int NW = UNB ? 8 : 4;  // index registers per winner column
+  uint32_t ik[NW], ic[NW];
+  // row j's index in a winner column
+  auto idx = [](const uint32_t* a, int j) -> uint32_t {
+    return UNB ? a[j] : ((a[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+  };
   uint32_t fold_lo = 0u, fold_hi = 0u;  // fold fit: the 8 rows' fold ids, one byte each
   // this thread's winner-column and fold loads for the chunk at `base`
   auto load_cols = [&]() {
@@ -136,13 +144,20 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
       fold_lo = (uint32_t)fv;
       fold_hi = (uint32_t)(fv >> 32);
     }
-    if (unb) {
+    if (UNB) {
       const uint32_t* XU = reinterpret_cast<const uint32_t*>(it.X);
       if (rows && use_t) load8c(XU + (size_t)kk * it.n_pad + base, ik);
       if (rows && (use_h || use_cc)) load8c(XU + (size_t)kc * it.n_pad + base, ic);
     } else {
-      if (rows && use_t) load8u(it.X + (size_t)kk * it.n_pad + base, ik);
-      if (rows && (use_h || use_cc)) load8u(it.X + (size_t)kc * it.n_pad + base, ic);
+      auto load4 = [&](int k, uint32_t* a) {
+        const u32x4 w = *(const GLOBAL u32x4*)(it.X + (size_t)k * it.n_pad + base);
+        a[0] = w.x;
+        a[1] = w.y;
+        a[2] = w.z;
+        a[3] = w.w;
+      };
+      if (rows && use_t) load4(kk, ik);
+      if (rows && (use_h || use_cc)) load4(kc, ic);
     }
   };
   load_cols();
@@ -164,8 +179,8 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
         const bool live = i < it.n;
         float fj = f[j];
         float hj = two ? hv[j] : 0.0f;
-        if (live && use_t) fj = fj + nu * table_at(unb, ik[j], tf);
-        if (live && use_h) hj = hj + eta * table_at(unb, ic[j], tc);
+        if (live && use_t) fj = fj + nu * table_at(unb, idx(ik, j), tf);
+        if (live && use_h) hj = hj + eta * table_at(unb, idx(ic, j), tc);
         const bool train =
             it.fold ? (int)(((j < 4 ? fold_lo : fold_hi) >> (8 * (j & 3))) & 0xffu) != it.fold_k
                     : i < it.n_train;
@@ -176,32 +191,36 @@ k_state(const FitDev* __restrict__ fits, const RowItem* __restrict__ items, int 
         }
         f[j] = fj;
         hv[j] = hj;
-        rr[j] = 0.0f;
-        cc[j] = 0.0f;
-        if (final_mode || !live) continue;
-        const bool fitrow = all_rows || train;
-        if (acwb) {
-          const float g = (1.0f - vt) * fj + vt * hj;
-          const float r = neg_gradient(it.loss, yv[j], g);
-          float c = r;
-          if (use_cc) c = r + cw * (cv[j] - table_at(unb, ic[j], tc));
-          f[j] = g;  // the primary model update f = g + nu b_k is pending
-          if (fitrow) {
-            rr[j] = r;
-            cc[j] = c;
+        float rj = 0.0f, cj = 0.0f;
+        if (!final_mode && live) {
+          const bool fitrow = all_rows || train;
+          if (acwb) {
+            const float g = (1.0f - vt) * fj + vt * hj;
+            const float r = neg_gradient(it.loss, yv[j], g);
+            float c = r;
+            if (use_cc) c = r + cw * (cv[j] - table_at(unb, idx(ic, j), tc));
+            f[j] = g;  // the primary model update f = g + nu b_k is pending
+            if (fitrow) {
+              rj = r;
+              cj = c;
+            }
+          } else {
+            const float r = neg_gradient(it.loss, yv[j], fj);
+            if (fitrow) rj = r;
           }
-        } else {
-          const float r = neg_gradient(it.loss, yv[j], fj);
-          if (fitrow) rr[j] = r;
         }
-        amax_r = fmaxf(amax_r, fabsf(rr[j]));
-        amax_c = fmaxf(amax_c, fabsf(cc[j]));
+        // r and c take the registers of y and the previous c, which this
+        // row no longer needs
+        yv[j] = rj;
+        cv[j] = cj;
+        amax_r = fmaxf(amax_r, fabsf(rj));
+        amax_c = fmaxf(amax_c, fabsf(cj));
       }
       store8f(it.fg + base, f);
       if (two) store8f(it.h + base, hv);
       if (!final_mode) {
-        store8f(it.r + base, rr);
-        if (acwb) store8f(it.c + base, cc);
+        store8f(it.r + base, yv);
+        if (acwb) store8f(it.c + base, cv);
       }
     }
     if (bad) s_bad = 1;
@@ -814,10 +833,13 @@ k_predict(const FitDev* __restrict__ fits, const double* __restrict__ x, int64_t
 // ---------------------------------------------------------------------------
 
 hipError_t launch_state(hipStream_t st, const FitDev* fits, const RowItem* items, int nitems,
-                        int nb_max, int final_mode) {
+                        int nb_max, int final_mode, bool unbinned) {
   if (nitems <= 0) return hipSuccess;
   const size_t lds = (size_t)2 * nb_max * sizeof(float);
-  hipLaunchKernelGGL(k_state, dim3(nitems), dim3(kStateThreads), lds, st, fits, items, final_mode);
+  if (unbinned)
+    hipLaunchKernelGGL(k_state<true>, dim3(nitems), dim3(kStateThreads), lds, st, fits, items, final_mode);
+  else
+    hipLaunchKernelGGL(k_state<false>, dim3(nitems), dim3(kStateThreads), lds, st, fits, items, final_mode);
   return hipGetLastError();
 }
 

@@ -614,7 +614,7 @@ int enqueue_iteration(hipStream_t st, const FitDev* d_fits, int nfits, const Sch
   int tm = timed ? timed->timing : 0;
   if (tm && (timed->timing_counter++ % timed->timing_period) != 0) tm = 0;
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
-  HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0));
+  HIP_TRY(launch_state(st, d_fits, d_st, n_st, nb_max, 0, S.unbinned));
   if (tm & 2) HIP_TRY(timer_mark(timed->t_state, st));
   if (tm & 1) HIP_TRY(timer_mark(timed->t_hist, st));
   HIP_TRY(launch_hist(st, t.nt, t.fmax, S.nsig_max, S.unbinned, S.folds, S.copies, S.blocks, S.lds, d_fits, d_segs, d_blk, d_part));
@@ -741,7 +741,7 @@ SelItem make_sel_item(int fit, int k, const FeatDev& fd, const FitDev& D, const 
 int finalize_fit(cwb_fit* f) {
   HIP_TRY(hipSetDevice(f->device));
   RowItem* d_st = dptr<RowItem>(f->ws, f->lay.st_items);
-  HIP_TRY(launch_state(f->stream, f->d_fit, d_st, f->n_st, f->shape.nb_max, 1));
+  HIP_TRY(launch_state(f->stream, f->d_fit, d_st, f->n_st, f->shape.nb_max, 1, f->shape.unbinned));
   HIP_TRY(launch_finalize(f->stream, f->d_fit, 1));
   return CWB_OK;
 }
