@@ -184,6 +184,38 @@ k_pack12(const uint16_t* __restrict__ X, int64_t groups, uint32_t* __restrict__ 
   }
 }
 
+// 10-bit copy (every index below 1,024): each learner's n_pad indices as one
+// stream of 10-bit fields, row i at bits [10 i, 10 i + 10); 16 rows fill 5
+// words.  `pairs` = p n_pad / 16; pair t is X[16t, 16t + 16) -> X10[5t, 5t + 5)
+// (n_pad is a multiple of 16, so no pair spans two learners).
+__global__ void __launch_bounds__(kSetupThreads)
+k_pack10(const uint16_t* __restrict__ X, int64_t pairs, uint32_t* __restrict__ X10) {
+  for (int64_t t = (int64_t)blockIdx.x * kSetupThreads + threadIdx.x; t < pairs;
+       t += (int64_t)gridDim.x * kSetupThreads) {
+    const uint4 v0 = *reinterpret_cast<const uint4*>(X + 16 * t);
+    const uint4 v1 = *reinterpret_cast<const uint4*>(X + 16 * t + 8);
+    const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    uint32_t out[5] = {0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t a = (w[i >> 1] >> (16 * (i & 1))) & 0x3ffu;
+      const int bit = 10 * i, m = bit >> 5, sh = bit & 31;
+      out[m] |= a << sh;
+      if (sh > 22) out[m + 1] |= a >> (32 - sh);  // the field runs into the next word
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) X10[5 * t + m] = out[m];
+  }
+}
+
+hipError_t launch_pack10(hipStream_t st, const uint16_t* X, int64_t pairs, uint32_t* X10) {
+  if (pairs <= 0) return hipSuccess;
+  const int64_t want = (pairs + kSetupThreads - 1) / kSetupThreads;
+  const int blocks = (int)(want < 65536 ? want : 65536);
+  hipLaunchKernelGGL(k_pack10, dim3(blocks), dim3(kSetupThreads), 0, st, X, pairs, X10);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack12(hipStream_t st, const uint16_t* X, int64_t groups, uint32_t* X12) {
   if (groups <= 0) return hipSuccess;
   const int64_t want = (groups + kSetupThreads - 1) / kSetupThreads;

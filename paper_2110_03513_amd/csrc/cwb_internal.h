@@ -86,7 +86,10 @@ struct FitDev {
                          // n_train (training rows first), or n for a fold fit
   const uint8_t* fold;   // fold fit: fold id of every row (rows of fold_k are
                          // held out and carry zero residuals), else null
-  int32_t fold_k, pad2_;
+  int32_t fold_k;
+  int32_t xbits;         // bits per index of the packed copy X12: 12 (8 rows in
+                         // 3 words), 10 (8 rows in 80 bits: learner k's rows
+                         // as one 10-bit stream of 5 n_pad / 16 words), or 0
   int32_t p, nb_max, d_max, sum_d;
   int32_t loss, variant, M, patience;
   double nu, gamma;
@@ -101,8 +104,9 @@ struct FitDev {
                          // than 2^acc32_bits rows then take 32-bit LDS words.
                          // 0: truncated at the int64 scale (scale_exponent).
   const uint16_t* X;
-  const uint32_t* X12;   // 12-bit copy of X read by 32-bit histogram groups (8 rows
-                         // in 3 words, learner k at word 3 k n_pad / 8), or null
+  const uint32_t* X12;   // packed copy of X read by 32-bit histogram groups, at
+                         // xbits per index (learner k at word 3 k n_pad / 8 for
+                         // 12 bits, 5 k n_pad / 16 for 10), or null
   const float* y;
   float* fg;
   float* h;

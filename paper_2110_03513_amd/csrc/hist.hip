@@ -146,6 +146,21 @@ __device__ __forceinline__ void hist_rows(const FitDev& F, const Seg& sg,
 
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 
+// The 8 bin indices of one 12-byte word triple of the 10-bit copy of X, in
+// the 16-bit layout of a uint16 load: the 80 bits start at bit 0 of w.x, or
+// at bit 16 for an odd 8-row block (`odd`).
+__device__ __forceinline__ u32x4 unpack10(const u32x3& w, bool odd) {
+  const uint32_t a = odd ? __builtin_amdgcn_alignbit(w.y, w.x, 16) : w.x;
+  const uint32_t b = odd ? __builtin_amdgcn_alignbit(w.z, w.y, 16) : w.y;
+  const uint32_t c = odd ? (w.z >> 16) : w.z;
+  u32x4 o;
+  o.x = (a & 0x3ffu) | (((a >> 10) & 0x3ffu) << 16);
+  o.y = ((a >> 20) & 0x3ffu) | ((__builtin_amdgcn_alignbit(b, a, 30) & 0x3ffu) << 16);
+  o.z = ((b >> 8) & 0x3ffu) | (((b >> 18) & 0x3ffu) << 16);
+  o.w = (__builtin_amdgcn_alignbit(c, b, 28) & 0x3ffu) | (((c >> 6) & 0x3ffu) << 16);
+  return o;
+}
+
 // The 8 bin indices of one 12-byte word triple of the 12-bit copy of X, in
 // the 16-bit layout of a uint16 load (two indices per word), so the same
 // adders serve both.
@@ -163,12 +178,14 @@ __device__ __forceinline__ u32x4 unpack12(const u32x3& w) {
 // (Seg.acc32).  One signal: 4-byte words, learner f at word f * nb.  Two
 // signals: both values of a row packed into one 8-byte word (pack_signals),
 // learner f at word f * nb, so an ACWB row costs one LDS atomic per
-// learner, as a CWB row does.  With X12 the indices come from the 12-bit
-// copy of X: 12 bytes instead of 16 per 8 rows and learner.  With COPIES a
-// learner of few bins spreads over copies of its histogram by lane, as in
-// hist_rows (the schedule takes 32-bit words for it only while each copy
-// receives fewer than 2^acc32_bits rows of the segment).
-template <int NT, int FMAX, int NSIG, bool X12, bool COPIES>
+// learner, as a CWB row does.  XB is the index width read: 16 (the uint16
+// matrix), 12 or 10 (the packed copy F.X12 at F.xbits; 12 or 10 bytes per 8
+// rows and learner instead of 16), a template parameter so that each
+// instantiation unpacks one way only.  With COPIES a learner of few bins
+// spreads over copies of its histogram by lane, as in hist_rows (the
+// schedule takes 32-bit words for it only while each copy receives fewer
+// than 2^acc32_bits rows of the segment).
+template <int NT, int FMAX, int NSIG, int XB, bool COPIES>
 __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void* __restrict__ hist,
                                             int nb, int64_t r0, int64_t r1, Exps& ex, bool need_e,
                                             int64_t n_fit, float* red, const int (*cp)[16]) {
@@ -179,12 +196,19 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
     cs[f] = COPIES ? __builtin_amdgcn_readfirstlane(cp[1][f]) : 0;
   }
   const uint16_t* __restrict__ Xg = F.X + (size_t)sg.k0 * F.n_pad;
-  const size_t ld12 = (size_t)F.n_pad / 8 * 3;  // words per learner in the 12-bit copy
-  const uint32_t* __restrict__ Xp = X12 ? F.X12 + (size_t)sg.k0 * ld12 : nullptr;
+  // the packed copy: 12 bits (3 words per 8-row block) or 10 bits (8 rows in
+  // 80 bits; block b starts at bit 80 b, and its 12-byte load at word
+  // floor(5 b / 2), so consecutive blocks' loads overlap by half a word)
+  constexpr bool X12 = XB != 16;
+  constexpr bool x10 = XB == 10;
+  const size_t ldp = x10 ? (size_t)F.n_pad / 16 * 5 : (size_t)F.n_pad / 8 * 3;  // words per learner
+  const uint32_t* __restrict__ Xp = X12 ? F.X12 + (size_t)sg.k0 * ldp : nullptr;
   const int nf = sg.nf;
   const size_t ld = (size_t)F.n_pad;
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
   const bool any = base < r1;
+  // a thread's 8-row blocks keep their parity: each step moves 8 NT rows
+  const bool odd = ((base >> 3) & 1) != 0;
   float rv[8], cv[8];
   u32x4 xw[FMAX];
   u32x3 xp[FMAX];
@@ -195,10 +219,11 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
     }
     load8f(F.r + b, rv);
     if (NSIG == 2) load8f(F.c + b, cv);
+    const size_t w0 = x10 ? (size_t)((b >> 3) * 5 >> 1) : (size_t)(b >> 3) * 3;
 #pragma unroll
     for (int f = 0; f < FMAX; ++f)
       if (f < nf)
-        xp[f] = __builtin_nontemporal_load((const GLOBAL u32x3*)(Xp + f * ld12 + (size_t)(b >> 3) * 3));
+        xp[f] = __builtin_nontemporal_load((const GLOBAL u32x3*)(Xp + f * ldp + w0));
   };
   if (any) load(base);
   if (need_e) fit_exponents<NT>(F, n_fit, &ex, red);
@@ -220,7 +245,7 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
     }
     u32x4 xc[FMAX];
 #pragma unroll
-    for (int f = 0; f < FMAX; ++f) xc[f] = X12 ? unpack12(xp[f]) : xw[f];
+    for (int f = 0; f < FMAX; ++f) xc[f] = X12 ? (x10 ? unpack10(xp[f], odd) : unpack12(xp[f])) : xw[f];
     if (more) load(nxt);
     const int lane = COPIES ? opaque_lane() : 0;
 #pragma unroll
@@ -479,16 +504,19 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
       else
         uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, ex.e[0], ex.e[1]);
     } else if (w32) {
-      if (F.X12) {
+      // the 10-bit copy is built for one-signal fits only
+      if (F.X12 && F.xbits == 10) {
+        hist_rows32<NT, FMAX, 1, 10, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+      } else if (F.X12) {
         if (NSMAX == 1 || nsig == 1)
-          hist_rows32<NT, FMAX, 1, true, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, 1, 12, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
         else
-          hist_rows32<NT, FMAX, NSMAX, true, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, NSMAX, 12, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       } else {
         if (NSMAX == 1 || nsig == 1)
-          hist_rows32<NT, FMAX, 1, false, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, 1, 16, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
         else
-          hist_rows32<NT, FMAX, NSMAX, false, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, NSMAX, 16, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       }
     } else {
       if (NSMAX == 1 || nsig == 1)

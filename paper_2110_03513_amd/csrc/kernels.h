@@ -45,5 +45,7 @@ hipError_t launch_solve(hipStream_t st, const SolveJob* jobs, int njobs, int d_m
 // The 12-bit copy of the index matrix (binning.hip): groups = p n_pad / 8,
 // every index below 4,096.
 hipError_t launch_pack12(hipStream_t st, const uint16_t* X, int64_t groups, uint32_t* X12);
+// The 10-bit copy (binning.hip): pairs = p n_pad / 16, every index below 1,024.
+hipError_t launch_pack10(hipStream_t st, const uint16_t* X, int64_t pairs, uint32_t* X10);
 
 }  // namespace cwb

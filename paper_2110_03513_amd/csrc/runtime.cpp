@@ -147,8 +147,9 @@ Tune tune_with(int nt, int lds_kb, int bpc, int slices, int blocks, int fset, in
 // threads; one signal with a 32 KiB histogram budget (four learners per
 // group at 1,000 bins), two signals with 128 KiB (eight).  Timed back to back
 // the 512- and 1,024-thread one-signal tiles tie, but inside the iteration
-// (after the row pass) the 512-thread tile ran 4 us faster in every trace,
-// so it is the one the autotuner keeps unless another is clearly faster.
+// (after the row pass) the 512-thread tile ran 1-4 us faster in every A/B
+// run, with either index copy, so it is the one the autotuner keeps unless
+// another is clearly faster.
 Tune make_tune(int nb_stride, int nsig_max, int p_max, bool unbinned) {
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -1149,6 +1150,12 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   const bool pack12 = sh.x12 && !fold && !sh.external_x && f->shape.acc32_bits > 0 &&
                       env_int("CWB_X12", 1) != 0;
   D.X12 = pack12 ? dptr<uint32_t>(ws, L.X12) : nullptr;
+  // 10 bits per index for a one-signal fit whose indices are all below
+  // 1,024 (CWB_X10=0 keeps 12): at the headline shape 84.6 us per iteration
+  // against 86.2 with the 12-bit copy.  With two signals the 10-bit
+  // unpacking's extra work outweighed the saved bytes in most tiles.
+  D.xbits = !pack12 ? 0
+            : (sh.nb_max <= 1024 && sh.nsig_max == 1 && env_int("CWB_X10", 1) != 0) ? 10 : 12;
   if (fold) {
     D.fold = fold->fold;
     D.fold_k = fold->k;
@@ -1205,7 +1212,10 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.XU.data(), hf.XU.size() * 4, hipMemcpyHostToDevice, st));
   else if (!bin_on_device && !fold)  // else X is in place already (device pass, shared folds)
     HIP_TRY(hipMemcpyAsync(ws + L.X, hf.X.data(), hf.X.size() * 2, hipMemcpyHostToDevice, st));
-  if (pack12)
+  if (D.xbits == 10)
+    HIP_TRY(launch_pack10(st, dptr<uint16_t>(ws, L.X), (int64_t)sh.p * sh.n_pad / 16,
+                          dptr<uint32_t>(ws, L.X12)));
+  else if (D.xbits == 12)
     HIP_TRY(launch_pack12(st, dptr<uint16_t>(ws, L.X), (int64_t)sh.p * sh.n_pad / 8,
                           dptr<uint32_t>(ws, L.X12)));
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));

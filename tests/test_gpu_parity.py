@@ -688,3 +688,25 @@ def test_select_merge_of_many_segments(n, blocks, variant, monkeypatch):
     for key in ("k", "kcor", "theta", "f", "coef_f", "risk_train"):
         np.testing.assert_array_equal(got[key], ref[key], err_msg=key)
     compare(got, prob)
+
+
+@pytest.mark.parametrize("nb,variant", [(1000, "cwb"), (1024, "acwb"), (2000, "cwb")])
+def test_packed_index_copies_bitwise(nb, variant, monkeypatch):
+    """The histogram pass reads a 10-bit copy of the bin indices when every
+    index is below 1,024, else a 12-bit copy below 4,096: both give bitwise
+    the results of the uint16 matrix (ragged n, odd and even 8-row blocks at
+    every segment start), and match the oracle."""
+    prob = datagen.additive_problem(50_003, 7, seed=191, n_informative=3, n_bins=nb, M=50,
+                                    variant=variant, gamma=0.05, loss="binomial")
+    ref = _run(prob)
+    runs = {}
+    for name, env in (("x12", {"CWB_X10": "0"}), ("u16", {"CWB_X12": "0"})):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        runs[name] = _run(prob)
+        for k in env:
+            monkeypatch.delenv(k)
+    for name, got in runs.items():
+        for key in ("k", "kcor", "theta", "f", "coef_f", "risk_train"):
+            np.testing.assert_array_equal(got[key], ref[key], err_msg=f"{name} {key}")
+    compare(ref, prob)
