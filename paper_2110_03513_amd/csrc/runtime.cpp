@@ -301,45 +301,98 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   }
   const int B = t.blocks > 0 ? t.blocks : std::max(1, t.cus * t.blocks_per_cu);
   S.blocks = B;
-  std::vector<int64_t> seg_vb;
-  int64_t vb = 0, wpos = 0;
-  for (const Item& it : items) {
-    int64_t u = it.u0;
-    const int64_t w = (int64_t)it.nf * it.nfit * sig_weight(*fits[it.fit]);  // work per 8-row unit
-    while (u < it.u1) {
-      const int64_t wp = wpos + (u - it.u0) * w;
-      while (vb < B - 1 && ((vb + 1) * W) / B <= wp) ++vb;
-      int64_t take;
-      if (vb == B - 1) {
-        take = it.u1 - u;
-      } else {
-        const int64_t bend = ((vb + 1) * W) / B;
-        take = (bend - wp + w - 1) / w;
+  // Blocks get equal shares of the work, counting for every segment a block
+  // starts a fixed cost of kSegUnits 8-row units of its group (at most a
+  // quarter of a block's share): zeroing and flushing its LDS histograms
+  // and refilling the row pipeline.  Timed per block at n = 1e6, p = 200
+  // (512- and 1,024-thread tiles), a block with two segments took 4 us more
+  // than one with a single segment of the same rows, about 1,600 units.
+  // Block v's share ends at (v + 1) Wt / B on the running cost; a segment
+  // that would hold less than its own fixed cost starts in the next block
+  // instead, and Wt (the work plus the fixed costs plus the room so left)
+  // is refined until the last block gets its share.
+  constexpr int64_t kSegUnits = 1600;
+  const int64_t cs_cap = std::max<int64_t>(1, W / B / 4);
+  auto seg_cost = [&](int64_t w) { return std::min(kSegUnits * w, cs_cap); };
+  struct Cut {
+    size_t item;
+    int64_t u0, u1, vb;
+  };
+  std::vector<Cut> cuts_out;
+  auto split = [&](int64_t Wt, std::vector<Cut>* out) -> int64_t {
+    out->clear();
+    int64_t vb = 0, pos = 0, used = -1;  // current block, running cost, last block given work
+    for (size_t ii = 0; ii < items.size(); ++ii) {
+      const Item& it = items[ii];
+      const int64_t w = (int64_t)it.nf * it.nfit * sig_weight(*fits[it.fit]);  // work per 8-row unit
+      const int64_t cs = seg_cost(w);
+      int64_t u = it.u0;
+      while (u < it.u1) {
+        while (vb < B - 1) {
+          const int64_t room = ((vb + 1) * Wt) / B - pos;
+          if (room > 0 && (vb != used || room >= cs + w)) break;
+          pos = std::max(pos, ((vb + 1) * Wt) / B);  // the block's unused room
+          ++vb;
+        }
+        pos += cs;
+        int64_t take = it.u1 - u;
+        if (vb < B - 1) take = (((vb + 1) * Wt) / B - pos + w - 1) / w;
+        const int64_t ue = std::min(it.u1, u + std::max<int64_t>(1, take));
+        pos += (ue - u) * w;
+        out->push_back({ii, u, ue, vb});
+        used = vb;
+        u = ue;
       }
-      const int64_t ue = std::min(it.u1, u + std::max<int64_t>(1, take));
-      Seg sg;
-      sg.fit = it.fit;
-      sg.k0 = it.k0;
-      sg.nf = it.nf;
-      sg.nfit = (int16_t)it.nfit;
-      sg.skip = -1;
-      sg.acc32 = 1;  // every fold of the group must keep 32-bit sums
-      for (int q = 0; q < it.nfit; ++q)
-        sg.acc32 &= group_acc32(*fits[it.fit + q], it.k0, it.nf, u, ue, t.nt);
-      sg.pad = 0;
-      if (it.nfit > 1) {
-        int64_t r0, r1;
-        unit_rows(*fits[it.fit], u, ue, &r0, &r1);
-        sg.skip = (int16_t)segment_fold(*fits[it.fit], r0, r1);
-      }
-      sg.u0 = u;
-      sg.u1 = ue;
-      sg.slot = 0;
-      S.segs.push_back(sg);
-      seg_vb.push_back(vb);
-      u = ue;
     }
-    wpos += w * (it.u1 - it.u0);
+    return pos;
+  };
+  {
+    // split() returns the running cost at the end: the last block's load
+    // is that minus (B - 1) Wt / B, and it falls as Wt grows (a step
+    // function, as segments move between blocks).  Bisect for the Wt that
+    // leaves the last block closest to its share.
+    int64_t cs_max = 0;
+    for (const Item& it : items)
+      cs_max = std::max(cs_max, seg_cost((int64_t)it.nf * it.nfit * sig_weight(*fits[it.fit])));
+    int64_t lo = W, hi = W + (int64_t)(items.size() + 2 * (size_t)B) * (cs_max + 1);
+    int64_t best = hi, best_err = INT64_MAX;
+    for (int step = 0; step < 48 && lo <= hi; ++step) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      const int64_t excess = split(mid, &cuts_out) - mid;  // the last block's load above its share
+      if (std::llabs(excess) < best_err) {
+        best_err = std::llabs(excess);
+        best = mid;
+      }
+      if (excess == 0) break;
+      if (excess > 0) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    split(best, &cuts_out);
+  }
+  std::vector<int64_t> seg_vb;
+  for (const Cut& cu : cuts_out) {
+    const Item& it = items[cu.item];
+    const int64_t u = cu.u0, ue = cu.u1, vb = cu.vb;
+    Seg sg;
+    sg.fit = it.fit;
+    sg.k0 = it.k0;
+    sg.nf = it.nf;
+    sg.nfit = (int16_t)it.nfit;
+    sg.skip = -1;
+    sg.acc32 = 1;  // every fold of the group must keep 32-bit sums
+    for (int q = 0; q < it.nfit; ++q)
+      sg.acc32 &= group_acc32(*fits[it.fit + q], it.k0, it.nf, u, ue, t.nt);
+    sg.pad = 0;
+    if (it.nfit > 1) {
+      int64_t r0, r1;
+      unit_rows(*fits[it.fit], u, ue, &r0, &r1);
+      sg.skip = (int16_t)segment_fold(*fits[it.fit], r0, r1);
+    }
+    sg.u0 = u;
+    sg.u1 = ue;
+    sg.slot = 0;
+    S.segs.push_back(sg);
+    seg_vb.push_back(vb);
   }
   // partial slots
   int64_t off = 0;
