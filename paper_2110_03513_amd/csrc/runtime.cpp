@@ -306,12 +306,14 @@ Schedule build_schedule(const std::vector<const FitShape*>& fits, const Tune& t)
   // quarter of a block's share): zeroing and flushing its LDS histograms
   // and refilling the row pipeline.  Timed per block at n = 1e6, p = 200
   // (512- and 1,024-thread tiles), a block with two segments took 4 us more
-  // than one with a single segment of the same rows, about 1,600 units.
+  // than one with a single segment of the same rows, about 1,700 units; with
+  // 1,600 units charged they still ran 1 us (about 400 units) over the
+  // others, so a segment counts 2,000.
   // Block v's share ends at (v + 1) Wt / B on the running cost; a segment
   // that would hold less than its own fixed cost starts in the next block
   // instead, and Wt (the work plus the fixed costs plus the room so left)
   // is refined until the last block gets its share.
-  constexpr int64_t kSegUnits = 1600;
+  constexpr int64_t kSegUnits = 2000;
   const int64_t cs_cap = std::max<int64_t>(1, W / B / 4);
   auto seg_cost = [&](int64_t w) { return std::min(kSegUnits * w, cs_cap); };
   struct Cut {
