@@ -46,6 +46,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def index_read(tile: dict) -> str:
+    """How the histogram pass reads the bin indices, from the tile report."""
+    bits = tile.get("index_bits", 16)
+    return f" (read as a {bits}-bit packed copy)" if bits in (10, 12) else ""
+
+
 def measured_traffic(tile: dict):
     """HBM bytes per hist launch from the committed rocprofv3 counter summary
     (one entry per profiled tile shape), or None if it is missing, was taken
@@ -732,7 +738,7 @@ def main():
                                 "P-splines d=24 df=5, nu=0.1 (synthetic, seed 2)"),
                    "n": args.n, "p": args.p, "n_bins": 1000, "variant": "cwb", "loss": "l2",
                    "iterations_in_fit": int(prob["M"])},
-        "precision": ("uint16 bin indices (read as a 12-bit packed copy); exact fixed-point "
+        "precision": (f"uint16 bin indices{index_read(h['tile'])}; exact fixed-point "
                       "histograms in 32-bit LDS words (int64 where a bin's count needs it); "
                       "fp32 model state; int64 merge; fp64 solves and selection"),
         "hbm_gbs": round(h["iter_gbs"], 1),

@@ -309,6 +309,10 @@ typedef struct {
                           fewer than 2^acc32_bits rows in each bin */
   int32_t acc32_bits;  /* the fit's count bound (the largest over the batch's
                           fits); 0: int64 sums at the int64 scale */
+  int32_t index_bits;  /* bits per bin index the histogram pass reads: 10 or
+                          12 (a packed copy of the index matrix) or 16 (the
+                          matrix itself); a batch reports the widest over
+                          its fits */
   double tuned_us;     /* measured pass time of the chosen shape (0: not tuned) */
 } cwb_tile;
 int cwb_fit_tile(const cwb_fit* f, cwb_tile* out);

@@ -295,77 +295,84 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
   if (base >= r1) return;
   uint32_t* __restrict__ h32 = reinterpret_cast<uint32_t*>(hist);
-  // software pipeline: the loads of the next fold (or of the next row step)
-  // are issued before the current fold's atomics
+  // Each row step loads the learners' indices once and the residuals of up
+  // to QB folds at a time, all issued before the first of their atomics, so
+  // that a step waits on one round of loads per QB folds rather than one per
+  // fold; the next step's indices are loaded before this step's atomics.
+  constexpr int QB = 4;
   u32x4 xw[FMAX];
-  float rv[8], cv[8];
 #pragma unroll
   for (int f = 0; f < FMAX; ++f)
     if (f < nf) xw[f] = load_idx(Xg + f * ld + base);
-  load8f(fits[sg.fit + first].r + base, rv);
-  if (NSIG == 2) load8f(fits[sg.fit + first].c + base, cv);
   for (;;) {
     const int64_t nxt = base + (int64_t)NT * 8;
     const bool more = nxt < r1;
     u32x4 xc[FMAX];
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) xc[f] = xw[f];
-    int q = first;
-    for (;;) {
-      const int qn = next_fold(q);
-      long long q0[8], q1[8];
-      int p0[8];
-      unsigned long long pk[8];
-      if (W32 && NSIG == 1) {
+    if (more) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) p0[j] = fixed32(rv[j], e[2 * q]);
-      } else if (W32) {
+      for (int f = 0; f < FMAX; ++f)
+        if (f < nf) xw[f] = load_idx(Xg + f * ld + nxt);
+    }
+    const int lane = COPIES ? opaque_lane() : 0;
+    for (int q = first; q >= 0;) {
+      int qs[QB];
+      float rv[QB][8], cv[QB][8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          pk[j] = pack_signals(fixed32(rv[j], e[2 * q]), fixed32(cv[j], e[2 * q + 1]));
-      } else if (r32) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) q0[j] = (long long)fixed32(rv[j], e[2 * q]);
-        if (NSIG == 2) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) q1[j] = (long long)fixed32(cv[j], e[2 * q + 1]);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[j], e[2 * q]);
-        if (NSIG == 2) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[j], e[2 * q + 1]);
+      for (int i = 0; i < QB; ++i) {
+        qs[i] = q;
+        if (q >= 0) {
+          load8f(fits[sg.fit + q].r + base, rv[i]);
+          if (NSIG == 2) load8f(fits[sg.fit + q].c + base, cv[i]);
+          q = next_fold(q);
         }
       }
-      if (qn >= 0) {
-        load8f(fits[sg.fit + qn].r + base, rv);
-        if (NSIG == 2) load8f(fits[sg.fit + qn].c + base, cv);
-      } else if (more) {
 #pragma unroll
-        for (int f = 0; f < FMAX; ++f)
-          if (f < nf) xw[f] = load_idx(Xg + f * ld + nxt);
-        load8f(fits[sg.fit + first].r + nxt, rv);
-        if (NSIG == 2) load8f(fits[sg.fit + first].c + nxt, cv);
-      }
-      const int lane = COPIES ? opaque_lane() : 0;
+      for (int i = 0; i < QB; ++i) {
+        const int qf = qs[i];
+        if (qf < 0) continue;
+        long long q0[8], q1[8];
+        int p0[8];
+        unsigned long long pk[8];
+        if (W32 && NSIG == 1) {
 #pragma unroll
-      for (int f = 0; f < FMAX; ++f) {
-        if (f < nf) {
-          const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;
-          if (W32) {
-            const size_t w = (size_t)(q * nf + f) * nb + cb;
-            if (NSIG == 1) hist_add32(h32 + w, xc[f], p0);
-            else hist_add_packed(hist + w, xc[f], pk);
-          } else {
-            unsigned long long* hq = hist + (size_t)q * NSIG * nf * nb;
-            hist_add<NSIG>(hq + (size_t)f * nb + cb, xc[f], q0);
-            if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb + cb, xc[f], q1);
+          for (int j = 0; j < 8; ++j) p0[j] = fixed32(rv[i][j], e[2 * qf]);
+        } else if (W32) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            pk[j] = pack_signals(fixed32(rv[i][j], e[2 * qf]), fixed32(cv[i][j], e[2 * qf + 1]));
+        } else if (r32) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) q0[j] = (long long)fixed32(rv[i][j], e[2 * qf]);
+          if (NSIG == 2) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) q1[j] = (long long)fixed32(cv[i][j], e[2 * qf + 1]);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) q0[j] = fixed_point(rv[i][j], e[2 * qf]);
+          if (NSIG == 2) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) q1[j] = fixed_point(cv[i][j], e[2 * qf + 1]);
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < FMAX; ++f) {
+          if (f < nf) {
+            const int cb = COPIES ? (lane & cm[f]) * cs[f] : 0;
+            if (W32) {
+              const size_t w = (size_t)(qf * nf + f) * nb + cb;
+              if (NSIG == 1) hist_add32(h32 + w, xc[f], p0);
+              else hist_add_packed(hist + w, xc[f], pk);
+            } else {
+              unsigned long long* hq = hist + (size_t)qf * NSIG * nf * nb;
+              hist_add<NSIG>(hq + (size_t)f * nb + cb, xc[f], q0);
+              if (NSIG == 2) hist_add<NSIG>(hq + (size_t)(nf + f) * nb + cb, xc[f], q1);
+            }
           }
         }
       }
-      if (qn < 0) break;
-      q = qn;
     }
     if (!more) break;
     base = nxt;

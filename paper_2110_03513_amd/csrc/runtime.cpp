@@ -1653,6 +1653,12 @@ int cwb_fit_kernel_time(cwb_fit* f, const char* kernel, double* total_ms, int64_
   return CWB_OK;
 }
 
+namespace {
+// Bits per bin index the fit's histogram pass reads (its packed copy, or
+// the uint16 matrix).
+int fit_index_bits(const cwb_fit* f) { return f->dev.X12 ? f->dev.xbits : 16; }
+}  // namespace
+
 int cwb_fit_tile(const cwb_fit* f, cwb_tile* out) {
   if (!f || !out) return set_error(CWB_E_INVALID_ARG, "null argument");
   out->threads = f->tune.nt;
@@ -1661,6 +1667,7 @@ int cwb_fit_tile(const cwb_fit* f, cwb_tile* out) {
   out->candidates = f->n_cands;
   out->learners32 = learners32(f->sched);
   out->acc32_bits = f->shape.acc32_bits;
+  out->index_bits = fit_index_bits(f);
   out->tuned_us = f->tuned_us;
   return CWB_OK;
 }
@@ -1926,7 +1933,11 @@ int cwb_batch_tile(const cwb_batch* b, cwb_tile* out) {
   out->candidates = b->n_cands;
   out->learners32 = learners32(b->sched);
   out->acc32_bits = 0;
-  for (const cwb_fit* f : b->fits) out->acc32_bits = std::max(out->acc32_bits, f->shape.acc32_bits);
+  out->index_bits = 0;
+  for (const cwb_fit* f : b->fits) {
+    out->acc32_bits = std::max(out->acc32_bits, f->shape.acc32_bits);
+    out->index_bits = std::max(out->index_bits, fit_index_bits(f));
+  }
   out->tuned_us = b->tuned_us;
   return CWB_OK;
 }

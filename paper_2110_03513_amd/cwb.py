@@ -53,7 +53,7 @@ class cwb_info(C.Structure):
 class cwb_tile(C.Structure):
     _fields_ = [("threads", C.c_int32), ("learners", C.c_int32), ("blocks", C.c_int32),
                 ("candidates", C.c_int32), ("learners32", C.c_int32), ("acc32_bits", C.c_int32),
-                ("tuned_us", C.c_double)]
+                ("index_bits", C.c_int32), ("tuned_us", C.c_double)]
 
 
 class cwb_server_cfg(C.Structure):

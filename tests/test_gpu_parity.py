@@ -699,10 +699,15 @@ def test_packed_index_copies_bitwise(nb, variant, monkeypatch):
     prob = datagen.additive_problem(50_003, 7, seed=191, n_informative=3, n_bins=nb, M=50,
                                     variant=variant, gamma=0.05, loss="binomial")
     ref = _run(prob)
+    # the tile report names the copy each run reads: 10 bits for one signal
+    # and indices below 1,024, else 12; 16 for the uint16 matrix
+    ten = nb <= 1024 and variant == "cwb"
+    assert cwb.Fit(prob).tile()["index_bits"] == (10 if ten else 12)
     runs = {}
     for name, env in (("x12", {"CWB_X10": "0"}), ("u16", {"CWB_X12": "0"})):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
+        assert cwb.Fit(prob).tile()["index_bits"] == (12 if name == "x12" else 16)
         runs[name] = _run(prob)
         for k in env:
             monkeypatch.delenv(k)
