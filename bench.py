@@ -128,7 +128,7 @@ def headline(args, torch, cwb, datagen):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     # measured bytes (the 12-bit index copy moves fewer than the
+                     # measured bytes (the packed index copy moves fewer than the
                      # uint16 formulation's algorithmic bytes) over the same time
                      "traffic_gbs": (round(traffic / hist_avg_s / 1e9, 1)
                                      if traffic else None)},

@@ -169,8 +169,6 @@ struct RowItem {
   Ctl* ctl;
   const double* q;      // the fit's criteria [kNumSig][p] of the last selection
   const uint16_t* X;
-  const uint32_t* X12;   // 12-bit copy of X read by 32-bit histogram groups (8 rows
-                         // in 3 words, learner k at word 3 k n_pad / 8), or null
   const float* y;
   float* fg;
   float* h;

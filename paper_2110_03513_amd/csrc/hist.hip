@@ -299,7 +299,8 @@ __device__ __forceinline__ void hist_rows_folds(const FitDev* __restrict__ fits,
   // to QB folds at a time, all issued before the first of their atomics, so
   // that a step waits on one round of loads per QB folds rather than one per
   // fold; the next step's indices are loaded before this step's atomics.
-  constexpr int QB = 4;
+  // Two signals hold r and c per fold, so they take two folds a round.
+  constexpr int QB = NSIG == 2 ? 2 : 4;
   u32x4 xw[FMAX];
 #pragma unroll
   for (int f = 0; f < FMAX; ++f)

@@ -1207,7 +1207,7 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   if (sh.unbinned != hf.unbinned)
     return set_error(CWB_E_INVALID_ARG, "learner kinds disagree with the specification");
   D.X = fold ? fold->X : dptr<uint16_t>(ws, L.X);
-  // the 12-bit copy serves the 32-bit histogram groups only
+  // the packed copy serves the 32-bit histogram groups only
   const bool pack12 = sh.x12 && !fold && !sh.external_x && f->shape.acc32_bits > 0 &&
                       env_int("CWB_X12", 1) != 0;
   D.X12 = pack12 ? dptr<uint32_t>(ws, L.X12) : nullptr;

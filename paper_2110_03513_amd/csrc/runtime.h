@@ -24,7 +24,8 @@ struct FitShape {
   int n_row_blocks = 0, n_val_blocks = 0;
   bool unbinned = false;  // learners are unbinned cubic P-splines
   bool copies = false;    // some binned learner gets LDS histogram copies (copy_mask)
-  bool x12 = false;       // the workspace holds a 12-bit copy of X (every bin below 4,096)
+  bool x12 = false;       // the workspace holds a packed copy of X, 10 or 12 bits
+                          // per index (every bin below 4,096)
   // Folds of a cross-validation share one index matrix and one histogram
   // pass: the first fold's shape has share = the number of folds (the
   // others follow it in the fit list, with share = 0); other fits have 1.
