@@ -212,10 +212,18 @@ int plan_candidates(const std::vector<const FitShape*>& shapes, bool all, std::v
 // Time the histogram pass of each candidate on the fits' current data and
 // return the index of the fastest.  The pass only reads the model state and
 // writes the histogram partials (exact integer sums), so trying candidates
-// changes no result.
+// changes no result.  With `row` (a fit that has made no selection yet,
+// whose row pass then recomputes the same residuals however often it runs),
+// every timed pass follows a row pass, as inside an iteration, and the row
+// pass's own time is taken off.
+struct TuneRowPass {
+  const RowItem* items = nullptr;
+  int n = 0, nb_max = 0;
+  bool unbinned = false;
+};
 int autotune_hist(hipStream_t st, const FitDev* d_fits, const std::vector<const FitShape*>& shapes,
                   const std::vector<Tune>& cands, const SchedCap& cap, Seg* d_segs, int64_t* d_blk,
-                  long long* d_part, int* best, double* best_us);
+                  long long* d_part, int* best, double* best_us, const TuneRowPass* row = nullptr);
 // Device bytes of a fit of this shape (its workspace layout, sized for every
 // candidate tile shape when `all`).
 int fit_footprint(const FitShape& sh, size_t* bytes, bool all);
