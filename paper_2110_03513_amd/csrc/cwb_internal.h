@@ -107,6 +107,8 @@ struct FitDev {
   const uint32_t* X12;   // packed copy of X read by 32-bit histogram groups, at
                          // xbits per index (learner k at word 3 k n_pad / 8 for
                          // 12 bits, 5 k n_pad / 16 for 10), or null
+  const uint32_t* X10h;  // HCWB: a 10-bit copy read by the one-signal passes
+                         // after the switch (the ACWB phase reads X12), or null
   const float* y;
   float* fg;
   float* h;

@@ -179,16 +179,18 @@ __device__ __forceinline__ u32x4 unpack12(const u32x3& w) {
 // signals: both values of a row packed into one 8-byte word (pack_signals),
 // learner f at word f * nb, so an ACWB row costs one LDS atomic per
 // learner, as a CWB row does.  XB is the index width read: 16 (the uint16
-// matrix), 12 or 10 (the packed copy F.X12 at F.xbits; 12 or 10 bytes per 8
-// rows and learner instead of 16), a template parameter so that each
+// matrix), 12 or 10 (the packed copy `xpk`: F.X12 at F.xbits, or an HCWB
+// fit's 10-bit F.X10h after its switch; 12 or 10 bytes per 8 rows and
+// learner instead of 16), a template parameter so that each
 // instantiation unpacks one way only.  With COPIES a learner of few bins
 // spreads over copies of its histogram by lane, as in hist_rows (the
 // schedule takes 32-bit words for it only while each copy receives fewer
 // than 2^acc32_bits rows of the segment).
 template <int NT, int FMAX, int NSIG, int XB, bool COPIES>
-__device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void* __restrict__ hist,
-                                            int nb, int64_t r0, int64_t r1, Exps& ex, bool need_e,
-                                            int64_t n_fit, float* red, const int (*cp)[16]) {
+__device__ __forceinline__ void hist_rows32(const FitDev& F, const uint32_t* xpk, const Seg& sg,
+                                            void* __restrict__ hist, int nb, int64_t r0, int64_t r1,
+                                            Exps& ex, bool need_e, int64_t n_fit, float* red,
+                                            const int (*cp)[16]) {
   int cm[FMAX], cs[FMAX];  // copy masks and strides, wave-uniform
 #pragma unroll
   for (int f = 0; f < FMAX; ++f) {
@@ -202,7 +204,7 @@ __device__ __forceinline__ void hist_rows32(const FitDev& F, const Seg& sg, void
   constexpr bool X12 = XB != 16;
   constexpr bool x10 = XB == 10;
   const size_t ldp = x10 ? (size_t)F.n_pad / 16 * 5 : (size_t)F.n_pad / 8 * 3;  // words per learner
-  const uint32_t* __restrict__ Xp = X12 ? F.X12 + (size_t)sg.k0 * ldp : nullptr;
+  const uint32_t* __restrict__ Xp = X12 ? xpk + (size_t)sg.k0 * ldp : nullptr;
   const int nf = sg.nf;
   const size_t ld = (size_t)F.n_pad;
   int64_t base = r0 + (int64_t)threadIdx.x * 8;
@@ -512,19 +514,22 @@ k_hist(const FitDev* __restrict__ fits, const Seg* __restrict__ segs,
       else
         uhist_rows<NT, FMAX, NSMAX>(F, sg, s_hist, nb, r0, r1, ex.e[0], ex.e[1]);
     } else if (w32) {
-      // the 10-bit copy is built for one-signal fits only
+      // 10-bit copies serve one-signal passes only: a one-signal fit's X12,
+      // or an HCWB fit's X10h after its switch
       if (F.X12 && F.xbits == 10) {
-        hist_rows32<NT, FMAX, 1, 10, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+        hist_rows32<NT, FMAX, 1, 10, COPIES>(F, F.X12, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+      } else if (nsig == 1 && F.X10h) {
+        hist_rows32<NT, FMAX, 1, 10, COPIES>(F, F.X10h, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       } else if (F.X12) {
         if (NSMAX == 1 || nsig == 1)
-          hist_rows32<NT, FMAX, 1, 12, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, 1, 12, COPIES>(F, F.X12, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
         else
-          hist_rows32<NT, FMAX, NSMAX, 12, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, NSMAX, 12, COPIES>(F, F.X12, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       } else {
         if (NSMAX == 1 || nsig == 1)
-          hist_rows32<NT, FMAX, 1, 16, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, 1, 16, COPIES>(F, nullptr, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
         else
-          hist_rows32<NT, FMAX, NSMAX, 16, COPIES>(F, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
+          hist_rows32<NT, FMAX, NSMAX, 16, COPIES>(F, nullptr, sg, s_hist, nb, r0, r1, ex, need_e, n_fit, s_red, s_cp);
       }
     } else {
       if (NSMAX == 1 || nsig == 1)

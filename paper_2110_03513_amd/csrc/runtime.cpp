@@ -601,6 +601,7 @@ Layout make_layout(const FitShape& sh, const SchedCap& s) {
   // inputs and tables
   L.X = take(sh.external_x ? 0 : (size_t)sh.p * np * (sh.unbinned ? 4 : 2));
   L.X12 = take(sh.x12 && !sh.external_x ? (size_t)sh.p * np / 8 * 12 : 0);
+  L.X10h = take(sh.x10_after_switch() ? (size_t)sh.p * np / 16 * 20 : 0);
   L.y = take(np * 4);
   L.r = take(np * 4);
   L.feat = take((size_t)sh.p * sizeof(FeatDev));
@@ -1238,6 +1239,11 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   // unpacking's extra work outweighed the saved bytes in most tiles.
   D.xbits = !pack12 ? 0
             : (sh.nb_max <= 1024 && sh.nsig_max == 1 && env_int("CWB_X10", 1) != 0) ? 10 : 12;
+  // HCWB: its passes after the switch have one signal and read a 10-bit copy
+  // of their own (at n = 2e6, p = 160 the CWB phase's pass is HBM-bound)
+  D.X10h = (pack12 && D.xbits == 12 && sh.x10_after_switch() && env_int("CWB_X10", 1) != 0)
+               ? dptr<uint32_t>(ws, L.X10h)
+               : nullptr;
   if (fold) {
     D.fold = fold->fold;
     D.fold_k = fold->k;
@@ -1300,6 +1306,9 @@ int fit_upload(const FitShape& sh, HostFit& hf, void* dev_ws, size_t ws_bytes, h
   else if (D.xbits == 12)
     HIP_TRY(launch_pack12(st, dptr<uint16_t>(ws, L.X), (int64_t)sh.p * sh.n_pad / 8,
                           dptr<uint32_t>(ws, L.X12)));
+  if (D.X10h)
+    HIP_TRY(launch_pack10(st, dptr<uint16_t>(ws, L.X), (int64_t)sh.p * sh.n_pad / 16,
+                          dptr<uint32_t>(ws, L.X10h)));
   HIP_TRY(hipMemcpyAsync(ws + L.y, hf.y.data(), hf.y.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(ws + L.r, 0, (size_t)sh.n_pad * 4, st));
   HIP_TRY(hipMemcpyAsync(ws + L.feat, feat.data(), feat.size() * sizeof(FeatDev), hipMemcpyHostToDevice, st));

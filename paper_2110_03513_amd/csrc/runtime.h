@@ -26,6 +26,11 @@ struct FitShape {
   bool copies = false;    // some binned learner gets LDS histogram copies (copy_mask)
   bool x12 = false;       // the workspace holds a packed copy of X, 10 or 12 bits
                           // per index (every bin below 4,096)
+  // HCWB with every bin below 1,024: a second, 10-bit copy for the
+  // one-signal passes after the switch (the ACWB phase reads 12 bits)
+  bool x10_after_switch() const {
+    return x12 && !external_x && variant == CWB_HCWB && nb_max <= 1024;
+  }
   // Folds of a cross-validation share one index matrix and one histogram
   // pass: the first fold's shape has share = the number of folds (the
   // others follow it in the fit list, with share = 0); other fits have 1.
@@ -105,7 +110,7 @@ struct Layout {
       coef_h;
   size_t state_begin, state_end;  // mutable state region (checkpoint)
   size_t X, y, r, feat, bstart, bval, jr, ainv[2], gram[2], riskpart, amaxpart, valpart, fitdev;
-  size_t X12;
+  size_t X12, X10h;
   size_t segs, blk, sel_off, partials, st_items, sel_items, val_items;
   size_t total;
 };

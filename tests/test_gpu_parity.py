@@ -108,6 +108,27 @@ def test_hcwb_forced_switch_by_mirrored_validation_labels():
     compare(gpu, prob)
 
 
+def test_hcwb_ten_bit_copy_after_the_switch_bitwise(monkeypatch):
+    """An HCWB fit with every bin below 1,024 reads a 10-bit copy of the
+    index matrix in its one-signal passes after the switch (its ACWB phase
+    reads the 12-bit copy): bitwise the run without it, and the oracle's."""
+    rng = np.random.default_rng(57)
+    half, p = 30_001, 6
+    x1 = rng.uniform(0, 1, (half, p))
+    y1 = np.sin(5 * x1[:, 0]) + 2 * x1[:, 1] + rng.normal(0, 0.1, half)
+    prob = {"x": np.vstack([x1, x1]), "y": np.concatenate([y1, 2 * y1.mean() - y1]),
+            "loss": "l2", "nu": 0.1, "M": 60, "variant": "hcwb", "gamma": 0.01, "patience": 4,
+            "val_mask": np.concatenate([np.zeros(half), np.ones(half)]).astype(np.uint8)}
+    prob.update(datagen.learner_specs(p, 1000))
+    ref = _run(prob)
+    assert ref["switch_iter"] == 5
+    monkeypatch.setenv("CWB_X10", "0")
+    got = _run(prob)
+    for key in ("k", "kcor", "theta", "f", "coef_f", "risk_train"):
+        np.testing.assert_array_equal(got[key], ref[key], err_msg=key)
+    compare(ref, prob)
+
+
 @pytest.mark.parametrize("patience", [0, 1000])
 def test_hcwb_limits(patience):
     prob = datagen.additive_problem(30_000, 8, seed=13, n_informative=3, loss="l2", n_bins=150,
