@@ -60,6 +60,20 @@ def test_workspace_sizes_and_schedule(n, p, nb, variant, env, monkeypatch):
     assert b % 256 == 0
 
 
+def test_hcwb_workspace_holds_a_ten_bit_copy_for_after_the_switch():
+    # bins below 1,024: an HCWB fit also keeps a 10-bit copy of the index
+    # matrix (1.25 n p bytes) for its one-signal passes after the switch;
+    # with more bins it has none, and an ACWB fit never has one
+    n, p = 100_000, 20
+    for nb, extra in ((1000, True), (2000, False)):
+        acwb = cwb.workspace_bytes(_shape_only_problem(n, p, nb, "acwb"))
+        hcwb = cwb.workspace_bytes(_shape_only_problem(n, p, nb, "hcwb"))
+        if extra:
+            assert hcwb - acwb >= 1.25 * n * p
+        else:
+            assert hcwb - acwb < 0.25 * n * p
+
+
 def _shape_only_problem(n, p, nb, variant):
     # x is never read by cwb_workspace_bytes beyond its shape
     x = np.zeros((n, p))
